@@ -1,0 +1,186 @@
+/*
+ * lbm.h -- C interface of the MI355X library for the modified lattice-BGK model of
+ * convection heat transfer in porous media at the REV scale (Wang, Mi & Guo,
+ * arXiv:1505.02976).
+ *
+ * One call of lbm_step advances the coupled D2Q9 flow and D2Q9 temperature populations by
+ * one time step: streaming (Sec. 3.1, Eq. LBEeq; Sec. 3.2, streaming substep of
+ * Eq. TEqColli), the non-equilibrium extrapolation boundary scheme (Sec. 3.4), the local
+ * macroscopic quantities (temperature, Sec. 3.2; velocity through the quadratic drag
+ * solve and pressure, Sec. 3.1; shear rate, Eq. ShearEqCom; temperature gradient,
+ * Eqs. SonaT-MatrN), the modified equilibria (Eqs. EQFIN, EQTSHIN, TeEDFEQ), the forcing
+ * and source terms (Eqs. FtermF, Eq:Tforce) and the BGK collision (Eqs. LBEeq, TEqColli).
+ *
+ * Conventions for every function:
+ *   - Pointers named "device" are HIP device pointers on the device that is current when
+ *     lbm_init is called; pointers named "host" are ordinary host memory.
+ *   - Every call returns an lbm_status and never aborts; on failure lbm_last_error()
+ *     returns a message (thread-local, valid until the next failing call on the thread).
+ *   - Work is enqueued on the HIP stream given to lbm_init, in call order.  Calls marked
+ *     "synchronizes" wait for that stream.
+ *   - A context is used from one host thread at a time; distinct contexts are independent.
+ *   - Asynchronous device faults surface as LBM_ERR_DEVICE on the next call that checks.
+ *
+ * Lattice units throughout: dx = dt = 1, cs^2 = 1/3, rho0 = 1.  Field arrays are
+ * row-major [ny][nx] (x fastest).  Population arrays are [2][9][ny][nx]: flow populations
+ * f_0..f_8 then temperature populations g_0..g_8, directions c_0 = (0,0), c_1 = (1,0),
+ * c_2 = (0,1), c_3 = (-1,0), c_4 = (0,-1), c_5 = (1,1), c_6 = (-1,1), c_7 = (-1,-1),
+ * c_8 = (1,-1) (Sec. 3.1).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_INVALID = 1,      /* a parameter or buffer is unusable; nothing was enqueued    */
+    LBM_ERR_DEVICE = 2,       /* a HIP call failed (launch, copy, synchronisation)          */
+    LBM_ERR_NONFINITE = 3,    /* a population or field became NaN or infinite               */
+    LBM_ERR_UNSUPPORTED = 4   /* valid request this build does not provide                  */
+} lbm_status;
+
+/* Storage precision of the populations.  F32 and F16 store deviations from the rest
+ * state (f_0 - rho0 and g_i - omega_i sigma T0; F16 additionally scaled by 256) and
+ * compute the collision in FP32, with the quadratic drag solve and every reduction in
+ * FP64.  F64 stores and computes in FP64. */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 } lbm_storage;
+
+/* Thermal wall condition (Sec. 3.4): isothermal (Eqs. TeEBounDFEQ, TNEESAp) or prescribed
+ * normal temperature derivative (Eq. TNEESApGra). */
+typedef enum { LBM_T_DIRICHLET = 0, LBM_T_NEUMANN = 1 } lbm_twall;
+
+/* One wall.  The velocity condition is always a prescribed wall velocity (ux, uy).
+ * dTdn is the derivative of T along the inward wall normal. */
+typedef struct {
+    double ux, uy;
+    int32_t t_kind;           /* lbm_twall */
+    int32_t reserved;
+    double T, dTdn;
+} lbm_wall;
+
+/* Problem description.  Derived lattice constants:
+ *   L     = characteristic length: L if > 0, else nx - 1 if x is walled, else ny - 1 if y is
+ *           walled, else nx (wet-node walls: n nodes across a walled direction span n - 1)
+ *   A, B  = given, or if either is NaN from Ma, Ra, Pr (Eq. EQA&B, with the factor J on
+ *           the A term):  A = tau_f - 1/2 - J Ma L sqrt(3 Pr / Ra),
+ *                         B = tau_T - 1/2 - (Ma / sigma) L sqrt(3 / (Pr Ra))
+ *   nu_e  = cs^2 (tau_f - A - 1/2) (Sec. 3.1),  nu = nu_e / J (Sec. 2),
+ *   alpha_e = sigma cs^2 (tau_T - B - 1/2) (Eq. Therdiff),
+ *   g beta = Ra nu alpha_e / (dT L^3) (Ra of Sec. 2; 0 when Ra = 0),
+ *   K     = Da L^2 (Sec. 2; Da = +inf removes the Darcy and Forchheimer drag),
+ *   F_eps = given, or if NaN the Ergun relation 1.75 / sqrt(150 eps^3) per node (Sec. 2),
+ *   T0    = (T_hot + T_cold) / 2, dT = T_hot - T_cold.
+ * Walls, in order x- (x = 0), x+ (x = nx-1), y- (y = 0), y+ (y = ny-1), exist only for
+ * non-periodic directions.  Corners: the inward diagonal neighbour is the reference
+ * node, the velocity is zero, an isothermal wall takes precedence over a Neumann wall and
+ * the x-wall over the y-wall.
+ * Initial state: the post-collision populations before the first step are the equilibria
+ * of (p_init, ux_init, uy_init, T_init) with zero shear rate and temperature gradient;
+ * a NULL field means p = 0, u = 0, and T = T0 except T = T_wall on isothermal wall nodes.
+ * Field pointers are device [ny][nx] FP64 arrays read during lbm_init only (the porosity
+ * field is copied into the workspace). */
+typedef struct {
+    int32_t nx, ny;
+    int32_t periodic_x, periodic_y;
+    lbm_wall wall[4];
+    double L;
+    double Da, Ra, Pr, J, Ma, sigma, Q;
+    double tau_f, tau_T;
+    double A, B;
+    double eps;                       /* uniform porosity, used when eps_field is NULL     */
+    double ax, ay;                    /* external acceleration a (Sec. 2)                  */
+    double T_hot, T_cold;
+    double F_eps;
+    const double *eps_field;          /* device, optional                                   */
+    const double *T_init;             /* device, optional                                   */
+    const double *p_init;             /* device, optional                                   */
+    const double *ux_init;            /* device, optional                                   */
+    const double *uy_init;            /* device, optional                                   */
+    int32_t storage;                  /* lbm_storage                                        */
+    int32_t reserved;
+} lbm_params;
+
+/* Lattice constants derived from a problem (see lbm_params). */
+typedef struct {
+    double L, A, B, nu_e, nu, alpha_e, gbeta, K, T0, dT;
+} lbm_derived;
+
+/* Validates params and fills *out (host).  LBM_ERR_INVALID when the parameters are
+ * unusable: nx or ny < 1; a walled direction with < 3 nodes (< 4 if a Neumann wall lies
+ * on either end); tau_f or tau_T <= 1/2; nu_e <= 0 (A >= tau_f - 1/2); alpha_e <= 0
+ * (B >= tau_T - 1/2); eps outside (0, 1]; Da <= 0; sigma, J <= 0; A or B NaN with
+ * Ra <= 0 or Pr <= 0; storage unknown. */
+lbm_status lbm_derive(const lbm_params *params, lbm_derived *out);
+
+/* Bytes of device workspace lbm_init needs for params (0 if params are invalid). */
+size_t lbm_workspace_bytes(const lbm_params *params);
+
+/* Creates a context on the current device.  workspace: device buffer of at least
+ * lbm_workspace_bytes(params) bytes, 256-byte aligned, owned by the caller and kept alive
+ * until lbm_destroy; the library owns its contents.  hip_stream: a hipStream_t (NULL =
+ * default stream).  Enqueues the initialisation.  *out receives a context that the
+ * caller releases with lbm_destroy. */
+lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_bytes,
+                    void *hip_stream, lbm_ctx **out);
+
+/* Enqueues nsteps >= 0 time steps (asynchronous). */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
+
+/* As lbm_step, with a HIP event recorded before and after every kernel launch; returns
+ * the summed kernel durations in milliseconds of the bulk-node kernel and of the
+ * wall-node kernel over the nsteps steps (host outputs; either may be NULL).  Used for
+ * measurement.  Synchronizes. */
+lbm_status lbm_step_timed(lbm_ctx *ctx, int64_t nsteps, double *bulk_ms_host, double *wall_ms_host);
+
+/* Number of steps taken since lbm_init. */
+int64_t lbm_time(const lbm_ctx *ctx);
+
+/* Macroscopic fields at the current time (device outputs, [ny][nx], NULL = skip):
+ * pressure p, velocity ux, uy, temperature T.  out_dtype 0 = FP64, 1 = FP32.
+ * Asynchronous. */
+lbm_status lbm_moments(lbm_ctx *ctx, int32_t out_dtype, void *p, void *ux, void *uy, void *T);
+
+/* Local gradients at the current time (device outputs, NULL = skip): shear rate
+ * S = grad u + (grad u)^T from Eq. ShearEqCom (Sxx, Sxy, Syy) and the temperature
+ * gradient from Eq. TeEqCom (dTdx, dTdy).  out_dtype as in lbm_moments. Asynchronous. */
+lbm_status lbm_gradients(lbm_ctx *ctx, int32_t out_dtype, void *Sxx, void *Sxy, void *Syy,
+                         void *dTdx, void *dTdy);
+
+/* Average Nusselt number on one wall (0..3) at the current time, Eq. AvNuss:
+ * Nu_j = -L (dT/dn_axis) / dT with the second-order one-sided difference along the
+ * wall-normal axis, averaged over the wall by the trapezoid rule; FP64 arithmetic,
+ * fixed summation order.  *nu_host receives the value.  Synchronizes. */
+lbm_status lbm_nusselt(lbm_ctx *ctx, int32_t wall, double *nu_host);
+
+/* Convergence measure of Sec. 4: r_u = sum |u(t) - u(s)|_2 / sum |u(t)|_2 and
+ * r_T = sum |T(t) - T(s)| / sum |T(t)| against the snapshot s taken at the previous
+ * call, then takes a new snapshot.  The first call after lbm_init only takes the
+ * snapshot and returns -1 in both.  FP64 arithmetic, fixed summation order.  Returns
+ * LBM_ERR_NONFINITE if any population is not finite.  Synchronizes. */
+lbm_status lbm_residual(lbm_ctx *ctx, double *r_u_host, double *r_T_host);
+
+/* Copies the post-collision populations of the last step as raw FP64 values
+ * ([2][9][ny][nx], device) out of / into the context.  lbm_set_state keeps the time.
+ * Asynchronous. */
+lbm_status lbm_get_state(lbm_ctx *ctx, double *dst_device);
+lbm_status lbm_set_state(lbm_ctx *ctx, const double *src_device);
+
+/* Releases the context (host memory only; the workspace stays with the caller). */
+void lbm_destroy(lbm_ctx *ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,365 @@
+// C interface (include/lbm.h): parameter validation and mapping, workspace layout,
+// context bookkeeping and dispatch to the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/lbm.h"
+#include "lbm_kernels.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+lbm_status fail(lbm_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+lbm_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(LBM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_size(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
+
+// Mapping of Sec. 2, Sec. 3.1, Eq. Therdiff and Eq. EQA&B (see lbm_params in lbm.h).
+lbm_status derive(const lbm_params *p, lbm_derived *d)
+{
+    if (!p) return fail(LBM_ERR_INVALID, "params is NULL");
+    if (p->nx < 1 || p->ny < 1) return fail(LBM_ERR_INVALID, "nx, ny must be >= 1");
+    if (p->storage < LBM_F64 || p->storage > LBM_F16) return fail(LBM_ERR_INVALID, "unknown storage %d", p->storage);
+    for (int ax = 0; ax < 2; ++ax) {
+        const int periodic = ax == 0 ? p->periodic_x : p->periodic_y;
+        const int n = ax == 0 ? p->nx : p->ny;
+        if (periodic) continue;
+        const bool neumann = p->wall[2 * ax].t_kind == LBM_T_NEUMANN || p->wall[2 * ax + 1].t_kind == LBM_T_NEUMANN;
+        const int need = neumann ? 4 : 3;
+        if (n < need) return fail(LBM_ERR_INVALID, "walled direction %c needs >= %d nodes", ax ? 'y' : 'x', need);
+        for (int k = 2 * ax; k < 2 * ax + 2; ++k)
+            if (p->wall[k].t_kind != LBM_T_DIRICHLET && p->wall[k].t_kind != LBM_T_NEUMANN)
+                return fail(LBM_ERR_INVALID, "wall %d: unknown thermal kind", k);
+    }
+    if (!(p->tau_f > 0.5) || !(p->tau_T > 0.5)) return fail(LBM_ERR_INVALID, "tau_f and tau_T must exceed 1/2");
+    if (!(p->sigma > 0) || !(p->J > 0)) return fail(LBM_ERR_INVALID, "sigma and J must be positive");
+    if (!(p->eps > 0 && p->eps <= 1)) return fail(LBM_ERR_INVALID, "eps must lie in (0, 1]");
+    if (!(p->Da > 0)) return fail(LBM_ERR_INVALID, "Da must be positive (inf allowed)");
+    if (!std::isfinite(p->Q) || !std::isfinite(p->ax) || !std::isfinite(p->ay))
+        return fail(LBM_ERR_INVALID, "Q, ax, ay must be finite");
+
+    if (p->L > 0) d->L = p->L;
+    else if (!p->periodic_x) d->L = p->nx - 1;
+    else if (!p->periodic_y) d->L = p->ny - 1;
+    else d->L = p->nx;
+    d->T0 = 0.5 * (p->T_hot + p->T_cold);
+    d->dT = p->T_hot - p->T_cold;
+    if (std::isnan(p->A) || std::isnan(p->B)) {
+        if (!(p->Ra > 0) || !(p->Pr > 0) || !(p->Ma > 0))
+            return fail(LBM_ERR_INVALID, "A, B from Ma need Ra > 0, Pr > 0, Ma > 0");
+        d->A = p->tau_f - 0.5 - p->J * p->Ma * d->L * std::sqrt(3.0 * p->Pr / p->Ra);
+        d->B = p->tau_T - 0.5 - (p->Ma / p->sigma) * d->L * std::sqrt(3.0 / (p->Pr * p->Ra));
+    } else {
+        d->A = p->A;
+        d->B = p->B;
+    }
+    d->nu_e = (p->tau_f - d->A - 0.5) / 3.0;
+    d->nu = d->nu_e / p->J;
+    d->alpha_e = p->sigma * (p->tau_T - d->B - 0.5) / 3.0;
+    if (!(d->nu_e > 0)) return fail(LBM_ERR_INVALID, "nu_e <= 0 (A = %g >= tau_f - 1/2)", d->A);
+    if (!(d->alpha_e > 0)) return fail(LBM_ERR_INVALID, "alpha_e <= 0 (B = %g >= tau_T - 1/2)", d->B);
+    d->gbeta = (p->Ra > 0 && d->dT != 0.0) ? p->Ra * d->nu * d->alpha_e / (d->dT * d->L * d->L * d->L) : 0.0;
+    d->K = p->Da * d->L * d->L;
+    if (!std::isnan(p->F_eps) && !(p->F_eps >= 0)) return fail(LBM_ERR_INVALID, "F_eps must be >= 0 or NaN");
+    return LBM_OK;
+}
+
+struct Layout {
+    int pitch;
+    long long plane;
+    size_t pop_bytes;     // one population buffer
+    size_t off_a, off_b, off_eps, off_snap, off_part, off_scalar, total;
+    long long nparts;
+};
+
+// Rows padded to 256 bytes; consecutive planes offset by an extra 256 bytes so that the
+// 18 planes of a node do not map to the same HBM channel when the plane size is a large
+// power of two.
+Layout layout(const lbm_params *p, const lbm::KParams &kp)
+{
+    Layout L;
+    const size_t es = elem_size(p->storage);
+    L.pitch = (int)align_up((size_t)p->nx, 256 / es);
+    L.plane = (long long)align_up((size_t)L.pitch * p->ny, 256 / es) + (long long)(256 / es);
+    L.pop_bytes = align_up((size_t)L.plane * 18 * es, 256);
+    const size_t N = (size_t)p->nx * p->ny;
+    L.nparts = lbm::residual_partials(kp) + 1;
+    size_t o = 0;
+    L.off_a = o; o += L.pop_bytes;
+    L.off_b = o; o += L.pop_bytes;
+    L.off_eps = o; o += align_up(p->eps_field ? N * 8 : 0, 256);
+    L.off_snap = o; o += align_up(3 * N * 8, 256);
+    L.off_part = o; o += align_up((size_t)L.nparts * 5 * 8, 256);
+    L.off_scalar = o; o += 256;
+    L.total = o;
+    return L;
+}
+
+void fill_kparams(const lbm_params *p, const lbm_derived &d, lbm::KParams &k)
+{
+    std::memset(&k, 0, sizeof(k));
+    k.nx = p->nx; k.ny = p->ny; k.px = p->periodic_x ? 1 : 0; k.py = p->periodic_y ? 1 : 0;
+    k.nwall = 2 * p->nx + 2 * p->ny;
+    if (k.px && k.py) k.nwall = 0;
+    k.tau_f = p->tau_f; k.tau_T = p->tau_T; k.A = d.A; k.B = d.B; k.sigma = p->sigma; k.Q = p->Q;
+    k.gbeta = d.gbeta; k.T0 = d.T0; k.ax = p->ax; k.ay = p->ay;
+    const bool kinf = std::isinf(d.K);
+    k.nu_over_K = kinf ? 0.0 : d.nu / d.K;
+    k.inv_sqrtK = kinf ? 0.0 : 1.0 / std::sqrt(d.K);
+    k.ergun = std::isnan(p->F_eps) ? 1 : 0;
+    k.Feps = k.ergun ? 0.0 : p->F_eps;
+    k.field = p->eps_field ? 1 : 0;
+    k.eps = p->eps;
+    const double Fe = k.ergun ? 1.75 / std::sqrt(150.0 * p->eps * p->eps * p->eps) : k.Feps;
+    k.c0 = 0.5 * (1.0 + 0.5 * p->eps * k.nu_over_K);
+    k.c1 = 0.5 * p->eps * Fe * k.inv_sqrtK;
+    k.dlin = p->eps * k.nu_over_K;
+    k.dquad = p->eps * Fe * k.inv_sqrtK;
+    for (int w = 0; w < 4; ++w) {
+        k.wall_ux[w] = p->wall[w].ux; k.wall_uy[w] = p->wall[w].uy;
+        k.wall_T[w] = p->wall[w].T; k.wall_dTdn[w] = p->wall[w].dTdn;
+        k.wall_kind[w] = p->wall[w].t_kind;
+    }
+    k.hscale = p->storage == LBM_F16 ? 256.0f : 1.0f;
+    k.hinv = 1.0f / k.hscale;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_params prm;
+    lbm_derived d;
+    lbm::KParams kp;
+    Layout lay;
+    char *ws;
+    hipStream_t stream;
+    int64_t t;
+    int have_snap;
+    int device;
+};
+
+static void *cur_buf(lbm_ctx *c) { return c->ws + ((c->t & 1) ? c->lay.off_b : c->lay.off_a); }
+static void *next_buf(lbm_ctx *c) { return c->ws + ((c->t & 1) ? c->lay.off_a : c->lay.off_b); }
+
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err; }
+
+lbm_status lbm_derive(const lbm_params *params, lbm_derived *out)
+{
+    if (!out) return fail(LBM_ERR_INVALID, "out is NULL");
+    return derive(params, out);
+}
+
+size_t lbm_workspace_bytes(const lbm_params *params)
+{
+    lbm_derived d;
+    if (derive(params, &d) != LBM_OK) return 0;
+    lbm::KParams kp;
+    fill_kparams(params, d, kp);
+    return layout(params, kp).total;
+}
+
+lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_bytes,
+                    void *hip_stream, lbm_ctx **out)
+{
+    if (!out) return fail(LBM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    lbm_derived d;
+    lbm_status st = derive(params, &d);
+    if (st != LBM_OK) return st;
+    if (!workspace) return fail(LBM_ERR_INVALID, "workspace is NULL");
+    if (((uintptr_t)workspace) % 256) return fail(LBM_ERR_INVALID, "workspace must be 256-byte aligned");
+    lbm::KParams kp;
+    fill_kparams(params, d, kp);
+    const Layout lay = layout(params, kp);
+    if (workspace_bytes < lay.total)
+        return fail(LBM_ERR_INVALID, "workspace too small: %zu < %zu bytes", workspace_bytes, lay.total);
+    kp.pitch = lay.pitch;
+    kp.plane = lay.plane;
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx;
+    if (!c) return fail(LBM_ERR_DEVICE, "out of host memory");
+    c->prm = *params;
+    c->prm.eps_field = c->prm.T_init = c->prm.p_init = c->prm.ux_init = c->prm.uy_init = nullptr;
+    c->d = d;
+    c->lay = lay;
+    c->ws = static_cast<char *>(workspace);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->t = 0;
+    c->have_snap = 0;
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+
+    hipError_t e;
+    if (params->eps_field) {
+        double *eps = reinterpret_cast<double *>(c->ws + lay.off_eps);
+        e = hipMemcpyAsync(eps, params->eps_field, (size_t)params->nx * params->ny * 8,
+                           hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) { delete c; return hip_fail(e, "copy of eps_field"); }
+        kp.eps_field = eps;
+    }
+    c->kp = kp;
+    e = hipMemsetAsync(c->ws + lay.off_b, 0, lay.pop_bytes, c->stream);
+    if (e == hipSuccess)
+        e = lbm::launch_init(params->storage, cur_buf(c), c->kp, params->T_init, params->p_init,
+                             params->ux_init, params->uy_init, c->stream);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "initialisation"); }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *c, int64_t nsteps)
+{
+    if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
+    if (nsteps < 0) return fail(LBM_ERR_INVALID, "nsteps < 0");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipError_t e = lbm::launch_step(c->prm.storage, cur_buf(c), next_buf(c), c->kp, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        c->t += 1;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, double *bulk_ms, double *wall_ms)
+{
+    if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
+    if (nsteps < 0) return fail(LBM_ERR_INVALID, "nsteps < 0");
+    // events are read back in batches so that the stream is not drained after every step
+    constexpr int BATCH = 32;
+    hipEvent_t ev[2 * BATCH + 1];
+    for (int i = 0; i < 2 * BATCH + 1; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+            return fail(LBM_ERR_DEVICE, "hipEventCreate failed");
+        }
+    double tb = 0.0, tw = 0.0;
+    hipError_t e = hipSuccess;
+    int64_t done = 0;
+    while (done < nsteps && e == hipSuccess) {
+        const int nb = (int)((nsteps - done) < BATCH ? (nsteps - done) : BATCH);
+        e = hipEventRecord(ev[0], c->stream);
+        for (int s = 0; s < nb && e == hipSuccess; ++s) {
+            e = lbm::launch_step_bulk(c->prm.storage, cur_buf(c), next_buf(c), c->kp, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], c->stream);
+            if (e == hipSuccess) e = lbm::launch_step_wall(c->prm.storage, cur_buf(c), next_buf(c), c->kp, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 2], c->stream);
+            if (e == hipSuccess) c->t += 1;
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(ev[2 * nb]);
+        for (int s = 0; s < nb && e == hipSuccess; ++s) {
+            float a = 0.f, b = 0.f;
+            e = hipEventElapsedTime(&a, ev[2 * s], ev[2 * s + 1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[2 * s + 1], ev[2 * s + 2]);
+            tb += a;
+            tw += b;
+        }
+        done += nb;
+    }
+    for (int i = 0; i < 2 * BATCH + 1; ++i) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return hip_fail(e, "timed step");
+    if (bulk_ms) *bulk_ms = tb;
+    if (wall_ms) *wall_ms = tw;
+    return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
+
+static lbm_status fields(lbm_ctx *c, int32_t out_dtype, void *const out[9])
+{
+    if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
+    if (out_dtype != 0 && out_dtype != 1) return fail(LBM_ERR_INVALID, "out_dtype must be 0 (FP64) or 1 (FP32)");
+    hipError_t e = lbm::launch_fields(c->prm.storage, cur_buf(c), c->kp, out, out_dtype, c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "fields launch");
+}
+
+lbm_status lbm_moments(lbm_ctx *c, int32_t out_dtype, void *p, void *ux, void *uy, void *T)
+{
+    void *const o[9] = {p, ux, uy, T, nullptr, nullptr, nullptr, nullptr, nullptr};
+    return fields(c, out_dtype, o);
+}
+
+lbm_status lbm_gradients(lbm_ctx *c, int32_t out_dtype, void *Sxx, void *Sxy, void *Syy,
+                         void *dTdx, void *dTdy)
+{
+    void *const o[9] = {nullptr, nullptr, nullptr, nullptr, Sxx, Sxy, Syy, dTdx, dTdy};
+    return fields(c, out_dtype, o);
+}
+
+lbm_status lbm_nusselt(lbm_ctx *c, int32_t wall, double *nu_host)
+{
+    if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
+    if (!nu_host) return fail(LBM_ERR_INVALID, "nu_host is NULL");
+    if (wall < 0 || wall > 3) return fail(LBM_ERR_INVALID, "wall must be 0..3");
+    const bool xwall = wall < 2;
+    if ((xwall && c->prm.periodic_x) || (!xwall && c->prm.periodic_y))
+        return fail(LBM_ERR_INVALID, "wall %d does not exist (periodic direction)", wall);
+    if ((xwall ? c->prm.nx : c->prm.ny) < 3) return fail(LBM_ERR_INVALID, "need 3 node layers");
+    if (c->d.dT == 0.0) return fail(LBM_ERR_INVALID, "T_hot == T_cold");
+    double *dev = reinterpret_cast<double *>(c->ws + c->lay.off_scalar);
+    hipError_t e = lbm::launch_nusselt(c->prm.storage, cur_buf(c), c->kp, wall, c->d.L, c->d.dT, dev, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "nusselt launch");
+    e = hipMemcpyAsync(nu_host, dev, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "nusselt");
+    if (!std::isfinite(*nu_host)) return fail(LBM_ERR_NONFINITE, "Nusselt number is not finite");
+    return LBM_OK;
+}
+
+lbm_status lbm_residual(lbm_ctx *c, double *r_u, double *r_T)
+{
+    if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
+    if (!r_u || !r_T) return fail(LBM_ERR_INVALID, "outputs are NULL");
+    double *snap = reinterpret_cast<double *>(c->ws + c->lay.off_snap);
+    double *part = reinterpret_cast<double *>(c->ws + c->lay.off_part);
+    double *res = reinterpret_cast<double *>(c->ws + c->lay.off_scalar) + 8;
+    hipError_t e = lbm::launch_residual(c->prm.storage, cur_buf(c), c->kp, snap, part, res, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "residual launch");
+    double h[5];
+    e = hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "residual");
+    const bool first = !c->have_snap;
+    c->have_snap = 1;
+    if (h[4] != 0.0) return fail(LBM_ERR_NONFINITE, "%.0f nodes hold non-finite values", h[4]);
+    if (first) { *r_u = -1.0; *r_T = -1.0; return LBM_OK; }
+    *r_u = h[1] > 0 ? h[0] / h[1] : (h[0] > 0 ? INFINITY : 0.0);
+    *r_T = h[3] > 0 ? h[2] / h[3] : (h[2] > 0 ? INFINITY : 0.0);
+    return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_ctx *c, double *dst)
+{
+    if (!c || !dst) return fail(LBM_ERR_INVALID, "NULL argument");
+    hipError_t e = lbm::launch_state(c->prm.storage, cur_buf(c), c->kp, dst, true, c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "get_state");
+}
+
+lbm_status lbm_set_state(lbm_ctx *c, const double *src)
+{
+    if (!c || !src) return fail(LBM_ERR_INVALID, "NULL argument");
+    hipError_t e = lbm::launch_state(c->prm.storage, cur_buf(c), c->kp, const_cast<double *>(src), false, c->stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "set_state");
+}
+
+void lbm_destroy(lbm_ctx *c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,503 @@
+// HIP kernels of the fused collide-stream step (pull scheme, structure-of-arrays) and of
+// the auxiliary passes (initialisation, macroscopic fields, residual, Nusselt number,
+// state conversion) for the modified lattice-BGK porous thermal model.
+//
+// Layout in device memory: one population buffer = 18 planes (f_0..f_8, g_0..g_8), each
+// plane ny rows of `pitch` elements, planes `plane` elements apart.  A step reads buffer
+// src and writes buffer dst; node (x, y) pulls f_i from (x - c_i) and stores its
+// post-collision populations at (x, y), so no two threads write the same element and no
+// thread reads what another thread writes in the same launch.
+#include "lbm_kernels.h"
+
+namespace lbm {
+
+constexpr int BULK_BX = 256;
+constexpr int WALL_B = 64;
+constexpr int RED_B = 256;
+
+// ---------------------------------------------------------------------------------
+// Initialisation: post-collision populations before the first step are the equilibria
+// of the initial fields with S = 0 and grad T = 0.
+// ---------------------------------------------------------------------------------
+template <typename S, typename R>
+__global__ void __launch_bounds__(BULK_BX)
+k_init(S *__restrict__ dst, KParams P, const double *__restrict__ T_init,
+       const double *__restrict__ p_init, const double *__restrict__ ux_init,
+       const double *__restrict__ uy_init)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= P.nx) return;
+    const long long n = (long long)y * P.nx + x;
+    const Cst<R> k = make_cst<R>(P);
+    const EpsC<R> e = eps_at<R>(P, x, y);
+    double T = P.T0;
+    if (T_init) {
+        T = T_init[n];
+    } else {
+        const WallInfo w = wall_info(P, x, y);
+        if (w.xw >= 0 && P.wall_kind[w.xw] == 0) T = P.wall_T[w.xw];
+        else if (w.yw >= 0 && P.wall_kind[w.yw] == 0) T = P.wall_T[w.yw];
+    }
+    const R p = p_init ? R(p_init[n]) : R(0);
+    const R ux = ux_init ? R(ux_init[n]) : R(0);
+    const R uy = uy_init ? R(uy_init[n]) : R(0);
+    const R Td = R(T - P.T0);
+    const R Tf = R(T);
+    const R ep = e.eps * p;
+    R f[9], g[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        f[i] = feq_i<R>(i, ep, ux, uy, e.ieps, R(0), R(0), R(0), k.A);
+        g[i] = geq_i<R>(i, Td, Tf, ux, uy, e.ieps, ep, R(0), R(0), k);
+    }
+    store_node<S, R>(dst, P, x, y, f, g);
+}
+
+// ---------------------------------------------------------------------------------
+// Fused step, bulk nodes: gather -> moments -> S, grad T -> equilibria -> collide -> store
+// ---------------------------------------------------------------------------------
+template <typename S, typename R>
+__global__ void __launch_bounds__(BULK_BX)
+k_step_bulk(const S *__restrict__ src, S *__restrict__ dst, KParams P)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= P.nx || on_wall(P, x, y)) return;
+    const Cst<R> k = make_cst<R>(P);
+    const EpsC<R> e = eps_at<R>(P, x, y);
+    R f[9], g[9];
+    gather<S, R>(src, P, x, y, f, g);
+    Macro<R> m;
+    const R T0 = R(P.T0);
+    node_macro_full<R>(f, g, T0, k, e, m);
+    node_collide<R>(f, g, m, T0, k, e);
+    store_node<S, R>(dst, P, x, y, f, g);
+}
+
+// Fused step, wall nodes: boundary scheme -> moments -> collide -> store
+template <typename S, typename R>
+__global__ void __launch_bounds__(WALL_B)
+k_step_wall(const S *__restrict__ src, S *__restrict__ dst, KParams P)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int x, y;
+    if (s >= P.nwall || !wall_slot(P, s, x, y)) return;
+    const Cst<R> k = make_cst<R>(P);
+    R f[9], g[9];
+    wall_populations<S, R>(src, P, k, x, y, f, g);
+    const EpsC<R> e = eps_at<R>(P, x, y);
+    Macro<R> m;
+    const R T0 = R(P.T0);
+    node_macro_full<R>(f, g, T0, k, e, m);
+    node_collide<R>(f, g, m, T0, k, e);
+    store_node<S, R>(dst, P, x, y, f, g);
+}
+
+// ---------------------------------------------------------------------------------
+// Macroscopic fields at the current time (same node code as the step, no collision)
+// ---------------------------------------------------------------------------------
+struct FieldOut {
+    void *ptr[9];   // p, ux, uy, T, Sxx, Sxy, Syy, dTdx, dTdy
+    int f32;
+};
+
+template <typename R>
+__device__ __forceinline__ void write_fields(const FieldOut &o, const KParams &P, int x, int y,
+                                             const Macro<R> &m)
+{
+    const long long n = (long long)y * P.nx + x;
+    const double v[9] = {double(m.p), double(m.ux), double(m.uy), P.T0 + double(m.Td),
+                         double(m.Sxx), double(m.Sxy), double(m.Syy), double(m.gx),
+                         double(m.gy)};
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        if (!o.ptr[q]) continue;
+        if (o.f32) static_cast<float *>(o.ptr[q])[n] = float(v[q]);
+        else static_cast<double *>(o.ptr[q])[n] = v[q];
+    }
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(BULK_BX)
+k_fields_bulk(const S *__restrict__ src, KParams P, FieldOut o)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= P.nx || on_wall(P, x, y)) return;
+    const Cst<R> k = make_cst<R>(P);
+    const EpsC<R> e = eps_at<R>(P, x, y);
+    R f[9], g[9];
+    gather<S, R>(src, P, x, y, f, g);
+    Macro<R> m;
+    node_macro_full<R>(f, g, R(P.T0), k, e, m);
+    write_fields<R>(o, P, x, y, m);
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(WALL_B)
+k_fields_wall(const S *__restrict__ src, KParams P, FieldOut o)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int x, y;
+    if (s >= P.nwall || !wall_slot(P, s, x, y)) return;
+    const Cst<R> k = make_cst<R>(P);
+    R f[9], g[9];
+    wall_populations<S, R>(src, P, k, x, y, f, g);
+    const EpsC<R> e = eps_at<R>(P, x, y);
+    Macro<R> m;
+    node_macro_full<R>(f, g, R(P.T0), k, e, m);
+    write_fields<R>(o, P, x, y, m);
+}
+
+// ---------------------------------------------------------------------------------
+// Residual against a snapshot (FP64, fixed-order reduction) and non-finite detection.
+// Each block writes 5 partial sums: |du|_2, |u|_2, |dT|, |T|, count of non-finite.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ void block_sum5(double v[5], double *out)
+{
+    __shared__ double sm[5][RED_B];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sm[q][t] = v[q];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (t < s) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) sm[q][t] += sm[q][t + s];
+        }
+        __syncthreads();
+    }
+    if (t < 5) out[t] = sm[t][0];
+}
+
+template <typename R>
+__device__ __forceinline__ void resid_node(const KParams &P, int x, int y, const R *f, const R *g,
+                                           const Macro<R> &m, double *snap, double v[5])
+{
+    const long long n = (long long)y * P.nx + x;
+    const long long N = (long long)P.nx * P.ny;
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) bad |= !isfinite(double(f[i])) || !isfinite(double(g[i]));
+    const double ux = double(m.ux), uy = double(m.uy), T = P.T0 + double(m.Td);
+    bad |= !isfinite(ux) || !isfinite(uy) || !isfinite(T);
+    const double dux = ux - snap[n], duy = uy - snap[N + n];
+    v[0] = sqrt(dux * dux + duy * duy);
+    v[1] = sqrt(ux * ux + uy * uy);
+    v[2] = fabs(T - snap[2 * N + n]);
+    v[3] = fabs(T);
+    v[4] = bad ? 1.0 : 0.0;
+    snap[n] = ux;
+    snap[N + n] = uy;
+    snap[2 * N + n] = T;
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(RED_B)
+k_resid_bulk(const S *__restrict__ src, KParams P, double *snap, double *partial)
+{
+    // 1-D over nodes so that every block has a fixed slot in the partial array
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[5] = {0, 0, 0, 0, 0};
+    if (idx < (long long)P.nx * P.ny) {
+        const int x = int(idx % P.nx), y = int(idx / P.nx);
+        if (!on_wall(P, x, y)) {
+            const Cst<R> k = make_cst<R>(P);
+            const EpsC<R> e = eps_at<R>(P, x, y);
+            R f[9], g[9];
+            gather<S, R>(src, P, x, y, f, g);
+            Macro<R> m;
+            node_macro_full<R>(f, g, R(P.T0), k, e, m);
+            resid_node<R>(P, x, y, f, g, m, snap, v);
+        }
+    }
+    block_sum5(v, partial + 5 * (long long)blockIdx.x);
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(RED_B)
+k_resid_wall(const S *__restrict__ src, KParams P, double *snap, double *partial)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[5] = {0, 0, 0, 0, 0};
+    int x, y;
+    if (s < P.nwall && wall_slot(P, s, x, y)) {
+        const Cst<R> k = make_cst<R>(P);
+        R f[9], g[9];
+        wall_populations<S, R>(src, P, k, x, y, f, g);
+        const EpsC<R> e = eps_at<R>(P, x, y);
+        Macro<R> m;
+        node_macro_full<R>(f, g, R(P.T0), k, e, m);
+        resid_node<R>(P, x, y, f, g, m, snap, v);
+    }
+    block_sum5(v, partial + 5 * (long long)blockIdx.x);
+}
+
+// Sums nparts partial 5-vectors in a fixed order (one block).
+__global__ void __launch_bounds__(RED_B) k_sum_partials(const double *partial, int nparts, double *out)
+{
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) v[q] += partial[5 * (long long)b + q];
+    block_sum5(v, out);
+}
+
+// ---------------------------------------------------------------------------------
+// Nusselt number (Eq. AvNuss): T on the three node layers next to a wall, one-sided
+// second-order derivative, trapezoid rule; FP64, fixed-order reduction in one block.
+// ---------------------------------------------------------------------------------
+template <typename S, typename R>
+__device__ __forceinline__ double node_Td_interior(const S *__restrict__ src, const KParams &P,
+                                                   const Cst<R> &k, int x, int y)
+{
+    R f[9], g[9];
+    gather<S, R>(src, P, x, y, f, g);
+    R sg = R(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sg += g[i];
+    return double((sg + k.halfQ) * k.isig);
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ double node_Td(const S *__restrict__ src, const KParams &P,
+                                          const Cst<R> &k, int x, int y)
+{
+    if (!on_wall(P, x, y)) return node_Td_interior<S, R>(src, P, k, x, y);
+    // wall node: the boundary scheme sets T(x_b) = T_b exactly (sum of g^eq is sigma T)
+    const WallInfo w = wall_info(P, x, y);
+    int dir = -1;
+    if (w.xw >= 0 && P.wall_kind[w.xw] == 0) dir = w.xw;
+    else if (w.yw >= 0 && P.wall_kind[w.yw] == 0) dir = w.yw;
+    if (dir >= 0) return P.wall_T[dir] - P.T0;
+    const double Tdf = node_Td_interior<S, R>(src, P, k, x + w.dx, y + w.dy);
+    const double Tdff = node_Td_interior<S, R>(src, P, k, x + 2 * w.dx, y + 2 * w.dy);
+    double dn = 0.0;
+    if (w.xw >= 0) dn += P.wall_dTdn[w.xw];
+    if (w.yw >= 0) dn += P.wall_dTdn[w.yw];
+    return (4.0 * Tdf - Tdff - 2.0 * dn) / 3.0;
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(RED_B)
+k_nusselt(const S *__restrict__ src, KParams P, int wall, double L, double dT, double *out)
+{
+    const Cst<R> k = make_cst<R>(P);
+    const int along = (wall < 2) ? P.ny : P.nx;
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < along; j += blockDim.x) {
+        double t0, t1, t2, sgn;
+        if (wall == 0) { t0 = node_Td<S, R>(src, P, k, 0, j); t1 = node_Td<S, R>(src, P, k, 1, j); t2 = node_Td<S, R>(src, P, k, 2, j); sgn = 1.0; }
+        else if (wall == 1) { t0 = node_Td<S, R>(src, P, k, P.nx - 1, j); t1 = node_Td<S, R>(src, P, k, P.nx - 2, j); t2 = node_Td<S, R>(src, P, k, P.nx - 3, j); sgn = -1.0; }
+        else if (wall == 2) { t0 = node_Td<S, R>(src, P, k, j, 0); t1 = node_Td<S, R>(src, P, k, j, 1); t2 = node_Td<S, R>(src, P, k, j, 2); sgn = 1.0; }
+        else { t0 = node_Td<S, R>(src, P, k, j, P.ny - 1); t1 = node_Td<S, R>(src, P, k, j, P.ny - 2); t2 = node_Td<S, R>(src, P, k, j, P.ny - 3); sgn = -1.0; }
+        const double d = sgn * (-3.0 * t0 + 4.0 * t1 - t2) * 0.5;
+        const double nu = -L * d / dT;
+        acc += (j == 0 || j == along - 1) ? 0.5 * nu : nu;
+    }
+    double v[5] = {acc, 0, 0, 0, 0};
+    __shared__ double res[5];
+    block_sum5(v, res);
+    if (threadIdx.x == 0) out[0] = res[0] / double(along - 1);
+}
+
+// ---------------------------------------------------------------------------------
+// State conversion: stored deviations <-> raw FP64 populations [2][9][ny][nx]
+// ---------------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(BULK_BX)
+k_get_state(const S *__restrict__ src, KParams P, double *__restrict__ out)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= P.nx) return;
+    const long long N = (long long)P.nx * P.ny, n = (long long)y * P.nx + x;
+    const long long o = (long long)y * P.pitch + x;
+    for (int q = 0; q < 18; ++q) {
+        double v = double(Store<S>::ld(src + q * P.plane + o, P.hinv));
+        if (q == 0) v += 1.0;
+        if (q >= 9) v += Wd(q - 9) * P.sigma * P.T0;
+        out[q * N + n] = v;
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(BULK_BX)
+k_set_state(S *__restrict__ dst, KParams P, const double *__restrict__ in)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= P.nx) return;
+    const long long N = (long long)P.nx * P.ny, n = (long long)y * P.nx + x;
+    const long long o = (long long)y * P.pitch + x;
+    for (int q = 0; q < 18; ++q) {
+        double v = in[q * N + n];
+        if (q == 0) v -= 1.0;
+        if (q >= 9) v -= Wd(q - 9) * P.sigma * P.T0;
+        Store<S>::st(dst + q * P.plane + o, decltype(Store<S>::ld(dst, 0.f))(v), P.hscale);
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------------
+static dim3 bulk_grid(const KParams &P) { return dim3((P.nx + BULK_BX - 1) / BULK_BX, P.ny); }
+static int wall_blocks(const KParams &P, int b) { return (P.nwall + b - 1) / b; }
+
+template <typename S, typename R>
+static hipError_t launch_init_t(void *dst, const KParams &P, const double *T, const double *p,
+                                const double *ux, const double *uy, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_init<S, R>), bulk_grid(P), dim3(BULK_BX), 0, st, (S *)dst, P, T, p, ux, uy);
+    return hipGetLastError();
+}
+
+template <typename S, typename R>
+static hipError_t launch_step_t(const void *src, void *dst, const KParams &P, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_step_bulk<S, R>), bulk_grid(P), dim3(BULK_BX), 0, st,
+                       (const S *)src, (S *)dst, P);
+    if (P.nwall > 0)
+        hipLaunchKernelGGL((k_step_wall<S, R>), dim3(wall_blocks(P, WALL_B)), dim3(WALL_B), 0, st,
+                           (const S *)src, (S *)dst, P);
+    return hipGetLastError();
+}
+
+template <typename S, typename R>
+static hipError_t launch_step_bulk_t(const void *src, void *dst, const KParams &P, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_step_bulk<S, R>), bulk_grid(P), dim3(BULK_BX), 0, st,
+                       (const S *)src, (S *)dst, P);
+    return hipGetLastError();
+}
+
+template <typename S, typename R>
+static hipError_t launch_step_wall_t(const void *src, void *dst, const KParams &P, hipStream_t st)
+{
+    if (P.nwall > 0)
+        hipLaunchKernelGGL((k_step_wall<S, R>), dim3(wall_blocks(P, WALL_B)), dim3(WALL_B), 0, st,
+                           (const S *)src, (S *)dst, P);
+    return hipGetLastError();
+}
+
+template <typename S, typename R>
+static hipError_t launch_fields_t(const void *src, const KParams &P, void *const out[9], int f32,
+                                  hipStream_t st)
+{
+    FieldOut o;
+    for (int q = 0; q < 9; ++q) o.ptr[q] = out[q];
+    o.f32 = f32;
+    hipLaunchKernelGGL((k_fields_bulk<S, R>), bulk_grid(P), dim3(BULK_BX), 0, st, (const S *)src, P, o);
+    if (P.nwall > 0)
+        hipLaunchKernelGGL((k_fields_wall<S, R>), dim3(wall_blocks(P, WALL_B)), dim3(WALL_B), 0, st,
+                           (const S *)src, P, o);
+    return hipGetLastError();
+}
+
+template <typename S, typename R>
+static hipError_t launch_resid_t(const void *src, const KParams &P, double *snap, double *partial,
+                                 double *out, hipStream_t st)
+{
+    const long long N = (long long)P.nx * P.ny;
+    const int nb = int((N + RED_B - 1) / RED_B);
+    const int nw = P.nwall > 0 ? wall_blocks(P, RED_B) : 0;
+    hipLaunchKernelGGL((k_resid_bulk<S, R>), dim3(nb), dim3(RED_B), 0, st, (const S *)src, P, snap, partial);
+    if (nw > 0)
+        hipLaunchKernelGGL((k_resid_wall<S, R>), dim3(nw), dim3(RED_B), 0, st, (const S *)src, P, snap,
+                           partial + 5 * (long long)nb);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RED_B), 0, st, (const double *)partial, nb + nw, out);
+    return hipGetLastError();
+}
+
+template <typename S, typename R>
+static hipError_t launch_nusselt_t(const void *src, const KParams &P, int wall, double L, double dT,
+                                   double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_nusselt<S, R>), dim3(1), dim3(RED_B), 0, st, (const S *)src, P, wall, L, dT, out);
+    return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t launch_state_t(void *buf, const KParams &P, double *io, bool get, hipStream_t st)
+{
+    if (get) hipLaunchKernelGGL((k_get_state<S>), bulk_grid(P), dim3(BULK_BX), 0, st, (const S *)buf, P, io);
+    else hipLaunchKernelGGL((k_set_state<S>), bulk_grid(P), dim3(BULK_BX), 0, st, (S *)buf, P, (const double *)io);
+    return hipGetLastError();
+}
+
+#define LBM_DISPATCH(storage, CALL_F64, CALL_F32, CALL_F16)   \
+    switch (storage) {                                         \
+    case 0: return CALL_F64;                                   \
+    case 1: return CALL_F32;                                   \
+    case 2: return CALL_F16;                                   \
+    default: return hipErrorInvalidValue;                      \
+    }
+
+hipError_t launch_init(int storage, void *dst, const KParams &P, const double *T, const double *p,
+                       const double *ux, const double *uy, hipStream_t st)
+{
+    LBM_DISPATCH(storage, (launch_init_t<double, double>(dst, P, T, p, ux, uy, st)),
+                 (launch_init_t<float, float>(dst, P, T, p, ux, uy, st)),
+                 (launch_init_t<__half, float>(dst, P, T, p, ux, uy, st)))
+}
+
+hipError_t launch_step(int storage, const void *src, void *dst, const KParams &P, hipStream_t st)
+{
+    LBM_DISPATCH(storage, (launch_step_t<double, double>(src, dst, P, st)),
+                 (launch_step_t<float, float>(src, dst, P, st)),
+                 (launch_step_t<__half, float>(src, dst, P, st)))
+}
+
+hipError_t launch_step_bulk(int storage, const void *src, void *dst, const KParams &P, hipStream_t st)
+{
+    LBM_DISPATCH(storage, (launch_step_bulk_t<double, double>(src, dst, P, st)),
+                 (launch_step_bulk_t<float, float>(src, dst, P, st)),
+                 (launch_step_bulk_t<__half, float>(src, dst, P, st)))
+}
+
+hipError_t launch_step_wall(int storage, const void *src, void *dst, const KParams &P, hipStream_t st)
+{
+    LBM_DISPATCH(storage, (launch_step_wall_t<double, double>(src, dst, P, st)),
+                 (launch_step_wall_t<float, float>(src, dst, P, st)),
+                 (launch_step_wall_t<__half, float>(src, dst, P, st)))
+}
+
+hipError_t launch_fields(int storage, const void *src, const KParams &P, void *const out[9], int f32,
+                         hipStream_t st)
+{
+    LBM_DISPATCH(storage, (launch_fields_t<double, double>(src, P, out, f32, st)),
+                 (launch_fields_t<float, float>(src, P, out, f32, st)),
+                 (launch_fields_t<__half, float>(src, P, out, f32, st)))
+}
+
+hipError_t launch_residual(int storage, const void *src, const KParams &P, double *snap,
+                           double *partial, double *out, hipStream_t st)
+{
+    LBM_DISPATCH(storage, (launch_resid_t<double, double>(src, P, snap, partial, out, st)),
+                 (launch_resid_t<float, float>(src, P, snap, partial, out, st)),
+                 (launch_resid_t<__half, float>(src, P, snap, partial, out, st)))
+}
+
+hipError_t launch_nusselt(int storage, const void *src, const KParams &P, int wall, double L,
+                          double dT, double *out, hipStream_t st)
+{
+    LBM_DISPATCH(storage, (launch_nusselt_t<double, double>(src, P, wall, L, dT, out, st)),
+                 (launch_nusselt_t<float, float>(src, P, wall, L, dT, out, st)),
+                 (launch_nusselt_t<__half, float>(src, P, wall, L, dT, out, st)))
+}
+
+hipError_t launch_state(int storage, void *buf, const KParams &P, double *io, bool get, hipStream_t st)
+{
+    LBM_DISPATCH(storage, (launch_state_t<double>(buf, P, io, get, st)),
+                 (launch_state_t<float>(buf, P, io, get, st)),
+                 (launch_state_t<__half>(buf, P, io, get, st)))
+}
+
+long long residual_partials(const KParams &P)
+{
+    const long long N = (long long)P.nx * P.ny;
+    return (N + RED_B - 1) / RED_B + (P.nwall + RED_B - 1) / RED_B;
+}
+
+}  // namespace lbm

@@ -1,0 +1,269 @@
+"""Python binding of the C interface in include/lbm.h (argument marshalling only).
+
+PyTorch supplies device memory (the workspace and field buffers) and the HIP stream;
+every step of the method runs in the HIP kernels of liblbm.so.  The binding refuses to
+run when the library is missing: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+OK, ERR_INVALID, ERR_DEVICE, ERR_NONFINITE, ERR_UNSUPPORTED = 0, 1, 2, 3, 4
+STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lbm status {status}: {msg}")
+        self.status = status
+
+
+class NonFiniteError(LbmError):
+    pass
+
+
+class _Wall(C.Structure):
+    _fields_ = [("ux", C.c_double), ("uy", C.c_double), ("t_kind", C.c_int32),
+                ("reserved", C.c_int32), ("T", C.c_double), ("dTdn", C.c_double)]
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("periodic_x", C.c_int32), ("periodic_y", C.c_int32),
+        ("wall", _Wall * 4),
+        ("L", C.c_double), ("Da", C.c_double), ("Ra", C.c_double), ("Pr", C.c_double),
+        ("J", C.c_double), ("Ma", C.c_double), ("sigma", C.c_double), ("Q", C.c_double),
+        ("tau_f", C.c_double), ("tau_T", C.c_double), ("A", C.c_double), ("B", C.c_double),
+        ("eps", C.c_double), ("ax", C.c_double), ("ay", C.c_double),
+        ("T_hot", C.c_double), ("T_cold", C.c_double), ("F_eps", C.c_double),
+        ("eps_field", C.c_void_p), ("T_init", C.c_void_p), ("p_init", C.c_void_p),
+        ("ux_init", C.c_void_p), ("uy_init", C.c_void_p),
+        ("storage", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class _Derived(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("L", "A", "B", "nu_e", "nu", "alpha_e", "gbeta", "K", "T0", "dT")]
+
+
+_lib = None
+
+EXPORTS = ("lbm_derive", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lbm_time",
+           "lbm_moments", "lbm_gradients", "lbm_nusselt", "lbm_residual", "lbm_get_state",
+           "lbm_set_state", "lbm_destroy", "lbm_last_error")
+
+
+def lib():
+    """Loads liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1505_02976_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, st = C.c_void_p, C.c_int
+    L.lbm_last_error.restype = C.c_char_p
+    L.lbm_derive.restype = st
+    L.lbm_derive.argtypes = [C.POINTER(_Params), C.POINTER(_Derived)]
+    L.lbm_workspace_bytes.restype = C.c_size_t
+    L.lbm_workspace_bytes.argtypes = [C.POINTER(_Params)]
+    L.lbm_init.restype = st
+    L.lbm_init.argtypes = [C.POINTER(_Params), vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.lbm_step.restype = st
+    L.lbm_step.argtypes = [vp, C.c_int64]
+    L.lbm_step_timed.restype = st
+    L.lbm_step_timed.argtypes = [vp, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.lbm_time.restype = C.c_int64
+    L.lbm_time.argtypes = [vp]
+    L.lbm_moments.restype = st
+    L.lbm_moments.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
+    L.lbm_gradients.restype = st
+    L.lbm_gradients.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp]
+    L.lbm_nusselt.restype = st
+    L.lbm_nusselt.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]
+    L.lbm_residual.restype = st
+    L.lbm_residual.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.lbm_get_state.restype = st
+    L.lbm_get_state.argtypes = [vp, vp]
+    L.lbm_set_state.restype = st
+    L.lbm_set_state.argtypes = [vp, vp]
+    L.lbm_destroy.restype = None
+    L.lbm_destroy.argtypes = [vp]
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != OK:
+        msg = lib().lbm_last_error().decode()
+        if status == ERR_NONFINITE:
+            raise NonFiniteError(status, msg)
+        raise LbmError(status, msg)
+
+
+def make_params(cfg: dict, fields: dict | None = None) -> _Params:
+    """Fills the C parameter block from a problem dictionary (see workloads.py);
+    `fields` maps eps_field/T_init/p_init/ux_init/uy_init to device pointers."""
+    p = _Params()
+    p.nx, p.ny = int(cfg["nx"]), int(cfg["ny"])
+    p.periodic_x = int(cfg.get("periodic_x", 0))
+    p.periodic_y = int(cfg.get("periodic_y", 0))
+    walls = cfg.get("walls", [{}] * 4)
+    for k in range(4):
+        w = walls[k] or {}
+        p.wall[k].ux = float(w.get("ux", 0.0))
+        p.wall[k].uy = float(w.get("uy", 0.0))
+        p.wall[k].t_kind = 1 if w.get("kind", "T") == "dTdn" else 0
+        p.wall[k].T = float(w.get("T", 0.0))
+        p.wall[k].dTdn = float(w.get("dTdn", 0.0))
+    nan = float("nan")
+    p.L = float(cfg.get("L", 0.0))
+    p.Da = float(cfg.get("Da", math.inf))
+    p.Ra = float(cfg.get("Ra", 0.0))
+    p.Pr = float(cfg.get("Pr", 1.0))
+    p.J = float(cfg.get("J", 1.0))
+    p.Ma = float(cfg.get("Ma", 0.1))
+    p.sigma = float(cfg.get("sigma", 1.0))
+    p.Q = float(cfg.get("Q", 0.0))
+    p.tau_f = float(cfg.get("tau_f", 1.0))
+    p.tau_T = float(cfg.get("tau_T", 1.0))
+    p.A = nan if cfg.get("A") is None else float(cfg["A"])
+    p.B = nan if cfg.get("B") is None else float(cfg["B"])
+    p.eps = float(cfg.get("eps", 1.0))
+    p.ax = float(cfg.get("ax", 0.0))
+    p.ay = float(cfg.get("ay", 0.0))
+    p.T_hot = float(cfg.get("T_hot", 1.0))
+    p.T_cold = float(cfg.get("T_cold", 0.0))
+    p.F_eps = nan if cfg.get("F_eps") is None else float(cfg["F_eps"])
+    p.storage = STORAGE[cfg.get("storage", "f64")]
+    fields = fields or {}
+    for key in ("eps_field", "T_init", "p_init", "ux_init", "uy_init"):
+        setattr(p, key, fields.get(key))
+    return p
+
+
+def derived(cfg: dict) -> dict:
+    d = _Derived()
+    _check(lib().lbm_derive(C.byref(make_params(cfg)), C.byref(d)))
+    return {k: getattr(d, k) for k, _ in _Derived._fields_}
+
+
+def workspace_bytes(cfg: dict) -> int:
+    return int(lib().lbm_workspace_bytes(C.byref(make_params(cfg))))
+
+
+class Sim:
+    """A simulation context on a CUDA (HIP) device; fields come back as torch tensors."""
+
+    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
+        L = lib()
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            dev = {}
+            keep = []
+            for key in ("eps_field", "T_init", "p_init", "ux_init", "uy_init"):
+                a = cfg.get(key)
+                if a is None:
+                    continue
+                t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(self.ny, self.nx),
+                                    device=self.device)
+                keep.append(t)
+                dev[key] = t.data_ptr()
+            prm = make_params(cfg, dev)
+            nbytes = int(L.lbm_workspace_bytes(C.byref(prm)))
+            if nbytes == 0:
+                _check(L.lbm_derive(C.byref(prm), C.byref(_Derived())))
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            h = C.c_void_p()
+            _check(L.lbm_init(C.byref(prm), C.c_void_p(aligned), nbytes,
+                              C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+            self.h = h
+            # initial fields are read by the init kernel: wait before releasing them
+            self.stream.synchronize()
+            del keep
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def time(self) -> int:
+        return int(lib().lbm_time(self.h))
+
+    def step(self, n: int = 1):
+        _check(lib().lbm_step(self.h, int(n)))
+
+    def step_timed(self, n: int):
+        """Steps with per-kernel HIP events; returns (bulk_ms, wall_ms) summed over n."""
+        b, w = C.c_double(), C.c_double()
+        _check(lib().lbm_step_timed(self.h, int(n), C.byref(b), C.byref(w)))
+        return b.value, w.value
+
+    def _alloc(self, dtype):
+        return self.torch.empty((self.ny, self.nx), dtype=dtype, device=self.device)
+
+    def fields(self, f32: bool = False, gradients: bool = True) -> dict:
+        dt = self.torch.float32 if f32 else self.torch.float64
+        out = {k: self._alloc(dt) for k in ("p", "ux", "uy", "T")}
+        _check(lib().lbm_moments(self.h, 1 if f32 else 0, *[out[k].data_ptr() for k in ("p", "ux", "uy", "T")]))
+        if gradients:
+            for k in ("Sxx", "Sxy", "Syy", "dTdx", "dTdy"):
+                out[k] = self._alloc(dt)
+            _check(lib().lbm_gradients(self.h, 1 if f32 else 0,
+                                       *[out[k].data_ptr() for k in ("Sxx", "Sxy", "Syy", "dTdx", "dTdy")]))
+        self.stream.synchronize()
+        return out
+
+    def nusselt(self, wall: int = 0) -> float:
+        v = C.c_double()
+        _check(lib().lbm_nusselt(self.h, int(wall), C.byref(v)))
+        return v.value
+
+    def residual(self):
+        ru, rT = C.c_double(), C.c_double()
+        _check(lib().lbm_residual(self.h, C.byref(ru), C.byref(rT)))
+        return (None, None) if ru.value < 0 else (ru.value, rT.value)
+
+    def run_to_steady(self, tol: float, max_steps: int, every: int = 100) -> bool:
+        self.residual()
+        while self.time < max_steps:
+            self.step(every)
+            ru, rT = self.residual()
+            if ru < tol and rT < tol:
+                return True
+        return False
+
+    def get_state(self):
+        """Post-collision populations of the last step, raw FP64, shape [2, 9, ny, nx]."""
+        out = self.torch.empty((2, 9, self.ny, self.nx), dtype=self.torch.float64, device=self.device)
+        _check(lib().lbm_get_state(self.h, out.data_ptr()))
+        self.stream.synchronize()
+        return out
+
+    def set_state(self, pops):
+        t = self.torch.as_tensor(pops, dtype=self.torch.float64, device=self.device).contiguous()
+        assert tuple(t.shape) == (2, 9, self.ny, self.nx)
+        _check(lib().lbm_set_state(self.h, t.data_ptr()))
+        self.stream.synchronize()

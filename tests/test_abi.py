@@ -1,0 +1,95 @@
+"""Host-side checks of the C interface (no GPU work): the library loads, exports every
+function declared in include/lbm.h, and validates parameters exactly as documented;
+the lattice constants it derives agree with the oracle's independent derivation."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_1505_02976_amd import lbm as L
+    if not os.path.exists(L.LIB_PATH):
+        from paper_1505_02976_amd import build
+        build.build()
+    return L
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "lbm.h")) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lbm):
+    lib = C.CDLL(lbm.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(lbm.EXPORTS) == set(names)
+
+
+def test_struct_sizes_match_header(lbm):
+    # lbm_wall: 2 doubles, 2 int32, 2 doubles; lbm_params ends on two int32
+    assert C.sizeof(lbm._Wall) == 40
+    assert C.sizeof(lbm._Params) == 4 * 4 + 4 * 40 + 18 * 8 + 5 * 8 + 8
+
+
+@pytest.mark.parametrize("cfg", [W.cavity(128), W.channel(), W.large_cavity(),
+                                 W.random_case(3, 40, 30), W.random_case(4, 17, 9, periodic_x=1)],
+                         ids=["cavity", "channel", "large", "rand3", "rand4"])
+def test_derived_constants_match_oracle(lbm, oracle_mod, cfg):
+    a = lbm.derived(cfg)
+    b = oracle_mod.derived(cfg)
+    for k in a:
+        assert math.isclose(a[k], b[k], rel_tol=1e-14, abs_tol=1e-300), k
+
+
+def _bad(**kw):
+    cfg = W.cavity(32)
+    cfg.update(kw)
+    return cfg
+
+
+@pytest.mark.parametrize("cfg,msg", [
+    (_bad(tau_f=0.5), "tau_f"),
+    (_bad(A=0.6, B=0.0), "nu_e"),
+    (_bad(A=0.0, B=0.5), "alpha_e"),
+    (_bad(eps=0.0), "eps"),
+    (_bad(eps=1.2), "eps"),
+    (_bad(Da=0.0), "Da"),
+    (_bad(Ra=0.0), "Ra"),
+    (_bad(nx=2), "needs"),
+    (_bad(ny=3), "needs"),          # Neumann walls on y need 4 nodes
+    (_bad(storage="f64", sigma=-1.0), "sigma"),
+])
+def test_invalid_parameters_are_rejected(lbm, cfg, msg):
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.derived(cfg)
+    assert ei.value.status == lbm.ERR_INVALID
+    assert msg in str(ei.value)
+    assert lbm.workspace_bytes(cfg) == 0
+
+
+def test_workspace_size_scales_with_storage(lbm):
+    sizes = {s: lbm.workspace_bytes(W.large_cavity(storage=s)) for s in ("f64", "f32", "f16")}
+    N = 4096 * 4096
+    # two buffers of 18 planes plus the FP64 residual snapshot (3 fields)
+    for s, es in (("f64", 8), ("f32", 4), ("f16", 2)):
+        assert 2 * 18 * N * es + 24 * N <= sizes[s] < 1.01 * (2 * 18 * N * es + 24 * N) + 2 ** 20
+
+
+def test_init_rejects_null_workspace(lbm):
+    prm = lbm.make_params(W.cavity(32))
+    h = C.c_void_p()
+    st = lbm.lib().lbm_init(C.byref(prm), None, 0, None, C.byref(h))
+    assert st == lbm.ERR_INVALID and not h.value
