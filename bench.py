@@ -32,6 +32,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(storage, n):
+    """HBM bytes per bulk launch from the committed rocprofv3 counter summary, if it was
+    taken on this workload and on the kernel sources as they are now (else None)."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_step_bulk_{storage}_cavity{n}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    src = b"".join(open(p, "rb").read() for p in
+                   sorted(glob.glob(os.path.join(ROOT, "paper_1505_02976_amd", "csrc", "*"))))
+    if hashlib.sha256(src).hexdigest() != rec.get("csrc_sha256"):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def timed_run(lbm, torch, cfg, warmup, steps):
     """Warm up, then time `steps` steps with HIP events on the simulation's stream."""
     sim = lbm.Sim(cfg)
@@ -119,6 +136,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--copy-reference-gib", type=float, default=0.0,
+                    help="first run a plain device-to-device copy of this size, as the "
+                         "reference for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path "
@@ -129,6 +149,15 @@ def main():
 
     import workloads as W
     from paper_1505_02976_amd import lbm
+
+    if args.copy_reference_gib > 0:
+        nbytes = int(args.copy_reference_gib * 2 ** 30)
+        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"bench: reference copy of {nbytes} bytes done")
+        del a, b
 
     n = args.size
     log(f"bench: {n}x{n} cavity, {args.storage}, warmup {args.warmup}, steps {args.steps}")
@@ -165,7 +194,8 @@ def main():
                                f"{args.storage} population storage",
                    "nodes": n * n, "storage": args.storage},
         "roofline": {"bound": "hbm", "achieved": main_res["bulk_GBps"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": main_res["frac"], "traffic": None,
+                     "unit": "GB/s", "frac": main_res["frac"],
+                     "traffic": measured_traffic(args.storage, n),
                      "kernel": "k_step_bulk",
                      "bytes_per_launch": main_res["bulk_bytes_per_launch"],
                      "avg_launch_us": main_res["bulk_kernel_us"]},

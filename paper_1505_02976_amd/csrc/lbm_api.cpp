@@ -84,7 +84,7 @@ lbm_status derive(const lbm_params *p, lbm_derived *d)
 }
 
 struct Layout {
-    int pitch;
+    int pitch, ntx;
     long long plane;
     size_t pop_bytes;     // one population buffer
     size_t off_a, off_b, off_eps, off_snap, off_part, off_scalar, total;
@@ -98,9 +98,18 @@ Layout layout(const lbm_params *p, const lbm::KParams &kp)
 {
     Layout L;
     const size_t es = elem_size(p->storage);
-    L.pitch = (int)align_up((size_t)p->nx, 256 / es);
-    L.plane = (long long)align_up((size_t)L.pitch * p->ny, 256 / es) + (long long)(256 / es);
-    L.pop_bytes = align_up((size_t)L.plane * 18 * es, 256);
+    const int tile = lbm::tile_of_storage(p->storage);
+    if (tile > 0) {
+        L.pitch = 0;
+        L.plane = 0;
+        L.ntx = (p->nx + tile - 1) / tile;
+        L.pop_bytes = align_up((size_t)p->ny * L.ntx * 18 * tile * es, 256);
+    } else {
+        L.ntx = 0;
+        L.pitch = (int)align_up((size_t)p->nx, 256 / es);
+        L.plane = (long long)align_up((size_t)L.pitch * p->ny, 256 / es) + (long long)(256 / es);
+        L.pop_bytes = align_up((size_t)L.plane * 18 * es, 256);
+    }
     const size_t N = (size_t)p->nx * p->ny;
     L.nparts = lbm::residual_partials(kp) + 1;
     size_t o = 0;
@@ -141,6 +150,46 @@ void fill_kparams(const lbm_params *p, const lbm_derived &d, lbm::KParams &k)
     }
     k.hscale = p->storage == LBM_F16 ? 256.0f : 1.0f;
     k.hinv = 1.0f / k.hscale;
+
+    lbm::Cst<double> &c = k.cd;
+    c.itf = 1.0 / p->tau_f;
+    c.itT = 1.0 / p->tau_T;
+    c.of = 1.0 - c.itf;
+    c.og = 1.0 - c.itT;
+    c.fF = 1.0 - 0.5 / p->tau_f;
+    c.fT = 1.0 - 0.5 / p->tau_T;
+    c.tau_f = p->tau_f;
+    c.A = d.A;
+    c.sigB = p->sigma * d.B;
+    c.sig = p->sigma;
+    c.isig = 1.0 / p->sigma;
+    c.Q = p->Q;
+    c.halfQ = 0.5 * p->Q;
+    c.gb = d.gbeta;
+    c.ax = p->ax;
+    c.ay = p->ay;
+    c.Sden = 3.0 / (d.A - p->tau_f);
+    c.aM0 = p->sigma * (d.B - p->tau_T) / 3.0;
+    c.w1 = 1.0 / 9.0;
+    c.w5 = 1.0 / 36.0;
+    c.w3a = 1.0 / 3.0;
+    c.w3d = (1.0 - 2.0 * c.w3a) / 4.0;
+    lbm::Cst<float> &cf = k.cf;
+    cf.itf = (float)c.itf; cf.itT = (float)c.itT; cf.of = (float)c.of; cf.og = (float)c.og;
+    cf.fF = (float)c.fF; cf.fT = (float)c.fT; cf.tau_f = (float)c.tau_f; cf.A = (float)c.A;
+    cf.sigB = (float)c.sigB; cf.sig = (float)c.sig; cf.isig = (float)c.isig; cf.Q = (float)c.Q;
+    cf.halfQ = (float)c.halfQ; cf.gb = (float)c.gb; cf.ax = (float)c.ax; cf.ay = (float)c.ay;
+    cf.Sden = (float)c.Sden; cf.aM0 = (float)c.aM0;
+    cf.w1 = (float)c.w1; cf.w5 = (float)c.w5;
+    cf.w3a = 1.0f / 3.0f;
+    cf.w3d = (1.0f - 2.0f * cf.w3a) / 4.0f;   // 2 w3a + 4 w3d == 1 exactly in FP32
+    k.ed.eps = p->eps;
+    k.ed.ieps = 1.0 / p->eps;
+    k.ed.dlin = k.dlin;
+    k.ed.dquad = k.dquad;
+    k.ed.bM = 0.5 * (1.0 / p->eps - 1.0 / p->sigma);
+    k.ef.eps = (float)k.ed.eps; k.ef.ieps = (float)k.ed.ieps; k.ef.dlin = (float)k.ed.dlin;
+    k.ef.dquad = (float)k.ed.dquad; k.ef.bM = (float)k.ed.bM;
 }
 
 }  // namespace
@@ -196,6 +245,7 @@ lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_
         return fail(LBM_ERR_INVALID, "workspace too small: %zu < %zu bytes", workspace_bytes, lay.total);
     kp.pitch = lay.pitch;
     kp.plane = lay.plane;
+    kp.ntx = lay.ntx;
 
     lbm_ctx *c = new (std::nothrow) lbm_ctx;
     if (!c) return fail(LBM_ERR_DEVICE, "out of host memory");

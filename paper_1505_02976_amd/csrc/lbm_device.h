@@ -14,17 +14,59 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+// Population layout per storage type.  Tile 0: 18 planes [q][y][pitch].  Tile n > 0 (a
+// power of two): rows of tiles of n consecutive nodes, each tile holding its 18 directions
+// contiguously, [y][x / n][q][x % n], so that the 36 streams of a wavefront touch one
+// contiguous block of memory per row instead of 36 distant planes.
+#ifndef LBM_TILE_F64
+#define LBM_TILE_F64 0
+#endif
+#ifndef LBM_TILE_F32
+#define LBM_TILE_F32 128
+#endif
+#ifndef LBM_TILE_F16
+#define LBM_TILE_F16 128
+#endif
+
 namespace lbm {
+
+template <typename S> struct TileOf;
+template <> struct TileOf<double> { static constexpr int v = LBM_TILE_F64; };
+template <> struct TileOf<float> { static constexpr int v = LBM_TILE_F32; };
+template <> struct TileOf<__half> { static constexpr int v = LBM_TILE_F16; };
+inline constexpr int tile_of_storage(int storage)
+{
+    return storage == 0 ? LBM_TILE_F64 : (storage == 1 ? LBM_TILE_F32 : LBM_TILE_F16);
+}
 
 // D2Q9 (Sec. 3.1)
 __device__ constexpr int CXd[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int CYd[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __host__ __device__ constexpr double Wd(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
 
+// Per-launch constants in the arithmetic type R, computed once on the host.
+template <typename R> struct Cst {
+    R itf, itT;        // 1 / tau
+    R of, og;          // 1 - 1 / tau
+    R fF, fT;          // 1 - 1 / (2 tau)
+    R tau_f;
+    R A, sigB, sig, isig, Q, halfQ, gb, ax, ay;
+    R Sden;            // 1 / (cs^2 (A - tau_f))
+    R aM0;             // cs^2 sigma (B - tau_T)
+    R w1, w5;          // lattice weights 1/9, 1/36
+    R w3a, w3d;        // 3 omega of axis / diagonal directions with 2 w3a + 4 w3d = 1 in R
+};
+
+// Porosity-dependent coefficients in R (uniform porosity: computed on the host).
+template <typename R> struct EpsR {
+    R eps, ieps, dlin, dquad, bM;
+};
+
 // Kernel parameter block (plain data, passed by value).
 struct KParams {
     int nx, ny, px, py;          // grid, periodic flags
-    int pitch;                   // row pitch in elements
+    int pitch;                   // row pitch in elements (plane layout)
+    int ntx;                     // tiles per row (tiled layout)
     int nwall;                   // number of wall-node slots enumerated by the wall kernels
     long long plane;             // stride between population planes, elements
     double tau_f, tau_T, A, B, sigma, Q, gbeta, T0, ax, ay;
@@ -38,52 +80,90 @@ struct KParams {
     double wall_ux[4], wall_uy[4], wall_T[4], wall_dTdn[4];
     int wall_kind[4];
     float hscale, hinv;          // FP16 storage scale
+    Cst<double> cd;
+    Cst<float> cf;
+    EpsR<double> ed;
+    EpsR<float> ef;
 };
 
-// Storage traits: load/store of a deviation value.
+template <typename R> __device__ __forceinline__ const Cst<R> &cst(const KParams &P);
+template <> __device__ __forceinline__ const Cst<double> &cst<double>(const KParams &P) { return P.cd; }
+template <> __device__ __forceinline__ const Cst<float> &cst<float>(const KParams &P) { return P.cf; }
+template <typename R> __device__ __forceinline__ const EpsR<R> &epsu(const KParams &P);
+template <> __device__ __forceinline__ const EpsR<double> &epsu<double>(const KParams &P) { return P.ed; }
+template <> __device__ __forceinline__ const EpsR<float> &epsu<float>(const KParams &P) { return P.ef; }
+
+// Reciprocal: IEEE division in FP64 arithmetic, the hardware reciprocal (1 ulp) in FP32.
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Element index of population q (0..17) of node (x, y) inside a population buffer of
+// storage type S.
+template <typename S>
+__device__ __forceinline__ long long pidx(const KParams &P, int q, int x, int y)
+{
+    constexpr int T = TileOf<S>::v;
+    if constexpr (T > 0)
+        return ((long long)(y * P.ntx + x / T) * 18 + q) * T + (x % T);
+    else
+        return q * P.plane + (long long)y * P.pitch + x;
+}
+
+// FP64 reciprocal from the hardware estimate refined by two Newton steps (used by the
+// FP64 drag solve of the FP32/FP16 paths, where the result is rounded to FP32).
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+#ifndef LBM_NT_LOAD
+#define LBM_NT_LOAD 0
+#endif
+#ifndef LBM_F32_MOMENTS_F64
+#define LBM_F32_MOMENTS_F64 0
+#endif
+#ifndef LBM_F32_COLLIDE_F64
+#define LBM_F32_COLLIDE_F64 0
+#endif
+
+// Storage traits: load/store of a deviation value.  Stores are non-temporal (the next
+// step reads them from HBM anyway); loads optionally so.
+template <typename T> __device__ __forceinline__ T ld_stream(const T *p)
+{
+#if LBM_NT_LOAD
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
 template <typename S> struct Store;
 template <> struct Store<double> {
-    static __device__ __forceinline__ double ld(const double *p, float) { return *p; }
+    static __device__ __forceinline__ double ld(const double *p, float) { return ld_stream(p); }
     static __device__ __forceinline__ void st(double *p, double v, float) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<float> {
-    static __device__ __forceinline__ float ld(const float *p, float) { return *p; }
+    static __device__ __forceinline__ float ld(const float *p, float) { return ld_stream(p); }
     static __device__ __forceinline__ void st(float *p, float v, float) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<__half> {
-    static __device__ __forceinline__ float ld(const __half *p, float inv) { return __half2float(*p) * inv; }
-    static __device__ __forceinline__ void st(__half *p, float v, float scale) { *p = __float2half(v * scale); }
+    static __device__ __forceinline__ float ld(const __half *p, float inv)
+    {
+        const unsigned short b = ld_stream(reinterpret_cast<const unsigned short *>(p));
+        return __half2float(__ushort_as_half(b)) * inv;
+    }
+    static __device__ __forceinline__ void st(__half *p, float v, float scale)
+    {
+        __builtin_nontemporal_store(__half_as_ushort(__float2half(v * scale)),
+                                    reinterpret_cast<unsigned short *>(p));
+    }
 };
 
-// Constants in the arithmetic type R.
-template <typename R> struct Cst {
-    R itf, itT;        // 1 / tau
-    R fF, fT;          // 1 - 1 / (2 tau)
-    R A, sigB, sig, isig, Q, gb, ax, ay;
-    R Sden;            // 1 / (cs^2 (A - tau_f))
-    R aM0;             // cs^2 sigma (B - tau_T)
-    R halfQ;
-};
-
-template <typename R> __device__ __forceinline__ Cst<R> make_cst(const KParams &P)
+template <typename R> __device__ __forceinline__ const Cst<R> &make_cst(const KParams &P)
 {
-    Cst<R> k;
-    k.itf = R(1.0 / P.tau_f);
-    k.itT = R(1.0 / P.tau_T);
-    k.fF = R(1.0 - 0.5 / P.tau_f);
-    k.fT = R(1.0 - 0.5 / P.tau_T);
-    k.A = R(P.A);
-    k.sigB = R(P.sigma * P.B);
-    k.sig = R(P.sigma);
-    k.isig = R(1.0 / P.sigma);
-    k.Q = R(P.Q);
-    k.halfQ = R(0.5 * P.Q);
-    k.gb = R(P.gbeta);
-    k.ax = R(P.ax);
-    k.ay = R(P.ay);
-    k.Sden = R(3.0 / (P.A - P.tau_f));
-    k.aM0 = R(P.sigma * (P.B - P.tau_T) / 3.0);
-    return k;
+    return cst<R>(P);
 }
 
 // Porosity-dependent coefficients (Sec. 3.1 for c0 and c1; Eq. ForceEq for the drag).
@@ -94,15 +174,16 @@ template <typename R> struct EpsC {
 
 template <typename R> __device__ __forceinline__ EpsC<R> eps_uniform(const KParams &P)
 {
+    const EpsR<R> &u = epsu<R>(P);
     EpsC<R> e;
     e.epsd = P.eps;
-    e.eps = R(P.eps);
-    e.ieps = R(1.0 / P.eps);
+    e.eps = u.eps;
+    e.ieps = u.ieps;
+    e.dlin = u.dlin;
+    e.dquad = u.dquad;
+    e.bM = u.bM;
     e.c0 = P.c0;
     e.c1 = P.c1;
-    e.dlin = R(P.dlin);
-    e.dquad = R(P.dquad);
-    e.bM = R(0.5 * (1.0 / P.eps - 1.0 / P.sigma));
     return e;
 }
 
@@ -110,16 +191,17 @@ template <typename R> __device__ __forceinline__ EpsC<R> eps_at(const KParams &P
 {
     if (!P.field) return eps_uniform<R>(P);
     const double eps = P.eps_field[(long long)y * P.nx + x];
+    const double ie = 1.0 / eps;
     const double Fe = P.ergun ? 1.75 / sqrt(150.0 * eps * eps * eps) : P.Feps;
     EpsC<R> e;
     e.epsd = eps;
     e.eps = R(eps);
-    e.ieps = R(1.0 / eps);
+    e.ieps = R(ie);
     e.c0 = 0.5 * (1.0 + 0.5 * eps * P.nu_over_K);
     e.c1 = 0.5 * eps * Fe * P.inv_sqrtK;
     e.dlin = R(eps * P.nu_over_K);
     e.dquad = R(eps * Fe * P.inv_sqrtK);
-    e.bM = R(0.5 * (1.0 / eps - 1.0 / P.sigma));
+    e.bM = R(0.5 * (ie - 1.0 / P.sigma));
     return e;
 }
 
@@ -127,6 +209,23 @@ template <typename R> __device__ __forceinline__ EpsC<R> eps_at(const KParams &P
 template <typename R> struct Macro {
     R Td, ux, uy, Fx, Fy, p, Sxx, Sxy, Syy, gx, gy;
 };
+
+// FP64 part of the velocity computation (Sec. 3.1): u = v / (c0 + sqrt(c0^2 + c1 |v|)).
+// Returns 1 / (c0 + sqrt(c0^2 + c1 |v|)) and |v|.
+template <typename R> __device__ __forceinline__ double drag_factor(double vx, double vy, double c0,
+                                                                    double c1, double &vm);
+template <> __device__ __forceinline__ double drag_factor<double>(double vx, double vy, double c0,
+                                                                  double c1, double &vm)
+{
+    vm = sqrt(vx * vx + vy * vy);
+    return 1.0 / (c0 + sqrt(c0 * c0 + c1 * vm));
+}
+template <> __device__ __forceinline__ double drag_factor<float>(double vx, double vy, double c0,
+                                                                 double c1, double &vm)
+{
+    vm = sqrt(vx * vx + vy * vy);
+    return rcp_nr(c0 + sqrt(c0 * c0 + c1 * vm));
+}
 
 // Local quantities from pre-collision deviations f'[9], g'[9]:
 //   sigma T = sum g + Q/2 (Sec. 3.2); G = g beta (T - T0) j + a (Sec. 2);
@@ -148,8 +247,8 @@ __device__ __forceinline__ void node_macro(const R *f, const R *g, const Cst<R> 
     const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
     const double vx = double(jx) + 0.5 * e.epsd * double(Gx);
     const double vy = double(jy) + 0.5 * e.epsd * double(Gy);
-    const double vm = sqrt(vx * vx + vy * vy);
-    const double iden = 1.0 / (e.c0 + sqrt(e.c0 * e.c0 + e.c1 * vm));
+    double vm;
+    const double iden = drag_factor<R>(vx, vy, e.c0, e.c1, vm);
     m.ux = R(vx * iden);
     m.uy = R(vy * iden);
     const R um = R(vm * iden);
@@ -164,8 +263,7 @@ __device__ __forceinline__ void node_macro(const R *f, const R *g, const Cst<R> 
     // s_0 = -omega_0 |u|^2 / (2 eps cs^2),  F_0 = -omega_0 fF (u.F) / (eps cs^2)
     const R s0 = R(-2.0 / 3.0) * uu * e.ieps;
     const R F0 = R(-4.0 / 3.0) * k.fF * uF * e.ieps;
-    const R tau_f = R(1) / k.itf;
-    m.p = R(0.6) * e.ieps * (s18 + tau_f * F0 + s0);
+    m.p = R(0.6) * e.ieps * (s18 + k.tau_f * F0 + s0);
 
     const R ep = e.eps * m.p;
     const R Pxx = ((f[1] + f[3]) + (f[5] + f[6])) + (f[7] + f[8]);
@@ -175,10 +273,8 @@ __device__ __forceinline__ void node_macro(const R *f, const R *g, const Cst<R> 
     m.Syy = (Pyy - ep - (m.uy * m.uy - m.uy * m.Fy) * e.ieps) * k.Sden;
     m.Sxy = (Pxy - (m.ux * m.uy - R(0.5) * (m.ux * m.Fy + m.Fx * m.uy)) * e.ieps) * k.Sden;
 
-    const R jgx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
-    const R jgy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
-    m.gx = jgx;   // temporarily hold the thermal flux; finished in node_gradT
-    m.gy = jgy;
+    m.gx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);   // thermal flux; finished in
+    m.gy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);   // node_gradT
 }
 
 // Completes grad T once the absolute temperature is known (T = T0 + Td).
@@ -191,8 +287,8 @@ __device__ __forceinline__ void node_gradT(Macro<R> &m, R T0, const Cst<R> &k, c
     const R a = k.aM0 - R(0.5) * e.eps * m.p;
     const R uu = m.ux * m.ux + m.uy * m.uy;
     const R uN = m.ux * Nx + m.uy * Ny;
-    const R c = e.bM * uN / (a - e.bM * uu);
-    const R ia = R(1) / a;
+    const R c = e.bM * uN * rcp(a - e.bM * uu);
+    const R ia = rcp(a);
     m.gx = (Nx + c * m.ux) * ia;
     m.gy = (Ny + c * m.uy) * ia;
 }
@@ -239,33 +335,93 @@ __device__ __forceinline__ R geq_i(int i, R Td, R T, R ux, R uy, R ieps, R ep, R
 
 // BGK collision with forcing and sources, in place (Eqs. LBEeq, FtermF, TEqColli,
 // Eq:Tforce):  f* = f - (f - f^eq)/tau_f + F_i,  g* = g - (g - g^eq)/tau_T + P_i + Q_i.
+//
+// Directions come in opposite pairs (i, i') with c_i' = -c_i and equal weights.  Every
+// term splits into a part even in c (f^eq: pressure, u u and S terms; F_i: the (c.u)(c.F)
+// and u.F terms; g^eq: sigma T, u u and pressure terms; Q_i: the constant part) and a part
+// odd in c (the c.u, c.F, c.grad T, P_i and (c.u) Q terms), so each pair is updated as
+//   f*_i = (1 - 1/tau) f_i + E + O,   f*_i' = (1 - 1/tau) f_i' + E - O.
+// E collects 1/tau times the even part of the equilibrium plus the even part of the source.
+//
+// The odd parts carry 3 omega_i (c_i . u) and friends, whose first moment over the lattice
+// must be exactly u: 3 omega is taken as w3a (axes) and w3d (diagonals) with
+// 2 w3a + 4 w3d = 1 in the arithmetic type, otherwise the rounded weights would scale the
+// momentum by a fixed factor every step.
+template <typename R>
+__device__ __forceinline__ void collide_pair(R &fa, R &fb, R &ga, R &gb, R w, R w3, R cu, R cF,
+                                             R cSc, R cg, R cv, const R (&b)[8], const Cst<R> &k,
+                                             R &Ef_sum, R &Eg_sum)
+{
+    // b: 0 eps p-u u-tr S base of f^eq, 1 base of g^eq, 2 1/eps, 3 A, 4 T, 5 fF (uF)/eps,
+    //    6 (1/eps - 1/sigma) u.grad T, 7 Q / sigma
+    const R cu2 = cu * cu;
+    const R ieps = b[2];
+    const R fe_even = w * (b[0] + R(4.5) * cu2 * ieps + R(1.5) * b[3] * cSc);
+    const R fe_odd = w3 * cu;
+    const R F_even = w * (k.fF * R(9) * cu * cF * ieps - R(3) * b[5]);
+    const R F_odd = w3 * k.fF * cF;
+    const R Ef = k.itf * fe_even + F_even;
+    const R Of = k.itf * fe_odd + F_odd;
+    fa = k.of * fa + (Ef + Of);
+    fb = k.of * fb + (Ef - Of);
+
+    const R T = b[4];
+    const R ge_even = w * (b[1] + R(4.5) * T * cu2 * ieps);
+    const R ge_odd = w3 * T * cu + w * k.sigB * cg;
+    const R P_odd = w3 * k.fT * (cv + b[6] * cu);
+    const R Q_even = w * k.fT * k.Q;
+    const R Q_odd = w3 * k.fT * b[7] * cu;   // omega fT 3 (c.u) Q / sigma
+    const R Eg = k.itT * ge_even + Q_even;
+    const R Og = k.itT * ge_odd + P_odd + Q_odd;
+    ga = k.og * ga + (Eg + Og);
+    gb = k.og * gb + (Eg - Og);
+    Ef_sum += Ef;
+    Eg_sum += Eg;
+}
+
+// The rest direction is updated from the other eight so that the moment identities
+// sum_i f^eq_i = rho0, sum_i F_i = 0, sum_i g^eq_i = sigma T and
+// sum_i Q_i = (1 - 1/(2 tau_T)) Q (App. A and Sec. 3.2 moment lists) hold in the
+// arithmetic itself, not only up to the rounding of the lattice weights: the zeroth
+// moments are what a step accumulates, so a rounding bias there would drift the mass
+// and the thermal energy.
 template <typename R>
 __device__ __forceinline__ void node_collide(R *f, R *g, const Macro<R> &m, R T0,
                                              const Cst<R> &k, const EpsC<R> &e)
 {
     const R T = T0 + m.Td;
     const R ep = e.eps * m.p;
+    const R uu = m.ux * m.ux + m.uy * m.uy;
+    const R trS = m.Sxx + m.Syy;
     const R uF = m.ux * m.Fx + m.uy * m.Fy;
     const R ugT = m.ux * m.gx + m.uy * m.gy;
     const R vx = T * m.Fx + ep * m.gx;   // T F + eps p grad T / rho0
     const R vy = T * m.Fy + ep * m.gy;
-    const R bP = e.ieps - k.isig;         // 1/eps - 1/sigma
-    const R of = R(1) - k.itf, og = R(1) - k.itT;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const R cx = R(CXd[i]), cy = R(CYd[i]);
-        const R w = R(Wd(i));
-        const R cu = cx * m.ux + cy * m.uy;
-        const R fe = feq_i<R>(i, ep, m.ux, m.uy, e.ieps, m.Sxx, m.Sxy, m.Syy, k.A);
-        const R cF = cx * m.Fx + cy * m.Fy;
-        const R Fi = w * k.fF * (R(3) * cF + (R(9) * cu * cF - R(3) * uF) * e.ieps);
-        f[i] = of * f[i] + k.itf * fe + Fi;
 
-        const R ge = geq_i<R>(i, m.Td, T, m.ux, m.uy, e.ieps, ep, m.gx, m.gy, k);
-        const R Pi = w * k.fT * R(3) * ((cx * vx + cy * vy) + bP * cu * ugT);
-        const R Qi = w * k.fT * (R(1) + R(3) * cu * k.isig) * k.Q;
-        g[i] = og * g[i] + k.itT * ge + Pi + Qi;
-    }
+    R b[8];
+    b[0] = R(3) * ep - R(1.5) * uu * e.ieps - R(0.5) * k.A * trS;
+    b[1] = k.sig * m.Td - R(1.5) * T * uu * e.ieps + R(3) * T * ep;
+    b[2] = e.ieps;
+    b[3] = k.A;
+    b[4] = T;
+    b[5] = k.fF * uF * e.ieps;
+    b[6] = (e.ieps - k.isig) * ugT;
+    b[7] = k.Q * k.isig;
+    const R w1 = k.w1, w5 = k.w5;
+    R Ef = R(0), Eg = R(0);
+    // (1, 3): c = (1, 0)
+    collide_pair<R>(f[1], f[3], g[1], g[3], w1, k.w3a, m.ux, m.Fx, m.Sxx, m.gx, vx, b, k, Ef, Eg);
+    // (2, 4): c = (0, 1)
+    collide_pair<R>(f[2], f[4], g[2], g[4], w1, k.w3a, m.uy, m.Fy, m.Syy, m.gy, vy, b, k, Ef, Eg);
+    // (5, 7): c = (1, 1)
+    collide_pair<R>(f[5], f[7], g[5], g[7], w5, k.w3d, m.ux + m.uy, m.Fx + m.Fy,
+                    m.Sxx + R(2) * m.Sxy + m.Syy, m.gx + m.gy, vx + vy, b, k, Ef, Eg);
+    // (6, 8): c = (-1, 1)
+    collide_pair<R>(f[6], f[8], g[6], g[8], w5, k.w3d, m.uy - m.ux, m.Fy - m.Fx,
+                    m.Sxx - R(2) * m.Sxy + m.Syy, m.gy - m.gx, vy - vx, b, k, Ef, Eg);
+    // rest direction: f^eq_0 + tau_f F_0 and g^eq_0 + tau_T Q_0 from the zeroth moments
+    f[0] = k.of * f[0] - R(2) * Ef;
+    g[0] = k.og * g[0] + (k.itT * k.sig * m.Td + k.fT * k.Q) - R(2) * Eg;
 }
 
 // ---------------------------------------------------------------------------------
@@ -285,15 +441,14 @@ __device__ __forceinline__ void gather(const S *__restrict__ src, const KParams 
     const int xp = (x == P.nx - 1) ? 0 : x + 1;
     const int ym = (y == 0) ? P.ny - 1 : y - 1;
     const int yp = (y == P.ny - 1) ? 0 : y + 1;
-    const long long r0 = (long long)y * P.pitch, rm = (long long)ym * P.pitch,
-                    rp = (long long)yp * P.pitch;
-    const long long off[9] = {r0 + x, r0 + xm, rm + x, r0 + xp, rp + x,
-                              rm + xm, rm + xp, rp + xp, rp + xm};
+    // source node of direction i: x - c_i
+    const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
+    const int sy[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
     const float inv = P.hinv;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        f[i] = R(Store<S>::ld(src + i * P.plane + off[i], inv));
-        g[i] = R(Store<S>::ld(src + (9 + i) * P.plane + off[i], inv));
+        f[i] = R(Store<S>::ld(src + pidx<S>(P, i, sx[i], sy[i]), inv));
+        g[i] = R(Store<S>::ld(src + pidx<S>(P, 9 + i, sx[i], sy[i]), inv));
     }
 }
 
@@ -301,12 +456,55 @@ template <typename S, typename R>
 __device__ __forceinline__ void store_node(S *__restrict__ dst, const KParams &P, int x, int y,
                                            const R *f, const R *g)
 {
-    const long long o = (long long)y * P.pitch + x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        Store<S>::st(dst + i * P.plane + o, f[i], P.hscale);
-        Store<S>::st(dst + (9 + i) * P.plane + o, g[i], P.hscale);
+        Store<S>::st(dst + pidx<S>(P, i, x, y), f[i], P.hscale);
+        Store<S>::st(dst + pidx<S>(P, 9 + i, x, y), g[i], P.hscale);
     }
+}
+
+// Arithmetic types per storage type: R for the collision, M for the node moments
+// (p, u, S, grad T).  FP32 storage may take its moments (LBM_F32_MOMENTS_F64) or its
+// whole update (LBM_F32_COLLIDE_F64) in FP64; both default off: with the exact
+// moment-preserving weights of node_collide, FP32 arithmetic keeps the FP32 path within
+// about 1e-6 of the FP64 result after 1000 steps of the 128 x 128 cavity.
+template <typename S> struct Prec;
+template <> struct Prec<double> { using R = double; using M = double; };
+template <> struct Prec<float> {
+#if LBM_F32_COLLIDE_F64
+    using R = double;
+#else
+    using R = float;
+#endif
+#if LBM_F32_MOMENTS_F64 || LBM_F32_COLLIDE_F64
+    using M = double;
+#else
+    using M = float;
+#endif
+};
+template <> struct Prec<__half> { using R = float; using M = float; };
+
+template <typename A, typename B> struct same_t { static constexpr bool v = false; };
+template <typename A> struct same_t<A, A> { static constexpr bool v = true; };
+
+// Moments in M, collision in R, in place on f, g (R).
+template <typename R, typename M>
+__device__ __forceinline__ void node_update(R *f, R *g, const KParams &P, int x, int y)
+{
+    Macro<R> m;
+    if constexpr (same_t<R, M>::v) {
+        node_macro_full<R>(f, g, R(P.T0), cst<R>(P), eps_at<R>(P, x, y), m);
+    } else {
+        M fm[9], gm[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) { fm[i] = M(f[i]); gm[i] = M(g[i]); }
+        Macro<M> mm;
+        node_macro_full<M>(fm, gm, M(P.T0), cst<M>(P), eps_at<M>(P, x, y), mm);
+        m.Td = R(mm.Td); m.ux = R(mm.ux); m.uy = R(mm.uy); m.Fx = R(mm.Fx); m.Fy = R(mm.Fy);
+        m.p = R(mm.p); m.Sxx = R(mm.Sxx); m.Sxy = R(mm.Sxy); m.Syy = R(mm.Syy);
+        m.gx = R(mm.gx); m.gy = R(mm.gy);
+    }
+    node_collide<R>(f, g, m, R(P.T0), cst<R>(P), eps_at<R>(P, x, y));
 }
 
 // Wall classification: xw in {-1, 0, 1}, yw in {-1, 2, 3}; inward step (dx, dy).
@@ -370,14 +568,12 @@ __device__ __forceinline__ void wall_populations(const S *__restrict__ src, cons
         const int xp = (xff == P.nx - 1) ? 0 : xff + 1;
         const int ym = (yff == 0) ? P.ny - 1 : yff - 1;
         const int yp = (yff == P.ny - 1) ? 0 : yff + 1;
-        const long long r0 = (long long)yff * P.pitch, rm = (long long)ym * P.pitch,
-                        rp = (long long)yp * P.pitch;
-        const long long off[9] = {r0 + xff, r0 + xm, rm + xff, r0 + xp, rp + xff,
-                                  rm + xm, rm + xp, rp + xp, rp + xm};
+        const int sx[9] = {xff, xm, xff, xp, xff, xm, xp, xp, xm};
+        const int sy[9] = {yff, yff, ym, yff, yp, ym, ym, yp, yp};
         R sgff = R(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            sgff += R(Store<S>::ld(src + (9 + i) * P.plane + off[i], P.hinv));
+            sgff += R(Store<S>::ld(src + pidx<S>(P, 9 + i, sx[i], sy[i]), P.hinv));
         const R Tdff = (sgff + k.halfQ) * k.isig;
         Tdb = (R(4) * mf.Td - Tdff - R(2) * (R(w.dx) * gbx + R(w.dy) * gby)) * R(1.0 / 3.0);
     }

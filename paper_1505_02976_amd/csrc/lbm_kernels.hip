@@ -11,7 +11,10 @@
 
 namespace lbm {
 
-constexpr int BULK_BX = 256;
+#ifndef LBM_BULK_BX
+#define LBM_BULK_BX 256
+#endif
+constexpr int BULK_BX = LBM_BULK_BX;
 constexpr int WALL_B = 64;
 constexpr int RED_B = 256;
 
@@ -29,7 +32,7 @@ k_init(S *__restrict__ dst, KParams P, const double *__restrict__ T_init,
     const int y = blockIdx.y;
     if (x >= P.nx) return;
     const long long n = (long long)y * P.nx + x;
-    const Cst<R> k = make_cst<R>(P);
+    const Cst<R> &k = make_cst<R>(P);
     const EpsC<R> e = eps_at<R>(P, x, y);
     double T = P.T0;
     if (T_init) {
@@ -56,23 +59,67 @@ k_init(S *__restrict__ dst, KParams P, const double *__restrict__ T_init,
 
 // ---------------------------------------------------------------------------------
 // Fused step, bulk nodes: gather -> moments -> S, grad T -> equilibria -> collide -> store
+//
+// A block of BULK_BX threads covers a tile of BULK_BX * NPT consecutive nodes of one row;
+// thread t handles nodes t, t + BULK_BX, ... so every load instruction stays coalesced and
+// each thread has NPT nodes' loads in flight before it computes.  Tiles are numbered so
+// that consecutive tiles of a row run on the same XCD (blocks are dealt to the 8 XCDs
+// round-robin), which keeps the cache lines shared by neighbouring tiles in one L2.
 // ---------------------------------------------------------------------------------
+#ifndef LBM_XCD
+#define LBM_XCD 0
+#endif
+#ifndef LBM_NPT_F64
+#define LBM_NPT_F64 1
+#endif
+#ifndef LBM_NPT_F32
+#define LBM_NPT_F32 1
+#endif
+#ifndef LBM_NPT_F16
+#define LBM_NPT_F16 2
+#endif
+
+template <typename S> struct Npt;
+template <> struct Npt<double> { static constexpr int v = LBM_NPT_F64; };
+template <> struct Npt<float> { static constexpr int v = LBM_NPT_F32; };
+template <> struct Npt<__half> { static constexpr int v = LBM_NPT_F16; };
+
+__device__ __forceinline__ int tile_of_block(int b, int nb)
+{
+#if LBM_XCD
+    const int q = nb >> 3, r = nb & 7, k = b & 7;
+    return k * q + (k < r ? k : r) + (b >> 3);
+#else
+    (void)nb;
+    return b;
+#endif
+}
+
 template <typename S, typename R>
 __global__ void __launch_bounds__(BULK_BX)
-k_step_bulk(const S *__restrict__ src, S *__restrict__ dst, KParams P)
+k_step_bulk(const S *__restrict__ src, S *__restrict__ dst, KParams P, int tiles_x)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
-    if (x >= P.nx || on_wall(P, x, y)) return;
-    const Cst<R> k = make_cst<R>(P);
-    const EpsC<R> e = eps_at<R>(P, x, y);
-    R f[9], g[9];
-    gather<S, R>(src, P, x, y, f, g);
-    Macro<R> m;
-    const R T0 = R(P.T0);
-    node_macro_full<R>(f, g, T0, k, e, m);
-    node_collide<R>(f, g, m, T0, k, e);
-    store_node<S, R>(dst, P, x, y, f, g);
+    constexpr int NPT = Npt<S>::v;
+    using RC = typename Prec<S>::R;
+    const int t = tile_of_block(blockIdx.x, gridDim.x);
+    const int y = t / tiles_x;
+    const int x0 = (t - y * tiles_x) * (BULK_BX * NPT) + threadIdx.x;
+    if (!P.py && (y == 0 || y == P.ny - 1)) return;
+    RC f[NPT][9], g[NPT][9];
+    bool act[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int x = x0 + k * BULK_BX;
+        act[k] = x < P.nx && (P.px || (x != 0 && x != P.nx - 1));
+        if (act[k]) gather<S, RC>(src, P, x, y, f[k], g[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        if (!act[k]) continue;
+        const int x = x0 + k * BULK_BX;
+        node_update<RC, typename Prec<S>::M>(f[k], g[k], P, x, y);
+        store_node<S, RC>(dst, P, x, y, f[k], g[k]);
+    }
 }
 
 // Fused step, wall nodes: boundary scheme -> moments -> collide -> store
@@ -83,15 +130,11 @@ k_step_wall(const S *__restrict__ src, S *__restrict__ dst, KParams P)
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     int x, y;
     if (s >= P.nwall || !wall_slot(P, s, x, y)) return;
-    const Cst<R> k = make_cst<R>(P);
-    R f[9], g[9];
-    wall_populations<S, R>(src, P, k, x, y, f, g);
-    const EpsC<R> e = eps_at<R>(P, x, y);
-    Macro<R> m;
-    const R T0 = R(P.T0);
-    node_macro_full<R>(f, g, T0, k, e, m);
-    node_collide<R>(f, g, m, T0, k, e);
-    store_node<S, R>(dst, P, x, y, f, g);
+    using M = typename Prec<S>::M;
+    M f[9], g[9];
+    wall_populations<S, M>(src, P, make_cst<M>(P), x, y, f, g);
+    node_update<M, M>(f, g, P, x, y);
+    store_node<S, M>(dst, P, x, y, f, g);
 }
 
 // ---------------------------------------------------------------------------------
@@ -125,13 +168,12 @@ k_fields_bulk(const S *__restrict__ src, KParams P, FieldOut o)
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= P.nx || on_wall(P, x, y)) return;
-    const Cst<R> k = make_cst<R>(P);
-    const EpsC<R> e = eps_at<R>(P, x, y);
-    R f[9], g[9];
-    gather<S, R>(src, P, x, y, f, g);
-    Macro<R> m;
-    node_macro_full<R>(f, g, R(P.T0), k, e, m);
-    write_fields<R>(o, P, x, y, m);
+    using M = typename Prec<S>::M;
+    M f[9], g[9];
+    gather<S, M>(src, P, x, y, f, g);
+    Macro<M> m;
+    node_macro_full<M>(f, g, M(P.T0), make_cst<M>(P), eps_at<M>(P, x, y), m);
+    write_fields<M>(o, P, x, y, m);
 }
 
 template <typename S, typename R>
@@ -141,13 +183,12 @@ k_fields_wall(const S *__restrict__ src, KParams P, FieldOut o)
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     int x, y;
     if (s >= P.nwall || !wall_slot(P, s, x, y)) return;
-    const Cst<R> k = make_cst<R>(P);
-    R f[9], g[9];
-    wall_populations<S, R>(src, P, k, x, y, f, g);
-    const EpsC<R> e = eps_at<R>(P, x, y);
-    Macro<R> m;
-    node_macro_full<R>(f, g, R(P.T0), k, e, m);
-    write_fields<R>(o, P, x, y, m);
+    using M = typename Prec<S>::M;
+    M f[9], g[9];
+    wall_populations<S, M>(src, P, make_cst<M>(P), x, y, f, g);
+    Macro<M> m;
+    node_macro_full<M>(f, g, M(P.T0), make_cst<M>(P), eps_at<M>(P, x, y), m);
+    write_fields<M>(o, P, x, y, m);
 }
 
 // ---------------------------------------------------------------------------------
@@ -203,13 +244,12 @@ k_resid_bulk(const S *__restrict__ src, KParams P, double *snap, double *partial
     if (idx < (long long)P.nx * P.ny) {
         const int x = int(idx % P.nx), y = int(idx / P.nx);
         if (!on_wall(P, x, y)) {
-            const Cst<R> k = make_cst<R>(P);
-            const EpsC<R> e = eps_at<R>(P, x, y);
-            R f[9], g[9];
-            gather<S, R>(src, P, x, y, f, g);
-            Macro<R> m;
-            node_macro_full<R>(f, g, R(P.T0), k, e, m);
-            resid_node<R>(P, x, y, f, g, m, snap, v);
+            using M = typename Prec<S>::M;
+            M f[9], g[9];
+            gather<S, M>(src, P, x, y, f, g);
+            Macro<M> m;
+            node_macro_full<M>(f, g, M(P.T0), make_cst<M>(P), eps_at<M>(P, x, y), m);
+            resid_node<M>(P, x, y, f, g, m, snap, v);
         }
     }
     block_sum5(v, partial + 5 * (long long)blockIdx.x);
@@ -223,13 +263,12 @@ k_resid_wall(const S *__restrict__ src, KParams P, double *snap, double *partial
     double v[5] = {0, 0, 0, 0, 0};
     int x, y;
     if (s < P.nwall && wall_slot(P, s, x, y)) {
-        const Cst<R> k = make_cst<R>(P);
-        R f[9], g[9];
-        wall_populations<S, R>(src, P, k, x, y, f, g);
-        const EpsC<R> e = eps_at<R>(P, x, y);
-        Macro<R> m;
-        node_macro_full<R>(f, g, R(P.T0), k, e, m);
-        resid_node<R>(P, x, y, f, g, m, snap, v);
+        using M = typename Prec<S>::M;
+        M f[9], g[9];
+        wall_populations<S, M>(src, P, make_cst<M>(P), x, y, f, g);
+        Macro<M> m;
+        node_macro_full<M>(f, g, M(P.T0), make_cst<M>(P), eps_at<M>(P, x, y), m);
+        resid_node<M>(P, x, y, f, g, m, snap, v);
     }
     block_sum5(v, partial + 5 * (long long)blockIdx.x);
 }
@@ -283,15 +322,16 @@ template <typename S, typename R>
 __global__ void __launch_bounds__(RED_B)
 k_nusselt(const S *__restrict__ src, KParams P, int wall, double L, double dT, double *out)
 {
-    const Cst<R> k = make_cst<R>(P);
+    using M = typename Prec<S>::M;
+    const Cst<M> &k = make_cst<M>(P);
     const int along = (wall < 2) ? P.ny : P.nx;
     double acc = 0.0;
     for (int j = threadIdx.x; j < along; j += blockDim.x) {
         double t0, t1, t2, sgn;
-        if (wall == 0) { t0 = node_Td<S, R>(src, P, k, 0, j); t1 = node_Td<S, R>(src, P, k, 1, j); t2 = node_Td<S, R>(src, P, k, 2, j); sgn = 1.0; }
-        else if (wall == 1) { t0 = node_Td<S, R>(src, P, k, P.nx - 1, j); t1 = node_Td<S, R>(src, P, k, P.nx - 2, j); t2 = node_Td<S, R>(src, P, k, P.nx - 3, j); sgn = -1.0; }
-        else if (wall == 2) { t0 = node_Td<S, R>(src, P, k, j, 0); t1 = node_Td<S, R>(src, P, k, j, 1); t2 = node_Td<S, R>(src, P, k, j, 2); sgn = 1.0; }
-        else { t0 = node_Td<S, R>(src, P, k, j, P.ny - 1); t1 = node_Td<S, R>(src, P, k, j, P.ny - 2); t2 = node_Td<S, R>(src, P, k, j, P.ny - 3); sgn = -1.0; }
+        if (wall == 0) { t0 = node_Td<S, M>(src, P, k, 0, j); t1 = node_Td<S, M>(src, P, k, 1, j); t2 = node_Td<S, M>(src, P, k, 2, j); sgn = 1.0; }
+        else if (wall == 1) { t0 = node_Td<S, M>(src, P, k, P.nx - 1, j); t1 = node_Td<S, M>(src, P, k, P.nx - 2, j); t2 = node_Td<S, M>(src, P, k, P.nx - 3, j); sgn = -1.0; }
+        else if (wall == 2) { t0 = node_Td<S, M>(src, P, k, j, 0); t1 = node_Td<S, M>(src, P, k, j, 1); t2 = node_Td<S, M>(src, P, k, j, 2); sgn = 1.0; }
+        else { t0 = node_Td<S, M>(src, P, k, j, P.ny - 1); t1 = node_Td<S, M>(src, P, k, j, P.ny - 2); t2 = node_Td<S, M>(src, P, k, j, P.ny - 3); sgn = -1.0; }
         const double d = sgn * (-3.0 * t0 + 4.0 * t1 - t2) * 0.5;
         const double nu = -L * d / dT;
         acc += (j == 0 || j == along - 1) ? 0.5 * nu : nu;
@@ -313,9 +353,8 @@ k_get_state(const S *__restrict__ src, KParams P, double *__restrict__ out)
     const int y = blockIdx.y;
     if (x >= P.nx) return;
     const long long N = (long long)P.nx * P.ny, n = (long long)y * P.nx + x;
-    const long long o = (long long)y * P.pitch + x;
     for (int q = 0; q < 18; ++q) {
-        double v = double(Store<S>::ld(src + q * P.plane + o, P.hinv));
+        double v = double(Store<S>::ld(src + pidx<S>(P, q, x, y), P.hinv));
         if (q == 0) v += 1.0;
         if (q >= 9) v += Wd(q - 9) * P.sigma * P.T0;
         out[q * N + n] = v;
@@ -330,12 +369,11 @@ k_set_state(S *__restrict__ dst, KParams P, const double *__restrict__ in)
     const int y = blockIdx.y;
     if (x >= P.nx) return;
     const long long N = (long long)P.nx * P.ny, n = (long long)y * P.nx + x;
-    const long long o = (long long)y * P.pitch + x;
     for (int q = 0; q < 18; ++q) {
         double v = in[q * N + n];
         if (q == 0) v -= 1.0;
         if (q >= 9) v -= Wd(q - 9) * P.sigma * P.T0;
-        Store<S>::st(dst + q * P.plane + o, decltype(Store<S>::ld(dst, 0.f))(v), P.hscale);
+        Store<S>::st(dst + pidx<S>(P, q, x, y), decltype(Store<S>::ld(dst, 0.f))(v), P.hscale);
     }
 }
 
@@ -343,6 +381,11 @@ k_set_state(S *__restrict__ dst, KParams P, const double *__restrict__ in)
 // Launchers
 // ---------------------------------------------------------------------------------
 static dim3 bulk_grid(const KParams &P) { return dim3((P.nx + BULK_BX - 1) / BULK_BX, P.ny); }
+template <typename S> static int step_tiles_x(const KParams &P)
+{
+    const int span = BULK_BX * Npt<S>::v;
+    return (P.nx + span - 1) / span;
+}
 static int wall_blocks(const KParams &P, int b) { return (P.nwall + b - 1) / b; }
 
 template <typename S, typename R>
@@ -356,8 +399,9 @@ static hipError_t launch_init_t(void *dst, const KParams &P, const double *T, co
 template <typename S, typename R>
 static hipError_t launch_step_t(const void *src, void *dst, const KParams &P, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_step_bulk<S, R>), bulk_grid(P), dim3(BULK_BX), 0, st,
-                       (const S *)src, (S *)dst, P);
+    const int tx = step_tiles_x<S>(P);
+    hipLaunchKernelGGL((k_step_bulk<S, R>), dim3(tx * P.ny), dim3(BULK_BX), 0, st,
+                       (const S *)src, (S *)dst, P, tx);
     if (P.nwall > 0)
         hipLaunchKernelGGL((k_step_wall<S, R>), dim3(wall_blocks(P, WALL_B)), dim3(WALL_B), 0, st,
                            (const S *)src, (S *)dst, P);
@@ -367,8 +411,9 @@ static hipError_t launch_step_t(const void *src, void *dst, const KParams &P, hi
 template <typename S, typename R>
 static hipError_t launch_step_bulk_t(const void *src, void *dst, const KParams &P, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_step_bulk<S, R>), bulk_grid(P), dim3(BULK_BX), 0, st,
-                       (const S *)src, (S *)dst, P);
+    const int tx = step_tiles_x<S>(P);
+    hipLaunchKernelGGL((k_step_bulk<S, R>), dim3(tx * P.ny), dim3(BULK_BX), 0, st,
+                       (const S *)src, (S *)dst, P, tx);
     return hipGetLastError();
 }
 
