@@ -134,11 +134,13 @@ lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_
 /* Enqueues nsteps >= 0 time steps (asynchronous). */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
-/* As lbm_step, with a HIP event recorded before and after every kernel launch; returns
- * the summed kernel durations in milliseconds of the bulk-node kernel and of the
- * wall-node kernel over the nsteps steps (host outputs; either may be NULL).  Used for
- * measurement.  Synchronizes. */
-lbm_status lbm_step_timed(lbm_ctx *ctx, int64_t nsteps, double *bulk_ms_host, double *wall_ms_host);
+/* As lbm_step, with HIP events around the launches of every step; returns the summed
+ * durations in milliseconds of the interior-tile launch (the nodes whose tile holds no
+ * wall node) and of the remaining launches (tiles holding a wall node, walled rows) over
+ * the nsteps steps, and the number of nodes the interior-tile launch updates per step
+ * (host outputs; any may be NULL).  Used for measurement.  Synchronizes. */
+lbm_status lbm_step_timed(lbm_ctx *ctx, int64_t nsteps, double *bulk_ms_host, double *wall_ms_host,
+                          int64_t *bulk_nodes_host);
 
 /* Number of steps taken since lbm_init. */
 int64_t lbm_time(const lbm_ctx *ctx);
@@ -172,6 +174,39 @@ lbm_status lbm_residual(lbm_ctx *ctx, double *r_u_host, double *r_T_host);
  * Asynchronous. */
 lbm_status lbm_get_state(lbm_ctx *ctx, double *dst_device);
 lbm_status lbm_set_state(lbm_ctx *ctx, const double *src_device);
+
+/* ---------------------------------------------------------------------------------- */
+/* Batches: many independent problems (uneven grids and parameters, one storage type)  */
+/* advanced together, one bulk and one wall launch per step for all of them, replayed  */
+/* from a HIP graph.                                                                   */
+/* ---------------------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch;
+
+/* Bytes of device workspace for a batch of n problems params[0..n-1] (0 if any problem is
+ * invalid or the problems do not share one storage type). */
+size_t lbm_batch_workspace_bytes(const lbm_params *params, int32_t n);
+
+/* Creates a batch: every problem is initialised as by lbm_init inside the workspace
+ * (same ownership rules), plus the work tables of the batched kernels.  The problems'
+ * contexts are owned by the batch; problems may be queried (lbm_moments, lbm_nusselt,
+ * lbm_residual, lbm_get_state, ...) through lbm_batch_problem but are advanced only by
+ * lbm_batch_step (lbm_step on them returns LBM_ERR_INVALID). */
+lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, size_t workspace_bytes,
+                          void *hip_stream, lbm_batch **out);
+
+/* Enqueues nsteps time steps of every problem: whole graphs of 64 steps, then single
+ * steps for the remainder.  The graph is built on the first call.  Asynchronous. */
+lbm_status lbm_batch_step(lbm_batch *batch, int64_t nsteps);
+
+/* Context of problem k (borrowed, valid until lbm_batch_destroy); NULL if k is out of range. */
+lbm_ctx *lbm_batch_problem(lbm_batch *batch, int32_t k);
+
+/* Per-problem non-finite flags (host array of n int32: 1 = some population of that problem
+ * is NaN or infinite).  Synchronizes. */
+lbm_status lbm_batch_check(lbm_batch *batch, int32_t *nonfinite_host);
+
+/* Releases the batch and its contexts (host memory only). */
+void lbm_batch_destroy(lbm_batch *batch);
 
 /* Releases the context (host memory only; the workspace stays with the caller). */
 void lbm_destroy(lbm_ctx *ctx);

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/lbm.h"
 #include "lbm_kernels.h"
@@ -129,6 +130,7 @@ void fill_kparams(const lbm_params *p, const lbm_derived &d, lbm::KParams &k)
     k.nx = p->nx; k.ny = p->ny; k.px = p->periodic_x ? 1 : 0; k.py = p->periodic_y ? 1 : 0;
     k.nwall = 2 * p->nx + 2 * p->ny;
     if (k.px && k.py) k.nwall = 0;
+    k.nwall_rows = k.py ? 0 : 2 * p->nx;
     k.tau_f = p->tau_f; k.tau_T = p->tau_T; k.A = d.A; k.B = d.B; k.sigma = p->sigma; k.Q = p->Q;
     k.gbeta = d.gbeta; k.T0 = d.T0; k.ax = p->ax; k.ay = p->ay;
     const bool kinf = std::isinf(d.K);
@@ -204,6 +206,7 @@ struct lbm_ctx {
     int64_t t;
     int have_snap;
     int device;
+    int in_batch;
 };
 
 static void *cur_buf(lbm_ctx *c) { return c->ws + ((c->t & 1) ? c->lay.off_b : c->lay.off_a); }
@@ -228,8 +231,8 @@ size_t lbm_workspace_bytes(const lbm_params *params)
     return layout(params, kp).total;
 }
 
-lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_bytes,
-                    void *hip_stream, lbm_ctx **out)
+static lbm_status init_ctx(const lbm_params *params, void *workspace, size_t workspace_bytes,
+                           void *hip_stream, lbm_ctx **out)
 {
     if (!out) return fail(LBM_ERR_INVALID, "out is NULL");
     *out = nullptr;
@@ -257,6 +260,7 @@ lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->t = 0;
     c->have_snap = 0;
+    c->in_batch = 0;
     if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
 
     hipError_t e;
@@ -277,9 +281,16 @@ lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_
     return LBM_OK;
 }
 
+lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_bytes,
+                    void *hip_stream, lbm_ctx **out)
+{
+    return init_ctx(params, workspace, workspace_bytes, hip_stream, out);
+}
+
 lbm_status lbm_step(lbm_ctx *c, int64_t nsteps)
 {
     if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
+    if (c->in_batch) return fail(LBM_ERR_INVALID, "problem belongs to a batch: use lbm_batch_step");
     if (nsteps < 0) return fail(LBM_ERR_INVALID, "nsteps < 0");
     for (int64_t s = 0; s < nsteps; ++s) {
         hipError_t e = lbm::launch_step(c->prm.storage, cur_buf(c), next_buf(c), c->kp, c->stream);
@@ -289,9 +300,11 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps)
     return LBM_OK;
 }
 
-lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, double *bulk_ms, double *wall_ms)
+lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, double *bulk_ms, double *wall_ms,
+                          int64_t *bulk_nodes)
 {
     if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
+    if (c->in_batch) return fail(LBM_ERR_INVALID, "problem belongs to a batch: use lbm_batch_step");
     if (nsteps < 0) return fail(LBM_ERR_INVALID, "nsteps < 0");
     // events are read back in batches so that the stream is not drained after every step
     constexpr int BATCH = 32;
@@ -328,6 +341,7 @@ lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, double *bulk_ms, double *w
     if (e != hipSuccess) return hip_fail(e, "timed step");
     if (bulk_ms) *bulk_ms = tb;
     if (wall_ms) *wall_ms = tw;
+    if (bulk_nodes) *bulk_nodes = lbm::interior_nodes(c->prm.storage, c->kp);
     return LBM_OK;
 }
 
@@ -410,6 +424,264 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *src)
     return e == hipSuccess ? LBM_OK : hip_fail(e, "set_state");
 }
 
-void lbm_destroy(lbm_ctx *c) { delete c; }
+void lbm_destroy(lbm_ctx *c)
+{
+    if (c && !c->in_batch) delete c;
+}
+
+// ---------------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------------
+struct lbm_batch {
+    std::vector<lbm_ctx *> ctx;
+    int storage;
+    hipStream_t stream;
+    lbm::BatchProblem *probs;   // device
+    int2 *bulk_items, *edge_items, *wall_items, *all_items;
+    int nbulk, nedge, nwall, nall;
+    int *flags;                 // device, one per problem
+    int64_t t;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int graph_steps;
+};
+
+namespace {
+
+struct BatchLayout {
+    std::vector<size_t> off;    // workspace offset of each problem
+    size_t off_probs, off_bulk, off_edge, off_wall, off_all, off_flags, total;
+    std::vector<int2> bulk, edge, wall, all;
+    std::vector<lbm::KParams> kp;
+    std::vector<int> tiles_x;
+};
+
+lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
+{
+    if (!params || n < 1) return fail(LBM_ERR_INVALID, "need at least one problem");
+    size_t o = 0;
+    B.off.resize(n);
+    B.kp.resize(n);
+    B.tiles_x.resize(n);
+    B.bulk.clear();
+    B.edge.clear();
+    B.wall.clear();
+    B.all.clear();
+    for (int k = 0; k < n; ++k) {
+        if (params[k].storage != params[0].storage)
+            return fail(LBM_ERR_INVALID, "problem %d: all problems of a batch share one storage type", k);
+        lbm_derived d;
+        lbm_status st = derive(&params[k], &d);
+        if (st != LBM_OK) return fail(st, "problem %d: %s", k, g_err);
+        lbm::KParams kp;
+        fill_kparams(&params[k], d, kp);
+        const Layout lay = layout(&params[k], kp);
+        kp.pitch = lay.pitch;
+        kp.plane = lay.plane;
+        kp.ntx = lay.ntx;
+        B.kp[k] = kp;
+        B.off[k] = o;
+        o += align_up(lay.total, 256);
+        const int tx = lbm::batch_tiles_x(params[k].storage, kp);
+        B.tiles_x[k] = tx;
+        const int y0 = kp.py ? 0 : 1, y1 = kp.py ? kp.ny : kp.ny - 1;
+        // Batched grids are small (a few tiles per row), so every tile goes to the
+        // wall-aware launch: one bulk launch per step instead of an interior and an edge one.
+        for (int y = y0; y < y1; ++y)
+            for (int t = 0; t < tx; ++t) B.edge.push_back(make_int2(k, y * tx + t));
+        for (int t = 0; t < tx * kp.ny; ++t) B.all.push_back(make_int2(k, t));
+        const int wb = lbm::wall_block_size();
+        for (int b = 0; b < (kp.nwall_rows + wb - 1) / wb; ++b) B.wall.push_back(make_int2(k, b));
+    }
+    B.off_probs = o; o += align_up((size_t)n * sizeof(lbm::BatchProblem), 256);
+    B.off_bulk = o; o += align_up(B.bulk.size() * sizeof(int2) + 8, 256);
+    B.off_edge = o; o += align_up(B.edge.size() * sizeof(int2) + 8, 256);
+    B.off_wall = o; o += align_up(B.wall.size() * sizeof(int2) + 8, 256);
+    B.off_all = o; o += align_up(B.all.size() * sizeof(int2), 256);
+    B.off_flags = o; o += align_up((size_t)n * sizeof(int), 256);
+    B.total = o;
+    if (B.all.size() > 0x7fffffff)
+        return fail(LBM_ERR_INVALID, "batch too large");
+    return LBM_OK;
+}
+
+constexpr int GRAPH_STEPS = 64;   // even: a replay leaves the buffers in their parity
+
+lbm_status batch_build_graph(lbm_batch *b)
+{
+    const lbm::BatchKernels K = lbm::batch_kernels(b->storage);
+    hipError_t e = hipGraphCreate(&b->graph, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+    std::vector<hipGraphNode_t> prev;
+    for (int s = 0; s < GRAPH_STEPS && e == hipSuccess; ++s) {
+        int parity = s & 1;
+        std::vector<hipGraphNode_t> cur;
+        for (int w = 0; w < 3 && e == hipSuccess; ++w) {
+            const int nblk = w == 0 ? b->nbulk : (w == 1 ? b->nedge : b->nwall);
+            if (nblk == 0) continue;
+            const lbm::BatchProblem *probs = b->probs;
+            const int2 *items = w == 0 ? b->bulk_items : (w == 1 ? b->edge_items : b->wall_items);
+            void *args[3] = {(void *)&probs, (void *)&items, (void *)&parity};
+            hipKernelNodeParams kp = {};
+            kp.func = const_cast<void *>(w == 0 ? K.bulk : (w == 1 ? K.edge : K.wall));
+            kp.gridDim = dim3(nblk);
+            kp.blockDim = dim3(w < 2 ? K.bulk_threads : K.wall_threads);
+            kp.sharedMemBytes = 0;
+            kp.kernelParams = args;
+            kp.extra = nullptr;
+            hipGraphNode_t node;
+            e = hipGraphAddKernelNode(&node, b->graph, prev.empty() ? nullptr : prev.data(), prev.size(), &kp);
+            if (e == hipSuccess) cur.push_back(node);
+        }
+        prev.swap(cur);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+        return hip_fail(e, "batch graph");
+    }
+    b->graph_steps = GRAPH_STEPS;
+    return LBM_OK;
+}
+
+}  // namespace
+
+size_t lbm_batch_workspace_bytes(const lbm_params *params, int32_t n)
+{
+    BatchLayout B;
+    if (batch_layout(params, n, B) != LBM_OK) return 0;
+    return B.total;
+}
+
+lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, size_t workspace_bytes,
+                          void *hip_stream, lbm_batch **out)
+{
+    if (!out) return fail(LBM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    BatchLayout B;
+    lbm_status st = batch_layout(params, n, B);
+    if (st != LBM_OK) return st;
+    if (!workspace || ((uintptr_t)workspace) % 256) return fail(LBM_ERR_INVALID, "workspace must be non-NULL and 256-byte aligned");
+    if (workspace_bytes < B.total) return fail(LBM_ERR_INVALID, "workspace too small: %zu < %zu bytes", workspace_bytes, B.total);
+    lbm_batch *b = new (std::nothrow) lbm_batch;
+    if (!b) return fail(LBM_ERR_DEVICE, "out of host memory");
+    char *ws = static_cast<char *>(workspace);
+    b->storage = params[0].storage;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->t = 0;
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->graph_steps = 0;
+    std::vector<lbm::BatchProblem> hp(n);
+    for (int k = 0; k < n; ++k) {
+        lbm_ctx *c = nullptr;
+        st = init_ctx(&params[k], ws + B.off[k], workspace_bytes - B.off[k], hip_stream, &c);
+        if (st != LBM_OK) {
+            for (lbm_ctx *q : b->ctx) delete q;
+            delete b;
+            return fail(st, "problem %d: %s", k, g_err);
+        }
+        c->in_batch = 1;
+        b->ctx.push_back(c);
+        hp[k].P = c->kp;
+        hp[k].buf[0] = c->ws + c->lay.off_a;
+        hp[k].buf[1] = c->ws + c->lay.off_b;
+        hp[k].tiles_x = B.tiles_x[k];
+    }
+    b->probs = reinterpret_cast<lbm::BatchProblem *>(ws + B.off_probs);
+    b->bulk_items = reinterpret_cast<int2 *>(ws + B.off_bulk);
+    b->edge_items = reinterpret_cast<int2 *>(ws + B.off_edge);
+    b->nedge = (int)B.edge.size();
+    b->wall_items = reinterpret_cast<int2 *>(ws + B.off_wall);
+    b->all_items = reinterpret_cast<int2 *>(ws + B.off_all);
+    b->nall = (int)B.all.size();
+    b->flags = reinterpret_cast<int *>(ws + B.off_flags);
+    b->nbulk = (int)B.bulk.size();
+    b->nwall = (int)B.wall.size();
+    hipError_t e = hipMemcpyAsync(b->probs, hp.data(), n * sizeof(lbm::BatchProblem), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && b->nbulk)
+        e = hipMemcpyAsync(b->bulk_items, B.bulk.data(), B.bulk.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && b->nedge)
+        e = hipMemcpyAsync(b->edge_items, B.edge.data(), B.edge.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && b->nwall)
+        e = hipMemcpyAsync(b->wall_items, B.wall.data(), B.wall.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && b->nall)
+        e = hipMemcpyAsync(b->all_items, B.all.data(), B.all.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
+    // the host vectors are released on return: wait for the copies
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        for (lbm_ctx *q : b->ctx) delete q;
+        delete b;
+        return hip_fail(e, "batch tables");
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
+{
+    if (!b) return fail(LBM_ERR_INVALID, "batch is NULL");
+    if (nsteps < 0) return fail(LBM_ERR_INVALID, "nsteps < 0");
+    int64_t done = 0;
+    hipError_t e = hipSuccess;
+    // whole graphs need the current parity to be even
+    while (done < nsteps && (b->t & 1)) {
+        e = lbm::launch_batch_step(b->storage, b->probs, b->bulk_items, b->nbulk, b->edge_items, b->nedge,
+                                   b->wall_items, b->nwall,
+                                   (int)(b->t & 1), b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch step");
+        ++done; ++b->t;
+    }
+    if (nsteps - done >= GRAPH_STEPS && !b->exec) {
+        lbm_status st = batch_build_graph(b);
+        if (st != LBM_OK) return st;
+    }
+    while (nsteps - done >= GRAPH_STEPS) {
+        e = hipGraphLaunch(b->exec, b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch graph launch");
+        done += GRAPH_STEPS;
+        b->t += GRAPH_STEPS;
+    }
+    while (done < nsteps) {
+        e = lbm::launch_batch_step(b->storage, b->probs, b->bulk_items, b->nbulk, b->edge_items, b->nedge,
+                                   b->wall_items, b->nwall,
+                                   (int)(b->t & 1), b->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch step");
+        ++done; ++b->t;
+    }
+    for (lbm_ctx *c : b->ctx) c->t = b->t;
+    return LBM_OK;
+}
+
+lbm_ctx *lbm_batch_problem(lbm_batch *b, int32_t k)
+{
+    if (!b || k < 0 || k >= (int32_t)b->ctx.size()) return nullptr;
+    return b->ctx[k];
+}
+
+lbm_status lbm_batch_check(lbm_batch *b, int32_t *flags_host)
+{
+    if (!b || !flags_host) return fail(LBM_ERR_INVALID, "NULL argument");
+    const int n = (int)b->ctx.size();
+    hipError_t e = hipMemsetAsync(b->flags, 0, n * sizeof(int), b->stream);
+    if (e == hipSuccess)
+        e = lbm::launch_batch_check(b->storage, b->probs, b->all_items, b->nall, (int)(b->t & 1), b->flags, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags_host, b->flags, n * sizeof(int), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch check");
+    for (int k = 0; k < n; ++k)
+        if (flags_host[k]) return fail(LBM_ERR_NONFINITE, "problem %d holds non-finite values", k);
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch *b)
+{
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (lbm_ctx *c : b->ctx) delete c;
+    delete b;
+}
 
 }  // extern "C"

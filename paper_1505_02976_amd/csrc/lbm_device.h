@@ -68,6 +68,7 @@ struct KParams {
     int pitch;                   // row pitch in elements (plane layout)
     int ntx;                     // tiles per row (tiled layout)
     int nwall;                   // number of wall-node slots enumerated by the wall kernels
+    int nwall_rows;              // slots of the two walled rows (the step's wall launch)
     long long plane;             // stride between population planes, elements
     double tau_f, tau_T, A, B, sigma, Q, gbeta, T0, ax, ay;
     double nu_over_K, inv_sqrtK; // 0 when K is infinite
@@ -524,14 +525,42 @@ __device__ __forceinline__ WallInfo wall_info(const KParams &P, int x, int y)
 // Non-equilibrium extrapolation (Sec. 3.4, Eqs. FNEESEQFIN, NEESVel, TeEBounDFEQ,
 // TNEESAp, TNEESApGra): rebuilds the pre-collision populations of wall node (x, y) from
 // the streamed populations of its reference node x_f (and x_ff on Neumann walls).
+// Thermal condition of a wall node: index of the isothermal wall that applies (-1 if the
+// node is on prescribed-gradient walls only).
+__device__ __forceinline__ int thermal_dirichlet_wall(const KParams &P, const WallInfo &w)
+{
+    if (w.xw >= 0 && P.wall_kind[w.xw] == 0) return w.xw;
+    if (w.yw >= 0 && P.wall_kind[w.yw] == 0) return w.yw;
+    return -1;
+}
+
+// Td = T - T0 of node (x, y) from its streamed temperature populations (sigma T = sum g + Q/2).
 template <typename S, typename R>
-__device__ __forceinline__ void wall_populations(const S *__restrict__ src, const KParams &P,
-                                                 const Cst<R> &k, int x, int y, R *f, R *g)
+__device__ __forceinline__ R gather_Td(const S *__restrict__ src, const KParams &P, const Cst<R> &k,
+                                       int x, int y)
+{
+    const int xm = (x == 0) ? P.nx - 1 : x - 1;
+    const int xp = (x == P.nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? P.ny - 1 : y - 1;
+    const int yp = (y == P.ny - 1) ? 0 : y + 1;
+    const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
+    const int sy[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
+    R sg = R(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sg += R(Store<S>::ld(src + pidx<S>(P, 9 + i, sx[i], sy[i]), P.hinv));
+    return (sg + k.halfQ) * k.isig;
+}
+
+// Non-equilibrium extrapolation (Sec. 3.4, Eqs. FNEESEQFIN, NEESVel, TeEBounDFEQ,
+// TNEESAp, TNEESApGra): pre-collision populations of wall node (x, y) from the streamed
+// populations ff, gf of its reference node x_f and, on prescribed-gradient walls, Td of
+// the next node x_ff.  f, g may alias ff, gf.
+template <typename R>
+__device__ __forceinline__ void wall_from_ref(const KParams &P, const Cst<R> &k, int x, int y,
+                                              const R *ff, const R *gf, R Tdff, R *f, R *g)
 {
     const WallInfo w = wall_info(P, x, y);
     const int xf = x + w.dx, yf = y + w.dy;
-    R ff[9], gf[9];
-    gather<S, R>(src, P, xf, yf, ff, gf);
     const EpsC<R> ef = eps_at<R>(P, xf, yf);
     Macro<R> mf;
     const R T0 = R(P.T0);
@@ -552,9 +581,7 @@ __device__ __forceinline__ void wall_populations(const S *__restrict__ src, cons
         f[i] = feb + (ff[i] - fef);
     }
 
-    int dir = -1;
-    if (w.xw >= 0 && P.wall_kind[w.xw] == 0) dir = w.xw;
-    else if (w.yw >= 0 && P.wall_kind[w.yw] == 0) dir = w.yw;
+    const int dir = thermal_dirichlet_wall(P, w);
     R Tdb, gbx, gby;
     if (dir >= 0) {
         Tdb = R(P.wall_T[dir] - P.T0);
@@ -563,18 +590,6 @@ __device__ __forceinline__ void wall_populations(const S *__restrict__ src, cons
     } else {
         gbx = (w.xw >= 0) ? R(w.dx * P.wall_dTdn[w.xw]) : mf.gx;
         gby = (w.yw >= 0) ? R(w.dy * P.wall_dTdn[w.yw]) : mf.gy;
-        const int xff = x + 2 * w.dx, yff = y + 2 * w.dy;
-        const int xm = (xff == 0) ? P.nx - 1 : xff - 1;
-        const int xp = (xff == P.nx - 1) ? 0 : xff + 1;
-        const int ym = (yff == 0) ? P.ny - 1 : yff - 1;
-        const int yp = (yff == P.ny - 1) ? 0 : yff + 1;
-        const int sx[9] = {xff, xm, xff, xp, xff, xm, xp, xp, xm};
-        const int sy[9] = {yff, yff, ym, yff, yp, ym, ym, yp, yp};
-        R sgff = R(0);
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            sgff += R(Store<S>::ld(src + pidx<S>(P, 9 + i, sx[i], sy[i]), P.hinv));
-        const R Tdff = (sgff + k.halfQ) * k.isig;
         Tdb = (R(4) * mf.Td - Tdff - R(2) * (R(w.dx) * gbx + R(w.dy) * gby)) * R(1.0 / 3.0);
     }
     const R Tb = T0 + Tdb;
@@ -584,6 +599,19 @@ __device__ __forceinline__ void wall_populations(const S *__restrict__ src, cons
         const R gef = geq_i<R>(i, mf.Td, Tf, mf.ux, mf.uy, ef.ieps, epf, mf.gx, mf.gy, k);
         g[i] = geb + (gf[i] - gef);
     }
+}
+
+// The boundary scheme with the reference nodes' populations gathered from memory.
+template <typename S, typename R>
+__device__ __forceinline__ void wall_populations(const S *__restrict__ src, const KParams &P,
+                                                 const Cst<R> &k, int x, int y, R *f, R *g)
+{
+    const WallInfo w = wall_info(P, x, y);
+    R ff[9], gf[9];
+    gather<S, R>(src, P, x + w.dx, y + w.dy, ff, gf);
+    R Tdff = R(0);
+    if (thermal_dirichlet_wall(P, w) < 0) Tdff = gather_Td<S, R>(src, P, k, x + 2 * w.dx, y + 2 * w.dy);
+    wall_from_ref<R>(P, k, x, y, ff, gf, Tdff, f, g);
 }
 
 // Wall-node slot s -> (x, y); returns false for slots that are not wall nodes of this

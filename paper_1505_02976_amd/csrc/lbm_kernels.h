@@ -5,10 +5,22 @@
 
 namespace lbm {
 
+// One problem of a batch: its kernel parameters and its two population buffers.
+struct BatchProblem {
+    KParams P;
+    void *buf[2];
+    int tiles_x;
+};
+
+struct BatchKernels {
+    const void *bulk, *edge, *wall;
+    int bulk_threads, wall_threads;
+};
+
 hipError_t launch_init(int storage, void *dst, const KParams &P, const double *T, const double *p,
                        const double *ux, const double *uy, hipStream_t st);
 hipError_t launch_step(int storage, const void *src, void *dst, const KParams &P, hipStream_t st);
-// The two launches of one step separately (bulk nodes, wall nodes).
+// The launches of one step separately: interior tiles; edge tiles and walled rows.
 hipError_t launch_step_bulk(int storage, const void *src, void *dst, const KParams &P, hipStream_t st);
 hipError_t launch_step_wall(int storage, const void *src, void *dst, const KParams &P, hipStream_t st);
 hipError_t launch_fields(int storage, const void *src, const KParams &P, void *const out[9], int f32,
@@ -19,5 +31,17 @@ hipError_t launch_nusselt(int storage, const void *src, const KParams &P, int wa
                           double dT, double *out, hipStream_t st);
 hipError_t launch_state(int storage, void *buf, const KParams &P, double *io, bool get, hipStream_t st);
 long long residual_partials(const KParams &P);
+
+// Batched stepping: items are (problem, tile) / (problem, wall block) pairs.
+hipError_t launch_batch_step(int storage, const BatchProblem *probs, const int2 *bulk_items, int nbulk,
+                             const int2 *edge_items, int nedge, const int2 *wall_items, int nwall,
+                             int parity, hipStream_t st);
+hipError_t launch_batch_check(int storage, const BatchProblem *probs, const int2 *items, int n,
+                              int parity, int *flags, hipStream_t st);
+BatchKernels batch_kernels(int storage);
+int batch_tiles_x(int storage, const KParams &P);
+int wall_block_size();
+// Nodes updated by the interior-tile launch of one step (single-problem path).
+long long interior_nodes(int storage, const KParams &P);
 
 }  // namespace lbm

@@ -95,46 +95,178 @@ __device__ __forceinline__ int tile_of_block(int b, int nb)
 #endif
 }
 
-template <typename S, typename R>
-__global__ void __launch_bounds__(BULK_BX)
-k_step_bulk(const S *__restrict__ src, S *__restrict__ dst, KParams P, int tiles_x)
+// One tile (a row segment of BX * NPT nodes, BX = block size) of the bulk update.
+//
+// Nodes on the walls x = 0 and x = nx - 1 (outside the walled rows) are updated here too:
+// the lanes of a wavefront hold consecutive x, so the reference node x_f = x -+ 1 of a
+// wall node (and x_ff = x -+ 2 on prescribed-gradient walls) normally sits in the
+// neighbouring lane, whose streamed populations are taken by cross-lane shuffles; only
+// when it falls in another wavefront is it gathered from memory.  Only wavefronts that
+// contain such a node take this branch.
+template <typename S, bool WALLS, int BX = BULK_BX>
+__device__ __forceinline__ void bulk_tile(const S *__restrict__ src, S *__restrict__ dst,
+                                          const KParams &P, int t, int tiles_x)
 {
     constexpr int NPT = Npt<S>::v;
     using RC = typename Prec<S>::R;
-    const int t = tile_of_block(blockIdx.x, gridDim.x);
     const int y = t / tiles_x;
-    const int x0 = (t - y * tiles_x) * (BULK_BX * NPT) + threadIdx.x;
+    const int x0 = (t - y * tiles_x) * (BX * NPT) + threadIdx.x;
     if (!P.py && (y == 0 || y == P.ny - 1)) return;
     RC f[NPT][9], g[NPT][9];
-    bool act[NPT];
+    bool act[NPT], vw[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int x = x0 + k * BULK_BX;
-        act[k] = x < P.nx && (P.px || (x != 0 && x != P.nx - 1));
+        const int x = x0 + k * BX;
+        vw[k] = WALLS && x < P.nx && !P.px && (x == 0 || x == P.nx - 1);
+        act[k] = x < P.nx && !vw[k];
         if (act[k]) gather<S, RC>(src, P, x, y, f[k], g[k]);
+    }
+    if (WALLS && !P.px) {
+        const Cst<RC> &c = make_cst<RC>(P);
+        const int lane = __lane_id();
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            if (!__ballot(vw[k])) continue;               // wavefront-uniform
+            const int x = x0 + k * BX;
+            const int dx = (x == 0) ? 1 : -1;
+            RC sg = RC(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) sg += g[k][i];
+            const RC Td_own = (sg + c.halfQ) * c.isig;
+            const int l1 = lane + dx, l2 = lane + 2 * dx;
+            const bool in1 = vw[k] && l1 >= 0 && l1 < warpSize;
+            const bool in2 = vw[k] && l2 >= 0 && l2 < warpSize;
+            const int s1 = in1 ? l1 : lane, s2 = in2 ? l2 : lane;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                f[k][i] = __shfl(f[k][i], s1);
+                g[k][i] = __shfl(g[k][i], s1);
+            }
+            RC Tdff = __shfl(Td_own, s2);
+            if (vw[k]) {
+                if (!in1) gather<S, RC>(src, P, x + dx, y, f[k], g[k]);
+                if (!in2 && thermal_dirichlet_wall(P, wall_info(P, x, y)) < 0)
+                    Tdff = gather_Td<S, RC>(src, P, c, x + 2 * dx, y);
+                wall_from_ref<RC>(P, c, x, y, f[k], g[k], Tdff, f[k], g[k]);
+                act[k] = true;
+            }
+        }
     }
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         if (!act[k]) continue;
-        const int x = x0 + k * BULK_BX;
+        const int x = x0 + k * BX;
         node_update<RC, typename Prec<S>::M>(f[k], g[k], P, x, y);
         store_node<S, RC>(dst, P, x, y, f[k], g[k]);
     }
 }
 
-// Fused step, wall nodes: boundary scheme -> moments -> collide -> store
-template <typename S, typename R>
-__global__ void __launch_bounds__(WALL_B)
-k_step_wall(const S *__restrict__ src, S *__restrict__ dst, KParams P)
+// One node of the walled rows y = 0 and y = ny - 1 (slot s < nwall_rows): boundary scheme
+// -> moments -> collide -> store.
+template <typename S>
+__device__ __forceinline__ void wall_node(const S *__restrict__ src, S *__restrict__ dst,
+                                          const KParams &P, int s)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
     int x, y;
-    if (s >= P.nwall || !wall_slot(P, s, x, y)) return;
+    if (s >= P.nwall_rows || !wall_slot(P, s, x, y)) return;
     using M = typename Prec<S>::M;
     M f[9], g[9];
     wall_populations<S, M>(src, P, make_cst<M>(P), x, y, f, g);
     node_update<M, M>(f, g, P, x, y);
     store_node<S, M>(dst, P, x, y, f, g);
+}
+
+// Tiles of a row: interior tiles hold no node of the walls x = 0, x = nx - 1; edge tiles
+// are the first and last tile of a row when x is walled.
+__host__ __device__ __forceinline__ int rows_begin(const KParams &P) { return P.py ? 0 : 1; }
+__host__ __device__ __forceinline__ int rows_count(const KParams &P) { return P.py ? P.ny : P.ny - 2; }
+__host__ __device__ __forceinline__ int interior_tiles(const KParams &P, int tx)
+{
+    return P.px ? tx : (tx > 2 ? tx - 2 : 0);
+}
+__host__ __device__ __forceinline__ int edge_tiles(const KParams &P, int tx)
+{
+    return P.px ? 0 : (tx < 2 ? tx : 2);
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(BULK_BX)
+k_step_bulk(const S *__restrict__ src, S *__restrict__ dst, KParams P, int tiles_x)
+{
+    const int ti = interior_tiles(P, tiles_x);
+    const int r = blockIdx.x / ti, c = blockIdx.x - r * ti + (P.px ? 0 : 1);
+    bulk_tile<S, false>(src, dst, P, (rows_begin(P) + r) * tiles_x + c, tiles_x);
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(BULK_BX)
+k_step_edge(const S *__restrict__ src, S *__restrict__ dst, KParams P, int tiles_x)
+{
+    const int te = edge_tiles(P, tiles_x);
+    const int r = blockIdx.x / te, c = (blockIdx.x - r * te == 0) ? 0 : tiles_x - 1;
+    bulk_tile<S, true>(src, dst, P, (rows_begin(P) + r) * tiles_x + c, tiles_x);
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(WALL_B)
+k_step_wall(const S *__restrict__ src, S *__restrict__ dst, KParams P)
+{
+    wall_node<S>(src, dst, P, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------------
+// Batched step over many problems: block b works on item items[b] = (problem, tile) of
+// the bulk update, or (problem, wall block) of the wall update.  parity selects which
+// of each problem's two buffers is the source.
+// ---------------------------------------------------------------------------------
+#ifndef LBM_BATCH_BX
+#define LBM_BATCH_BX 64
+#endif
+constexpr int BATCH_BX = LBM_BATCH_BX;
+
+template <typename S, bool WALLS>
+__global__ void __launch_bounds__(BATCH_BX)
+k_batch_bulk(const BatchProblem *__restrict__ probs, const int2 *__restrict__ items, int parity)
+{
+    const int2 it = items[blockIdx.x];
+    const BatchProblem &B = probs[it.x];
+    bulk_tile<S, WALLS, BATCH_BX>(static_cast<const S *>(B.buf[parity]),
+                                  static_cast<S *>(B.buf[parity ^ 1]), B.P, it.y, B.tiles_x);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(WALL_B)
+k_batch_wall(const BatchProblem *__restrict__ probs, const int2 *__restrict__ items, int parity)
+{
+    const int2 it = items[blockIdx.x];
+    const BatchProblem &B = probs[it.x];
+    wall_node<S>(static_cast<const S *>(B.buf[parity]), static_cast<S *>(B.buf[parity ^ 1]), B.P,
+                 it.y * WALL_B + threadIdx.x);
+}
+
+// Non-finite check of each problem's current populations (one flag per problem; a block
+// that finds a bad value stores 1, stores of the same value from several blocks are
+// harmless).
+template <typename S>
+__global__ void __launch_bounds__(BATCH_BX)
+k_batch_check(const BatchProblem *__restrict__ probs, const int2 *__restrict__ items, int parity,
+              int *flags)
+{
+    const int2 it = items[blockIdx.x];
+    const BatchProblem &B = probs[it.x];
+    const KParams &P = B.P;
+    constexpr int NPT = Npt<S>::v;
+    const S *src = static_cast<const S *>(B.buf[parity]);
+    const int y = it.y / B.tiles_x;
+    const int x0 = (it.y - y * B.tiles_x) * (BATCH_BX * NPT) + threadIdx.x;
+    bool bad = false;
+    for (int k = 0; k < NPT; ++k) {
+        const int x = x0 + k * BATCH_BX;
+        if (x >= P.nx) continue;
+        for (int q = 0; q < 18; ++q)
+            bad |= !isfinite(float(Store<S>::ld(src + pidx<S>(P, q, x, y), 1.0f)));
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) flags[it.x] = 1;
 }
 
 // ---------------------------------------------------------------------------------
@@ -397,13 +529,30 @@ static hipError_t launch_init_t(void *dst, const KParams &P, const double *T, co
 }
 
 template <typename S, typename R>
-static hipError_t launch_step_t(const void *src, void *dst, const KParams &P, hipStream_t st)
+static void launch_interior(const void *src, void *dst, const KParams &P, hipStream_t st)
 {
     const int tx = step_tiles_x<S>(P);
-    hipLaunchKernelGGL((k_step_bulk<S, R>), dim3(tx * P.ny), dim3(BULK_BX), 0, st,
-                       (const S *)src, (S *)dst, P, tx);
-    if (P.nwall > 0)
-        hipLaunchKernelGGL((k_step_wall<S, R>), dim3(wall_blocks(P, WALL_B)), dim3(WALL_B), 0, st,
+    const int n = interior_tiles(P, tx) * rows_count(P);
+    if (n > 0)
+        hipLaunchKernelGGL((k_step_bulk<S, R>), dim3(n), dim3(BULK_BX), 0, st, (const S *)src, (S *)dst, P, tx);
+}
+
+template <typename S, typename R>
+static void launch_edges(const void *src, void *dst, const KParams &P, hipStream_t st)
+{
+    const int tx = step_tiles_x<S>(P);
+    const int n = edge_tiles(P, tx) * rows_count(P);
+    if (n > 0)
+        hipLaunchKernelGGL((k_step_edge<S, R>), dim3(n), dim3(BULK_BX), 0, st, (const S *)src, (S *)dst, P, tx);
+}
+
+template <typename S, typename R>
+static hipError_t launch_step_t(const void *src, void *dst, const KParams &P, hipStream_t st)
+{
+    launch_interior<S, R>(src, dst, P, st);
+    launch_edges<S, R>(src, dst, P, st);
+    if (P.nwall_rows > 0)
+        hipLaunchKernelGGL((k_step_wall<S, R>), dim3((P.nwall_rows + WALL_B - 1) / WALL_B), dim3(WALL_B), 0, st,
                            (const S *)src, (S *)dst, P);
     return hipGetLastError();
 }
@@ -411,17 +560,16 @@ static hipError_t launch_step_t(const void *src, void *dst, const KParams &P, hi
 template <typename S, typename R>
 static hipError_t launch_step_bulk_t(const void *src, void *dst, const KParams &P, hipStream_t st)
 {
-    const int tx = step_tiles_x<S>(P);
-    hipLaunchKernelGGL((k_step_bulk<S, R>), dim3(tx * P.ny), dim3(BULK_BX), 0, st,
-                       (const S *)src, (S *)dst, P, tx);
+    launch_interior<S, R>(src, dst, P, st);
     return hipGetLastError();
 }
 
 template <typename S, typename R>
 static hipError_t launch_step_wall_t(const void *src, void *dst, const KParams &P, hipStream_t st)
 {
-    if (P.nwall > 0)
-        hipLaunchKernelGGL((k_step_wall<S, R>), dim3(wall_blocks(P, WALL_B)), dim3(WALL_B), 0, st,
+    launch_edges<S, R>(src, dst, P, st);
+    if (P.nwall_rows > 0)
+        hipLaunchKernelGGL((k_step_wall<S, R>), dim3((P.nwall_rows + WALL_B - 1) / WALL_B), dim3(WALL_B), 0, st,
                            (const S *)src, (S *)dst, P);
     return hipGetLastError();
 }
@@ -537,6 +685,90 @@ hipError_t launch_state(int storage, void *buf, const KParams &P, double *io, bo
     LBM_DISPATCH(storage, (launch_state_t<double>(buf, P, io, get, st)),
                  (launch_state_t<float>(buf, P, io, get, st)),
                  (launch_state_t<__half>(buf, P, io, get, st)))
+}
+
+template <typename S>
+static hipError_t batch_step_t(const BatchProblem *probs, const int2 *bulk_items, int nbulk,
+                               const int2 *edge_items, int nedge, const int2 *wall_items, int nwall,
+                               int parity, hipStream_t st)
+{
+    if (nbulk > 0)
+        hipLaunchKernelGGL((k_batch_bulk<S, false>), dim3(nbulk), dim3(BATCH_BX), 0, st, probs, bulk_items, parity);
+    if (nedge > 0)
+        hipLaunchKernelGGL((k_batch_bulk<S, true>), dim3(nedge), dim3(BATCH_BX), 0, st, probs, edge_items, parity);
+    if (nwall > 0)
+        hipLaunchKernelGGL((k_batch_wall<S>), dim3(nwall), dim3(WALL_B), 0, st, probs, wall_items, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(int storage, const BatchProblem *probs, const int2 *bulk_items, int nbulk,
+                             const int2 *edge_items, int nedge, const int2 *wall_items, int nwall,
+                             int parity, hipStream_t st)
+{
+    LBM_DISPATCH(storage,
+                 (batch_step_t<double>(probs, bulk_items, nbulk, edge_items, nedge, wall_items, nwall, parity, st)),
+                 (batch_step_t<float>(probs, bulk_items, nbulk, edge_items, nedge, wall_items, nwall, parity, st)),
+                 (batch_step_t<__half>(probs, bulk_items, nbulk, edge_items, nedge, wall_items, nwall, parity, st)))
+}
+
+BatchKernels batch_kernels(int storage)
+{
+    BatchKernels k;
+    switch (storage) {
+    case 0:
+        k.bulk = (const void *)k_batch_bulk<double, false>;
+        k.edge = (const void *)k_batch_bulk<double, true>;
+        k.wall = (const void *)k_batch_wall<double>;
+        break;
+    case 1:
+        k.bulk = (const void *)k_batch_bulk<float, false>;
+        k.edge = (const void *)k_batch_bulk<float, true>;
+        k.wall = (const void *)k_batch_wall<float>;
+        break;
+    default:
+        k.bulk = (const void *)k_batch_bulk<__half, false>;
+        k.edge = (const void *)k_batch_bulk<__half, true>;
+        k.wall = (const void *)k_batch_wall<__half>;
+        break;
+    }
+    k.bulk_threads = BATCH_BX;
+    k.wall_threads = WALL_B;
+    return k;
+}
+
+template <typename S>
+static hipError_t batch_check_t(const BatchProblem *probs, const int2 *items, int n, int parity,
+                                int *flags, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL((k_batch_check<S>), dim3(n), dim3(BATCH_BX), 0, st, probs, items, parity, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_check(int storage, const BatchProblem *probs, const int2 *items, int n,
+                              int parity, int *flags, hipStream_t st)
+{
+    LBM_DISPATCH(storage, (batch_check_t<double>(probs, items, n, parity, flags, st)),
+                 (batch_check_t<float>(probs, items, n, parity, flags, st)),
+                 (batch_check_t<__half>(probs, items, n, parity, flags, st)))
+}
+
+int batch_tiles_x(int storage, const KParams &P)
+{
+    const int npt = storage == 0 ? Npt<double>::v : (storage == 1 ? Npt<float>::v : Npt<__half>::v);
+    const int span = BATCH_BX * npt;
+    return (P.nx + span - 1) / span;
+}
+
+int wall_block_size() { return WALL_B; }
+
+long long interior_nodes(int storage, const KParams &P)
+{
+    const int npt = storage == 0 ? Npt<double>::v : (storage == 1 ? Npt<float>::v : Npt<__half>::v);
+    const int span = BULK_BX * npt;
+    const int tx = (P.nx + span - 1) / span;
+    long long cols = P.px ? P.nx : (tx > 2 ? (long long)(tx - 2) * span : 0);
+    return cols * rows_count(P);
 }
 
 long long residual_partials(const KParams &P)

@@ -58,7 +58,9 @@ _lib = None
 
 EXPORTS = ("lbm_derive", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lbm_time",
            "lbm_moments", "lbm_gradients", "lbm_nusselt", "lbm_residual", "lbm_get_state",
-           "lbm_set_state", "lbm_destroy", "lbm_last_error")
+           "lbm_set_state", "lbm_destroy", "lbm_last_error",
+           "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_problem",
+           "lbm_batch_check", "lbm_batch_destroy")
 
 
 def lib():
@@ -80,7 +82,8 @@ def lib():
     L.lbm_step.restype = st
     L.lbm_step.argtypes = [vp, C.c_int64]
     L.lbm_step_timed.restype = st
-    L.lbm_step_timed.argtypes = [vp, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.lbm_step_timed.argtypes = [vp, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_int64)]
     L.lbm_time.restype = C.c_int64
     L.lbm_time.argtypes = [vp]
     L.lbm_moments.restype = st
@@ -97,6 +100,18 @@ def lib():
     L.lbm_set_state.argtypes = [vp, vp]
     L.lbm_destroy.restype = None
     L.lbm_destroy.argtypes = [vp]
+    L.lbm_batch_workspace_bytes.restype = C.c_size_t
+    L.lbm_batch_workspace_bytes.argtypes = [C.POINTER(_Params), C.c_int32]
+    L.lbm_batch_init.restype = st
+    L.lbm_batch_init.argtypes = [C.POINTER(_Params), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.lbm_batch_step.restype = st
+    L.lbm_batch_step.argtypes = [vp, C.c_int64]
+    L.lbm_batch_problem.restype = vp
+    L.lbm_batch_problem.argtypes = [vp, C.c_int32]
+    L.lbm_batch_check.restype = st
+    L.lbm_batch_check.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.lbm_batch_destroy.restype = None
+    L.lbm_batch_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -160,11 +175,38 @@ def workspace_bytes(cfg: dict) -> int:
     return int(lib().lbm_workspace_bytes(C.byref(make_params(cfg))))
 
 
+def _device_fields(torch, cfg, device, nx, ny):
+    """Initial fields of a problem as FP64 device tensors; returns (pointer map, tensors)."""
+    dev, keep = {}, []
+    for key in ("eps_field", "T_init", "p_init", "ux_init", "uy_init"):
+        a = cfg.get(key)
+        if a is None:
+            continue
+        t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(ny, nx), device=device)
+        keep.append(t)
+        dev[key] = t.data_ptr()
+    return dev, keep
+
+
 class Sim:
     """A simulation context on a CUDA (HIP) device; fields come back as torch tensors."""
 
+    @classmethod
+    def _wrap(cls, handle, cfg, device, stream, owner):
+        import torch
+        self = cls.__new__(cls)
+        self.torch = torch
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.nx, self.ny = int(cfg["nx"]), int(cfg["ny"])
+        self.stream = stream
+        self.h = C.c_void_p(handle)
+        self._owner = owner      # the batch owns the context
+        return self
+
     def __init__(self, cfg: dict, device: str = "cuda:0", stream=None):
         import torch
+        self._owner = None
         self.torch = torch
         self.cfg = cfg
         self.device = torch.device(device)
@@ -198,9 +240,9 @@ class Sim:
             del keep
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and getattr(self, "_owner", None) is None:
             lib().lbm_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -216,10 +258,11 @@ class Sim:
         _check(lib().lbm_step(self.h, int(n)))
 
     def step_timed(self, n: int):
-        """Steps with per-kernel HIP events; returns (bulk_ms, wall_ms) summed over n."""
-        b, w = C.c_double(), C.c_double()
-        _check(lib().lbm_step_timed(self.h, int(n), C.byref(b), C.byref(w)))
-        return b.value, w.value
+        """Steps with HIP events around the launches; returns (interior_ms, other_ms,
+        interior_nodes): summed durations over n steps and the nodes per interior launch."""
+        b, w, nodes = C.c_double(), C.c_double(), C.c_int64()
+        _check(lib().lbm_step_timed(self.h, int(n), C.byref(b), C.byref(w), C.byref(nodes)))
+        return b.value, w.value, nodes.value
 
     def _alloc(self, dtype):
         return self.torch.empty((self.ny, self.nx), dtype=dtype, device=self.device)
@@ -267,3 +310,68 @@ class Sim:
         assert tuple(t.shape) == (2, 9, self.ny, self.nx)
         _check(lib().lbm_set_state(self.h, t.data_ptr()))
         self.stream.synchronize()
+
+
+class Batch:
+    """Many problems advanced together (see lbm_batch_* in include/lbm.h)."""
+
+    def __init__(self, cfgs: list, device: str = "cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.cfgs = cfgs
+        self.device = torch.device(device)
+        L = lib()
+        n = len(cfgs)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            keep = []
+            arr = (_Params * n)()
+            for k, cfg in enumerate(cfgs):
+                dev, kk = _device_fields(torch, cfg, self.device, int(cfg["nx"]), int(cfg["ny"]))
+                keep += kk
+                arr[k] = make_params(cfg, dev)
+            nbytes = int(L.lbm_batch_workspace_bytes(arr, n))
+            if nbytes == 0:
+                for k in range(n):
+                    _check(L.lbm_derive(C.byref(arr[k]), C.byref(_Derived())))
+                raise LbmError(ERR_INVALID, "batch rejected (mixed storage types?)")
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+            h = C.c_void_p()
+            _check(L.lbm_batch_init(arr, n, C.c_void_p(aligned), nbytes,
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+            self.h = h
+            self.stream.synchronize()
+            del keep
+        self.problems = [Sim._wrap(L.lbm_batch_problem(self.h, k), cfgs[k], self.device, self.stream, self)
+                         for k in range(n)]
+
+    def __len__(self):
+        return len(self.problems)
+
+    def __getitem__(self, k):
+        return self.problems[k]
+
+    def step(self, n: int = 1):
+        _check(lib().lbm_batch_step(self.h, int(n)))
+
+    def check(self):
+        """Per-problem non-finite flags (numpy int32 array)."""
+        flags = (C.c_int32 * len(self.problems))()
+        st = lib().lbm_batch_check(self.h, flags)
+        if st not in (OK, ERR_NONFINITE):
+            _check(st)
+        return np.array(flags[:], dtype=np.int32)
+
+    def close(self):
+        if getattr(self, "h", None):
+            for p in self.problems:
+                p.h = None
+            lib().lbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -93,3 +93,16 @@ def test_init_rejects_null_workspace(lbm):
     h = C.c_void_p()
     st = lbm.lib().lbm_init(C.byref(prm), None, 0, None, C.byref(h))
     assert st == lbm.ERR_INVALID and not h.value
+
+
+def test_batch_rejects_mixed_storage(lbm):
+    cfgs = [W.cavity(32, storage="f32"), W.cavity(40, storage="f64")]
+    arr = (lbm._Params * 2)()
+    for k, c in enumerate(cfgs):
+        arr[k] = lbm.make_params(c)
+    assert lbm.lib().lbm_batch_workspace_bytes(arr, 2) == 0
+    assert "storage" in lbm.lib().lbm_last_error().decode()
+    cfgs[1]["storage"] = "f32"
+    arr[1] = lbm.make_params(cfgs[1])
+    single = lbm.workspace_bytes(cfgs[0]) + lbm.workspace_bytes(cfgs[1])
+    assert lbm.lib().lbm_batch_workspace_bytes(arr, 2) >= single

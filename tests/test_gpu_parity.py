@@ -162,3 +162,33 @@ def test_get_set_state_roundtrip(gpu):
         sim.set_state(st)
         st2 = sim.get_state()
         assert float((st - st2).abs().max()) <= tol
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 2e-6), ("f16", 5e-3)])
+def test_full_size_cavity(gpu, oracle_mod, storage, tol):
+    """The 4096 x 4096 throughput workload in the launch configuration bench.py times,
+    started from smooth random pressure and velocity fields so that every term of the
+    step is active at every node; three steps against the oracle on the whole grid.
+    FP64: max-abs on all fields; FP32/FP16: relative L2 of u, T and p."""
+    n = 4096
+    cfg = W.large_cavity(n, storage=storage)
+    rng = np.random.default_rng(42)
+    cfg["p_init"] = W.smooth_field(n, n, rng, 1e-3)
+    cfg["ux_init"] = W.smooth_field(n, n, rng, 0.02)
+    cfg["uy_init"] = W.smooth_field(n, n, rng, 0.02)
+    _say(f"case: full-size cavity {n}x{n} {storage}, 3 steps")
+    sim = gpu.Sim(cfg)
+    sim.step(3)
+    g = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+    del sim
+    ref = oracle_mod.Oracle(cfg)
+    ref.step(3)
+    o = ref.fields()
+    if storage == "f64":
+        worst = {k: float(np.max(np.abs(g[k] - o[k]))) for k in FIELDS}
+        _say(f"  worst {worst}")
+        assert max(worst.values()) < tol, worst
+    else:
+        errs = {k: _rel_l2(g[k], o[k]) for k in ("ux", "uy", "T", "p")}
+        _say(f"  rel L2 {errs}")
+        assert max(errs.values()) < tol, errs
