@@ -208,6 +208,32 @@ lbm_status lbm_batch_check(lbm_batch *batch, int32_t *nonfinite_host);
 /* Releases the batch and its contexts (host memory only). */
 void lbm_batch_destroy(lbm_batch *batch);
 
+/* ---------------------------------------------------------------------------------- */
+/* Adjoint: gradient of an average Nusselt number (Eq. AvNuss) after nsteps steps with   */
+/* respect to the porosity of every node, by the discrete adjoint of the step           */
+/* (reverse sweep over sqrt(nsteps)-spaced checkpoints, forward states recomputed per    */
+/* segment; vector-Jacobian products of each node update from FP64 dual numbers through  */
+/* the same node code as the forward step).                                             */
+/* ---------------------------------------------------------------------------------- */
+typedef struct lbm_adjoint lbm_adjoint;
+
+/* Bytes of device workspace for an adjoint over nsteps steps of ctx's problem. */
+size_t lbm_adjoint_workspace_bytes(const lbm_ctx *ctx, int64_t nsteps);
+
+/* Advances ctx by nsteps >= 1 steps from its current state (as lbm_step) while keeping
+ * checkpoints in the workspace (device, 256-byte aligned, caller-owned, kept alive until
+ * lbm_adjoint_destroy), then evaluates J = average Nusselt number of `wall` (as
+ * lbm_nusselt) into *nu_host.  *out receives the adjoint handle.  Synchronizes. */
+lbm_status lbm_adjoint_forward(lbm_ctx *ctx, int32_t wall, int64_t nsteps, void *workspace,
+                               size_t workspace_bytes, lbm_adjoint **out, double *nu_host);
+
+/* Writes dJ * dJ/deps(x) for every node into grad_eps_device ([ny][nx] FP64, device,
+ * overwritten).  May be called repeatedly; leaves ctx's state untouched.  Synchronizes. */
+lbm_status lbm_adjoint_backward(lbm_adjoint *adj, double dJ, double *grad_eps_device);
+
+/* Releases the adjoint handle (host memory only). */
+void lbm_adjoint_destroy(lbm_adjoint *adj);
+
 /* Releases the context (host memory only; the workspace stays with the caller). */
 void lbm_destroy(lbm_ctx *ctx);
 

@@ -5,4 +5,4 @@ The compute path is the HIP library liblbm.so (C interface in include/lbm.h);
 ``paper_1505_02976_amd.lbm`` is its Python binding.
 """
 from . import lbm  # noqa: F401
-from .lbm import Sim, derived, workspace_bytes  # noqa: F401
+from .lbm import Adjoint, Batch, Sim, derived, nusselt_of_porosity, workspace_bytes  # noqa: F401

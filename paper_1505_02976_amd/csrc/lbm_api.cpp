@@ -2,6 +2,7 @@
 // context bookkeeping and dispatch to the HIP kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -368,16 +369,23 @@ lbm_status lbm_gradients(lbm_ctx *c, int32_t out_dtype, void *Sxx, void *Sxy, vo
     return fields(c, out_dtype, o);
 }
 
-lbm_status lbm_nusselt(lbm_ctx *c, int32_t wall, double *nu_host)
+static lbm_status check_nusselt_wall(const lbm_ctx *c, int32_t wall)
 {
-    if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
-    if (!nu_host) return fail(LBM_ERR_INVALID, "nu_host is NULL");
     if (wall < 0 || wall > 3) return fail(LBM_ERR_INVALID, "wall must be 0..3");
     const bool xwall = wall < 2;
     if ((xwall && c->prm.periodic_x) || (!xwall && c->prm.periodic_y))
         return fail(LBM_ERR_INVALID, "wall %d does not exist (periodic direction)", wall);
     if ((xwall ? c->prm.nx : c->prm.ny) < 3) return fail(LBM_ERR_INVALID, "need 3 node layers");
     if (c->d.dT == 0.0) return fail(LBM_ERR_INVALID, "T_hot == T_cold");
+    return LBM_OK;
+}
+
+lbm_status lbm_nusselt(lbm_ctx *c, int32_t wall, double *nu_host)
+{
+    if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
+    if (!nu_host) return fail(LBM_ERR_INVALID, "nu_host is NULL");
+    const lbm_status chk = check_nusselt_wall(c, wall);
+    if (chk != LBM_OK) return chk;
     double *dev = reinterpret_cast<double *>(c->ws + c->lay.off_scalar);
     hipError_t e = lbm::launch_nusselt(c->prm.storage, cur_buf(c), c->kp, wall, c->d.L, c->d.dT, dev, c->stream);
     if (e != hipSuccess) return hip_fail(e, "nusselt launch");
@@ -428,6 +436,183 @@ void lbm_destroy(lbm_ctx *c)
 {
     if (c && !c->in_batch) delete c;
 }
+
+// ---------------------------------------------------------------------------------
+// Adjoint
+// ---------------------------------------------------------------------------------
+struct lbm_adjoint {
+    lbm_ctx *ctx;
+    int wall;
+    int64_t nsteps, K, nck;
+    char *ws;
+    size_t pop;
+    size_t off_ck, off_seg, off_lam0, off_lam1, off_mu, off_wf, off_wt, off_we, off_wtj;
+    double J;
+};
+
+namespace {
+
+struct AdjLayout {
+    int64_t K, nck;
+    size_t off_ck, off_seg, off_lam0, off_lam1, off_mu, off_wf, off_wt, off_we, off_wtj, total;
+};
+
+AdjLayout adj_layout(const lbm_ctx *c, int64_t nsteps)
+{
+    AdjLayout L;
+    int64_t K = (int64_t)std::ceil(std::sqrt((double)nsteps));
+    if (K < 1) K = 1;
+    L.K = K;
+    L.nck = (nsteps + K - 1) / K;
+    const size_t N = (size_t)c->prm.nx * c->prm.ny;
+    const size_t pop = c->lay.pop_bytes;
+    size_t o = 0;
+    L.off_ck = o; o += (size_t)L.nck * pop;
+    L.off_seg = o; o += (size_t)K * pop;
+    L.off_lam0 = o; o += align_up(18 * N * 8, 256);
+    L.off_lam1 = o; o += align_up(18 * N * 8, 256);
+    L.off_mu = o; o += align_up(18 * N * 8, 256);
+    L.off_wf = o; o += align_up(18 * N * 8, 256);
+    L.off_wt = o; o += align_up(N * 8, 256);
+    L.off_we = o; o += align_up(N * 8, 256);
+    L.off_wtj = o; o += align_up(N * 8, 256);
+    L.total = o;
+    return L;
+}
+
+// Host copy of the device wall classification.
+void host_wall(const lbm_ctx *c, int x, int y, int &xw, int &yw, int &dx, int &dy)
+{
+    const lbm_params &p = c->prm;
+    xw = -1; yw = -1;
+    if (!p.periodic_x) { if (x == 0) xw = 0; else if (x == p.nx - 1) xw = 1; }
+    if (!p.periodic_y) { if (y == 0) yw = 2; else if (y == p.ny - 1) yw = 3; }
+    dx = xw == 0 ? 1 : (xw == 1 ? -1 : 0);
+    dy = yw == 2 ? 1 : (yw == 3 ? -1 : 0);
+}
+
+// dJ/dT at interior nodes for J = average Nusselt number of `wall` (same definition as
+// lbm_nusselt), T at wall nodes expressed through their reference nodes.
+void nusselt_weights(const lbm_ctx *c, int wall, double scale, std::vector<double> &w)
+{
+    const int nx = c->prm.nx, ny = c->prm.ny;
+    w.assign((size_t)nx * ny, 0.0);
+    const int along = wall < 2 ? ny : nx;
+    const double sgn = (wall == 0 || wall == 2) ? 1.0 : -1.0;
+    const double cf[3] = {-3.0, 4.0, -1.0};
+    auto add = [&](int x, int y, double v) {
+        int xw, yw, dx, dy;
+        host_wall(c, x, y, xw, yw, dx, dy);
+        if (xw < 0 && yw < 0) { w[(size_t)y * nx + x] += v; return; }
+        const bool dir = (xw >= 0 && c->prm.wall[xw].t_kind == LBM_T_DIRICHLET) ||
+                         (yw >= 0 && c->prm.wall[yw].t_kind == LBM_T_DIRICHLET);
+        if (dir) return;   // T fixed at an isothermal wall
+        w[(size_t)(y + dy) * nx + (x + dx)] += v * 4.0 / 3.0;
+        w[(size_t)(y + 2 * dy) * nx + (x + 2 * dx)] -= v / 3.0;
+    };
+    for (int j = 0; j < along; ++j) {
+        const double wtr = (j == 0 || j == along - 1) ? 0.5 : 1.0;
+        const double base = scale * wtr / (along - 1) * (-c->d.L / c->d.dT) * sgn * 0.5;
+        for (int k = 0; k < 3; ++k) {
+            int x, y;
+            if (wall == 0) { x = k; y = j; }
+            else if (wall == 1) { x = nx - 1 - k; y = j; }
+            else if (wall == 2) { x = j; y = k; }
+            else { x = j; y = ny - 1 - k; }
+            add(x, y, base * cf[k]);
+        }
+    }
+}
+
+}  // namespace
+
+size_t lbm_adjoint_workspace_bytes(const lbm_ctx *c, int64_t nsteps)
+{
+    if (!c || nsteps < 1) return 0;
+    return adj_layout(c, nsteps).total;
+}
+
+lbm_status lbm_adjoint_forward(lbm_ctx *c, int32_t wall, int64_t nsteps, void *workspace,
+                               size_t workspace_bytes, lbm_adjoint **out, double *nu_host)
+{
+    if (!c || !out || !nu_host) return fail(LBM_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    if (c->in_batch) return fail(LBM_ERR_INVALID, "problem belongs to a batch");
+    if (nsteps < 1) return fail(LBM_ERR_INVALID, "nsteps must be >= 1");
+    const lbm_status chk = check_nusselt_wall(c, wall);
+    if (chk != LBM_OK) return chk;
+    const AdjLayout L = adj_layout(c, nsteps);
+    if (!workspace || ((uintptr_t)workspace) % 256) return fail(LBM_ERR_INVALID, "workspace must be non-NULL and 256-byte aligned");
+    if (workspace_bytes < L.total) return fail(LBM_ERR_INVALID, "workspace too small: %zu < %zu bytes", workspace_bytes, L.total);
+    char *ws = static_cast<char *>(workspace);
+    hipError_t e = hipSuccess;
+    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+        if (s % L.K == 0)
+            e = hipMemcpyAsync(ws + L.off_ck + (size_t)(s / L.K) * c->lay.pop_bytes, cur_buf(c),
+                               c->lay.pop_bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess) e = lbm::launch_step(c->prm.storage, cur_buf(c), next_buf(c), c->kp, c->stream);
+        if (e == hipSuccess) c->t += 1;
+    }
+    if (e != hipSuccess) return hip_fail(e, "adjoint forward");
+    double J;
+    lbm_status st = lbm_nusselt(c, wall, &J);
+    if (st != LBM_OK) return st;
+    lbm_adjoint *a = new (std::nothrow) lbm_adjoint;
+    if (!a) return fail(LBM_ERR_DEVICE, "out of host memory");
+    a->ctx = c; a->wall = wall; a->nsteps = nsteps; a->K = L.K; a->nck = L.nck; a->ws = ws;
+    a->pop = c->lay.pop_bytes;
+    a->off_ck = L.off_ck; a->off_seg = L.off_seg; a->off_lam0 = L.off_lam0; a->off_lam1 = L.off_lam1;
+    a->off_mu = L.off_mu; a->off_wf = L.off_wf; a->off_wt = L.off_wt; a->off_we = L.off_we;
+    a->off_wtj = L.off_wtj;
+    a->J = J;
+    *nu_host = J;
+    *out = a;
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_backward(lbm_adjoint *a, double dJ, double *grad)
+{
+    if (!a || !grad) return fail(LBM_ERR_INVALID, "NULL argument");
+    lbm_ctx *c = a->ctx;
+    const size_t N = (size_t)c->prm.nx * c->prm.ny;
+    std::vector<double> wtj;
+    nusselt_weights(c, a->wall, dJ, wtj);
+    char *ws = a->ws;
+    double *lam[2] = {reinterpret_cast<double *>(ws + a->off_lam0), reinterpret_cast<double *>(ws + a->off_lam1)};
+    lbm::AdjBufs A;
+    A.mu = reinterpret_cast<double *>(ws + a->off_mu);
+    A.wf = reinterpret_cast<double *>(ws + a->off_wf);
+    A.wt = reinterpret_cast<double *>(ws + a->off_wt);
+    A.we = reinterpret_cast<double *>(ws + a->off_we);
+    A.grad = grad;
+    A.wtj = reinterpret_cast<double *>(ws + a->off_wtj);
+    hipError_t e = hipMemcpyAsync(const_cast<double *>(A.wtj), wtj.data(), N * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(grad, 0, N * 8, c->stream);
+    int cur = 0;
+    A.lam_next = nullptr;
+    A.lam = lam[cur];
+    if (e == hipSuccess) e = lbm::launch_adjoint_seed(c->kp, A, c->stream);
+    auto seg = [&](int64_t i) { return ws + a->off_seg + (size_t)i * a->pop; };
+    for (int64_t sg = a->nck - 1; sg >= 0 && e == hipSuccess; --sg) {
+        const int64_t t0 = sg * a->K;
+        const int64_t t1 = std::min<int64_t>(a->nsteps, t0 + a->K);
+        e = hipMemcpyAsync(seg(0), ws + a->off_ck + (size_t)sg * a->pop, a->pop, hipMemcpyDeviceToDevice, c->stream);
+        for (int64_t i = 1; i < t1 - t0 && e == hipSuccess; ++i)
+            e = lbm::launch_step(c->prm.storage, seg(i - 1), seg(i), c->kp, c->stream);
+        for (int64_t i = t1 - t0 - 1; i >= 0 && e == hipSuccess; --i) {
+            A.lam_next = lam[cur];
+            A.lam = lam[cur ^ 1];
+            e = lbm::launch_adjoint_step(c->prm.storage, seg(i), c->kp, A, c->stream);
+            cur ^= 1;
+        }
+    }
+    // the seed array on the host must outlive the copy
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint backward");
+    return LBM_OK;
+}
+
+void lbm_adjoint_destroy(lbm_adjoint *a) { delete a; }
 
 // ---------------------------------------------------------------------------------
 // Batches

@@ -44,6 +44,35 @@ __device__ constexpr int CXd[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int CYd[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __host__ __device__ constexpr double Wd(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
 
+// Forward-mode dual number (value, derivative) in FP64, used by the adjoint to evaluate
+// directional derivatives of the node update with the same templated code.
+struct Dual {
+    double v, d;
+    __host__ __device__ constexpr Dual() : v(0.0), d(0.0) {}
+    __host__ __device__ explicit constexpr Dual(double a) : v(a), d(0.0) {}
+    __host__ __device__ constexpr Dual(double a, double b) : v(a), d(b) {}
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b)
+{
+    const double q = a.v / b.v;
+    return Dual(q, (a.d - q * b.d) / b.v);
+}
+__device__ __forceinline__ Dual &operator+=(Dual &a, Dual b) { a = a + b; return a; }
+__device__ __forceinline__ Dual sqrt(Dual a)
+{
+    const double r = ::sqrt(a.v);
+    return Dual(r, r > 0.0 ? 0.5 * a.d / r : 0.0);
+}
+using ::sqrt;   // keep the FP32/FP64 overloads visible next to the dual one
+
+// Type of the FP64 quantities of the drag solve for arithmetic type R.
+template <typename R> struct DragT { using T = double; };
+template <> struct DragT<Dual> { using T = Dual; };
+
 // Per-launch constants in the arithmetic type R, computed once on the host.
 template <typename R> struct Cst {
     R itf, itT;        // 1 / tau
@@ -97,6 +126,7 @@ template <> __device__ __forceinline__ const EpsR<float> &epsu<float>(const KPar
 // Reciprocal: IEEE division in FP64 arithmetic, the hardware reciprocal (1 ulp) in FP32.
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ Dual rcp(Dual x) { return Dual(1.0) / x; }
 
 // Element index of population q (0..17) of node (x, y) inside a population buffer of
 // storage type S.
@@ -169,8 +199,9 @@ template <typename R> __device__ __forceinline__ const Cst<R> &make_cst(const KP
 
 // Porosity-dependent coefficients (Sec. 3.1 for c0 and c1; Eq. ForceEq for the drag).
 template <typename R> struct EpsC {
+    using D = typename DragT<R>::T;
     R eps, ieps, dlin, dquad, bM;
-    double c0, c1, epsd;
+    D c0, c1, epsd;
 };
 
 template <typename R> __device__ __forceinline__ EpsC<R> eps_uniform(const KParams &P)
@@ -188,22 +219,36 @@ template <typename R> __device__ __forceinline__ EpsC<R> eps_uniform(const KPara
     return e;
 }
 
-template <typename R> __device__ __forceinline__ EpsC<R> eps_at(const KParams &P, int x, int y)
+// Coefficients at porosity eps (any of double, Dual): F_eps from the Ergun relation or
+// as given, c0 and c1 of the velocity solve, the drag coefficients of Eq. ForceEq and
+// b = (1/eps - 1/sigma)/2 of Eq. MatrM.
+template <typename R>
+__device__ __forceinline__ EpsC<R> eps_coeffs(const KParams &P, typename DragT<R>::T eps)
 {
-    if (!P.field) return eps_uniform<R>(P);
-    const double eps = P.eps_field[(long long)y * P.nx + x];
-    const double ie = 1.0 / eps;
-    const double Fe = P.ergun ? 1.75 / sqrt(150.0 * eps * eps * eps) : P.Feps;
+    using D = typename DragT<R>::T;
+    const D ie = D(1.0) / eps;
+    const D Fe = P.ergun ? D(1.75) / sqrt(D(150.0) * eps * eps * eps) : D(P.Feps);
     EpsC<R> e;
     e.epsd = eps;
     e.eps = R(eps);
     e.ieps = R(ie);
-    e.c0 = 0.5 * (1.0 + 0.5 * eps * P.nu_over_K);
-    e.c1 = 0.5 * eps * Fe * P.inv_sqrtK;
-    e.dlin = R(eps * P.nu_over_K);
-    e.dquad = R(eps * Fe * P.inv_sqrtK);
-    e.bM = R(0.5 * (ie - 1.0 / P.sigma));
+    e.c0 = D(0.5) * (D(1.0) + D(0.5) * eps * D(P.nu_over_K));
+    e.c1 = D(0.5) * eps * Fe * D(P.inv_sqrtK);
+    e.dlin = R(eps * D(P.nu_over_K));
+    e.dquad = R(eps * Fe * D(P.inv_sqrtK));
+    e.bM = R(D(0.5) * (ie - D(1.0 / P.sigma)));
     return e;
+}
+
+__device__ __forceinline__ double eps_value(const KParams &P, int x, int y)
+{
+    return P.field ? P.eps_field[(long long)y * P.nx + x] : P.eps;
+}
+
+template <typename R> __device__ __forceinline__ EpsC<R> eps_at(const KParams &P, int x, int y)
+{
+    if (!P.field) return eps_uniform<R>(P);
+    return eps_coeffs<R>(P, P.eps_field[(long long)y * P.nx + x]);
 }
 
 // Macroscopic quantities of a node (Td = T - T0).
@@ -212,17 +257,18 @@ template <typename R> struct Macro {
 };
 
 // FP64 part of the velocity computation (Sec. 3.1): u = v / (c0 + sqrt(c0^2 + c1 |v|)).
-// Returns 1 / (c0 + sqrt(c0^2 + c1 |v|)) and |v|.
-template <typename R> __device__ __forceinline__ double drag_factor(double vx, double vy, double c0,
-                                                                    double c1, double &vm);
-template <> __device__ __forceinline__ double drag_factor<double>(double vx, double vy, double c0,
-                                                                  double c1, double &vm)
+// Returns 1 / (c0 + sqrt(c0^2 + c1 |v|)) and |v|.  |v| is not differentiable at v = 0; the
+// dual version takes the derivative of |v| there as 0, the limit in which u(v) is C^1
+// with du/dv = I / (2 c0).
+template <typename R, typename D>
+__device__ __forceinline__ D drag_factor(D vx, D vy, D c0, D c1, D &vm)
 {
     vm = sqrt(vx * vx + vy * vy);
-    return 1.0 / (c0 + sqrt(c0 * c0 + c1 * vm));
+    return D(1.0) / (c0 + sqrt(c0 * c0 + c1 * vm));
 }
-template <> __device__ __forceinline__ double drag_factor<float>(double vx, double vy, double c0,
-                                                                 double c1, double &vm)
+template <>
+__device__ __forceinline__ double drag_factor<float, double>(double vx, double vy, double c0, double c1,
+                                                             double &vm)
 {
     vm = sqrt(vx * vx + vy * vy);
     return rcp_nr(c0 + sqrt(c0 * c0 + c1 * vm));
@@ -246,10 +292,11 @@ __device__ __forceinline__ void node_macro(const R *f, const R *g, const Cst<R> 
 
     const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const double vx = double(jx) + 0.5 * e.epsd * double(Gx);
-    const double vy = double(jy) + 0.5 * e.epsd * double(Gy);
-    double vm;
-    const double iden = drag_factor<R>(vx, vy, e.c0, e.c1, vm);
+    using D = typename DragT<R>::T;
+    const D vx = D(jx) + D(0.5) * e.epsd * D(Gx);
+    const D vy = D(jy) + D(0.5) * e.epsd * D(Gy);
+    D vm;
+    const D iden = drag_factor<R, D>(vx, vy, e.c0, e.c1, vm);
     m.ux = R(vx * iden);
     m.uy = R(vy * iden);
     const R um = R(vm * iden);
@@ -557,11 +604,10 @@ __device__ __forceinline__ R gather_Td(const S *__restrict__ src, const KParams 
 // the next node x_ff.  f, g may alias ff, gf.
 template <typename R>
 __device__ __forceinline__ void wall_from_ref(const KParams &P, const Cst<R> &k, int x, int y,
+                                              const EpsC<R> &ef, const EpsC<R> &eb,
                                               const R *ff, const R *gf, R Tdff, R *f, R *g)
 {
     const WallInfo w = wall_info(P, x, y);
-    const int xf = x + w.dx, yf = y + w.dy;
-    const EpsC<R> ef = eps_at<R>(P, xf, yf);
     Macro<R> mf;
     const R T0 = R(P.T0);
     node_macro_full<R>(ff, gf, T0, k, ef, mf);
@@ -571,7 +617,6 @@ __device__ __forceinline__ void wall_from_ref(const KParams &P, const Cst<R> &k,
     R ubx = R(0), uby = R(0);
     if (w.xw >= 0 && w.yw < 0) { ubx = R(P.wall_ux[w.xw]); uby = R(P.wall_uy[w.xw]); }
     if (w.yw >= 0 && w.xw < 0) { ubx = R(P.wall_ux[w.yw]); uby = R(P.wall_uy[w.yw]); }
-    const EpsC<R> eb = eps_at<R>(P, x, y);
     const R epb = eb.eps * mf.p;   // eps at the wall node, pressure of x_f
 
 #pragma unroll
@@ -611,7 +656,7 @@ __device__ __forceinline__ void wall_populations(const S *__restrict__ src, cons
     gather<S, R>(src, P, x + w.dx, y + w.dy, ff, gf);
     R Tdff = R(0);
     if (thermal_dirichlet_wall(P, w) < 0) Tdff = gather_Td<S, R>(src, P, k, x + 2 * w.dx, y + 2 * w.dy);
-    wall_from_ref<R>(P, k, x, y, ff, gf, Tdff, f, g);
+    wall_from_ref<R>(P, k, x, y, eps_at<R>(P, x + w.dx, y + w.dy), eps_at<R>(P, x, y), ff, gf, Tdff, f, g);
 }
 
 // Wall-node slot s -> (x, y); returns false for slots that are not wall nodes of this

@@ -12,6 +12,18 @@ struct BatchProblem {
     int tiles_x;
 };
 
+// Device buffers of the adjoint sweep (FP64, [18][ny][nx] for the 18-component arrays).
+struct AdjBufs {
+    const double *lam_next;   // adjoint of s_{t+1}
+    double *lam;              // adjoint of s_t (output)
+    double *mu;               // adjoint of the pre-collision populations
+    double *wf;               // wall nodes: adjoint of the reference node's populations
+    double *wt;               // wall nodes: adjoint of T at x_ff
+    double *we;               // wall nodes: adjoint of eps at the reference node
+    double *grad;             // dJ/deps, accumulated
+    const double *wtj;        // dJ/dT at interior nodes (seed)
+};
+
 struct BatchKernels {
     const void *bulk, *edge, *wall;
     int bulk_threads, wall_threads;
@@ -31,6 +43,11 @@ hipError_t launch_nusselt(int storage, const void *src, const KParams &P, int wa
                           double dT, double *out, hipStream_t st);
 hipError_t launch_state(int storage, void *buf, const KParams &P, double *io, bool get, hipStream_t st);
 long long residual_partials(const KParams &P);
+
+// Adjoint sweep.
+hipError_t launch_adjoint_step(int storage, const void *state, const KParams &P, const AdjBufs &A,
+                               hipStream_t st);
+hipError_t launch_adjoint_seed(const KParams &P, const AdjBufs &A, hipStream_t st);
 
 // Batched stepping: items are (problem, tile) / (problem, wall block) pairs.
 hipError_t launch_batch_step(int storage, const BatchProblem *probs, const int2 *bulk_items, int nbulk,

@@ -147,7 +147,8 @@ __device__ __forceinline__ void bulk_tile(const S *__restrict__ src, S *__restri
                 if (!in1) gather<S, RC>(src, P, x + dx, y, f[k], g[k]);
                 if (!in2 && thermal_dirichlet_wall(P, wall_info(P, x, y)) < 0)
                     Tdff = gather_Td<S, RC>(src, P, c, x + 2 * dx, y);
-                wall_from_ref<RC>(P, c, x, y, f[k], g[k], Tdff, f[k], g[k]);
+                wall_from_ref<RC>(P, c, x, y, eps_at<RC>(P, x + dx, y), eps_at<RC>(P, x, y),
+                                  f[k], g[k], Tdff, f[k], g[k]);
                 act[k] = true;
             }
         }

@@ -60,7 +60,9 @@ EXPORTS = ("lbm_derive", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_ste
            "lbm_moments", "lbm_gradients", "lbm_nusselt", "lbm_residual", "lbm_get_state",
            "lbm_set_state", "lbm_destroy", "lbm_last_error",
            "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_problem",
-           "lbm_batch_check", "lbm_batch_destroy")
+           "lbm_batch_check", "lbm_batch_destroy",
+           "lbm_adjoint_workspace_bytes", "lbm_adjoint_forward", "lbm_adjoint_backward",
+           "lbm_adjoint_destroy")
 
 
 def lib():
@@ -112,6 +114,15 @@ def lib():
     L.lbm_batch_check.argtypes = [vp, C.POINTER(C.c_int32)]
     L.lbm_batch_destroy.restype = None
     L.lbm_batch_destroy.argtypes = [vp]
+    L.lbm_adjoint_workspace_bytes.restype = C.c_size_t
+    L.lbm_adjoint_workspace_bytes.argtypes = [vp, C.c_int64]
+    L.lbm_adjoint_forward.restype = st
+    L.lbm_adjoint_forward.argtypes = [vp, C.c_int32, C.c_int64, vp, C.c_size_t, C.POINTER(vp),
+                                      C.POINTER(C.c_double)]
+    L.lbm_adjoint_backward.restype = st
+    L.lbm_adjoint_backward.argtypes = [vp, C.c_double, vp]
+    L.lbm_adjoint_destroy.restype = None
+    L.lbm_adjoint_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -176,13 +187,17 @@ def workspace_bytes(cfg: dict) -> int:
 
 
 def _device_fields(torch, cfg, device, nx, ny):
-    """Initial fields of a problem as FP64 device tensors; returns (pointer map, tensors)."""
+    """Initial fields of a problem as FP64 device tensors (numpy arrays or torch tensors in
+    the problem dictionary); returns (pointer map, tensors to keep alive)."""
     dev, keep = {}, []
     for key in ("eps_field", "T_init", "p_init", "ux_init", "uy_init"):
         a = cfg.get(key)
         if a is None:
             continue
-        t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(ny, nx), device=device)
+        if isinstance(a, torch.Tensor):
+            t = a.detach().to(device=device, dtype=torch.float64).reshape(ny, nx).contiguous()
+        else:
+            t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(ny, nx), device=device)
         keep.append(t)
         dev[key] = t.data_ptr()
     return dev, keep
@@ -214,16 +229,7 @@ class Sim:
         L = lib()
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-            dev = {}
-            keep = []
-            for key in ("eps_field", "T_init", "p_init", "ux_init", "uy_init"):
-                a = cfg.get(key)
-                if a is None:
-                    continue
-                t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(self.ny, self.nx),
-                                    device=self.device)
-                keep.append(t)
-                dev[key] = t.data_ptr()
+            dev, keep = _device_fields(torch, cfg, self.device, self.nx, self.ny)
             prm = make_params(cfg, dev)
             nbytes = int(L.lbm_workspace_bytes(C.byref(prm)))
             if nbytes == 0:
@@ -310,6 +316,82 @@ class Sim:
         assert tuple(t.shape) == (2, 9, self.ny, self.nx)
         _check(lib().lbm_set_state(self.h, t.data_ptr()))
         self.stream.synchronize()
+
+
+class Adjoint:
+    """Average Nusselt number of one wall after `steps` steps from the simulation's current
+    state, and its gradient with respect to the porosity of every node (discrete adjoint;
+    lbm_adjoint_* in include/lbm.h).  The simulation advances by `steps`."""
+
+    def __init__(self, sim: Sim, steps: int, wall: int = 0):
+        L = lib()
+        torch = sim.torch
+        self.sim = sim
+        nbytes = int(L.lbm_adjoint_workspace_bytes(sim.h, int(steps)))
+        if nbytes == 0:
+            raise LbmError(ERR_INVALID, "adjoint workspace size is 0 (invalid steps?)")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=sim.device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        h = C.c_void_p()
+        nu = C.c_double()
+        _check(L.lbm_adjoint_forward(sim.h, int(wall), int(steps), C.c_void_p(aligned), nbytes,
+                                     C.byref(h), C.byref(nu)))
+        self.h = h
+        self.value = nu.value
+
+    def gradient(self, dJ: float = 1.0):
+        """dJ * dNu/deps as an FP64 device tensor [ny, nx]."""
+        out = self.sim.torch.empty((self.sim.ny, self.sim.nx), dtype=self.sim.torch.float64,
+                                   device=self.sim.device)
+        _check(lib().lbm_adjoint_backward(self.h, float(dJ), out.data_ptr()))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_adjoint_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _nusselt_function():
+    import torch
+
+    class NusseltOfPorosity(torch.autograd.Function):
+        """Nu(eps): a fresh simulation of `cfg` with porosity field eps is advanced `steps`
+        steps; backward runs the discrete adjoint."""
+
+        @staticmethod
+        def forward(ctx, eps, cfg, steps, wall):
+            c = dict(cfg, eps_field=eps.detach())
+            sim = Sim(c, device=str(eps.device))
+            adj = Adjoint(sim, steps, wall)
+            ctx.adj = adj
+            return torch.tensor(adj.value, dtype=torch.float64, device=eps.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = ctx.adj.gradient(float(grad_out))
+            ctx.adj.close()
+            return g, None, None, None
+
+    return NusseltOfPorosity
+
+
+_NusseltFn = None
+
+
+def nusselt_of_porosity(eps, cfg: dict, steps: int, wall: int = 0):
+    """Differentiable average Nusselt number of `wall` after `steps` steps of the problem
+    `cfg` with porosity field `eps` (a [ny, nx] FP64 CUDA tensor)."""
+    global _NusseltFn
+    if _NusseltFn is None:
+        _NusseltFn = _nusselt_function()
+    return _NusseltFn.apply(eps, cfg, steps, wall)
 
 
 class Batch:
