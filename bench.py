@@ -32,18 +32,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# the sources the bulk-node kernel is compiled from
+BULK_SOURCES = ("lbm_device.h", "lbm_kernels.h", "lbm_kernels.hip")
+
+
 def measured_traffic(storage, n):
     """HBM bytes per bulk launch from the committed rocprofv3 counter summary, if it was
     taken on this workload and on the kernel sources as they are now (else None)."""
-    import glob
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_step_bulk_{storage}_cavity{n}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    src = b"".join(open(p, "rb").read() for p in
-                   sorted(glob.glob(os.path.join(ROOT, "paper_1505_02976_amd", "csrc", "*"))))
+    csrc = os.path.join(ROOT, "paper_1505_02976_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, p), "rb").read() for p in BULK_SOURCES)
     if hashlib.sha256(src).hexdigest() != rec.get("csrc_sha256"):
         return None
     return rec["traffic_bytes_per_launch"]
@@ -87,6 +90,8 @@ def ensemble_run(lbm, torch, W, count=256, steps=10000, warmup=64):
     nodes = sum(c["nx"] * c["ny"] for c in cfgs)
     b = lbm.Batch(cfgs)
     b.step(warmup)
+    width, tune_ms = b.autotune(10)
+    log(f"ensemble: autotuner chose block width {width} ({tune_ms} ms/step)")
     b.stream.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -101,7 +106,8 @@ def ensemble_run(lbm, torch, W, count=256, steps=10000, warmup=64):
                        f"eps U(0.4,0.9), Pr 1, FP32 storage, seed 0",
            "nodes": nodes, "steps": steps, "mlups": nodes * steps / (ms * 1e-3) / 1e6,
            "ms_per_step": ms / steps, "GBps_algorithmic": nodes * 144 * steps / (ms * 1e-3) / 1e9,
-           "nonfinite_problems": int(flags.sum())}
+           "nonfinite_problems": int(flags.sum()),
+           "block_width": width, "autotune_ms_per_step": {str(k): v for k, v in tune_ms.items()}}
     b.close()
     del b
     torch.cuda.synchronize()

@@ -205,6 +205,20 @@ lbm_ctx *lbm_batch_problem(lbm_batch *batch, int32_t k);
  * is NaN or infinite).  Synchronizes. */
 lbm_status lbm_batch_check(lbm_batch *batch, int32_t *nonfinite_host);
 
+/* Block-width autotuner of the batched update.  Times each candidate width (threads per
+ * block along x: 64, 128, 256, in that order) over `steps` steps and keeps the fastest for
+ * later lbm_batch_step calls.  The problems' states are unchanged (the timed launches read
+ * the current populations and overwrite only the buffers the next step writes anyway) and
+ * the results of later steps do not depend on the width.  *width (optional) receives the
+ * chosen width; ms_per_step (optional, host, LBM_BATCH_NUM_WIDTHS entries) the timings.
+ * Synchronizes. */
+#define LBM_BATCH_NUM_WIDTHS 3
+lbm_status lbm_batch_autotune(lbm_batch *batch, int32_t steps, int32_t *width, double *ms_per_step);
+
+/* Sets the block width of the batched update without timing (64 after lbm_batch_init);
+ * LBM_ERR_INVALID for any other value than 64, 128, 256.  Synchronizes. */
+lbm_status lbm_batch_set_width(lbm_batch *batch, int32_t width);
+
 /* Releases the batch and its contexts (host memory only). */
 void lbm_batch_destroy(lbm_batch *batch);
 

@@ -629,6 +629,9 @@ struct lbm_batch {
     hipGraph_t graph;
     hipGraphExec_t exec;
     int graph_steps;
+    int bx;                     // block width of the batched update
+    size_t edge_cap;            // capacity of the edge item table (items)
+    std::vector<lbm::BatchProblem> hp;
 };
 
 namespace {
@@ -667,14 +670,16 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
         B.kp[k] = kp;
         B.off[k] = o;
         o += align_up(lay.total, 256);
-        const int tx = lbm::batch_tiles_x(params[k].storage, kp);
+        const int tx = lbm::batch_tiles_x(params[k].storage, kp, lbm::batch_width(0));
         B.tiles_x[k] = tx;
         const int y0 = kp.py ? 0 : 1, y1 = kp.py ? kp.ny : kp.ny - 1;
         // Batched grids are small (a few tiles per row), so every tile goes to the
         // wall-aware launch: one bulk launch per step instead of an interior and an edge one.
+        // The table is sized for the narrowest block width (the most items).
         for (int y = y0; y < y1; ++y)
             for (int t = 0; t < tx; ++t) B.edge.push_back(make_int2(k, y * tx + t));
-        for (int t = 0; t < tx * kp.ny; ++t) B.all.push_back(make_int2(k, t));
+        const int cx = lbm::batch_check_tiles_x(params[k].storage, kp);
+        for (int t = 0; t < cx * kp.ny; ++t) B.all.push_back(make_int2(k, t));
         const int wb = lbm::wall_block_size();
         for (int b = 0; b < (kp.nwall_rows + wb - 1) / wb; ++b) B.wall.push_back(make_int2(k, b));
     }
@@ -694,7 +699,8 @@ constexpr int GRAPH_STEPS = 64;   // even: a replay leaves the buffers in their 
 
 lbm_status batch_build_graph(lbm_batch *b)
 {
-    const lbm::BatchKernels K = lbm::batch_kernels(b->storage);
+    lbm::BatchKernels K;
+    if (!lbm::batch_kernels(b->storage, b->bx, K)) return fail(LBM_ERR_INVALID, "block width %d", b->bx);
     hipError_t e = hipGraphCreate(&b->graph, 0);
     if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
     std::vector<hipGraphNode_t> prev;
@@ -730,6 +736,40 @@ lbm_status batch_build_graph(lbm_batch *b)
     return LBM_OK;
 }
 
+void batch_drop_graph(lbm_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Work tables of the batched update for block width bx: per-problem tile counts and the
+// (problem, tile) items, uploaded synchronously.
+lbm_status batch_set_width(lbm_batch *b, int bx)
+{
+    std::vector<int2> edge;
+    for (size_t k = 0; k < b->hp.size(); ++k) {
+        const lbm::KParams &kp = b->hp[k].P;
+        const int tx = lbm::batch_tiles_x(b->storage, kp, bx);
+        b->hp[k].tiles_x = tx;
+        const int y0 = kp.py ? 0 : 1, y1 = kp.py ? kp.ny : kp.ny - 1;
+        for (int y = y0; y < y1; ++y)
+            for (int t = 0; t < tx; ++t) edge.push_back(make_int2((int)k, y * tx + t));
+    }
+    if (edge.size() > b->edge_cap) return fail(LBM_ERR_INVALID, "block width %d: item table too small", bx);
+    batch_drop_graph(b);
+    hipError_t e = hipMemcpyAsync(b->probs, b->hp.data(), b->hp.size() * sizeof(lbm::BatchProblem),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !edge.empty())
+        e = hipMemcpyAsync(b->edge_items, edge.data(), edge.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch tables");
+    b->nedge = (int)edge.size();
+    b->bx = bx;
+    return LBM_OK;
+}
+
 }  // namespace
 
 size_t lbm_batch_workspace_bytes(const lbm_params *params, int32_t n)
@@ -758,7 +798,10 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
     b->graph = nullptr;
     b->exec = nullptr;
     b->graph_steps = 0;
-    std::vector<lbm::BatchProblem> hp(n);
+    b->bx = lbm::batch_width(0);
+    b->edge_cap = B.edge.size();
+    std::vector<lbm::BatchProblem> &hp = b->hp;
+    hp.resize(n);
     for (int k = 0; k < n; ++k) {
         lbm_ctx *c = nullptr;
         st = init_ctx(&params[k], ws + B.off[k], workspace_bytes - B.off[k], hip_stream, &c);
@@ -793,7 +836,7 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
         e = hipMemcpyAsync(b->wall_items, B.wall.data(), B.wall.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && b->nall)
         e = hipMemcpyAsync(b->all_items, B.all.data(), B.all.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
-    // the host vectors are released on return: wait for the copies
+    // the layout's host vectors are released on return: wait for the copies
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         for (lbm_ctx *q : b->ctx) delete q;
@@ -812,7 +855,7 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
     hipError_t e = hipSuccess;
     // whole graphs need the current parity to be even
     while (done < nsteps && (b->t & 1)) {
-        e = lbm::launch_batch_step(b->storage, b->probs, b->bulk_items, b->nbulk, b->edge_items, b->nedge,
+        e = lbm::launch_batch_step(b->storage, b->bx, b->probs, b->bulk_items, b->nbulk, b->edge_items, b->nedge,
                                    b->wall_items, b->nwall,
                                    (int)(b->t & 1), b->stream);
         if (e != hipSuccess) return hip_fail(e, "batch step");
@@ -829,7 +872,7 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
         b->t += GRAPH_STEPS;
     }
     while (done < nsteps) {
-        e = lbm::launch_batch_step(b->storage, b->probs, b->bulk_items, b->nbulk, b->edge_items, b->nedge,
+        e = lbm::launch_batch_step(b->storage, b->bx, b->probs, b->bulk_items, b->nbulk, b->edge_items, b->nedge,
                                    b->wall_items, b->nwall,
                                    (int)(b->t & 1), b->stream);
         if (e != hipSuccess) return hip_fail(e, "batch step");
@@ -860,11 +903,64 @@ lbm_status lbm_batch_check(lbm_batch *b, int32_t *flags_host)
     return LBM_OK;
 }
 
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *width, double *ms_per_step)
+{
+    if (!b) return fail(LBM_ERR_INVALID, "batch is NULL");
+    if (steps < 1) return fail(LBM_ERR_INVALID, "steps must be >= 1");
+    const int parity = (int)(b->t & 1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int best = -1;
+    float best_ms = 0.0f;
+    lbm_status st = LBM_OK;
+    for (int i = 0; i < LBM_BATCH_NUM_WIDTHS && e == hipSuccess && st == LBM_OK; ++i) {
+        const int bx = lbm::batch_width(i);
+        st = batch_set_width(b, bx);
+        if (st != LBM_OK) break;
+        // every launch reads the current buffers and writes the other ones: the state is kept
+        auto run = [&](int n) {
+            hipError_t r = hipSuccess;
+            for (int s = 0; s < n && r == hipSuccess; ++s)
+                r = lbm::launch_batch_step(b->storage, b->bx, b->probs, b->bulk_items, b->nbulk, b->edge_items,
+                                           b->nedge, b->wall_items, b->nwall, parity, b->stream);
+            return r;
+        };
+        e = run(2);
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        if (e == hipSuccess) e = run(steps);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) {
+            ms /= steps;
+            if (ms_per_step) ms_per_step[i] = ms;
+            if (best < 0 || ms < best_ms) { best = i; best_ms = ms; }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st != LBM_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "batch autotune");
+    st = batch_set_width(b, lbm::batch_width(best));
+    if (st != LBM_OK) return st;
+    if (width) *width = b->bx;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_width(lbm_batch *b, int32_t width)
+{
+    if (!b) return fail(LBM_ERR_INVALID, "batch is NULL");
+    for (int i = 0; i < LBM_BATCH_NUM_WIDTHS; ++i)
+        if (lbm::batch_width(i) == width) return batch_set_width(b, width);
+    return fail(LBM_ERR_INVALID, "width %d is not one of 64, 128, 256", width);
+}
+
 void lbm_batch_destroy(lbm_batch *b)
 {
     if (!b) return;
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    batch_drop_graph(b);
     for (lbm_ctx *c : b->ctx) delete c;
     delete b;
 }

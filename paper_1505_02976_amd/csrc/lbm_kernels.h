@@ -50,13 +50,16 @@ hipError_t launch_adjoint_step(int storage, const void *state, const KParams &P,
 hipError_t launch_adjoint_seed(const KParams &P, const AdjBufs &A, hipStream_t st);
 
 // Batched stepping: items are (problem, tile) / (problem, wall block) pairs.
-hipError_t launch_batch_step(int storage, const BatchProblem *probs, const int2 *bulk_items, int nbulk,
+// bx: block width of the batched update, one of batch_width(0..2).
+hipError_t launch_batch_step(int storage, int bx, const BatchProblem *probs, const int2 *bulk_items, int nbulk,
                              const int2 *edge_items, int nedge, const int2 *wall_items, int nwall,
                              int parity, hipStream_t st);
 hipError_t launch_batch_check(int storage, const BatchProblem *probs, const int2 *items, int n,
                               int parity, int *flags, hipStream_t st);
-BatchKernels batch_kernels(int storage);
-int batch_tiles_x(int storage, const KParams &P);
+bool batch_kernels(int storage, int bx, BatchKernels &k);
+int batch_width(int i);
+int batch_tiles_x(int storage, const KParams &P, int bx);
+int batch_check_tiles_x(int storage, const KParams &P);
 int wall_block_size();
 // Nodes updated by the interior-tile launch of one step (single-problem path).
 long long interior_nodes(int storage, const KParams &P);

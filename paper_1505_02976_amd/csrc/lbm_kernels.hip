@@ -220,19 +220,18 @@ k_step_wall(const S *__restrict__ src, S *__restrict__ dst, KParams P)
 // the bulk update, or (problem, wall block) of the wall update.  parity selects which
 // of each problem's two buffers is the source.
 // ---------------------------------------------------------------------------------
-#ifndef LBM_BATCH_BX
-#define LBM_BATCH_BX 64
-#endif
-constexpr int BATCH_BX = LBM_BATCH_BX;
+// Candidate block widths of the batched update (picked per batch by timing them).
+constexpr int BATCH_WIDTHS[3] = {64, 128, 256};
+constexpr int CHECK_BX = 64;
 
-template <typename S, bool WALLS>
-__global__ void __launch_bounds__(BATCH_BX)
+template <typename S, bool WALLS, int BX>
+__global__ void __launch_bounds__(BX)
 k_batch_bulk(const BatchProblem *__restrict__ probs, const int2 *__restrict__ items, int parity)
 {
     const int2 it = items[blockIdx.x];
     const BatchProblem &B = probs[it.x];
-    bulk_tile<S, WALLS, BATCH_BX>(static_cast<const S *>(B.buf[parity]),
-                                  static_cast<S *>(B.buf[parity ^ 1]), B.P, it.y, B.tiles_x);
+    bulk_tile<S, WALLS, BX>(static_cast<const S *>(B.buf[parity]),
+                            static_cast<S *>(B.buf[parity ^ 1]), B.P, it.y, B.tiles_x);
 }
 
 template <typename S>
@@ -248,8 +247,9 @@ k_batch_wall(const BatchProblem *__restrict__ probs, const int2 *__restrict__ it
 // Non-finite check of each problem's current populations (one flag per problem; a block
 // that finds a bad value stores 1, stores of the same value from several blocks are
 // harmless).
+// Items are (problem, segment) with segments of CHECK_BX * NPT nodes of a row.
 template <typename S>
-__global__ void __launch_bounds__(BATCH_BX)
+__global__ void __launch_bounds__(CHECK_BX)
 k_batch_check(const BatchProblem *__restrict__ probs, const int2 *__restrict__ items, int parity,
               int *flags)
 {
@@ -258,11 +258,12 @@ k_batch_check(const BatchProblem *__restrict__ probs, const int2 *__restrict__ i
     const KParams &P = B.P;
     constexpr int NPT = Npt<S>::v;
     const S *src = static_cast<const S *>(B.buf[parity]);
-    const int y = it.y / B.tiles_x;
-    const int x0 = (it.y - y * B.tiles_x) * (BATCH_BX * NPT) + threadIdx.x;
+    const int tx = (P.nx + CHECK_BX * NPT - 1) / (CHECK_BX * NPT);
+    const int y = it.y / tx;
+    const int x0 = (it.y - y * tx) * (CHECK_BX * NPT) + threadIdx.x;
     bool bad = false;
     for (int k = 0; k < NPT; ++k) {
-        const int x = x0 + k * BATCH_BX;
+        const int x = x0 + k * CHECK_BX;
         if (x >= P.nx) continue;
         for (int q = 0; q < 18; ++q)
             bad |= !isfinite(float(Store<S>::ld(src + pidx<S>(P, q, x, y), 1.0f)));
@@ -688,61 +689,82 @@ hipError_t launch_state(int storage, void *buf, const KParams &P, double *io, bo
                  (launch_state_t<__half>(buf, P, io, get, st)))
 }
 
-template <typename S>
-static hipError_t batch_step_t(const BatchProblem *probs, const int2 *bulk_items, int nbulk,
+template <typename S, int BX>
+static hipError_t batch_step_w(const BatchProblem *probs, const int2 *bulk_items, int nbulk,
                                const int2 *edge_items, int nedge, const int2 *wall_items, int nwall,
                                int parity, hipStream_t st)
 {
     if (nbulk > 0)
-        hipLaunchKernelGGL((k_batch_bulk<S, false>), dim3(nbulk), dim3(BATCH_BX), 0, st, probs, bulk_items, parity);
+        hipLaunchKernelGGL((k_batch_bulk<S, false, BX>), dim3(nbulk), dim3(BX), 0, st, probs, bulk_items, parity);
     if (nedge > 0)
-        hipLaunchKernelGGL((k_batch_bulk<S, true>), dim3(nedge), dim3(BATCH_BX), 0, st, probs, edge_items, parity);
+        hipLaunchKernelGGL((k_batch_bulk<S, true, BX>), dim3(nedge), dim3(BX), 0, st, probs, edge_items, parity);
     if (nwall > 0)
         hipLaunchKernelGGL((k_batch_wall<S>), dim3(nwall), dim3(WALL_B), 0, st, probs, wall_items, parity);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_step(int storage, const BatchProblem *probs, const int2 *bulk_items, int nbulk,
+template <typename S>
+static hipError_t batch_step_t(int bx, const BatchProblem *probs, const int2 *bulk_items, int nbulk,
+                               const int2 *edge_items, int nedge, const int2 *wall_items, int nwall,
+                               int parity, hipStream_t st)
+{
+    switch (bx) {
+    case 64: return batch_step_w<S, 64>(probs, bulk_items, nbulk, edge_items, nedge, wall_items, nwall, parity, st);
+    case 128: return batch_step_w<S, 128>(probs, bulk_items, nbulk, edge_items, nedge, wall_items, nwall, parity, st);
+    case 256: return batch_step_w<S, 256>(probs, bulk_items, nbulk, edge_items, nedge, wall_items, nwall, parity, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_step(int storage, int bx, const BatchProblem *probs, const int2 *bulk_items, int nbulk,
                              const int2 *edge_items, int nedge, const int2 *wall_items, int nwall,
                              int parity, hipStream_t st)
 {
     LBM_DISPATCH(storage,
-                 (batch_step_t<double>(probs, bulk_items, nbulk, edge_items, nedge, wall_items, nwall, parity, st)),
-                 (batch_step_t<float>(probs, bulk_items, nbulk, edge_items, nedge, wall_items, nwall, parity, st)),
-                 (batch_step_t<__half>(probs, bulk_items, nbulk, edge_items, nedge, wall_items, nwall, parity, st)))
+                 (batch_step_t<double>(bx, probs, bulk_items, nbulk, edge_items, nedge, wall_items, nwall, parity, st)),
+                 (batch_step_t<float>(bx, probs, bulk_items, nbulk, edge_items, nedge, wall_items, nwall, parity, st)),
+                 (batch_step_t<__half>(bx, probs, bulk_items, nbulk, edge_items, nedge, wall_items, nwall, parity, st)))
 }
 
-BatchKernels batch_kernels(int storage)
+template <typename S, int BX>
+static void batch_kernels_w(BatchKernels &k)
 {
-    BatchKernels k;
-    switch (storage) {
-    case 0:
-        k.bulk = (const void *)k_batch_bulk<double, false>;
-        k.edge = (const void *)k_batch_bulk<double, true>;
-        k.wall = (const void *)k_batch_wall<double>;
-        break;
-    case 1:
-        k.bulk = (const void *)k_batch_bulk<float, false>;
-        k.edge = (const void *)k_batch_bulk<float, true>;
-        k.wall = (const void *)k_batch_wall<float>;
-        break;
-    default:
-        k.bulk = (const void *)k_batch_bulk<__half, false>;
-        k.edge = (const void *)k_batch_bulk<__half, true>;
-        k.wall = (const void *)k_batch_wall<__half>;
-        break;
-    }
-    k.bulk_threads = BATCH_BX;
+    k.bulk = (const void *)k_batch_bulk<S, false, BX>;
+    k.edge = (const void *)k_batch_bulk<S, true, BX>;
+    k.wall = (const void *)k_batch_wall<S>;
+    k.bulk_threads = BX;
     k.wall_threads = WALL_B;
-    return k;
 }
+
+template <typename S>
+static bool batch_kernels_t(int bx, BatchKernels &k)
+{
+    switch (bx) {
+    case 64: batch_kernels_w<S, 64>(k); return true;
+    case 128: batch_kernels_w<S, 128>(k); return true;
+    case 256: batch_kernels_w<S, 256>(k); return true;
+    default: return false;
+    }
+}
+
+bool batch_kernels(int storage, int bx, BatchKernels &k)
+{
+    switch (storage) {
+    case 0: return batch_kernels_t<double>(bx, k);
+    case 1: return batch_kernels_t<float>(bx, k);
+    case 2: return batch_kernels_t<__half>(bx, k);
+    default: return false;
+    }
+}
+
+int batch_width(int i) { return (i >= 0 && i < 3) ? BATCH_WIDTHS[i] : 0; }
 
 template <typename S>
 static hipError_t batch_check_t(const BatchProblem *probs, const int2 *items, int n, int parity,
                                 int *flags, hipStream_t st)
 {
     if (n > 0)
-        hipLaunchKernelGGL((k_batch_check<S>), dim3(n), dim3(BATCH_BX), 0, st, probs, items, parity, flags);
+        hipLaunchKernelGGL((k_batch_check<S>), dim3(n), dim3(CHECK_BX), 0, st, probs, items, parity, flags);
     return hipGetLastError();
 }
 
@@ -754,10 +776,20 @@ hipError_t launch_batch_check(int storage, const BatchProblem *probs, const int2
                  (batch_check_t<__half>(probs, items, n, parity, flags, st)))
 }
 
-int batch_tiles_x(int storage, const KParams &P)
+static int npt_of(int storage)
 {
-    const int npt = storage == 0 ? Npt<double>::v : (storage == 1 ? Npt<float>::v : Npt<__half>::v);
-    const int span = BATCH_BX * npt;
+    return storage == 0 ? Npt<double>::v : (storage == 1 ? Npt<float>::v : Npt<__half>::v);
+}
+
+int batch_tiles_x(int storage, const KParams &P, int bx)
+{
+    const int span = bx * npt_of(storage);
+    return (P.nx + span - 1) / span;
+}
+
+int batch_check_tiles_x(int storage, const KParams &P)
+{
+    const int span = CHECK_BX * npt_of(storage);
     return (P.nx + span - 1) / span;
 }
 

@@ -60,7 +60,8 @@ EXPORTS = ("lbm_derive", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_ste
            "lbm_moments", "lbm_gradients", "lbm_nusselt", "lbm_residual", "lbm_get_state",
            "lbm_set_state", "lbm_destroy", "lbm_last_error",
            "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_problem",
-           "lbm_batch_check", "lbm_batch_destroy",
+           "lbm_batch_check", "lbm_batch_destroy", "lbm_batch_autotune",
+           "lbm_batch_set_width",
            "lbm_adjoint_workspace_bytes", "lbm_adjoint_forward", "lbm_adjoint_backward",
            "lbm_adjoint_destroy")
 
@@ -112,6 +113,10 @@ def lib():
     L.lbm_batch_problem.argtypes = [vp, C.c_int32]
     L.lbm_batch_check.restype = st
     L.lbm_batch_check.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.lbm_batch_autotune.restype = st
+    L.lbm_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    L.lbm_batch_set_width.restype = st
+    L.lbm_batch_set_width.argtypes = [vp, C.c_int32]
     L.lbm_batch_destroy.restype = None
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_adjoint_workspace_bytes.restype = C.c_size_t
@@ -436,6 +441,17 @@ class Batch:
 
     def step(self, n: int = 1):
         _check(lib().lbm_batch_step(self.h, int(n)))
+
+    def autotune(self, steps: int = 10):
+        """Times the candidate block widths (64, 128, 256) and keeps the fastest; returns
+        (chosen width, {width: ms per step}).  The problems' states are unchanged."""
+        w = C.c_int32()
+        ms = (C.c_double * 3)()
+        _check(lib().lbm_batch_autotune(self.h, int(steps), C.byref(w), ms))
+        return w.value, {64: ms[0], 128: ms[1], 256: ms[2]}
+
+    def set_width(self, width: int):
+        _check(lib().lbm_batch_set_width(self.h, int(width)))
 
     def check(self):
         """Per-problem non-finite flags (numpy int32 array)."""

@@ -90,3 +90,36 @@ def test_batch_member_cannot_step_alone(gpu):
     batch = gpu.Batch(_cases("f32")[:2])
     with pytest.raises(gpu.LbmError):
         batch[0].step(1)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
+def test_batch_block_widths_and_autotune(gpu, storage):
+    """Every block width gives bitwise the single-problem result; the autotuner leaves the
+    states untouched and keeps one of the candidates."""
+    import torch
+    cfgs = _cases(storage)
+    _say(f"case: batch of {len(cfgs)} {storage} problems, widths 64/128/256 and autotune")
+    singles = [gpu.Sim(c) for c in cfgs]
+    for s in singles:
+        s.step(70)
+    for width in (64, 128, 256):
+        batch = gpu.Batch(cfgs)
+        batch.set_width(width)
+        batch.step(70)          # one graph replay and 6 eager steps
+        torch.cuda.synchronize()
+        for k, s in enumerate(singles):
+            assert bool((batch[k].get_state() == s.get_state()).all()), (width, k)
+        batch.close()
+    batch = gpu.Batch(cfgs)
+    batch.step(5)
+    before = [p.get_state() for p in batch.problems]
+    w, ms = batch.autotune(4)
+    _say(f"  autotune: chose {w}, ms/step {ms}")
+    assert w in (64, 128, 256) and all(v > 0 for v in ms.values())
+    for k, p in enumerate(batch.problems):
+        assert bool((p.get_state() == before[k]).all()), k
+    batch.step(65)
+    for k, s in enumerate(singles):
+        assert bool((batch[k].get_state() == s.get_state()).all()), ("tuned", k)
+    with pytest.raises(gpu.LbmError):
+        batch.set_width(96)
