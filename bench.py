@@ -52,8 +52,11 @@ def measured_traffic(storage, n):
     return rec["traffic_bytes_per_launch"]
 
 
-def timed_run(lbm, torch, cfg, warmup, steps):
-    """Warm up, then time `steps` steps with HIP events on the simulation's stream."""
+def timed_run(lbm, torch, cfg, warmup, steps, every=16):
+    """Warm up, then time `steps` steps with HIP events on the simulation's stream; inside
+    that region the two launches of every `every`-th step are bracketed by further events,
+    which give the mean launch durations (the events cost a few microseconds per bracketed
+    step, included in the total)."""
     sim = lbm.Sim(cfg)
     sim.step(warmup)
     sim.stream.synchronize()
@@ -61,7 +64,7 @@ def timed_run(lbm, torch, cfg, warmup, steps):
     t1 = torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(sim.stream):
         t0.record()
-        bulk_ms, wall_ms, bulk_nodes = sim.step_timed(steps)
+        bulk_ms, wall_ms, bulk_nodes = sim.step_timed(steps, every)
         t1.record()
     t1.synchronize()
     total_ms = t0.elapsed_time(t1)
@@ -69,14 +72,14 @@ def timed_run(lbm, torch, cfg, warmup, steps):
     mlups = nx * ny * steps / (total_ms * 1e-3) / 1e6
     es = ELEM[cfg["storage"]]
     bytes_per_launch = bulk_nodes * 36 * es
-    bulk_avg_s = bulk_ms / steps * 1e-3
-    achieved = bytes_per_launch / bulk_avg_s / 1e9
+    achieved = bytes_per_launch / (bulk_ms * 1e-3) / 1e9
     res = {
         "mlups": mlups, "ms_per_step": total_ms / steps,
-        "bulk_kernel_us": bulk_ms / steps * 1e3, "edge_and_wall_us": wall_ms / steps * 1e3,
-        "bulk_nodes": bulk_nodes,
+        "bulk_kernel_us": bulk_ms * 1e3, "edge_and_wall_us": wall_ms * 1e3,
+        "bulk_nodes": bulk_nodes, "timed_every": every,
         "bulk_bytes_per_launch": bytes_per_launch, "bulk_GBps": achieved,
         "frac": achieved / HBM_PEAK_GBS,
+        "all_nodes_GBps": nx * ny * 36 * es * steps / (total_ms * 1e-3) / 1e9,
     }
     del sim
     torch.cuda.synchronize()

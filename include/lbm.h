@@ -131,18 +131,20 @@ size_t lbm_workspace_bytes(const lbm_params *params);
 lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_bytes,
                     void *hip_stream, lbm_ctx **out);
 
-/* Enqueues nsteps >= 0 time steps (asynchronous). */
+/* Enqueues nsteps >= 0 time steps (asynchronous).  Each step is two launches on the
+ * context's stream: the interior columns, then the columns next to the walls x = 0,
+ * x = nx - 1 together with the walled rows. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
-/* As lbm_step, with HIP events around the launches of every step; returns the summed
- * durations in milliseconds of the interior-tile launch (the nodes whose tile holds no
- * wall node) and of the remaining launches (tiles holding a wall node, walled rows) over
- * the nsteps steps, and the number of nodes the interior-tile launch updates per step
- * (host outputs; any may be NULL).  Used for measurement.  Synchronizes. */
-lbm_status lbm_step_timed(lbm_ctx *ctx, int64_t nsteps, double *bulk_ms_host, double *wall_ms_host,
-                          int64_t *bulk_nodes_host);
+/* As lbm_step (nsteps >= 1), with HIP events around the two launches of every `every`-th
+ * step (every >= 1; steps 0, every, 2 every, ...); returns the mean duration in
+ * milliseconds of the interior launch and of the wall-side launch over those steps, and
+ * the number of nodes the interior launch updates per step (host outputs; any may be
+ * NULL).  Used for measurement; events between launches cost a few microseconds per
+ * bracketed step.  Synchronizes on the events, not on the whole stream. */
+lbm_status lbm_step_timed(lbm_ctx *ctx, int64_t nsteps, int32_t every, double *bulk_ms_host,
+                          double *wall_ms_host, int64_t *bulk_nodes_host);
 
-/* Number of steps taken since lbm_init. */
 int64_t lbm_time(const lbm_ctx *ctx);
 
 /* Macroscopic fields at the current time (device outputs, [ny][nx], NULL = skip):

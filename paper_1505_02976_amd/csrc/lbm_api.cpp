@@ -288,60 +288,87 @@ lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_
     return init_ctx(params, workspace, workspace_bytes, hip_stream, out);
 }
 
+namespace {
+
+// Timing events of one step.
+struct StepEvents { hipEvent_t i0, i1, e1; };
+
+// nsteps steps on the context's stream: the interior launch, then the launch of the
+// columns next to the walls x = 0, x = nx - 1 and of the walled rows.  With tev, every
+// `every`-th step (s = 0, every, 2 every, ...) is bracketed by the events tev[s / every].
+hipError_t run_steps(lbm_ctx *c, int64_t nsteps, const StepEvents *tev, int every)
+{
+    hipError_t e = hipSuccess;
+    const int sto = c->prm.storage;
+    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+        void *src = cur_buf(c), *dst = next_buf(c);
+        const StepEvents *t = (tev && s % every == 0) ? tev + s / every : nullptr;
+        if (t) e = hipEventRecord(t->i0, c->stream);
+        if (e == hipSuccess) e = lbm::launch_step_bulk(sto, src, dst, c->kp, c->stream);
+        if (e == hipSuccess && t) e = hipEventRecord(t->i1, c->stream);
+        if (e == hipSuccess) e = lbm::launch_step_wall(sto, src, dst, c->kp, c->stream);
+        if (e == hipSuccess && t) e = hipEventRecord(t->e1, c->stream);
+        if (e == hipSuccess) c->t += 1;
+    }
+    return e;
+}
+
+}  // namespace
+
 lbm_status lbm_step(lbm_ctx *c, int64_t nsteps)
 {
     if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
     if (c->in_batch) return fail(LBM_ERR_INVALID, "problem belongs to a batch: use lbm_batch_step");
     if (nsteps < 0) return fail(LBM_ERR_INVALID, "nsteps < 0");
-    for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = lbm::launch_step(c->prm.storage, cur_buf(c), next_buf(c), c->kp, c->stream);
-        if (e != hipSuccess) return hip_fail(e, "step launch");
-        c->t += 1;
-    }
+    if (nsteps == 0) return LBM_OK;
+    hipError_t e = run_steps(c, nsteps, nullptr, 1);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
     return LBM_OK;
 }
 
-lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, double *bulk_ms, double *wall_ms,
+lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, int32_t every, double *bulk_ms, double *wall_ms,
                           int64_t *bulk_nodes)
 {
     if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
     if (c->in_batch) return fail(LBM_ERR_INVALID, "problem belongs to a batch: use lbm_batch_step");
-    if (nsteps < 0) return fail(LBM_ERR_INVALID, "nsteps < 0");
-    // events are read back in batches so that the stream is not drained after every step
-    constexpr int BATCH = 32;
-    hipEvent_t ev[2 * BATCH + 1];
-    for (int i = 0; i < 2 * BATCH + 1; ++i)
-        if (hipEventCreate(&ev[i]) != hipSuccess) {
-            for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
-            return fail(LBM_ERR_DEVICE, "hipEventCreate failed");
-        }
-    double tb = 0.0, tw = 0.0;
+    if (nsteps < 1) return fail(LBM_ERR_INVALID, "nsteps < 1");
+    if (every < 1) return fail(LBM_ERR_INVALID, "every < 1");
+    // events are read back in groups so that the stream is not drained after every step
+    constexpr int GROUP = 32;
+    std::vector<StepEvents> ev(GROUP);
+    int made = 0;
     hipError_t e = hipSuccess;
-    int64_t done = 0;
+    for (; made < GROUP && e == hipSuccess; ++made) {
+        e = hipEventCreate(&ev[made].i0);
+        if (e == hipSuccess) e = hipEventCreate(&ev[made].i1);
+        if (e == hipSuccess) e = hipEventCreate(&ev[made].e1);
+    }
+    double tb = 0.0, tw = 0.0;
+    int64_t done = 0, sampled = 0;
+    const int64_t chunk = (int64_t)GROUP * every;
     while (done < nsteps && e == hipSuccess) {
-        const int nb = (int)((nsteps - done) < BATCH ? (nsteps - done) : BATCH);
-        e = hipEventRecord(ev[0], c->stream);
-        for (int s = 0; s < nb && e == hipSuccess; ++s) {
-            e = lbm::launch_step_bulk(c->prm.storage, cur_buf(c), next_buf(c), c->kp, c->stream);
-            if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], c->stream);
-            if (e == hipSuccess) e = lbm::launch_step_wall(c->prm.storage, cur_buf(c), next_buf(c), c->kp, c->stream);
-            if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 2], c->stream);
-            if (e == hipSuccess) c->t += 1;
-        }
-        if (e == hipSuccess) e = hipEventSynchronize(ev[2 * nb]);
-        for (int s = 0; s < nb && e == hipSuccess; ++s) {
+        const int64_t nb = (nsteps - done) < chunk ? (nsteps - done) : chunk;
+        const int ns = (int)((nb + every - 1) / every);
+        e = run_steps(c, nb, ev.data(), every);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[ns - 1].e1);
+        for (int s = 0; s < ns && e == hipSuccess; ++s) {
             float a = 0.f, b = 0.f;
-            e = hipEventElapsedTime(&a, ev[2 * s], ev[2 * s + 1]);
-            if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[2 * s + 1], ev[2 * s + 2]);
+            e = hipEventElapsedTime(&a, ev[s].i0, ev[s].i1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[s].i1, ev[s].e1);
             tb += a;
             tw += b;
         }
+        sampled += ns;
         done += nb;
     }
-    for (int i = 0; i < 2 * BATCH + 1; ++i) (void)hipEventDestroy(ev[i]);
+    for (auto &x : ev) {
+        if (x.i0) (void)hipEventDestroy(x.i0);
+        if (x.i1) (void)hipEventDestroy(x.i1);
+        if (x.e1) (void)hipEventDestroy(x.e1);
+    }
     if (e != hipSuccess) return hip_fail(e, "timed step");
-    if (bulk_ms) *bulk_ms = tb;
-    if (wall_ms) *wall_ms = tw;
+    if (bulk_ms) *bulk_ms = tb / (double)sampled;
+    if (wall_ms) *wall_ms = tw / (double)sampled;
     if (bulk_nodes) *bulk_nodes = lbm::interior_nodes(c->prm.storage, c->kp);
     return LBM_OK;
 }

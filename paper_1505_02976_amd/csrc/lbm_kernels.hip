@@ -60,15 +60,10 @@ k_init(S *__restrict__ dst, KParams P, const double *__restrict__ T_init,
 // ---------------------------------------------------------------------------------
 // Fused step, bulk nodes: gather -> moments -> S, grad T -> equilibria -> collide -> store
 //
-// A block of BULK_BX threads covers a tile of BULK_BX * NPT consecutive nodes of one row;
-// thread t handles nodes t, t + BULK_BX, ... so every load instruction stays coalesced and
-// each thread has NPT nodes' loads in flight before it computes.  Tiles are numbered so
-// that consecutive tiles of a row run on the same XCD (blocks are dealt to the 8 XCDs
-// round-robin), which keeps the cache lines shared by neighbouring tiles in one L2.
+// A block of BX threads covers a segment of BX * NPT consecutive nodes of one row;
+// thread t handles nodes t, t + BX, ... so every load instruction stays coalesced and
+// each thread has NPT nodes' loads in flight before it computes.
 // ---------------------------------------------------------------------------------
-#ifndef LBM_XCD
-#define LBM_XCD 0
-#endif
 #ifndef LBM_NPT_F64
 #define LBM_NPT_F64 1
 #endif
@@ -84,18 +79,8 @@ template <> struct Npt<double> { static constexpr int v = LBM_NPT_F64; };
 template <> struct Npt<float> { static constexpr int v = LBM_NPT_F32; };
 template <> struct Npt<__half> { static constexpr int v = LBM_NPT_F16; };
 
-__device__ __forceinline__ int tile_of_block(int b, int nb)
-{
-#if LBM_XCD
-    const int q = nb >> 3, r = nb & 7, k = b & 7;
-    return k * q + (k < r ? k : r) + (b >> 3);
-#else
-    (void)nb;
-    return b;
-#endif
-}
-
-// One tile (a row segment of BX * NPT nodes, BX = block size) of the bulk update.
+// One row segment of the bulk update: nodes x = xbeg + tid + k BX (k < NPT) with
+// x < xend, of row y (tid: the thread's index among the BX threads of the segment).
 //
 // Nodes on the walls x = 0 and x = nx - 1 (outside the walled rows) are updated here too:
 // the lanes of a wavefront hold consecutive x, so the reference node x_f = x -+ 1 of a
@@ -103,22 +88,22 @@ __device__ __forceinline__ int tile_of_block(int b, int nb)
 // neighbouring lane, whose streamed populations are taken by cross-lane shuffles; only
 // when it falls in another wavefront is it gathered from memory.  Only wavefronts that
 // contain such a node take this branch.
-template <typename S, bool WALLS, int BX = BULK_BX>
+template <typename S, bool WALLS, int BX>
 __device__ __forceinline__ void bulk_tile(const S *__restrict__ src, S *__restrict__ dst,
-                                          const KParams &P, int t, int tiles_x)
+                                          const KParams &P, int y, int xbeg, int xend,
+                                          int tid)
 {
     constexpr int NPT = Npt<S>::v;
     using RC = typename Prec<S>::R;
-    const int y = t / tiles_x;
-    const int x0 = (t - y * tiles_x) * (BX * NPT) + threadIdx.x;
+    const int x0 = xbeg + tid;
     if (!P.py && (y == 0 || y == P.ny - 1)) return;
     RC f[NPT][9], g[NPT][9];
     bool act[NPT], vw[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int x = x0 + k * BX;
-        vw[k] = WALLS && x < P.nx && !P.px && (x == 0 || x == P.nx - 1);
-        act[k] = x < P.nx && !vw[k];
+        vw[k] = WALLS && x < xend && !P.px && (x == 0 || x == P.nx - 1);
+        act[k] = x < xend && !vw[k];
         if (act[k]) gather<S, RC>(src, P, x, y, f[k], g[k]);
     }
     if (WALLS && !P.px) {
@@ -177,42 +162,73 @@ __device__ __forceinline__ void wall_node(const S *__restrict__ src, S *__restri
     store_node<S, M>(dst, P, x, y, f, g);
 }
 
-// Tiles of a row: interior tiles hold no node of the walls x = 0, x = nx - 1; edge tiles
-// are the first and last tile of a row when x is walled.
+// Columns of the interior launch: [xa, xb) of every non-walled row, no node of the walls
+// x = 0, x = nx - 1.  The edge launch covers the rest of those rows in segments of one
+// wavefront (EDGE_BX * NPT nodes): [0, xa) and [xb, nx) -- a single segment at each end
+// when the row is at least two segments long, else the whole row -- and the walled rows.
+constexpr int EDGE_BX = 64;
+
+struct Cols { int xa, xb, nseg, span_e; bool split; };
+
+template <typename S> __host__ __device__ __forceinline__ Cols step_cols(const KParams &P)
+{
+    Cols c;
+    c.span_e = EDGE_BX * Npt<S>::v;
+    c.split = !P.px && P.nx >= 2 * c.span_e;
+    if (P.px) { c.xa = 0; c.xb = P.nx; c.nseg = 0; }
+    else if (c.split) { c.xa = c.span_e; c.xb = P.nx - c.span_e; c.nseg = 2; }
+    else { c.xa = c.xb = P.nx; c.nseg = (P.nx + c.span_e - 1) / c.span_e; }
+    return c;
+}
+
 __host__ __device__ __forceinline__ int rows_begin(const KParams &P) { return P.py ? 0 : 1; }
 __host__ __device__ __forceinline__ int rows_count(const KParams &P) { return P.py ? P.ny : P.ny - 2; }
-__host__ __device__ __forceinline__ int interior_tiles(const KParams &P, int tx)
+
+template <typename S> __host__ __device__ __forceinline__ int interior_segments(const KParams &P)
 {
-    return P.px ? tx : (tx > 2 ? tx - 2 : 0);
-}
-__host__ __device__ __forceinline__ int edge_tiles(const KParams &P, int tx)
-{
-    return P.px ? 0 : (tx < 2 ? tx : 2);
+    const Cols c = step_cols<S>(P);
+    const int span = BULK_BX * Npt<S>::v;
+    return (c.xb - c.xa + span - 1) / span;
 }
 
 template <typename S, typename R>
 __global__ void __launch_bounds__(BULK_BX)
-k_step_bulk(const S *__restrict__ src, S *__restrict__ dst, KParams P, int tiles_x)
+k_step_bulk(const S *__restrict__ src, S *__restrict__ dst, KParams P, int nseg)
 {
-    const int ti = interior_tiles(P, tiles_x);
-    const int r = blockIdx.x / ti, c = blockIdx.x - r * ti + (P.px ? 0 : 1);
-    bulk_tile<S, false>(src, dst, P, (rows_begin(P) + r) * tiles_x + c, tiles_x);
+    const Cols c = step_cols<S>(P);
+    const int r = blockIdx.x / nseg, s = blockIdx.x - r * nseg;
+    bulk_tile<S, false, BULK_BX>(src, dst, P, rows_begin(P) + r, c.xa + s * (BULK_BX * Npt<S>::v), c.xb,
+                                 threadIdx.x);
+}
+
+// Work item `item` of the wall-side update (one wavefront): items [0, ne) are the edge
+// segments (row by row), the remaining ones blocks of EDGE_BX walled-row nodes.
+template <typename S>
+__device__ __forceinline__ void edge_item(const S *__restrict__ src, S *__restrict__ dst, const KParams &P,
+                                          int item, int ne, int lane)
+{
+    if (item >= ne) {
+        wall_node<S>(src, dst, P, (item - ne) * EDGE_BX + lane);
+        return;
+    }
+    const Cols c = step_cols<S>(P);
+    const int r = item / c.nseg, s = item - r * c.nseg;
+    int xbeg, xend;
+    if (c.split) {
+        xbeg = (s == 0) ? 0 : c.xb;
+        xend = (s == 0) ? c.xa : P.nx;
+    } else {
+        xbeg = s * c.span_e;
+        xend = min(P.nx, xbeg + c.span_e);
+    }
+    bulk_tile<S, true, EDGE_BX>(src, dst, P, rows_begin(P) + r, xbeg, xend, lane);
 }
 
 template <typename S, typename R>
-__global__ void __launch_bounds__(BULK_BX)
-k_step_edge(const S *__restrict__ src, S *__restrict__ dst, KParams P, int tiles_x)
+__global__ void __launch_bounds__(EDGE_BX)
+k_step_edge(const S *__restrict__ src, S *__restrict__ dst, KParams P, int ne)
 {
-    const int te = edge_tiles(P, tiles_x);
-    const int r = blockIdx.x / te, c = (blockIdx.x - r * te == 0) ? 0 : tiles_x - 1;
-    bulk_tile<S, true>(src, dst, P, (rows_begin(P) + r) * tiles_x + c, tiles_x);
-}
-
-template <typename S, typename R>
-__global__ void __launch_bounds__(WALL_B)
-k_step_wall(const S *__restrict__ src, S *__restrict__ dst, KParams P)
-{
-    wall_node<S>(src, dst, P, blockIdx.x * blockDim.x + threadIdx.x);
+    edge_item<S>(src, dst, P, blockIdx.x, ne, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------------
@@ -230,8 +246,10 @@ k_batch_bulk(const BatchProblem *__restrict__ probs, const int2 *__restrict__ it
 {
     const int2 it = items[blockIdx.x];
     const BatchProblem &B = probs[it.x];
+    const int y = it.y / B.tiles_x;
+    const int xbeg = (it.y - y * B.tiles_x) * (BX * Npt<S>::v);
     bulk_tile<S, WALLS, BX>(static_cast<const S *>(B.buf[parity]),
-                            static_cast<S *>(B.buf[parity ^ 1]), B.P, it.y, B.tiles_x);
+                            static_cast<S *>(B.buf[parity ^ 1]), B.P, y, xbeg, B.P.nx, threadIdx.x);
 }
 
 template <typename S>
@@ -515,11 +533,6 @@ k_set_state(S *__restrict__ dst, KParams P, const double *__restrict__ in)
 // Launchers
 // ---------------------------------------------------------------------------------
 static dim3 bulk_grid(const KParams &P) { return dim3((P.nx + BULK_BX - 1) / BULK_BX, P.ny); }
-template <typename S> static int step_tiles_x(const KParams &P)
-{
-    const int span = BULK_BX * Npt<S>::v;
-    return (P.nx + span - 1) / span;
-}
 static int wall_blocks(const KParams &P, int b) { return (P.nwall + b - 1) / b; }
 
 template <typename S, typename R>
@@ -533,19 +546,19 @@ static hipError_t launch_init_t(void *dst, const KParams &P, const double *T, co
 template <typename S, typename R>
 static void launch_interior(const void *src, void *dst, const KParams &P, hipStream_t st)
 {
-    const int tx = step_tiles_x<S>(P);
-    const int n = interior_tiles(P, tx) * rows_count(P);
+    const int nseg = interior_segments<S>(P);
+    const int n = nseg * rows_count(P);
     if (n > 0)
-        hipLaunchKernelGGL((k_step_bulk<S, R>), dim3(n), dim3(BULK_BX), 0, st, (const S *)src, (S *)dst, P, tx);
+        hipLaunchKernelGGL((k_step_bulk<S, R>), dim3(n), dim3(BULK_BX), 0, st, (const S *)src, (S *)dst, P, nseg);
 }
 
 template <typename S, typename R>
 static void launch_edges(const void *src, void *dst, const KParams &P, hipStream_t st)
 {
-    const int tx = step_tiles_x<S>(P);
-    const int n = edge_tiles(P, tx) * rows_count(P);
-    if (n > 0)
-        hipLaunchKernelGGL((k_step_edge<S, R>), dim3(n), dim3(BULK_BX), 0, st, (const S *)src, (S *)dst, P, tx);
+    const int ne = step_cols<S>(P).nseg * rows_count(P);
+    const int nw = (P.nwall_rows + EDGE_BX - 1) / EDGE_BX;
+    if (ne + nw > 0)
+        hipLaunchKernelGGL((k_step_edge<S, R>), dim3(ne + nw), dim3(EDGE_BX), 0, st, (const S *)src, (S *)dst, P, ne);
 }
 
 template <typename S, typename R>
@@ -553,9 +566,6 @@ static hipError_t launch_step_t(const void *src, void *dst, const KParams &P, hi
 {
     launch_interior<S, R>(src, dst, P, st);
     launch_edges<S, R>(src, dst, P, st);
-    if (P.nwall_rows > 0)
-        hipLaunchKernelGGL((k_step_wall<S, R>), dim3((P.nwall_rows + WALL_B - 1) / WALL_B), dim3(WALL_B), 0, st,
-                           (const S *)src, (S *)dst, P);
     return hipGetLastError();
 }
 
@@ -570,9 +580,6 @@ template <typename S, typename R>
 static hipError_t launch_step_wall_t(const void *src, void *dst, const KParams &P, hipStream_t st)
 {
     launch_edges<S, R>(src, dst, P, st);
-    if (P.nwall_rows > 0)
-        hipLaunchKernelGGL((k_step_wall<S, R>), dim3((P.nwall_rows + WALL_B - 1) / WALL_B), dim3(WALL_B), 0, st,
-                           (const S *)src, (S *)dst, P);
     return hipGetLastError();
 }
 
@@ -795,13 +802,16 @@ int batch_check_tiles_x(int storage, const KParams &P)
 
 int wall_block_size() { return WALL_B; }
 
+template <typename S> static long long interior_nodes_t(const KParams &P)
+{
+    const Cols c = step_cols<S>(P);
+    return (long long)(c.xb - c.xa) * rows_count(P);
+}
+
 long long interior_nodes(int storage, const KParams &P)
 {
-    const int npt = storage == 0 ? Npt<double>::v : (storage == 1 ? Npt<float>::v : Npt<__half>::v);
-    const int span = BULK_BX * npt;
-    const int tx = (P.nx + span - 1) / span;
-    long long cols = P.px ? P.nx : (tx > 2 ? (long long)(tx - 2) * span : 0);
-    return cols * rows_count(P);
+    return storage == 0 ? interior_nodes_t<double>(P)
+                        : (storage == 1 ? interior_nodes_t<float>(P) : interior_nodes_t<__half>(P));
 }
 
 long long residual_partials(const KParams &P)

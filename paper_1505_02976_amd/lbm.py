@@ -85,7 +85,7 @@ def lib():
     L.lbm_step.restype = st
     L.lbm_step.argtypes = [vp, C.c_int64]
     L.lbm_step_timed.restype = st
-    L.lbm_step_timed.argtypes = [vp, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+    L.lbm_step_timed.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.POINTER(C.c_int64)]
     L.lbm_time.restype = C.c_int64
     L.lbm_time.argtypes = [vp]
@@ -268,11 +268,12 @@ class Sim:
     def step(self, n: int = 1):
         _check(lib().lbm_step(self.h, int(n)))
 
-    def step_timed(self, n: int):
-        """Steps with HIP events around the launches; returns (interior_ms, other_ms,
-        interior_nodes): summed durations over n steps and the nodes per interior launch."""
+    def step_timed(self, n: int, every: int = 1):
+        """Steps with HIP events around the two launches of every `every`-th step; returns
+        (interior_ms, wall_side_ms, interior_nodes): mean launch durations over the bracketed
+        steps and the nodes the interior launch updates per step."""
         b, w, nodes = C.c_double(), C.c_double(), C.c_int64()
-        _check(lib().lbm_step_timed(self.h, int(n), C.byref(b), C.byref(w), C.byref(nodes)))
+        _check(lib().lbm_step_timed(self.h, int(n), int(every), C.byref(b), C.byref(w), C.byref(nodes)))
         return b.value, w.value, nodes.value
 
     def _alloc(self, dtype):

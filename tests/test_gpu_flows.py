@@ -1,0 +1,99 @@
+"""The HIP path (through the C interface) on the channel flows of Sec. 4.1, against the
+closed forms directly (not only against the oracle): porous Poiseuille flow with heat
+conduction (Brinkman closed form, linear temperature), the mixed-convection channel with
+a moving wall and injection (closed forms for u_x, T, du_x/dy, dT/dy), and the exact
+conduction fixed point.  Second-order convergence on the GPU, in FP64 storage, and the
+FP32-storage error next to it."""
+import numpy as np
+import pytest
+
+from closed_forms import (E, brinkman_profile, mixed_convection_cfg, mixed_convection_errors, order,
+                          poiseuille_cfg)
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1505_02976_amd import lbm
+    lbm.lib()
+    return lbm
+
+
+def _fields(sim):
+    return {k: v.cpu().numpy() for k, v in sim.fields().items()}
+
+
+def test_porous_poiseuille_with_conduction(gpu):
+    """The 4 x ny periodic channel (eps 0.5, Da 1e-2, tau 0.8, A = B = 0.1, Re = 1,
+    walls at T = 0 and 1, linear initial T) run to residual 1e-10 in FP64; FP32 storage
+    runs the same number of steps."""
+    ns = (17, 33, 65)
+    eu, es, e32 = [], [], []
+    for ny in ns:
+        cfg, c = poiseuille_cfg(ny, 0.1, F_eps=0.0)
+        sim = gpu.Sim(dict(cfg, storage="f64"))
+        assert sim.run_to_steady(1e-10, 300000)
+        f = _fields(sim)
+        y = np.arange(ny, dtype=float)
+        ua, dua = brinkman_profile(y, c)
+        eu.append(E(ua, f["ux"][:, 0]))
+        es.append(E(dua[1:-1], f["Sxy"][1:-1, 0]))
+        # the linear profile holds up to the O(u^2) terms of the discrete thermal model
+        assert np.abs(f["T"] - (y / (ny - 1))[:, None]).max() < 1e-5
+        s32 = gpu.Sim(dict(cfg, storage="f32"))
+        s32.step(sim.time)
+        g = _fields(s32)
+        e32.append(float(np.abs(g["ux"] - f["ux"]).max() / np.abs(f["ux"]).max()))
+        _say(f"  ny {ny}: {sim.time} steps, E(u) {eu[-1]:.3e}, E(du/dy) {es[-1]:.3e}, "
+             f"FP32 vs FP64 max rel {e32[-1]:.2e}")
+    assert eu[-1] < 2e-3 and es[-1] < 5e-3
+    assert order(eu[1], eu[2], ns[1], ns[2]) > 1.7
+    assert order(es[1], es[2], ns[1], ns[2]) > 1.8
+    assert max(e32) < 1e-4
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.0])
+def test_mixed_convection_channel(gpu, tau):
+    ns = (17, 33, 65)
+    res, res32 = [], []
+    for ny in ns:
+        cfg, steps, exact = mixed_convection_cfg(ny, tau)
+        sim = gpu.Sim(dict(cfg, storage="f64"))
+        sim.step(steps)
+        res.append(mixed_convection_errors(_fields(sim), exact))
+        s32 = gpu.Sim(dict(cfg, storage="f32"))
+        s32.step(steps)
+        res32.append(mixed_convection_errors(_fields(s32), exact))
+        _say(f"  tau {tau} ny {ny}: {steps} steps, FP64 E = {np.round(res[-1], 7)}, FP32 E = {np.round(res32[-1], 7)}")
+    for k, lo in zip(range(4), (1.5, 1.75, 1.75, 1.75)):
+        e1, e2 = res[1][k], res[2][k]
+        assert e2 < 1e-2, (k, res)
+        assert order(e1, e2, ns[1], ns[2]) > lo, (k, res)
+        # FP32 storage stays well below the discretisation error (over 192k steps it adds
+        # about 6 % to E(T) on the finest grid)
+        assert abs(res32[2][k] - e2) < 0.1 * e2, (k, res32)
+    assert res[-1][4] < 1e-3
+
+
+@pytest.mark.parametrize("kind", ["dirichlet", "neumann"])
+def test_conduction_fixed_point(gpu, kind):
+    ny, slope = 24, 0.8 / 23
+    cfg = W.channel(ny=ny, nx=5, ax=0.0, A=0.05, B=-0.1, tau=0.9, T_bottom=0.1, T_top=0.9)
+    if kind == "neumann":
+        cfg["walls"][2] = {"kind": "dTdn", "dTdn": slope}
+    sim = gpu.Sim(dict(cfg, storage="f64"))
+    sim.step(10000)
+    f = _fields(sim)
+    y = np.arange(ny, dtype=float)
+    assert np.abs(f["T"] - (0.1 + slope * y)[:, None]).max() < 1e-12
+    assert np.abs(f["dTdy"] - slope).max() < 1e-12
+    assert np.abs(f["dTdx"]).max() < 1e-12

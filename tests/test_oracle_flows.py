@@ -5,41 +5,10 @@ AccurGradFig).  Errors use the relative global error E of Sec. 4.
 """
 import numpy as np
 import pytest
-from scipy.linalg import solve_banded
 
 import workloads as W
-
-CS2 = 1.0 / 3.0
-
-
-def E(a, n):
-    return np.abs(a - n).sum() / np.abs(a).sum()
-
-
-def order(e_coarse, e_fine, n_coarse, n_fine):
-    return np.log(e_coarse / e_fine) / np.log((n_fine - 1) / (n_coarse - 1))
-
-
-def _poiseuille_cfg(ny, A, F_eps):
-    """Porous plane Poiseuille: eps 0.5, Da 1e-2, tau 0.8, Re = 1 (drive from the
-    Brinkman closed form so that the centreline speed is Re nu / H)."""
-    eps, Da, tau, J = 0.5, 1e-2, 0.8, 1.0
-    H = ny - 1
-    nu = CS2 * (tau - A - 0.5)
-    K = Da * H * H
-    r = np.sqrt(eps / (J * K))
-    a = (nu / H) * nu / (K * (1 - 1 / np.cosh(r * H / 2)))
-    cfg = W.channel(ny=ny, A=A, B=A, tau=tau, ax=a, F_eps=F_eps, eps=eps, Da=Da)
-    return cfg, dict(H=H, nu=nu, K=K, r=r, a=a, eps=eps)
-
-
-def _brinkman_profile(y, c):
-    """Steady Brinkman flow between fixed walls (Sec. 2 momentum eq. with F_eps = 0):
-    nu_e u'' - (eps nu / K) u + eps a = 0, u(0) = u(H) = 0."""
-    H, a, K, nu, r = c["H"], c["a"], c["K"], c["nu"], c["r"]
-    u = a * K / nu * (1 - np.cosh(r * (y - H / 2)) / np.cosh(r * H / 2))
-    du = -a * K / nu * r * np.sinh(r * (y - H / 2)) / np.cosh(r * H / 2)
-    return u, du
+from closed_forms import (CS2, E, brinkman_profile, forchheimer_bvp, mixed_convection_cfg,
+                          mixed_convection_errors, order, poiseuille_cfg)
 
 
 @pytest.mark.parametrize("A", [0.1, 0.0, -0.2])
@@ -47,12 +16,12 @@ def test_brinkman_poiseuille_second_order(oracle_mod, A):
     errs_u, errs_s = [], []
     ns = (17, 33, 65)
     for ny in ns:
-        cfg, c = _poiseuille_cfg(ny, A, F_eps=0.0)
+        cfg, c = poiseuille_cfg(ny, A, F_eps=0.0)
         o = oracle_mod.Oracle(cfg)
         assert o.run_to_steady(1e-10, 300000)
         f = o.fields()
         y = np.arange(ny, dtype=float)
-        ua, dua = _brinkman_profile(y, c)
+        ua, dua = brinkman_profile(y, c)
         errs_u.append(E(ua, f["ux"][:, 0]))
         errs_s.append(E(dua[1:-1], f["Sxy"][1:-1, 0]))
         # the boundary scheme is not exactly mass conserving: a small wall-normal
@@ -63,40 +32,12 @@ def test_brinkman_poiseuille_second_order(oracle_mod, A):
     assert order(errs_s[1], errs_s[2], ns[1], ns[2]) > 1.8
 
 
-def _forchheimer_bvp(c, Feps, npts=20001):
-    """Independent Newton finite-difference solve of
-    nu_e u'' - (eps nu/K) u - (eps F_eps/sqrt K) |u| u + eps a = 0, u(0) = u(H) = 0,
-    then Richardson extrapolation from npts and (npts + 1) / 2 points."""
-    def solve(n):
-        H, eps, K, nu, a = c["H"], c["eps"], c["K"], c["nu"], c["a"]
-        h = H / (n - 1)
-        u = np.zeros(n)
-        for _ in range(50):
-            ui = u[1:-1]
-            lap = (u[:-2] - 2 * ui + u[2:]) / h ** 2
-            R = nu * lap - eps * nu / K * ui - eps * Feps / np.sqrt(K) * np.abs(ui) * ui + eps * a
-            diag = -2 * nu / h ** 2 - eps * nu / K - 2 * eps * Feps / np.sqrt(K) * np.abs(ui)
-            off = np.full(n - 3, nu / h ** 2)
-            ab = np.zeros((3, n - 2))
-            ab[0, 1:] = off
-            ab[1] = diag
-            ab[2, :-1] = off
-            du = solve_banded((1, 1), ab, -R)
-            u[1:-1] += du
-            if np.abs(du).max() < 1e-17:
-                break
-        return u
-    fine = solve(npts)
-    coarse = solve((npts + 1) // 2)
-    return (4 * fine[::2] - coarse) / 3, (npts + 1) // 2
-
-
 def test_brinkman_forchheimer_channel(oracle_mod):
     """Ergun F_eps: compare with an independent 1-D boundary-value solve."""
     errs = []
     ns = (33, 65)
     for ny in ns:
-        cfg, c = _poiseuille_cfg(ny, 0.1, F_eps=None)
+        cfg, c = poiseuille_cfg(ny, 0.1, F_eps=None)
         c["nu"] = CS2 * (0.8 - 0.1 - 0.5)
         Feps = 1.75 / np.sqrt(150 * c["eps"] ** 3)
         # drive at Re close to 12 so that the quadratic drag is not negligible
@@ -104,14 +45,14 @@ def test_brinkman_forchheimer_channel(oracle_mod):
         c["a"] = cfg["ax"]
         o = oracle_mod.Oracle(cfg)
         assert o.run_to_steady(1e-10, 300000)
-        ref, m = _forchheimer_bvp(c, Feps)
+        ref, m = forchheimer_bvp(c, Feps)
         yref = np.linspace(0, c["H"], m)
         y = np.arange(ny, dtype=float)
         ua = np.interp(y, yref, ref)
         un = o.fields()["ux"][:, 0]
         errs.append(E(ua, un))
         # the quadratic drag changes the profile noticeably
-        brink, _ = _brinkman_profile(y, c)
+        brink, _ = brinkman_profile(y, c)
         assert E(brink, ua) > 0.01
     assert errs[-1] < 2e-3
     assert order(errs[0], errs[1], ns[0], ns[1]) > 1.7
@@ -159,43 +100,11 @@ def test_conduction_is_an_exact_fixed_point(oracle_mod, kind):
     assert np.abs(f["ux"]).max() < 1e-14 and np.abs(f["uy"]).max() < 1e-14
 
 
-def _mixed_convection(oracle_mod, ny, tau, Re=5.0):
-    """Sec. 4.1: porous channel with a moving hot top wall and injection through the
-    walls; eps 0.6, Ra 100, Pr 1, Da 0.01, F_eps = 0, u0 = v0.
-
-    The boundary scheme does not balance the normal mass flux exactly, so the pressure
-    level drifts slowly (at a rate that falls roughly 15-fold per grid doubling) and the
-    residual never settles to round-off; the run therefore stops at a fixed diffusive
-    time 3 H^2 / nu, after which the slowest transient has decayed by e^-30."""
-    H = ny - 1
-    eps, Da, Pr, J = 0.6, 1e-2, 1.0, 1.0
-    v0 = 0.01 * 32.0 / H
-    u0 = v0
-    nu = H * v0 / Re
-    A = tau - 0.5 - nu / CS2
-    B = tau - 0.5 - nu / Pr / CS2
-    K = Da * H * H
-    cfg = W.channel(ny=ny, A=A, B=B, tau=tau, eps=eps, Da=Da, F_eps=0.0, ax=0.0,
-                    T_bottom=0.0, T_top=1.0)
-    cfg["walls"][2].update({"ux": 0.0, "uy": v0})
-    cfg["walls"][3].update({"ux": u0, "uy": v0})
-    cfg["ay"] = nu / K * v0          # balances the Darcy drag on the injected flow
-    cfg["Ra"], cfg["Pr"] = 100.0, Pr
+def _mixed_convection(oracle_mod, ny, tau):
+    cfg, steps, exact = mixed_convection_cfg(ny, tau)
     o = oracle_mod.Oracle(cfg)
-    o.step(int(3 * H * H / nu))
-    f = o.fields()
-    z1 = Re / (2 * eps * J)
-    z2 = np.sqrt(Re ** 2 + 4 * eps ** 3 * J / Da) / (2 * eps * J)
-    eta = np.arange(ny) / H
-    ua = u0 * np.exp(z1 * (eta - 1)) * np.sinh(z2 * eta) / np.sinh(z2)
-    dua = u0 / np.sinh(z2) * np.exp(z1 * (eta - 1)) * (z1 * np.sinh(z2 * eta) + z2 * np.cosh(z2 * eta)) / H
-    Pe = Pr * Re
-    Ta = (np.exp(Pe * eta) - 1) / (np.exp(Pe) - 1)
-    dTa = Pe / H * np.exp(Pe * eta) / (np.exp(Pe) - 1)
-    inner = slice(1, -1)
-    return (E(ua, f["ux"][:, 0]), E(Ta, f["T"][:, 0]),
-            E(dua[inner], f["Sxy"][inner, 0]), E(dTa[inner], f["dTdy"][inner, 0]),
-            np.abs(f["uy"][:, 0] - v0).max() / v0)
+    o.step(steps)
+    return mixed_convection_errors(o.fields(), exact)
 
 
 @pytest.mark.parametrize("tau", [0.8, 1.0])

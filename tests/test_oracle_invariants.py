@@ -105,3 +105,40 @@ def test_paper_table_context(oracle_mod):
         o = oracle_mod.Oracle(cfg)
         assert o.run_to_steady(1e-6, 200000)
         assert abs(o.nusselt(0) - row["Nu"]) < 0.005 * row["Nu"]
+
+
+def test_residual_of_decaying_waves(oracle_mod):
+    """The convergence residuals (Sec. 4; reading R13) on two shear waves of different
+    wave numbers (u_x along y, u_y along x) and a temperature wave in a periodic box: the
+    waves decay at nu_e k^2 and alpha_e k^2 / sigma, so the fields at t and t - 100 are
+    known in closed form and so are both residuals.  Within 1 %: the Euclidean norm of u
+    per node (a sum of |u_x| + |u_y| gives 18 % more), normalisation by the newer fields
+    (the older ones give 17 % less) and T itself, not T - T0, in the L1 denominator."""
+    n, cs2 = 64, 1.0 / 3.0
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    k1, k2 = 2 * np.pi / n, 4 * np.pi / n
+    a, b, c = 1e-3, 1e-3, 0.1
+    cfg = {"nx": n, "ny": n, "periodic_x": 1, "periodic_y": 1, "walls": [{}] * 4,
+           "Da": float("inf"), "Ra": 0.0, "F_eps": 0.0, "tau_f": 1.0, "tau_T": 1.0,
+           "A": 0.0, "B": 0.0, "eps": 1.0, "sigma": 1.0, "T_hot": 1.0, "T_cold": 0.0,
+           "ux_init": a * np.sin(k1 * y), "uy_init": b * np.sin(k2 * x),
+           "T_init": 0.5 + c * np.sin(k1 * x + 0.3)}
+    nu = alpha = cs2 * 0.5
+    o = oracle_mod.Oracle(cfg)
+    t0, lag = 300, 100
+    o.step(t0)
+    assert o.residual() == (None, None)
+    o.step(lag)
+    ru, rT = o.residual()
+
+    def exact(t):
+        return (a * np.exp(-nu * k1 * k1 * t) * np.sin(k1 * y),
+                b * np.exp(-nu * k2 * k2 * t) * np.sin(k2 * x),
+                0.5 + c * np.exp(-alpha * k1 * k1 * t) * np.sin(k1 * x + 0.3))
+
+    ux1, uy1, T1 = exact(t0 + lag)
+    ux0, uy0, T0 = exact(t0)
+    Ru = np.sum(np.hypot(ux1 - ux0, uy1 - uy0)) / np.sum(np.hypot(ux1, uy1))
+    RT = np.sum(np.abs(T1 - T0)) / np.sum(np.abs(T1))
+    assert abs(ru / Ru - 1) < 0.01, (ru, Ru)
+    assert abs(rT / RT - 1) < 0.01, (rT, RT)
