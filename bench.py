@@ -117,6 +117,30 @@ def ensemble_run(lbm, torch, W, count=256, steps=10000, warmup=64):
     return res
 
 
+def adjoint_run(lbm, torch, W, n=256, steps=5000, storage="f32"):
+    """Gradient of the hot-wall Nusselt number after `steps` steps with respect to the
+    porosity of every node of the 256 x 256 adjoint cavity: time of the forward sweep
+    (steps + checkpoints) and of the backward sweep (segment recomputation + adjoint steps)."""
+    sim = lbm.Sim(W.adjoint_cavity(n, storage=storage))
+    sim.stream.synchronize()
+    t0 = time.perf_counter()
+    adj = lbm.Adjoint(sim, steps, 0)
+    t1 = time.perf_counter()
+    g = adj.gradient()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    res = {"workload": f"adjoint cavity {n}x{n} (Ra 1e5, Pr 1, Da 1e-2, porosity field), {steps} steps, "
+                       f"{storage} storage, FP64 adjoint arithmetic",
+           "Nu": adj.value, "forward_s": t1 - t0, "backward_s": t2 - t1,
+           "backward_us_per_step": (t2 - t1) / steps * 1e6,
+           "backward_node_steps_per_s": n * n * steps / (t2 - t1),
+           "grad_l2": float(torch.linalg.vector_norm(g))}
+    adj.close()
+    del sim
+    torch.cuda.synchronize()
+    return res
+
+
 def accuracy(lbm, W, n=128, tol=1e-9, max_steps=200000):
     """Steady average Nusselt number of the hot wall on the n x n cavity per precision."""
     out = {}
@@ -174,6 +198,7 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=10000)
     ap.add_argument("--copy-reference-gib", type=float, default=0.0,
                     help="first run a plain device-to-device copy of this size, as the "
@@ -217,6 +242,11 @@ def main():
     if not args.no_ensemble:
         ens = ensemble_run(lbm, torch, W, steps=args.ensemble_steps)
         log(f"bench: ensemble {ens['mlups']:.0f} MLUPS aggregate, {ens['nonfinite_problems']} non-finite")
+    adj = None
+    if not args.no_adjoint:
+        adj = adjoint_run(lbm, torch, W)
+        log(f"bench: adjoint forward {adj['forward_s']:.2f} s, backward {adj['backward_s']:.2f} s "
+            f"({adj['backward_us_per_step']:.0f} us per step)")
     acc = None if args.no_accuracy else accuracy(lbm, W)
     cpu = None if args.no_cpu else cpu_baseline(W, n)
 
@@ -244,6 +274,7 @@ def main():
                      "avg_launch_us": main_res["bulk_kernel_us"]},
         "modes": {s: {k: v for k, v in r.items()} for s, r in modes.items()},
         "ensemble": ens,
+        "adjoint": adj,
         "accuracy": acc,
         "cpu_baseline": cpu,
     }

@@ -133,6 +133,9 @@ __global__ void __launch_bounds__(ADJ_B) k_adj_pull(KParams P, AdjBufs A)
     if (n >= N) return;
     const int x = int(n % P.nx), y = int(n / P.nx);
     const double isig = 1.0 / P.sigma;
+    // only nodes within three nodes of a wall can be (or neighbour) a reference node x_f
+    // or x_ff of a wall node
+    const bool near = (!P.px && (x < 4 || x >= P.nx - 4)) || (!P.py && (y < 4 || y >= P.ny - 4));
     for (int q = 0; q < 18; ++q) {
         const int i = q < 9 ? q : q - 9;
         int zx = x + CXd[i], zy = y + CYd[i];
@@ -141,12 +144,15 @@ __global__ void __launch_bounds__(ADJ_B) k_adj_pull(KParams P, AdjBufs A)
         double v = 0.0;
         if (zx >= 0 && zx < P.nx && zy >= 0 && zy < P.ny && !on_wall(P, zx, zy)) {
             const long long nz = (long long)zy * P.nx + zx;
-            v = A.mu[q * N + nz] + sum_wall_refs(P, A.wf, N, q, zx, zy, 1, false);
-            if (q >= 9) v += isig * sum_wall_refs(P, A.wt, N, 0, zx, zy, 2, true);
+            v = A.mu[q * N + nz];
+            if (near) {
+                v += sum_wall_refs(P, A.wf, N, q, zx, zy, 1, false);
+                if (q >= 9) v += isig * sum_wall_refs(P, A.wt, N, 0, zx, zy, 2, true);
+            }
         }
         A.lam[q * N + n] = v;
     }
-    if (!on_wall(P, x, y)) A.grad[n] += sum_wall_refs(P, A.we, N, 0, x, y, 1, false);
+    if (near && !on_wall(P, x, y)) A.grad[n] += sum_wall_refs(P, A.we, N, 0, x, y, 1, false);
 }
 
 // Seed lambda_N = dJ/ds_N for J depending on T at interior nodes with weights wtj

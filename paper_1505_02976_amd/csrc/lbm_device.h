@@ -150,6 +150,16 @@ __device__ __forceinline__ double rcp_nr(double x)
     return r;
 }
 
+// FP64 square root from the hardware reciprocal-square-root estimate and one Newton step
+// (relative error below 1e-13, used where the result is rounded to FP32); 0 for x <= 0.
+__device__ __forceinline__ double sqrt_nr(double x)
+{
+    const double r = __builtin_amdgcn_rsq(x);
+    const double s = x * r;
+    const double e = fma(-s, s, x);
+    return x > 0.0 ? fma(e, 0.5 * r, s) : 0.0;
+}
+
 #ifndef LBM_NT_LOAD
 #define LBM_NT_LOAD 0
 #endif
@@ -183,7 +193,8 @@ template <> struct Store<__half> {
     static __device__ __forceinline__ float ld(const __half *p, float inv)
     {
         const unsigned short b = ld_stream(reinterpret_cast<const unsigned short *>(p));
-        return __half2float(__ushort_as_half(b)) * inv;
+        // one mixed-precision FMA converts and scales (the +0 keeps it an FMA)
+        return __builtin_fmaf(__half2float(__ushort_as_half(b)), inv, 0.0f);
     }
     static __device__ __forceinline__ void st(__half *p, float v, float scale)
     {
@@ -270,8 +281,8 @@ template <>
 __device__ __forceinline__ double drag_factor<float, double>(double vx, double vy, double c0, double c1,
                                                              double &vm)
 {
-    vm = sqrt(vx * vx + vy * vy);
-    return rcp_nr(c0 + sqrt(c0 * c0 + c1 * vm));
+    vm = sqrt_nr(vx * vx + vy * vy);
+    return rcp_nr(c0 + sqrt_nr(c0 * c0 + c1 * vm));
 }
 
 // Local quantities from pre-collision deviations f'[9], g'[9]:
@@ -480,6 +491,14 @@ __device__ __forceinline__ bool on_wall(const KParams &P, int x, int y)
     return (!P.px && (x == 0 || x == P.nx - 1)) || (!P.py && (y == 0 || y == P.ny - 1));
 }
 
+// Offsets in the tiled layout: element of (q, x, y) = y * row + tile_off(x) + q * T with
+// row = ntx * 18 * T and tile_off(x) = (x / T) * 18 * T + x % T (32-bit within a row).
+template <int T> __device__ __forceinline__ unsigned tile_off(int x)
+{
+    const unsigned u = (unsigned)x;
+    return (u / T) * (18u * T) + (u % T);
+}
+
 // Pull gather: pre-collision f_i(x, t) = f*_i(x - c_i, t - 1), periodic wrap.
 template <typename S, typename R>
 __device__ __forceinline__ void gather(const S *__restrict__ src, const KParams &P, int x, int y,
@@ -489,14 +508,28 @@ __device__ __forceinline__ void gather(const S *__restrict__ src, const KParams 
     const int xp = (x == P.nx - 1) ? 0 : x + 1;
     const int ym = (y == 0) ? P.ny - 1 : y - 1;
     const int yp = (y == P.ny - 1) ? 0 : y + 1;
-    // source node of direction i: x - c_i
-    const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
-    const int sy[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
     const float inv = P.hinv;
+    constexpr int T = TileOf<S>::v;
+    if constexpr (T > 0) {
+        // three row bases and three in-row offsets; direction i comes from (x - cx_i, y - cy_i)
+        const long long row = (long long)P.ntx * (18 * T);
+        const S *r0 = src + (long long)y * row, *rm = src + (long long)ym * row, *rp = src + (long long)yp * row;
+        const unsigned o0 = tile_off<T>(x), om = tile_off<T>(xm), op = tile_off<T>(xp);
+        const S *b[9] = {r0 + o0, r0 + om, rm + o0, r0 + op, rp + o0, rm + om, rm + op, rp + op, rp + om};
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        f[i] = R(Store<S>::ld(src + pidx<S>(P, i, sx[i], sy[i]), inv));
-        g[i] = R(Store<S>::ld(src + pidx<S>(P, 9 + i, sx[i], sy[i]), inv));
+        for (int i = 0; i < 9; ++i) {
+            f[i] = R(Store<S>::ld(b[i] + i * T, inv));
+            g[i] = R(Store<S>::ld(b[i] + (9 + i) * T, inv));
+        }
+    } else {
+        // source node of direction i: x - c_i
+        const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
+        const int sy[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            f[i] = R(Store<S>::ld(src + pidx<S>(P, i, sx[i], sy[i]), inv));
+            g[i] = R(Store<S>::ld(src + pidx<S>(P, 9 + i, sx[i], sy[i]), inv));
+        }
     }
 }
 
@@ -504,10 +537,20 @@ template <typename S, typename R>
 __device__ __forceinline__ void store_node(S *__restrict__ dst, const KParams &P, int x, int y,
                                            const R *f, const R *g)
 {
+    constexpr int T = TileOf<S>::v;
+    if constexpr (T > 0) {
+        S *b = dst + (long long)y * ((long long)P.ntx * (18 * T)) + tile_off<T>(x);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        Store<S>::st(dst + pidx<S>(P, i, x, y), f[i], P.hscale);
-        Store<S>::st(dst + pidx<S>(P, 9 + i, x, y), g[i], P.hscale);
+        for (int i = 0; i < 9; ++i) {
+            Store<S>::st(b + i * T, f[i], P.hscale);
+            Store<S>::st(b + (9 + i) * T, g[i], P.hscale);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            Store<S>::st(dst + pidx<S>(P, i, x, y), f[i], P.hscale);
+            Store<S>::st(dst + pidx<S>(P, 9 + i, x, y), g[i], P.hscale);
+        }
     }
 }
 
