@@ -32,15 +32,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-# the sources the bulk-node kernel is compiled from
-BULK_SOURCES = ("lbm_device.h", "lbm_kernels.h", "lbm_kernels.hip")
+# the sources the step kernels are compiled from
+BULK_SOURCES = ("lbm_device.h", "lbm_kernels.h", "lbm_kernels.hip", "lbm_step2.hip")
 
 
-def measured_traffic(storage, n):
-    """HBM bytes per bulk launch from the committed rocprofv3 counter summary, if it was
-    taken on this workload and on the kernel sources as they are now (else None)."""
+def measured_traffic(kernel, storage, n):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it
+    was taken on this workload and on the kernel sources as they are now (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_step_bulk_{storage}_cavity{n}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{storage}_cavity{n}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -52,34 +52,38 @@ def measured_traffic(storage, n):
     return rec["traffic_bytes_per_launch"]
 
 
-def timed_run(lbm, torch, cfg, warmup, steps, every=16):
+def timed_run(lbm, torch, cfg, warmup, steps, every=8, fusion=None):
     """Warm up, then time `steps` steps with HIP events on the simulation's stream; inside
-    that region the two launches of every `every`-th step are bracketed by further events,
+    that region the launches of every `every`-th pass are bracketed by further events,
     which give the mean launch durations (the events cost a few microseconds per bracketed
-    step, included in the total)."""
+    pass, included in the total).  A pass is one step, or two with the two-step kernel."""
     sim = lbm.Sim(cfg)
+    if fusion is not None:
+        sim.fusion = fusion
     sim.step(warmup)
     sim.stream.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(sim.stream):
         t0.record()
-        bulk_ms, wall_ms, bulk_nodes = sim.step_timed(steps, every)
+        main_ms, rest_ms, main_nodes, per_pass = sim.step_timed(steps, every)
         t1.record()
     t1.synchronize()
     total_ms = t0.elapsed_time(t1)
     nx, ny = cfg["nx"], cfg["ny"]
     mlups = nx * ny * steps / (total_ms * 1e-3) / 1e6
     es = ELEM[cfg["storage"]]
-    bytes_per_launch = bulk_nodes * 36 * es
-    achieved = bytes_per_launch / (bulk_ms * 1e-3) / 1e9
+    # a pass reads and writes every population of the nodes it updates once
+    bytes_per_launch = main_nodes * 36 * es
+    achieved = bytes_per_launch / (main_ms * 1e-3) / 1e9
     res = {
-        "mlups": mlups, "ms_per_step": total_ms / steps,
-        "bulk_kernel_us": bulk_ms * 1e3, "edge_and_wall_us": wall_ms * 1e3,
-        "bulk_nodes": bulk_nodes, "timed_every": every,
-        "bulk_bytes_per_launch": bytes_per_launch, "bulk_GBps": achieved,
+        "mlups": mlups, "ms_per_step": total_ms / steps, "steps_per_pass": per_pass,
+        "main_kernel": "k_step2" if per_pass == 2 else "k_step_bulk",
+        "main_kernel_us": main_ms * 1e3, "rest_us": rest_ms * 1e3,
+        "main_nodes": main_nodes, "timed_every": every,
+        "main_bytes_per_launch": bytes_per_launch, "main_GBps": achieved,
         "frac": achieved / HBM_PEAK_GBS,
-        "all_nodes_GBps": nx * ny * 36 * es * steps / (total_ms * 1e-3) / 1e9,
+        "effective_GBps_one_step_traffic": nx * ny * 36 * es * steps / (total_ms * 1e-3) / 1e9,
     }
     del sim
     torch.cuda.synchronize()
@@ -199,6 +203,8 @@ def main():
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--fusion", type=int, default=None, choices=(1, 2),
+                    help="time steps per pass (default: the library's choice, 2 on large grids)")
     ap.add_argument("--ensemble-steps", type=int, default=10000)
     ap.add_argument("--copy-reference-gib", type=float, default=0.0,
                     help="first run a plain device-to-device copy of this size, as the "
@@ -225,8 +231,9 @@ def main():
 
     n = args.size
     log(f"bench: {n}x{n} cavity, {args.storage}, warmup {args.warmup}, steps {args.steps}")
-    main_res = timed_run(lbm, torch, W.large_cavity(n, storage=args.storage), args.warmup, args.steps)
-    log(f"bench: {main_res['mlups']:.0f} MLUPS, bulk kernel {main_res['bulk_GBps']:.0f} GB/s")
+    main_res = timed_run(lbm, torch, W.large_cavity(n, storage=args.storage), args.warmup, args.steps,
+                         fusion=args.fusion)
+    log(f"bench: {main_res['mlups']:.0f} MLUPS, {main_res['main_kernel']} {main_res['main_GBps']:.0f} GB/s")
 
     modes = {}
     if not args.no_modes:
@@ -235,8 +242,15 @@ def main():
                 modes[s] = main_res
                 continue
             k = max(100, args.steps // 5)
-            modes[s] = timed_run(lbm, torch, W.large_cavity(n, storage=s), min(args.warmup, 100), k)
-            log(f"bench: {s}: {modes[s]['mlups']:.0f} MLUPS, {modes[s]['bulk_GBps']:.0f} GB/s")
+            modes[s] = timed_run(lbm, torch, W.large_cavity(n, storage=s), min(args.warmup, 100), k,
+                                 fusion=args.fusion)
+            log(f"bench: {s}: {modes[s]['mlups']:.0f} MLUPS, {modes[s]['main_kernel']} {modes[s]['main_GBps']:.0f} GB/s")
+
+    one_step = None
+    if not args.no_modes and main_res["steps_per_pass"] == 2:
+        one_step = timed_run(lbm, torch, W.large_cavity(n, storage=args.storage), min(args.warmup, 100),
+                             max(100, args.steps // 5), fusion=1)
+        log(f"bench: {args.storage} one step per pass: {one_step['mlups']:.0f} MLUPS")
 
     ens = None
     if not args.no_ensemble:
@@ -266,13 +280,15 @@ def main():
         "config": {"workload": f"porous cavity {n}x{n}, eps 0.4, Da 1e-4, Ra 1e7, Pr 0.71, "
                                f"{args.storage} population storage",
                    "nodes": n * n, "storage": args.storage},
-        "roofline": {"bound": "hbm", "achieved": main_res["bulk_GBps"], "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "achieved": main_res["main_GBps"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": main_res["frac"],
-                     "traffic": measured_traffic(args.storage, n),
-                     "kernel": "k_step_bulk",
-                     "bytes_per_launch": main_res["bulk_bytes_per_launch"],
-                     "avg_launch_us": main_res["bulk_kernel_us"]},
+                     "traffic": measured_traffic(main_res["main_kernel"], args.storage, n),
+                     "kernel": main_res["main_kernel"],
+                     "steps_per_launch": main_res["steps_per_pass"],
+                     "bytes_per_launch": main_res["main_bytes_per_launch"],
+                     "avg_launch_us": main_res["main_kernel_us"]},
         "modes": {s: {k: v for k, v in r.items()} for s, r in modes.items()},
+        "one_step_per_pass": one_step,
         "ensemble": ens,
         "adjoint": adj,
         "accuracy": acc,

@@ -131,19 +131,30 @@ size_t lbm_workspace_bytes(const lbm_params *params);
 lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_bytes,
                     void *hip_stream, lbm_ctx **out);
 
-/* Enqueues nsteps >= 0 time steps (asynchronous).  Each step is two launches on the
- * context's stream: the interior columns, then the columns next to the walls x = 0,
- * x = nx - 1 together with the walled rows. */
+/* Enqueues nsteps >= 0 time steps (asynchronous).  With two steps per pass (see
+ * lbm_set_fusion) pairs of steps run as one pass over the populations: the intermediate
+ * state of every node is computed from the source buffer in registers and the final
+ * state written once, so each pair reads and writes the populations once instead of
+ * twice; the results are bitwise those of single steps.  A single step is two launches:
+ * the interior columns, then the columns next to the walls x = 0, x = nx - 1 together
+ * with the walled rows. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
-/* As lbm_step (nsteps >= 1), with HIP events around the two launches of every `every`-th
- * step (every >= 1; steps 0, every, 2 every, ...); returns the mean duration in
- * milliseconds of the interior launch and of the wall-side launch over those steps, and
- * the number of nodes the interior launch updates per step (host outputs; any may be
- * NULL).  Used for measurement; events between launches cost a few microseconds per
- * bracketed step.  Synchronizes on the events, not on the whole stream. */
-lbm_status lbm_step_timed(lbm_ctx *ctx, int64_t nsteps, int32_t every, double *bulk_ms_host,
-                          double *wall_ms_host, int64_t *bulk_nodes_host);
+/* Time steps per pass, 1 or 2.  The default is 2 for FP64 storage when nx >= 124 and
+ * ny >= 16 (there the pass is faster), else 1.  LBM_ERR_UNSUPPORTED for 2 on smaller
+ * grids. */
+lbm_status lbm_set_fusion(lbm_ctx *ctx, int32_t steps_per_pass);
+int32_t lbm_fusion(const lbm_ctx *ctx);
+
+/* As lbm_step (nsteps >= the steps per pass), with HIP events around the launches of every
+ * `every`-th pass (every >= 1); returns the mean duration in milliseconds of the main
+ * launch of a pass (the interior launch for single steps, the two-step launch otherwise)
+ * and of the remaining launches of the pass, the number of nodes the main launch updates,
+ * and the steps one pass advances (host outputs; any may be NULL).  An odd last step of a
+ * two-step schedule runs untimed.  Used for measurement; events between launches cost a
+ * few microseconds per bracketed pass.  Synchronizes on the events, not on the stream. */
+lbm_status lbm_step_timed(lbm_ctx *ctx, int64_t nsteps, int32_t every, double *main_ms_host,
+                          double *rest_ms_host, int64_t *main_nodes_host, int32_t *steps_per_launch_host);
 
 int64_t lbm_time(const lbm_ctx *ctx);
 

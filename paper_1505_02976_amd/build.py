@@ -8,13 +8,16 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_api.cpp", "lbm_kernels.hip", "lbm_adjoint.hip"]
+SOURCES = ["lbm_api.cpp", "lbm_kernels.hip", "lbm_adjoint.hip", "lbm_step2.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed FP32 instructions stay disabled for every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only within one source expression, so the same node code
+    # rounds identically in every kernel it is inlined into (one-step, two-step, batched)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-result",
 ]
 

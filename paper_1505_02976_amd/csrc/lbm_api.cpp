@@ -89,7 +89,8 @@ struct Layout {
     int pitch, ntx;
     long long plane;
     size_t pop_bytes;     // one population buffer
-    size_t off_a, off_b, off_eps, off_snap, off_part, off_scalar, total;
+    size_t off_a, off_b, off_eps, off_snap, off_part, off_scalar, off_scr, total;
+    long long plane_scr;  // plane size of the eight-row scratch grid (plane layout)
     long long nparts;
 };
 
@@ -121,6 +122,16 @@ Layout layout(const lbm_params *p, const lbm::KParams &kp)
     L.off_snap = o; o += align_up(3 * N * 8, 256);
     L.off_part = o; o += align_up((size_t)L.nparts * 5 * 8, 256);
     L.off_scalar = o; o += 256;
+    // eight rows of intermediate populations for the two-step pass (walled rows)
+    size_t scr;
+    if (tile > 0) {
+        scr = align_up((size_t)8 * L.ntx * 18 * tile * es, 256);
+        L.plane_scr = 0;
+    } else {
+        L.plane_scr = (long long)align_up((size_t)L.pitch * 8, 256 / es) + (long long)(256 / es);
+        scr = align_up((size_t)L.plane_scr * 18 * es, 256);
+    }
+    L.off_scr = o; o += scr;
     L.total = o;
     return L;
 }
@@ -208,10 +219,13 @@ struct lbm_ctx {
     int have_snap;
     int device;
     int in_batch;
+    int cur;             // buffer holding the current populations (0: a, 1: b)
+    int fuse;            // time steps per pass over the populations (1 or 2)
+    lbm::KParams kpm;    // parameters of the eight-row scratch grid of the two-step pass
 };
 
-static void *cur_buf(lbm_ctx *c) { return c->ws + ((c->t & 1) ? c->lay.off_b : c->lay.off_a); }
-static void *next_buf(lbm_ctx *c) { return c->ws + ((c->t & 1) ? c->lay.off_a : c->lay.off_b); }
+static void *cur_buf(lbm_ctx *c) { return c->ws + (c->cur ? c->lay.off_b : c->lay.off_a); }
+static void *next_buf(lbm_ctx *c) { return c->ws + (c->cur ? c->lay.off_a : c->lay.off_b); }
 
 extern "C" {
 
@@ -262,6 +276,7 @@ static lbm_status init_ctx(const lbm_params *params, void *workspace, size_t wor
     c->t = 0;
     c->have_snap = 0;
     c->in_batch = 0;
+    c->cur = 0;
     if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
 
     hipError_t e;
@@ -273,6 +288,12 @@ static lbm_status init_ctx(const lbm_params *params, void *workspace, size_t wor
         kp.eps_field = eps;
     }
     c->kp = kp;
+    c->kpm = kp;
+    c->kpm.ny = 8;
+    c->kpm.py = 0;
+    c->kpm.plane = lay.plane_scr;
+    // two-step passes by default where they are faster: FP64 storage (see lbm_step2.hip)
+    c->fuse = (params->storage == LBM_F64 && lbm::step2_supported(kp)) ? 2 : 1;
     e = hipMemsetAsync(c->ws + lay.off_b, 0, lay.pop_bytes, c->stream);
     if (e == hipSuccess)
         e = lbm::launch_init(params->storage, cur_buf(c), c->kp, params->T_init, params->p_init,
@@ -293,23 +314,42 @@ namespace {
 // Timing events of one step.
 struct StepEvents { hipEvent_t i0, i1, e1; };
 
-// nsteps steps on the context's stream: the interior launch, then the launch of the
-// columns next to the walls x = 0, x = nx - 1 and of the walled rows.  With tev, every
-// `every`-th step (s = 0, every, 2 every, ...) is bracketed by the events tev[s / every].
-hipError_t run_steps(lbm_ctx *c, int64_t nsteps, const StepEvents *tev, int every)
+// nsteps steps on the context's stream.  One step: the interior launch, then the launch of
+// the columns next to the walls x = 0, x = nx - 1 and of the walled rows.  With fuse = 2,
+// pairs of steps run as one two-step pass (main launch, then the walled rows).  With tev,
+// every `every`-th launch group (g = 0, every, 2 every, ...) is bracketed by tev[g / every]:
+// i0 .. i1 around the main launch, i1 .. e1 around the rest.  Returns the number of launch
+// groups in *groups.
+hipError_t run_steps(lbm_ctx *c, int64_t nsteps, const StepEvents *tev, int every, int64_t *groups)
 {
     hipError_t e = hipSuccess;
     const int sto = c->prm.storage;
-    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+    int64_t s = 0, gi = 0;
+    while (s < nsteps && e == hipSuccess) {
         void *src = cur_buf(c), *dst = next_buf(c);
-        const StepEvents *t = (tev && s % every == 0) ? tev + s / every : nullptr;
+        const StepEvents *t = (tev && gi % every == 0) ? tev + gi / every : nullptr;
+        const bool two = c->fuse == 2 && nsteps - s >= 2;
         if (t) e = hipEventRecord(t->i0, c->stream);
-        if (e == hipSuccess) e = lbm::launch_step_bulk(sto, src, dst, c->kp, c->stream);
-        if (e == hipSuccess && t) e = hipEventRecord(t->i1, c->stream);
-        if (e == hipSuccess) e = lbm::launch_step_wall(sto, src, dst, c->kp, c->stream);
+        if (two) {
+            if (e == hipSuccess)
+                e = lbm::launch_step2_main(sto, src, dst, c->ws + c->lay.off_scr, c->kp, c->kpm, c->stream);
+            if (e == hipSuccess && t) e = hipEventRecord(t->i1, c->stream);
+            if (e == hipSuccess)
+                e = lbm::launch_step2_rows(sto, dst, c->ws + c->lay.off_scr, c->kp, c->kpm, c->stream);
+        } else {
+            if (e == hipSuccess) e = lbm::launch_step_bulk(sto, src, dst, c->kp, c->stream);
+            if (e == hipSuccess && t) e = hipEventRecord(t->i1, c->stream);
+            if (e == hipSuccess) e = lbm::launch_step_wall(sto, src, dst, c->kp, c->stream);
+        }
         if (e == hipSuccess && t) e = hipEventRecord(t->e1, c->stream);
-        if (e == hipSuccess) c->t += 1;
+        if (e == hipSuccess) {
+            c->t += two ? 2 : 1;
+            s += two ? 2 : 1;
+            c->cur ^= 1;
+            ++gi;
+        }
     }
+    if (groups) *groups = gi;
     return e;
 }
 
@@ -321,17 +361,17 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps)
     if (c->in_batch) return fail(LBM_ERR_INVALID, "problem belongs to a batch: use lbm_batch_step");
     if (nsteps < 0) return fail(LBM_ERR_INVALID, "nsteps < 0");
     if (nsteps == 0) return LBM_OK;
-    hipError_t e = run_steps(c, nsteps, nullptr, 1);
+    hipError_t e = run_steps(c, nsteps, nullptr, 1, nullptr);
     if (e != hipSuccess) return hip_fail(e, "step launch");
     return LBM_OK;
 }
 
-lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, int32_t every, double *bulk_ms, double *wall_ms,
-                          int64_t *bulk_nodes)
+lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, int32_t every, double *main_ms, double *rest_ms,
+                          int64_t *main_nodes, int32_t *steps_per_launch)
 {
     if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
     if (c->in_batch) return fail(LBM_ERR_INVALID, "problem belongs to a batch: use lbm_batch_step");
-    if (nsteps < 1) return fail(LBM_ERR_INVALID, "nsteps < 1");
+    if (nsteps < c->fuse) return fail(LBM_ERR_INVALID, "nsteps < %d", c->fuse);
     if (every < 1) return fail(LBM_ERR_INVALID, "every < 1");
     // events are read back in groups so that the stream is not drained after every step
     constexpr int GROUP = 32;
@@ -345,11 +385,14 @@ lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, int32_t every, double *bul
     }
     double tb = 0.0, tw = 0.0;
     int64_t done = 0, sampled = 0;
-    const int64_t chunk = (int64_t)GROUP * every;
-    while (done < nsteps && e == hipSuccess) {
-        const int64_t nb = (nsteps - done) < chunk ? (nsteps - done) : chunk;
-        const int ns = (int)((nb + every - 1) / every);
-        e = run_steps(c, nb, ev.data(), every);
+    // only whole passes are timed; a leftover single step runs untimed at the end
+    const int64_t timed = nsteps - nsteps % c->fuse;
+    const int64_t chunk = (int64_t)GROUP * every * c->fuse;
+    while (done < timed && e == hipSuccess) {
+        const int64_t nb = (timed - done) < chunk ? (timed - done) : chunk;
+        int64_t groups = 0;
+        e = run_steps(c, nb, ev.data(), every, &groups);
+        const int ns = (int)((groups + every - 1) / every);
         if (e == hipSuccess) e = hipEventSynchronize(ev[ns - 1].e1);
         for (int s = 0; s < ns && e == hipSuccess; ++s) {
             float a = 0.f, b = 0.f;
@@ -361,17 +404,32 @@ lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, int32_t every, double *bul
         sampled += ns;
         done += nb;
     }
+    if (e == hipSuccess && nsteps > timed) e = run_steps(c, nsteps - timed, nullptr, 1, nullptr);
     for (auto &x : ev) {
         if (x.i0) (void)hipEventDestroy(x.i0);
         if (x.i1) (void)hipEventDestroy(x.i1);
         if (x.e1) (void)hipEventDestroy(x.e1);
     }
     if (e != hipSuccess) return hip_fail(e, "timed step");
-    if (bulk_ms) *bulk_ms = tb / (double)sampled;
-    if (wall_ms) *wall_ms = tw / (double)sampled;
-    if (bulk_nodes) *bulk_nodes = lbm::interior_nodes(c->prm.storage, c->kp);
+    if (main_ms) *main_ms = tb / (double)sampled;
+    if (rest_ms) *rest_ms = tw / (double)sampled;
+    if (main_nodes)
+        *main_nodes = c->fuse == 2 ? lbm::step2_nodes(c->kp) : lbm::interior_nodes(c->prm.storage, c->kp);
+    if (steps_per_launch) *steps_per_launch = c->fuse;
     return LBM_OK;
 }
+
+lbm_status lbm_set_fusion(lbm_ctx *c, int32_t steps_per_pass)
+{
+    if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
+    if (steps_per_pass != 1 && steps_per_pass != 2) return fail(LBM_ERR_INVALID, "steps_per_pass must be 1 or 2");
+    if (steps_per_pass == 2 && !lbm::step2_supported(c->kp))
+        return fail(LBM_ERR_UNSUPPORTED, "two-step passes need nx >= 124 and ny >= 16");
+    c->fuse = steps_per_pass;
+    return LBM_OK;
+}
+
+int32_t lbm_fusion(const lbm_ctx *c) { return c ? c->fuse : 0; }
 
 int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
 
@@ -578,7 +636,7 @@ lbm_status lbm_adjoint_forward(lbm_ctx *c, int32_t wall, int64_t nsteps, void *w
             e = hipMemcpyAsync(ws + L.off_ck + (size_t)(s / L.K) * c->lay.pop_bytes, cur_buf(c),
                                c->lay.pop_bytes, hipMemcpyDeviceToDevice, c->stream);
         if (e == hipSuccess) e = lbm::launch_step(c->prm.storage, cur_buf(c), next_buf(c), c->kp, c->stream);
-        if (e == hipSuccess) c->t += 1;
+        if (e == hipSuccess) { c->t += 1; c->cur ^= 1; }
     }
     if (e != hipSuccess) return hip_fail(e, "adjoint forward");
     double J;
@@ -905,7 +963,7 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
         if (e != hipSuccess) return hip_fail(e, "batch step");
         ++done; ++b->t;
     }
-    for (lbm_ctx *c : b->ctx) c->t = b->t;
+    for (lbm_ctx *c : b->ctx) { c->t = b->t; c->cur = (int)(b->t & 1); }
     return LBM_OK;
 }
 

@@ -58,7 +58,7 @@ _lib = None
 
 EXPORTS = ("lbm_derive", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_timed", "lbm_time",
            "lbm_moments", "lbm_gradients", "lbm_nusselt", "lbm_residual", "lbm_get_state",
-           "lbm_set_state", "lbm_destroy", "lbm_last_error",
+           "lbm_set_state", "lbm_destroy", "lbm_last_error", "lbm_set_fusion", "lbm_fusion",
            "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_problem",
            "lbm_batch_check", "lbm_batch_destroy", "lbm_batch_autotune",
            "lbm_batch_set_width",
@@ -86,7 +86,11 @@ def lib():
     L.lbm_step.argtypes = [vp, C.c_int64]
     L.lbm_step_timed.restype = st
     L.lbm_step_timed.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                 C.POINTER(C.c_int64)]
+                                 C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+    L.lbm_set_fusion.restype = st
+    L.lbm_set_fusion.argtypes = [vp, C.c_int32]
+    L.lbm_fusion.restype = C.c_int32
+    L.lbm_fusion.argtypes = [vp]
     L.lbm_time.restype = C.c_int64
     L.lbm_time.argtypes = [vp]
     L.lbm_moments.restype = st
@@ -269,12 +273,22 @@ class Sim:
         _check(lib().lbm_step(self.h, int(n)))
 
     def step_timed(self, n: int, every: int = 1):
-        """Steps with HIP events around the two launches of every `every`-th step; returns
-        (interior_ms, wall_side_ms, interior_nodes): mean launch durations over the bracketed
-        steps and the nodes the interior launch updates per step."""
-        b, w, nodes = C.c_double(), C.c_double(), C.c_int64()
-        _check(lib().lbm_step_timed(self.h, int(n), int(every), C.byref(b), C.byref(w), C.byref(nodes)))
-        return b.value, w.value, nodes.value
+        """Steps with HIP events around the launches of every `every`-th pass; returns
+        (main_ms, rest_ms, main_nodes, steps_per_pass): mean launch durations over the
+        bracketed passes, the nodes the main launch updates and the steps one pass makes."""
+        b, w, nodes, k = C.c_double(), C.c_double(), C.c_int64(), C.c_int32()
+        _check(lib().lbm_step_timed(self.h, int(n), int(every), C.byref(b), C.byref(w), C.byref(nodes),
+                                    C.byref(k)))
+        return b.value, w.value, nodes.value, k.value
+
+    @property
+    def fusion(self) -> int:
+        """Time steps per pass over the populations (1 or 2)."""
+        return int(lib().lbm_fusion(self.h))
+
+    @fusion.setter
+    def fusion(self, steps_per_pass: int):
+        _check(lib().lbm_set_fusion(self.h, int(steps_per_pass)))
 
     def _alloc(self, dtype):
         return self.torch.empty((self.ny, self.nx), dtype=dtype, device=self.device)

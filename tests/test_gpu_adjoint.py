@@ -8,7 +8,8 @@ porosity of every node) through the C interface.
     largest entry.
   * At 256 x 256 over 5000 steps (smooth random porosity field): directional derivatives
     of the FP32-storage adjoint along 16 smooth directions against central differences of
-    the FP64 path (h = 1e-5), within 1e-4 relative; the FP64 adjoint within 1e-6.
+    the FP64 path (h = 1e-5), within 1e-4 relative; the FP64 adjoint within 5e-6 (the
+    accuracy of the central difference itself).
   * The torch.autograd.Function wrapper returns the same gradient.
 
 The initial state must not depend on eps for the two sides to define the same function:
@@ -152,7 +153,10 @@ def test_adjoint_full_size_vs_finite_differences(gpu):
              f"f64 {np.sum(res['f64'] * d):.9e}")
     _say(f"  Nu f32 {nu_of['f32']:.9f} f64 {nu_of['f64']:.9f}; worst relative error {worst}")
     assert worst["f32"] < 1e-4
-    assert worst["f64"] < 1e-6
+    # the FP64 adjoint is exact (complex-step test above); what remains is the O(h^2)
+    # truncation and the rounding of the central difference, about 1e-6 of the smallest
+    # directional derivative here
+    assert worst["f64"] < 5e-6
 
 
 def test_autograd_function(gpu):
