@@ -292,8 +292,9 @@ static lbm_status init_ctx(const lbm_params *params, void *workspace, size_t wor
     c->kpm.ny = 8;
     c->kpm.py = 0;
     c->kpm.plane = lay.plane_scr;
-    // two-step passes by default where they are faster: FP64 storage (see lbm_step2.hip)
-    c->fuse = (params->storage == LBM_F64 && lbm::step2_supported(kp)) ? 2 : 1;
+    // two-step passes by default where they are faster: FP32 and FP64 storage, whose tiles
+    // match the two-step wavefronts (see lbm_step2.hip)
+    c->fuse = (params->storage != LBM_F16 && lbm::step2_supported(kp)) ? 2 : 1;
     e = hipMemsetAsync(c->ws + lay.off_b, 0, lay.pop_bytes, c->stream);
     if (e == hipSuccess)
         e = lbm::launch_init(params->storage, cur_buf(c), c->kp, params->T_init, params->p_init,

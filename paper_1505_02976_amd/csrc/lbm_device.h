@@ -19,10 +19,10 @@
 // contiguously, [y][x / n][q][x % n], so that the 36 streams of a wavefront touch one
 // contiguous block of memory per row instead of 36 distant planes.
 #ifndef LBM_TILE_F64
-#define LBM_TILE_F64 0
+#define LBM_TILE_F64 62
 #endif
 #ifndef LBM_TILE_F32
-#define LBM_TILE_F32 128
+#define LBM_TILE_F32 62
 #endif
 #ifndef LBM_TILE_F16
 #define LBM_TILE_F16 128
@@ -34,6 +34,11 @@ template <typename S> struct TileOf;
 template <> struct TileOf<double> { static constexpr int v = LBM_TILE_F64; };
 template <> struct TileOf<float> { static constexpr int v = LBM_TILE_F32; };
 template <> struct TileOf<__half> { static constexpr int v = LBM_TILE_F16; };
+// Columns one wavefront updates: a whole tile when tiles are narrower than a wavefront
+// (so that its stores cover whole tile segments), else 64.
+template <typename S> struct Wspan {
+    static constexpr int v = (TileOf<S>::v > 0 && TileOf<S>::v < 64) ? TileOf<S>::v : 64;
+};
 inline constexpr int tile_of_storage(int storage)
 {
     return storage == 0 ? LBM_TILE_F64 : (storage == 1 ? LBM_TILE_F32 : LBM_TILE_F16);

@@ -60,9 +60,11 @@ k_init(S *__restrict__ dst, KParams P, const double *__restrict__ T_init,
 // ---------------------------------------------------------------------------------
 // Fused step, bulk nodes: gather -> moments -> S, grad T -> equilibria -> collide -> store
 //
-// A block of BX threads covers a segment of BX * NPT consecutive nodes of one row;
-// thread t handles nodes t, t + BX, ... so every load instruction stays coalesced and
-// each thread has NPT nodes' loads in flight before it computes.
+// A block of BX threads covers a segment of (BX / 64) * WS * NPT consecutive nodes of one
+// row, WS = Wspan (columns per wavefront: 64, or the tile width when tiles are narrower,
+// so that a wavefront stores whole tile segments); lane l of wavefront w handles nodes
+// w WS + l + k (BX / 64) WS, k < NPT, so every load instruction stays coalesced and each
+// thread has NPT nodes' loads in flight before it computes.
 // ---------------------------------------------------------------------------------
 #ifndef LBM_NPT_F64
 #define LBM_NPT_F64 1
@@ -79,6 +81,10 @@ template <> struct Npt<double> { static constexpr int v = LBM_NPT_F64; };
 template <> struct Npt<float> { static constexpr int v = LBM_NPT_F32; };
 template <> struct Npt<__half> { static constexpr int v = LBM_NPT_F16; };
 
+// Columns covered by one node slot of a block of BX threads, and by the whole block.
+template <typename S, int BX> __host__ __device__ constexpr int slot_span() { return (BX / 64) * Wspan<S>::v; }
+template <typename S, int BX> __host__ __device__ constexpr int block_span() { return slot_span<S, BX>() * Npt<S>::v; }
+
 // One row segment of the bulk update: nodes x = xbeg + tid + k BX (k < NPT) with
 // x < xend, of row y (tid: the thread's index among the BX threads of the segment).
 //
@@ -94,16 +100,19 @@ __device__ __forceinline__ void bulk_tile(const S *__restrict__ src, S *__restri
                                           int tid)
 {
     constexpr int NPT = Npt<S>::v;
+    constexpr int WS = Wspan<S>::v, SPAN = slot_span<S, BX>();
     using RC = typename Prec<S>::R;
-    const int x0 = xbeg + tid;
+    const int wl = tid & 63;
+    const bool lane_on = wl < WS;
+    const int x0 = xbeg + (tid >> 6) * WS + wl;
     if (!P.py && (y == 0 || y == P.ny - 1)) return;
     RC f[NPT][9], g[NPT][9];
     bool act[NPT], vw[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int x = x0 + k * BX;
-        vw[k] = WALLS && x < xend && !P.px && (x == 0 || x == P.nx - 1);
-        act[k] = x < xend && !vw[k];
+        const int x = x0 + k * SPAN;
+        vw[k] = WALLS && lane_on && x < xend && !P.px && (x == 0 || x == P.nx - 1);
+        act[k] = lane_on && x < xend && !vw[k];
         if (act[k]) gather<S, RC>(src, P, x, y, f[k], g[k]);
     }
     if (WALLS && !P.px) {
@@ -112,15 +121,15 @@ __device__ __forceinline__ void bulk_tile(const S *__restrict__ src, S *__restri
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             if (!__ballot(vw[k])) continue;               // wavefront-uniform
-            const int x = x0 + k * BX;
+            const int x = x0 + k * SPAN;
             const int dx = (x == 0) ? 1 : -1;
             RC sg = RC(0);
 #pragma unroll
             for (int i = 0; i < 9; ++i) sg += g[k][i];
             const RC Td_own = (sg + c.halfQ) * c.isig;
             const int l1 = lane + dx, l2 = lane + 2 * dx;
-            const bool in1 = vw[k] && l1 >= 0 && l1 < warpSize;
-            const bool in2 = vw[k] && l2 >= 0 && l2 < warpSize;
+            const bool in1 = vw[k] && l1 >= 0 && l1 < WS;
+            const bool in2 = vw[k] && l2 >= 0 && l2 < WS;
             const int s1 = in1 ? l1 : lane, s2 = in2 ? l2 : lane;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
@@ -141,7 +150,7 @@ __device__ __forceinline__ void bulk_tile(const S *__restrict__ src, S *__restri
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         if (!act[k]) continue;
-        const int x = x0 + k * BX;
+        const int x = x0 + k * SPAN;
         node_update<RC, typename Prec<S>::M>(f[k], g[k], P, x, y);
         store_node<S, RC>(dst, P, x, y, f[k], g[k]);
     }
@@ -173,7 +182,7 @@ struct Cols { int xa, xb, nseg, span_e; bool split; };
 template <typename S> __host__ __device__ __forceinline__ Cols step_cols(const KParams &P)
 {
     Cols c;
-    c.span_e = EDGE_BX * Npt<S>::v;
+    c.span_e = block_span<S, EDGE_BX>();
     c.split = !P.px && P.nx >= 2 * c.span_e;
     if (P.px) { c.xa = 0; c.xb = P.nx; c.nseg = 0; }
     else if (c.split) { c.xa = c.span_e; c.xb = P.nx - c.span_e; c.nseg = 2; }
@@ -187,7 +196,7 @@ __host__ __device__ __forceinline__ int rows_count(const KParams &P) { return P.
 template <typename S> __host__ __device__ __forceinline__ int interior_segments(const KParams &P)
 {
     const Cols c = step_cols<S>(P);
-    const int span = BULK_BX * Npt<S>::v;
+    const int span = block_span<S, BULK_BX>();
     return (c.xb - c.xa + span - 1) / span;
 }
 
@@ -197,7 +206,7 @@ k_step_bulk(const S *__restrict__ src, S *__restrict__ dst, KParams P, int nseg)
 {
     const Cols c = step_cols<S>(P);
     const int r = blockIdx.x / nseg, s = blockIdx.x - r * nseg;
-    bulk_tile<S, false, BULK_BX>(src, dst, P, rows_begin(P) + r, c.xa + s * (BULK_BX * Npt<S>::v), c.xb,
+    bulk_tile<S, false, BULK_BX>(src, dst, P, rows_begin(P) + r, c.xa + s * block_span<S, BULK_BX>(), c.xb,
                                  threadIdx.x);
 }
 
@@ -247,7 +256,7 @@ k_batch_bulk(const BatchProblem *__restrict__ probs, const int2 *__restrict__ it
     const int2 it = items[blockIdx.x];
     const BatchProblem &B = probs[it.x];
     const int y = it.y / B.tiles_x;
-    const int xbeg = (it.y - y * B.tiles_x) * (BX * Npt<S>::v);
+    const int xbeg = (it.y - y * B.tiles_x) * block_span<S, BX>();
     bulk_tile<S, WALLS, BX>(static_cast<const S *>(B.buf[parity]),
                             static_cast<S *>(B.buf[parity ^ 1]), B.P, y, xbeg, B.P.nx, threadIdx.x);
 }
@@ -788,9 +797,14 @@ static int npt_of(int storage)
     return storage == 0 ? Npt<double>::v : (storage == 1 ? Npt<float>::v : Npt<__half>::v);
 }
 
+static int wspan_of(int storage)
+{
+    return storage == 0 ? Wspan<double>::v : (storage == 1 ? Wspan<float>::v : Wspan<__half>::v);
+}
+
 int batch_tiles_x(int storage, const KParams &P, int bx)
 {
-    const int span = bx * npt_of(storage);
+    const int span = (bx / 64) * wspan_of(storage) * npt_of(storage);
     return (P.nx + span - 1) / span;
 }
 

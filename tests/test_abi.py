@@ -85,7 +85,8 @@ def test_workspace_size_scales_with_storage(lbm):
     N = 4096 * 4096
     # two buffers of 18 planes plus the FP64 residual snapshot (3 fields)
     for s, es in (("f64", 8), ("f32", 4), ("f16", 2)):
-        assert 2 * 18 * N * es + 24 * N <= sizes[s] < 1.01 * (2 * 18 * N * es + 24 * N) + 2 ** 20
+        # tiles of 62 columns pad 4096 to 4154 (1.4 %)
+        assert 2 * 18 * N * es + 24 * N <= sizes[s] < 1.03 * (2 * 18 * N * es + 24 * N) + 2 ** 20
 
 
 def test_init_rejects_null_workspace(lbm):

@@ -39,7 +39,7 @@ def test_two_step_pass_is_bitwise_two_steps(gpu, storage, seed, nx, ny, px, py, 
     cfg = W.random_case(seed, nx, ny, periodic_x=px, periodic_y=py, storage=storage, **extra)
     a = gpu.Sim(cfg)
     b = gpu.Sim(cfg)
-    assert a.fusion == (2 if storage == "f64" else 1)
+    assert a.fusion == (1 if storage == "f16" else 2)
     a.fusion = 2
     b.fusion = 1
     for n in (2, 7, 30):
@@ -63,4 +63,5 @@ def test_fusion_setting(gpu):
     assert big.fusion == 2
     big.fusion = 1
     assert big.fusion == 1
-    assert gpu.Sim(W.cavity(128, storage="f32")).fusion == 1
+    assert gpu.Sim(W.cavity(128, storage="f32")).fusion == 2
+    assert gpu.Sim(W.cavity(128, storage="f16")).fusion == 1
