@@ -148,11 +148,13 @@ int32_t lbm_fusion(const lbm_ctx *ctx);
 
 /* As lbm_step (nsteps >= the steps per pass), with HIP events around the launches of every
  * `every`-th pass (every >= 1); returns the mean duration in milliseconds of the main
- * launch of a pass (the interior launch for single steps, the two-step launch otherwise)
- * and of the remaining launches of the pass, the number of nodes the main launch updates,
- * and the steps one pass advances (host outputs; any may be NULL).  An odd last step of a
- * two-step schedule runs untimed.  Used for measurement; events between launches cost a
- * few microseconds per bracketed pass.  Synchronizes on the events, not on the stream. */
+ * launch of a pass (the interior launch of a single step; the launch of the wavefronts
+ * away from walls of a two-step pass) and of the remaining launches of the pass (for
+ * two-step passes these run on a second stream, beside the main launch), the number of
+ * nodes the main launch updates, and the steps one pass advances (host outputs; any may
+ * be NULL).  An odd last step of a two-step schedule runs untimed.  Used for measurement;
+ * events between launches cost a few microseconds per bracketed pass.  Synchronizes on
+ * the events, not on the stream. */
 lbm_status lbm_step_timed(lbm_ctx *ctx, int64_t nsteps, int32_t every, double *main_ms_host,
                           double *rest_ms_host, int64_t *main_nodes_host, int32_t *steps_per_launch_host);
 

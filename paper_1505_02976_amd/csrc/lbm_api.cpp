@@ -222,6 +222,10 @@ struct lbm_ctx {
     int cur;             // buffer holding the current populations (0: a, 1: b)
     int fuse;            // time steps per pass over the populations (1 or 2)
     lbm::KParams kpm;    // parameters of the eight-row scratch grid of the two-step pass
+    // Second stream of the two-step pass: the wavefronts next to walls (few, long) run
+    // there beside the lean launch; events order each launch after both of the previous pass.
+    hipStream_t side;
+    hipEvent_t ev_join, ev_main, ev_side;
 };
 
 static void *cur_buf(lbm_ctx *c) { return c->ws + (c->cur ? c->lay.off_b : c->lay.off_a); }
@@ -277,6 +281,8 @@ static lbm_status init_ctx(const lbm_params *params, void *workspace, size_t wor
     c->have_snap = 0;
     c->in_batch = 0;
     c->cur = 0;
+    c->side = nullptr;
+    c->ev_join = c->ev_main = c->ev_side = nullptr;
     if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
 
     hipError_t e;
@@ -312,40 +318,97 @@ lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_
 
 namespace {
 
-// Timing events of one step.
-struct StepEvents { hipEvent_t i0, i1, e1; };
+// Timing events of one launch group: i0 .. i1 around the main launch, e0 .. e1 around the
+// rest (on the side stream for two-step passes).
+struct StepEvents { hipEvent_t i0, i1, e0, e1; };
+
+#ifndef LBM_STEP2_STREAMS
+#define LBM_STEP2_STREAMS 2
+#endif
+
+hipError_t ensure_side(lbm_ctx *c)
+{
+    if (c->side) return hipSuccess;
+    hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming);
+    return e;
+}
+
+// npass two-step passes.  The lean launch goes to the context's stream, the full launch and
+// the walled rows to the side stream; pass p's lean launch waits for the side stream's
+// pass p - 1, its full launch for the lean launch of pass p - 1 (both read the source and
+// write disjoint nodes of the destination).  Every wait names an event recorded earlier in
+// host order; the side stream first waits for the caller's stream and the caller's stream
+// finally waits for the side stream, so the call is ordered like launches on the caller's
+// stream.
+hipError_t run_passes(lbm_ctx *c, int64_t npass, const StepEvents *tev, int every, int64_t gi0)
+{
+    const int sto = c->prm.storage;
+    void *scr = c->ws + c->lay.off_scr;
+    hipStream_t side = LBM_STEP2_STREAMS == 2 ? c->side : c->stream;
+    hipError_t e = hipSuccess;
+    if (LBM_STEP2_STREAMS == 2) {
+        e = ensure_side(c);
+        side = c->side;
+        if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, c->ev_join, 0);
+    }
+    for (int64_t p = 0; p < npass && e == hipSuccess; ++p) {
+        void *src = cur_buf(c), *dst = next_buf(c);
+        const int64_t gi = gi0 + p;
+        const StepEvents *t = (tev && gi % every == 0) ? tev + gi / every : nullptr;
+        if (LBM_STEP2_STREAMS == 2 && p > 0) {
+            e = hipStreamWaitEvent(c->stream, c->ev_side, 0);
+            if (e == hipSuccess) e = hipStreamWaitEvent(side, c->ev_main, 0);
+        }
+        if (e == hipSuccess && t) e = hipEventRecord(t->i0, c->stream);
+        if (e == hipSuccess) e = lbm::launch_step2_main(sto, false, src, dst, scr, c->kp, c->kpm, c->stream);
+        if (e == hipSuccess && t) e = hipEventRecord(t->i1, c->stream);
+        if (e == hipSuccess && LBM_STEP2_STREAMS == 2) e = hipEventRecord(c->ev_main, c->stream);
+        if (e == hipSuccess && t) e = hipEventRecord(t->e0, side);
+        if (e == hipSuccess) e = lbm::launch_step2_main(sto, true, src, dst, scr, c->kp, c->kpm, side);
+        if (e == hipSuccess) e = lbm::launch_step2_rows(sto, dst, scr, c->kp, c->kpm, side);
+        if (e == hipSuccess && t) e = hipEventRecord(t->e1, side);
+        if (e == hipSuccess && LBM_STEP2_STREAMS == 2) e = hipEventRecord(c->ev_side, side);
+        if (e == hipSuccess) {
+            c->t += 2;
+            c->cur ^= 1;
+        }
+    }
+    if (e == hipSuccess && LBM_STEP2_STREAMS == 2 && npass > 0) e = hipStreamWaitEvent(c->stream, c->ev_side, 0);
+    return e;
+}
 
 // nsteps steps on the context's stream.  One step: the interior launch, then the launch of
 // the columns next to the walls x = 0, x = nx - 1 and of the walled rows.  With fuse = 2,
-// pairs of steps run as one two-step pass (main launch, then the walled rows).  With tev,
-// every `every`-th launch group (g = 0, every, 2 every, ...) is bracketed by tev[g / every]:
-// i0 .. i1 around the main launch, i1 .. e1 around the rest.  Returns the number of launch
-// groups in *groups.
+// pairs of steps run as two-step passes (run_passes), a last odd step as one step.  With
+// tev, every `every`-th launch group (g = 0, every, 2 every, ...) is bracketed by
+// tev[g / every].  Returns the number of launch groups in *groups.
 hipError_t run_steps(lbm_ctx *c, int64_t nsteps, const StepEvents *tev, int every, int64_t *groups)
 {
     hipError_t e = hipSuccess;
     const int sto = c->prm.storage;
     int64_t s = 0, gi = 0;
+    if (c->fuse == 2 && nsteps >= 2) {
+        const int64_t npass = nsteps / 2;
+        e = run_passes(c, npass, tev, every, 0);
+        s = 2 * npass;
+        gi = npass;
+    }
     while (s < nsteps && e == hipSuccess) {
         void *src = cur_buf(c), *dst = next_buf(c);
         const StepEvents *t = (tev && gi % every == 0) ? tev + gi / every : nullptr;
-        const bool two = c->fuse == 2 && nsteps - s >= 2;
         if (t) e = hipEventRecord(t->i0, c->stream);
-        if (two) {
-            if (e == hipSuccess)
-                e = lbm::launch_step2_main(sto, src, dst, c->ws + c->lay.off_scr, c->kp, c->kpm, c->stream);
-            if (e == hipSuccess && t) e = hipEventRecord(t->i1, c->stream);
-            if (e == hipSuccess)
-                e = lbm::launch_step2_rows(sto, dst, c->ws + c->lay.off_scr, c->kp, c->kpm, c->stream);
-        } else {
-            if (e == hipSuccess) e = lbm::launch_step_bulk(sto, src, dst, c->kp, c->stream);
-            if (e == hipSuccess && t) e = hipEventRecord(t->i1, c->stream);
-            if (e == hipSuccess) e = lbm::launch_step_wall(sto, src, dst, c->kp, c->stream);
-        }
+        if (e == hipSuccess) e = lbm::launch_step_bulk(sto, src, dst, c->kp, c->stream);
+        if (e == hipSuccess && t) e = hipEventRecord(t->i1, c->stream);
+        if (e == hipSuccess && t) e = hipEventRecord(t->e0, c->stream);
+        if (e == hipSuccess) e = lbm::launch_step_wall(sto, src, dst, c->kp, c->stream);
         if (e == hipSuccess && t) e = hipEventRecord(t->e1, c->stream);
         if (e == hipSuccess) {
-            c->t += two ? 2 : 1;
-            s += two ? 2 : 1;
+            c->t += 1;
+            s += 1;
             c->cur ^= 1;
             ++gi;
         }
@@ -382,6 +445,7 @@ lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, int32_t every, double *mai
     for (; made < GROUP && e == hipSuccess; ++made) {
         e = hipEventCreate(&ev[made].i0);
         if (e == hipSuccess) e = hipEventCreate(&ev[made].i1);
+        if (e == hipSuccess) e = hipEventCreate(&ev[made].e0);
         if (e == hipSuccess) e = hipEventCreate(&ev[made].e1);
     }
     double tb = 0.0, tw = 0.0;
@@ -395,10 +459,11 @@ lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, int32_t every, double *mai
         e = run_steps(c, nb, ev.data(), every, &groups);
         const int ns = (int)((groups + every - 1) / every);
         if (e == hipSuccess) e = hipEventSynchronize(ev[ns - 1].e1);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[ns - 1].i1);
         for (int s = 0; s < ns && e == hipSuccess; ++s) {
             float a = 0.f, b = 0.f;
             e = hipEventElapsedTime(&a, ev[s].i0, ev[s].i1);
-            if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[s].i1, ev[s].e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[s].e0, ev[s].e1);
             tb += a;
             tw += b;
         }
@@ -409,13 +474,14 @@ lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, int32_t every, double *mai
     for (auto &x : ev) {
         if (x.i0) (void)hipEventDestroy(x.i0);
         if (x.i1) (void)hipEventDestroy(x.i1);
+        if (x.e0) (void)hipEventDestroy(x.e0);
         if (x.e1) (void)hipEventDestroy(x.e1);
     }
     if (e != hipSuccess) return hip_fail(e, "timed step");
     if (main_ms) *main_ms = tb / (double)sampled;
     if (rest_ms) *rest_ms = tw / (double)sampled;
     if (main_nodes)
-        *main_nodes = c->fuse == 2 ? lbm::step2_nodes(c->kp) : lbm::interior_nodes(c->prm.storage, c->kp);
+        *main_nodes = c->fuse == 2 ? lbm::step2_lean_nodes(c->kp) : lbm::interior_nodes(c->prm.storage, c->kp);
     if (steps_per_launch) *steps_per_launch = c->fuse;
     return LBM_OK;
 }
@@ -520,7 +586,15 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *src)
 
 void lbm_destroy(lbm_ctx *c)
 {
-    if (c && !c->in_batch) delete c;
+    if (!c || c->in_batch) return;
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_main) (void)hipEventDestroy(c->ev_main);
+    if (c->ev_side) (void)hipEventDestroy(c->ev_side);
+    delete c;
 }
 
 // ---------------------------------------------------------------------------------

@@ -44,12 +44,15 @@ hipError_t launch_nusselt(int storage, const void *src, const KParams &P, int wa
 hipError_t launch_state(int storage, void *buf, const KParams &P, double *io, bool get, hipStream_t st);
 long long residual_partials(const KParams &P);
 
-// Two time steps per pass: the main launches (every node outside the walled rows y = 0,
-// y = ny - 1, also writing the intermediate populations of rows 0-3 and ny-4..ny-1 to the
-// eight-row scratch grid described by Pm), then the walled rows from the scratch grid.
+// Two time steps per pass: the main launches (lean and full instances; together every
+// node outside the walled rows y = 0, y = ny - 1; the full one also writes the
+// intermediate populations of rows 0-3 and ny-4..ny-1 to the eight-row scratch grid
+// described by Pm), then the walled rows from the scratch grid.
 bool step2_supported(const KParams &P);
 long long step2_nodes(const KParams &P);
-hipError_t launch_step2_main(int storage, const void *src, void *dst, void *scr, const KParams &P,
+long long step2_lean_nodes(const KParams &P);   // output nodes of the lean launch
+// full = false: the wavefronts away from walls (lean code); full = true: the others.
+hipError_t launch_step2_main(int storage, bool full, const void *src, void *dst, void *scr, const KParams &P,
                              const KParams &Pm, hipStream_t st);
 hipError_t launch_step2_rows(int storage, void *dst, const void *scr, const KParams &P, const KParams &Pm,
                              hipStream_t st);

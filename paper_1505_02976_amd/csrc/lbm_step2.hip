@@ -35,6 +35,7 @@ namespace lbm {
 #define LBM_STEP2_TY 8
 #endif
 constexpr int S2_TY = LBM_STEP2_TY;   // output rows per wavefront
+
 constexpr int S2_OUT = 62;            // output columns per wavefront
 constexpr int S2_B = 256;             // threads per block (independent wavefronts)
 
@@ -239,7 +240,7 @@ k_step2_rows(const S *__restrict__ scr, S *__restrict__ dst, KParams P, KParams 
     store_node<S, M>(dst, P, x, y, f, g);
 }
 
-template <typename S>
+template <typename S, bool FULL>
 static hipError_t step2_main_t(const void *src, void *dst, void *scr, const KParams &P, const KParams &Pm,
                                hipStream_t st)
 {
@@ -247,9 +248,7 @@ static hipError_t step2_main_t(const void *src, void *dst, void *scr, const KPar
     const int ncy = (P.ny + S2_TY - 1) / S2_TY;
     const long long waves = (long long)ncx * ncy;
     const int blocks = (int)((waves + S2_B / 64 - 1) / (S2_B / 64));
-    hipLaunchKernelGGL((k_step2<S, false>), dim3(blocks), dim3(S2_B), 0, st, (const S *)src, (S *)dst, (S *)scr,
-                       P, Pm, ncx, ncy);
-    hipLaunchKernelGGL((k_step2<S, true>), dim3(blocks), dim3(S2_B), 0, st, (const S *)src, (S *)dst, (S *)scr,
+    hipLaunchKernelGGL((k_step2<S, FULL>), dim3(blocks), dim3(S2_B), 0, st, (const S *)src, (S *)dst, (S *)scr,
                        P, Pm, ncx, ncy);
     return hipGetLastError();
 }
@@ -267,14 +266,32 @@ bool step2_supported(const KParams &P) { return P.nx >= 2 * S2_OUT && P.ny >= 2 
 
 long long step2_nodes(const KParams &P) { return (long long)P.nx * (P.py ? P.ny : P.ny - 2); }
 
-hipError_t launch_step2_main(int storage, const void *src, void *dst, void *scr, const KParams &P,
+// Output nodes of the lean launch (column chunks and row bands away from walls).
+long long step2_lean_nodes(const KParams &P)
+{
+    const int ncx = (P.nx + S2_OUT - 1) / S2_OUT;
+    const int ncy = (P.ny + S2_TY - 1) / S2_TY;
+    long long n = 0;
+    for (int cy = 0; cy < ncy; ++cy)
+        for (int cx = 0; cx < ncx; ++cx)
+            if (s2_lean(P, cx, cy)) {
+                const int Y0 = cy * S2_TY, Y1 = min(Y0 + S2_TY, P.ny);
+                n += (long long)S2_OUT * (Y1 - Y0);
+            }
+    return n;
+}
+
+hipError_t launch_step2_main(int storage, bool full, const void *src, void *dst, void *scr, const KParams &P,
                              const KParams &Pm, hipStream_t st)
 {
     if (!step2_supported(P)) return hipErrorInvalidValue;
     switch (storage) {
-    case 0: return step2_main_t<double>(src, dst, scr, P, Pm, st);
-    case 1: return step2_main_t<float>(src, dst, scr, P, Pm, st);
-    case 2: return step2_main_t<__half>(src, dst, scr, P, Pm, st);
+    case 0: return full ? step2_main_t<double, true>(src, dst, scr, P, Pm, st)
+                        : step2_main_t<double, false>(src, dst, scr, P, Pm, st);
+    case 1: return full ? step2_main_t<float, true>(src, dst, scr, P, Pm, st)
+                        : step2_main_t<float, false>(src, dst, scr, P, Pm, st);
+    case 2: return full ? step2_main_t<__half, true>(src, dst, scr, P, Pm, st)
+                        : step2_main_t<__half, false>(src, dst, scr, P, Pm, st);
     default: return hipErrorInvalidValue;
     }
 }
