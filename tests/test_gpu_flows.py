@@ -97,3 +97,27 @@ def test_conduction_fixed_point(gpu, kind):
     assert np.abs(f["T"] - (0.1 + slope * y)[:, None]).max() < 1e-12
     assert np.abs(f["dTdy"] - slope).max() < 1e-12
     assert np.abs(f["dTdx"]).max() < 1e-12
+
+
+@pytest.mark.parametrize("storage,A", [("f64", 0.3), ("f64", -0.2), ("f32", 0.0)])
+def test_shear_wave_decay_clear_fluid(gpu, storage, A):
+    """Clear-fluid limit (eps = 1, Da = infinity, no Forchheimer term, no buoyancy): a shear
+    wave in a periodic 128 x 64 box decays at nu_e k^2 with nu_e = cs^2 (tau_f - A - 1/2)
+    (Sec. 3.1), as in the oracle's pin; the two-step pass runs here (nx >= 124)."""
+    n, nx, tau = 64, 128, 1.0
+    y = np.arange(n, dtype=float)
+    k = 2 * np.pi / n
+    cfg = {"nx": nx, "ny": n, "periodic_x": 1, "periodic_y": 1, "walls": [{}] * 4,
+           "Da": float("inf"), "Ra": 0.0, "F_eps": 0.0, "tau_f": tau, "tau_T": tau, "A": A, "B": 0.0,
+           "eps": 1.0, "sigma": 1.0, "T_hot": 1.0, "T_cold": 0.0, "storage": storage,
+           "ux_init": np.repeat((1e-3 * np.sin(k * y))[:, None], nx, axis=1)}
+    sim = gpu.Sim(cfg)
+    nu_e = (tau - A - 0.5) / 3.0
+    t1, t2 = int(0.1 / (nu_e * k * k)), int(0.6 / (nu_e * k * k))
+    sim.step(t1)
+    a1 = 2 / n * (sim.fields()["ux"].cpu().numpy()[:, 0] * np.sin(k * y)).sum()
+    sim.step(t2 - t1)
+    a2 = 2 / n * (sim.fields()["ux"].cpu().numpy()[:, 0] * np.sin(k * y)).sum()
+    rate = np.log(a1 / a2) / (t2 - t1) / (nu_e * k * k)
+    _say(f"  {storage} A {A}: decay rate / nu_e k^2 = {rate:.6f}")
+    assert abs(rate - 1) < 2e-3
