@@ -140,9 +140,9 @@ lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_
  * with the walled rows. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
-/* Time steps per pass, 1 or 2.  The default is 2 for FP64 and FP32 storage when
- * nx >= 124 and ny >= 16 (there the pass is faster), else 1.  LBM_ERR_UNSUPPORTED for 2
- * on smaller grids. */
+/* Time steps per pass, 1 or 2.  The default is 2 for FP64 and FP32 storage when nx >= 4
+ * and ny >= 8, else 1 (FP16 storage is faster with one step per pass).
+ * LBM_ERR_UNSUPPORTED for 2 on smaller grids. */
 lbm_status lbm_set_fusion(lbm_ctx *ctx, int32_t steps_per_pass);
 int32_t lbm_fusion(const lbm_ctx *ctx);
 

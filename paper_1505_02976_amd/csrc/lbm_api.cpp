@@ -491,7 +491,7 @@ lbm_status lbm_set_fusion(lbm_ctx *c, int32_t steps_per_pass)
     if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
     if (steps_per_pass != 1 && steps_per_pass != 2) return fail(LBM_ERR_INVALID, "steps_per_pass must be 1 or 2");
     if (steps_per_pass == 2 && !lbm::step2_supported(c->kp))
-        return fail(LBM_ERR_UNSUPPORTED, "two-step passes need nx >= 124 and ny >= 16");
+        return fail(LBM_ERR_UNSUPPORTED, "two-step passes need nx >= 4 and ny >= 8");
     c->fuse = steps_per_pass;
     return LBM_OK;
 }

@@ -108,9 +108,9 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KPa
     const int cxi = wave % ncx, cyi = wave / ncx;
     if (s2_lean(P, cxi, cyi) == FULL) return;            // the other instance's wavefront
     const int X0 = min(cxi * S2_OUT, P.nx - S2_OUT);
-    int x = X0 - 1 + lane;
+    int x = X0 - 1 + lane;                               // X0 < 0 when nx < 62
     bool xok = true;
-    if (P.px) x = (x + P.nx) % P.nx;
+    if (P.px) x = ((x % P.nx) + P.nx) % P.nx;
     else xok = x >= 0 && x < P.nx;
     const bool xout = lane >= 1 && lane <= S2_OUT && xok;
     const bool vwall = xok && !P.px && (x == 0 || x == P.nx - 1);
@@ -262,7 +262,10 @@ static hipError_t step2_rows_t(void *dst, const void *scr, const KParams &P, con
     return hipGetLastError();
 }
 
-bool step2_supported(const KParams &P) { return P.nx >= 2 * S2_OUT && P.ny >= 2 * S2_TY && P.ny >= 8; }
+// nx >= 4 (a wall column needs its two inner neighbours), ny >= 8 (the scratch grid holds
+// rows 0-3 and ny-4..ny-1 without overlap).  Grids narrower than a wavefront start their
+// only column chunk left of x = 0 (those lanes idle, or wrapped when x is periodic).
+bool step2_supported(const KParams &P) { return P.nx >= 4 && P.ny >= 8; }
 
 long long step2_nodes(const KParams &P) { return (long long)P.nx * (P.py ? P.ny : P.ny - 2); }
 

@@ -30,6 +30,13 @@ CASES = [
     (45, 150, 70, 1, 1, {"with_Q": True}),
     (46, 311, 97, 0, 0, {"eps_field": True}),
     (47, 124, 32, 0, 0, {}),
+    (48, 17, 9, 0, 0, {"moving_walls": True, "with_Q": True}),
+    (49, 40, 30, 1, 0, {"eps_field": True}),
+    (50, 64, 8, 0, 0, {}),
+    (51, 5, 12, 0, 1, {}),
+    (52, 33, 33, 1, 1, {"with_Q": True}),
+    (53, 61, 20, 0, 0, {"eps_field": True, "moving_walls": True}),
+    (54, 63, 21, 1, 0, {}),
 ]
 
 
@@ -53,7 +60,7 @@ def test_two_step_pass_is_bitwise_two_steps(gpu, storage, seed, nx, ny, px, py, 
 
 
 def test_fusion_setting(gpu):
-    small = gpu.Sim(W.random_case(48, 100, 40))
+    small = gpu.Sim(W.random_case(48, 100, 7))
     assert small.fusion == 1
     with pytest.raises(gpu.LbmError):
         small.fusion = 2
