@@ -104,20 +104,34 @@ def ensemble_run(lbm, torch, W, count=256, steps=10000, warmup=64):
     width, tune_ms = b.autotune(10)
     log(f"ensemble: autotuner chose block width {width} ({tune_ms} ms/step)")
     b.stream.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(b.stream):
-        t0.record()
-        b.step(steps)
-        t1.record()
-    t1.synchronize()
-    ms = t0.elapsed_time(t1)
+
+    def timed(n):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(b.stream):
+            t0.record()
+            b.step(n)
+            t1.record()
+        t1.synchronize()
+        return t0.elapsed_time(t1)
+
+    fusion = b.fusion
+    ms = timed(steps)
     flags = b.check()
+    one_step = None
+    if fusion == 2:
+        # the one-step batched schedule on the same states, for comparison
+        b.fusion = 1
+        n1 = max(64, steps // 5 // 64 * 64)
+        ms1 = timed(n1)
+        one_step = {"steps": n1, "mlups": nodes * n1 / (ms1 * 1e-3) / 1e6, "ms_per_step": ms1 / n1}
+        b.fusion = fusion
     res = {"workload": f"{count} porous cavities, side U{{64..512}}, Ra 10^U(3,6), Da 10^U(-4,-1), "
                        f"eps U(0.4,0.9), Pr 1, FP32 storage, seed 0",
            "nodes": nodes, "steps": steps, "mlups": nodes * steps / (ms * 1e-3) / 1e6,
            "ms_per_step": ms / steps, "GBps_algorithmic": nodes * 144 * steps / (ms * 1e-3) / 1e9,
            "nonfinite_problems": int(flags.sum()),
+           "steps_per_pass": fusion, "one_step_per_pass": one_step,
            "block_width": width, "autotune_ms_per_step": {str(k): v for k, v in tune_ms.items()}}
     b.close()
     del b

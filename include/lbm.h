@@ -192,8 +192,8 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const double *src_device);
 
 /* ---------------------------------------------------------------------------------- */
 /* Batches: many independent problems (uneven grids and parameters, one storage type)  */
-/* advanced together, one bulk and one wall launch per step for all of them, replayed  */
-/* from a HIP graph.                                                                   */
+/* advanced together: the same launches per step (or per two-step pass) for all of    */
+/* them, replayed from a HIP graph.                                                    */
 /* ---------------------------------------------------------------------------------- */
 typedef struct lbm_batch lbm_batch;
 
@@ -209,9 +209,16 @@ size_t lbm_batch_workspace_bytes(const lbm_params *params, int32_t n);
 lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, size_t workspace_bytes,
                           void *hip_stream, lbm_batch **out);
 
-/* Enqueues nsteps time steps of every problem: whole graphs of 64 steps, then single
- * steps for the remainder.  The graph is built on the first call.  Asynchronous. */
+/* Enqueues nsteps time steps of every problem: whole graphs of 64 steps, then two-step
+ * passes and single steps for the remainder.  The graph is built on the first call that
+ * needs it.  Results are bitwise those of lbm_step on each problem alone.  Asynchronous. */
 lbm_status lbm_batch_step(lbm_batch *batch, int64_t nsteps);
+
+/* Time steps per batched pass, 1 or 2 (as lbm_set_fusion, for all problems at once).  The
+ * default is 2 when the storage is FP64 or FP32 and every grid has nx >= 4 and ny >= 8,
+ * else 1; LBM_ERR_UNSUPPORTED for 2 otherwise. */
+lbm_status lbm_batch_set_fusion(lbm_batch *batch, int32_t steps_per_pass);
+int32_t lbm_batch_fusion(const lbm_batch *batch);
 
 /* Context of problem k (borrowed, valid until lbm_batch_destroy); NULL if k is out of range. */
 lbm_ctx *lbm_batch_problem(lbm_batch *batch, int32_t k);
@@ -220,7 +227,8 @@ lbm_ctx *lbm_batch_problem(lbm_batch *batch, int32_t k);
  * is NaN or infinite).  Synchronizes. */
 lbm_status lbm_batch_check(lbm_batch *batch, int32_t *nonfinite_host);
 
-/* Block-width autotuner of the batched update.  Times each candidate width (threads per
+/* Block-width autotuner of the batched one-step update (with two steps per pass it serves
+ * the single steps only).  Times each candidate width (threads per
  * block along x: 64, 128, 256, in that order) over `steps` steps and keeps the fastest for
  * later lbm_batch_step calls.  The problems' states are unchanged (the timed launches read
  * the current populations and overwrite only the buffers the next step writes anyway) and

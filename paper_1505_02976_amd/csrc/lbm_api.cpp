@@ -786,9 +786,16 @@ struct lbm_batch {
     int nbulk, nedge, nwall, nall;
     int *flags;                 // device, one per problem
     int64_t t;
+    int cur;                    // buffer (0/1) of every problem that holds the current state
+    int fuse;                   // time steps per batched pass (1, or 2: two-step passes)
+    int can_fuse;               // 1 if every problem admits the two-step pass
+    int2 *lean2, *full2, *rows2;   // item tables of the batched two-step pass
+    int nlean2, nfull2, nrows2;
     hipGraph_t graph;
     hipGraphExec_t exec;
     int graph_steps;
+    int graph_cur;              // value of cur the graph's launches assume (replays keep it)
+    int graph_fuse;
     int bx;                     // block width of the batched update
     size_t edge_cap;            // capacity of the edge item table (items)
     std::vector<lbm::BatchProblem> hp;
@@ -798,8 +805,9 @@ namespace {
 
 struct BatchLayout {
     std::vector<size_t> off;    // workspace offset of each problem
-    size_t off_probs, off_bulk, off_edge, off_wall, off_all, off_flags, total;
-    std::vector<int2> bulk, edge, wall, all;
+    size_t off_probs, off_bulk, off_edge, off_wall, off_all, off_flags, off_lean2, off_full2, off_rows2, total;
+    std::vector<int2> bulk, edge, wall, all, lean2, full2, rows2;
+    bool two;
     std::vector<lbm::KParams> kp;
     std::vector<int> tiles_x;
 };
@@ -815,6 +823,10 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
     B.edge.clear();
     B.wall.clear();
     B.all.clear();
+    B.lean2.clear();
+    B.full2.clear();
+    B.rows2.clear();
+    B.two = params[0].storage != LBM_F16;
     for (int k = 0; k < n; ++k) {
         if (params[k].storage != params[0].storage)
             return fail(LBM_ERR_INVALID, "problem %d: all problems of a batch share one storage type", k);
@@ -842,6 +854,21 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
         for (int t = 0; t < cx * kp.ny; ++t) B.all.push_back(make_int2(k, t));
         const int wb = lbm::wall_block_size();
         for (int b = 0; b < (kp.nwall_rows + wb - 1) / wb; ++b) B.wall.push_back(make_int2(k, b));
+        if (B.two && lbm::step2_supported(kp)) {
+            std::vector<int> lean, full;
+            int rb = 0;
+            lbm::step2_wave_lists(kp, lean, full, rb);
+            for (int w : lean) B.lean2.push_back(make_int2(k, w));
+            for (int w : full) B.full2.push_back(make_int2(k, w));
+            for (int r = 0; r < rb; ++r) B.rows2.push_back(make_int2(k, r));
+        } else {
+            B.two = false;
+        }
+    }
+    if (!B.two) {
+        B.lean2.clear();
+        B.full2.clear();
+        B.rows2.clear();
     }
     B.off_probs = o; o += align_up((size_t)n * sizeof(lbm::BatchProblem), 256);
     B.off_bulk = o; o += align_up(B.bulk.size() * sizeof(int2) + 8, 256);
@@ -849,42 +876,89 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
     B.off_wall = o; o += align_up(B.wall.size() * sizeof(int2) + 8, 256);
     B.off_all = o; o += align_up(B.all.size() * sizeof(int2), 256);
     B.off_flags = o; o += align_up((size_t)n * sizeof(int), 256);
+    B.off_lean2 = o; o += align_up(B.lean2.size() * sizeof(int2), 256);
+    B.off_full2 = o; o += align_up(B.full2.size() * sizeof(int2), 256);
+    B.off_rows2 = o; o += align_up(B.rows2.size() * sizeof(int2), 256);
     B.total = o;
-    if (B.all.size() > 0x7fffffff)
+    if (B.all.size() > 0x7fffffff || B.lean2.size() > 0x7fffffff)
         return fail(LBM_ERR_INVALID, "batch too large");
     return LBM_OK;
 }
 
-constexpr int GRAPH_STEPS = 64;   // even: a replay leaves the buffers in their parity
+constexpr int GRAPH_STEPS = 64;   // even, and even in two-step passes: a replay keeps `cur`
 
+hipError_t add_kernel_node(hipGraph_t g, const void *func, int grid, int threads, void **args,
+                           const std::vector<hipGraphNode_t> &deps, hipGraphNode_t *node)
+{
+    hipKernelNodeParams kp = {};
+    kp.func = const_cast<void *>(func);
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(threads);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    return hipGraphAddKernelNode(node, g, deps.empty() ? nullptr : deps.data(), deps.size(), &kp);
+}
+
+// GRAPH_STEPS steps of every problem as one graph, starting from buffer b->cur.  One-step
+// mode: per step the bulk and the wall launches, both after the previous step.  Two-step
+// mode: per pass the lean and the full launches after the previous pass, the walled-row
+// launch after the full one (it reads the scratch rows the full launch writes).
 lbm_status batch_build_graph(lbm_batch *b)
 {
-    lbm::BatchKernels K;
-    if (!lbm::batch_kernels(b->storage, b->bx, K)) return fail(LBM_ERR_INVALID, "block width %d", b->bx);
     hipError_t e = hipGraphCreate(&b->graph, 0);
     if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+    const lbm::BatchProblem *probs = b->probs;
     std::vector<hipGraphNode_t> prev;
-    for (int s = 0; s < GRAPH_STEPS && e == hipSuccess; ++s) {
-        int parity = s & 1;
-        std::vector<hipGraphNode_t> cur;
-        for (int w = 0; w < 3 && e == hipSuccess; ++w) {
-            const int nblk = w == 0 ? b->nbulk : (w == 1 ? b->nedge : b->nwall);
-            if (nblk == 0) continue;
-            const lbm::BatchProblem *probs = b->probs;
-            const int2 *items = w == 0 ? b->bulk_items : (w == 1 ? b->edge_items : b->wall_items);
-            void *args[3] = {(void *)&probs, (void *)&items, (void *)&parity};
-            hipKernelNodeParams kp = {};
-            kp.func = const_cast<void *>(w == 0 ? K.bulk : (w == 1 ? K.edge : K.wall));
-            kp.gridDim = dim3(nblk);
-            kp.blockDim = dim3(w < 2 ? K.bulk_threads : K.wall_threads);
-            kp.sharedMemBytes = 0;
-            kp.kernelParams = args;
-            kp.extra = nullptr;
-            hipGraphNode_t node;
-            e = hipGraphAddKernelNode(&node, b->graph, prev.empty() ? nullptr : prev.data(), prev.size(), &kp);
-            if (e == hipSuccess) cur.push_back(node);
+    if (b->fuse == 2) {
+        const lbm::Batch2Kernels K = lbm::batch2_kernels(b->storage);
+        const int W = K.waves_per_block;
+        for (int s = 0; s < GRAPH_STEPS / 2 && e == hipSuccess; ++s) {
+            int parity = (b->cur + s) & 1;
+            std::vector<hipGraphNode_t> cur;
+            hipGraphNode_t full = nullptr, node;
+            const int2 *lean = b->lean2, *fullv = b->full2, *rows = b->rows2;
+            int nlean = b->nlean2, nfull = b->nfull2;
+            void *al[4] = {(void *)&probs, (void *)&lean, (void *)&nlean, (void *)&parity};
+            void *af[4] = {(void *)&probs, (void *)&fullv, (void *)&nfull, (void *)&parity};
+            void *ar[3] = {(void *)&probs, (void *)&rows, (void *)&parity};
+            if (nlean > 0) {
+                e = add_kernel_node(b->graph, K.lean, (nlean + W - 1) / W, K.threads, al, prev, &node);
+                if (e == hipSuccess) cur.push_back(node);
+            }
+            if (e == hipSuccess && nfull > 0) {
+                e = add_kernel_node(b->graph, K.full, (nfull + W - 1) / W, K.threads, af, prev, &full);
+                if (e == hipSuccess) cur.push_back(full);
+            }
+            if (e == hipSuccess && b->nrows2 > 0) {
+                std::vector<hipGraphNode_t> dep = full ? std::vector<hipGraphNode_t>{full} : prev;
+                e = add_kernel_node(b->graph, K.rows, b->nrows2, 64, ar, dep, &node);
+                if (e == hipSuccess) cur.push_back(node);
+            }
+            prev.swap(cur);
         }
-        prev.swap(cur);
+    } else {
+        lbm::BatchKernels K;
+        if (!lbm::batch_kernels(b->storage, b->bx, K)) {
+            (void)hipGraphDestroy(b->graph);
+            b->graph = nullptr;
+            return fail(LBM_ERR_INVALID, "block width %d", b->bx);
+        }
+        for (int s = 0; s < GRAPH_STEPS && e == hipSuccess; ++s) {
+            int parity = (b->cur + s) & 1;
+            std::vector<hipGraphNode_t> cur;
+            for (int w = 0; w < 3 && e == hipSuccess; ++w) {
+                const int nblk = w == 0 ? b->nbulk : (w == 1 ? b->nedge : b->nwall);
+                if (nblk == 0) continue;
+                const int2 *items = w == 0 ? b->bulk_items : (w == 1 ? b->edge_items : b->wall_items);
+                void *args[3] = {(void *)&probs, (void *)&items, (void *)&parity};
+                hipGraphNode_t node;
+                e = add_kernel_node(b->graph, w == 0 ? K.bulk : (w == 1 ? K.edge : K.wall), nblk,
+                                    w < 2 ? K.bulk_threads : K.wall_threads, args, prev, &node);
+                if (e == hipSuccess) cur.push_back(node);
+            }
+            prev.swap(cur);
+        }
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -893,6 +967,8 @@ lbm_status batch_build_graph(lbm_batch *b)
         return hip_fail(e, "batch graph");
     }
     b->graph_steps = GRAPH_STEPS;
+    b->graph_cur = b->cur;
+    b->graph_fuse = b->fuse;
     return LBM_OK;
 }
 
@@ -955,9 +1031,14 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
     b->storage = params[0].storage;
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->t = 0;
+    b->cur = 0;
+    b->can_fuse = B.two ? 1 : 0;
+    b->fuse = B.two ? 2 : 1;
     b->graph = nullptr;
     b->exec = nullptr;
     b->graph_steps = 0;
+    b->graph_cur = 0;
+    b->graph_fuse = 0;
     b->bx = lbm::batch_width(0);
     b->edge_cap = B.edge.size();
     std::vector<lbm::BatchProblem> &hp = b->hp;
@@ -975,6 +1056,8 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
         hp[k].P = c->kp;
         hp[k].buf[0] = c->ws + c->lay.off_a;
         hp[k].buf[1] = c->ws + c->lay.off_b;
+        hp[k].Pm = c->kpm;
+        hp[k].scr = c->ws + c->lay.off_scr;
         hp[k].tiles_x = B.tiles_x[k];
     }
     b->probs = reinterpret_cast<lbm::BatchProblem *>(ws + B.off_probs);
@@ -987,6 +1070,12 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
     b->flags = reinterpret_cast<int *>(ws + B.off_flags);
     b->nbulk = (int)B.bulk.size();
     b->nwall = (int)B.wall.size();
+    b->lean2 = reinterpret_cast<int2 *>(ws + B.off_lean2);
+    b->full2 = reinterpret_cast<int2 *>(ws + B.off_full2);
+    b->rows2 = reinterpret_cast<int2 *>(ws + B.off_rows2);
+    b->nlean2 = (int)B.lean2.size();
+    b->nfull2 = (int)B.full2.size();
+    b->nrows2 = (int)B.rows2.size();
     hipError_t e = hipMemcpyAsync(b->probs, hp.data(), n * sizeof(lbm::BatchProblem), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && b->nbulk)
         e = hipMemcpyAsync(b->bulk_items, B.bulk.data(), B.bulk.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
@@ -996,6 +1085,12 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
         e = hipMemcpyAsync(b->wall_items, B.wall.data(), B.wall.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && b->nall)
         e = hipMemcpyAsync(b->all_items, B.all.data(), B.all.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && b->nlean2)
+        e = hipMemcpyAsync(b->lean2, B.lean2.data(), B.lean2.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && b->nfull2)
+        e = hipMemcpyAsync(b->full2, B.full2.data(), B.full2.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && b->nrows2)
+        e = hipMemcpyAsync(b->rows2, B.rows2.data(), B.rows2.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
     // the layout's host vectors are released on return: wait for the copies
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
@@ -1007,40 +1102,84 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
     return LBM_OK;
 }
 
+namespace {
+
+// One step of every problem (bulk and wall launches) from buffer b->cur.
+hipError_t batch_single(lbm_batch *b)
+{
+    hipError_t e = lbm::launch_batch_step(b->storage, b->bx, b->probs, b->bulk_items, b->nbulk, b->edge_items,
+                                          b->nedge, b->wall_items, b->nwall, b->cur, b->stream);
+    if (e == hipSuccess) {
+        ++b->t;
+        b->cur ^= 1;
+    }
+    return e;
+}
+
+// One two-step pass of every problem from buffer b->cur (the state two steps later lands
+// in the other buffer).
+hipError_t batch_pass(lbm_batch *b)
+{
+    hipError_t e = lbm::launch_batch_step2(b->storage, b->probs, b->lean2, b->nlean2, b->full2, b->nfull2,
+                                           b->rows2, b->nrows2, b->cur, b->stream);
+    if (e == hipSuccess) {
+        b->t += 2;
+        b->cur ^= 1;
+    }
+    return e;
+}
+
+}  // namespace
+
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
 {
     if (!b) return fail(LBM_ERR_INVALID, "batch is NULL");
     if (nsteps < 0) return fail(LBM_ERR_INVALID, "nsteps < 0");
-    int64_t done = 0;
+    int64_t left = nsteps;
     hipError_t e = hipSuccess;
-    // whole graphs need the current parity to be even
-    while (done < nsteps && (b->t & 1)) {
-        e = lbm::launch_batch_step(b->storage, b->bx, b->probs, b->bulk_items, b->nbulk, b->edge_items, b->nedge,
-                                   b->wall_items, b->nwall,
-                                   (int)(b->t & 1), b->stream);
+    if (b->exec && b->graph_fuse != b->fuse) batch_drop_graph(b);
+    // a graph replays from the buffer it was built for: one single step realigns `cur`
+    if (b->exec && b->cur != b->graph_cur && left > GRAPH_STEPS) {
+        e = batch_single(b);
         if (e != hipSuccess) return hip_fail(e, "batch step");
-        ++done; ++b->t;
+        --left;
     }
-    if (nsteps - done >= GRAPH_STEPS && !b->exec) {
+    if (left >= GRAPH_STEPS && !b->exec) {
         lbm_status st = batch_build_graph(b);
         if (st != LBM_OK) return st;
     }
-    while (nsteps - done >= GRAPH_STEPS) {
+    while (left >= GRAPH_STEPS && b->cur == b->graph_cur) {
         e = hipGraphLaunch(b->exec, b->stream);
         if (e != hipSuccess) return hip_fail(e, "batch graph launch");
-        done += GRAPH_STEPS;
+        left -= GRAPH_STEPS;
         b->t += GRAPH_STEPS;
     }
-    while (done < nsteps) {
-        e = lbm::launch_batch_step(b->storage, b->bx, b->probs, b->bulk_items, b->nbulk, b->edge_items, b->nedge,
-                                   b->wall_items, b->nwall,
-                                   (int)(b->t & 1), b->stream);
-        if (e != hipSuccess) return hip_fail(e, "batch step");
-        ++done; ++b->t;
+    while (b->fuse == 2 && left >= 2) {
+        e = batch_pass(b);
+        if (e != hipSuccess) return hip_fail(e, "batch pass");
+        left -= 2;
     }
-    for (lbm_ctx *c : b->ctx) { c->t = b->t; c->cur = (int)(b->t & 1); }
+    while (left > 0) {
+        e = batch_single(b);
+        if (e != hipSuccess) return hip_fail(e, "batch step");
+        --left;
+    }
+    for (lbm_ctx *c : b->ctx) { c->t = b->t; c->cur = b->cur; }
     return LBM_OK;
 }
+
+lbm_status lbm_batch_set_fusion(lbm_batch *b, int32_t steps_per_pass)
+{
+    if (!b) return fail(LBM_ERR_INVALID, "batch is NULL");
+    if (steps_per_pass != 1 && steps_per_pass != 2) return fail(LBM_ERR_INVALID, "steps per pass must be 1 or 2");
+    if (steps_per_pass == 2 && !b->can_fuse)
+        return fail(LBM_ERR_UNSUPPORTED, "two-step passes need FP32/FP64 storage and every grid at least 4 x 8 nodes");
+    if (b->fuse != steps_per_pass) batch_drop_graph(b);
+    b->fuse = steps_per_pass;
+    return LBM_OK;
+}
+
+int32_t lbm_batch_fusion(const lbm_batch *b) { return b ? b->fuse : 0; }
 
 lbm_ctx *lbm_batch_problem(lbm_batch *b, int32_t k)
 {
@@ -1054,7 +1193,7 @@ lbm_status lbm_batch_check(lbm_batch *b, int32_t *flags_host)
     const int n = (int)b->ctx.size();
     hipError_t e = hipMemsetAsync(b->flags, 0, n * sizeof(int), b->stream);
     if (e == hipSuccess)
-        e = lbm::launch_batch_check(b->storage, b->probs, b->all_items, b->nall, (int)(b->t & 1), b->flags, b->stream);
+        e = lbm::launch_batch_check(b->storage, b->probs, b->all_items, b->nall, b->cur, b->flags, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(flags_host, b->flags, n * sizeof(int), hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch check");
@@ -1067,7 +1206,7 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *width, doubl
 {
     if (!b) return fail(LBM_ERR_INVALID, "batch is NULL");
     if (steps < 1) return fail(LBM_ERR_INVALID, "steps must be >= 1");
-    const int parity = (int)(b->t & 1);
+    const int parity = b->cur;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);

@@ -1,6 +1,8 @@
 // Launchers of the HIP kernels (host side).  storage: 0 = FP64, 1 = FP32, 2 = FP16.
 #pragma once
 
+#include <vector>
+
 #include "lbm_device.h"
 
 namespace lbm {
@@ -8,8 +10,15 @@ namespace lbm {
 // One problem of a batch: its kernel parameters and its two population buffers.
 struct BatchProblem {
     KParams P;
+    KParams Pm;      // the eight-row scratch grid of the two-step pass
     void *buf[2];
+    void *scr;
     int tiles_x;
+};
+
+struct Batch2Kernels {
+    const void *lean, *full, *rows;
+    int threads, waves_per_block;
 };
 
 // Device buffers of the adjoint sweep (FP64, [18][ny][nx] for the 18-component arrays).
@@ -56,6 +65,13 @@ hipError_t launch_step2_main(int storage, bool full, const void *src, void *dst,
                              const KParams &Pm, hipStream_t st);
 hipError_t launch_step2_rows(int storage, void *dst, const void *scr, const KParams &P, const KParams &Pm,
                              hipStream_t st);
+
+// Batched two-step passes: items (problem, wavefront index) in the lean and full lists,
+// (problem, block of 64 walled-row nodes) in the rows list.
+void step2_wave_lists(const KParams &P, std::vector<int> &lean, std::vector<int> &full, int &row_blocks);
+hipError_t launch_batch_step2(int storage, const BatchProblem *probs, const int2 *lean, int nlean,
+                              const int2 *full, int nfull, const int2 *rows, int nrows, int parity, hipStream_t st);
+Batch2Kernels batch2_kernels(int storage);
 
 // Adjoint sweep.
 hipError_t launch_adjoint_step(int storage, const void *state, const KParams &P, const AdjBufs &A,

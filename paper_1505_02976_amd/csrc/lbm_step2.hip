@@ -27,6 +27,8 @@
 // copy with such writes runs at 3.3 TB/s against 5.4 aligned); the pass pays off where
 // the one-step kernel is furthest from its arithmetic limit, FP64 storage, and is the
 // default there only.
+#include <vector>
+
 #include "lbm_kernels.h"
 
 namespace lbm {
@@ -96,17 +98,12 @@ __host__ __device__ __forceinline__ bool s2_lean(const KParams &P, int cxi, int 
     return xin && yin;
 }
 
+// One wavefront's walk: column chunk cxi, row band cyi.
 template <typename S, bool FULL>
-__global__ void __launch_bounds__(S2_B)
-k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KParams P, KParams Pm,
-        int ncx, int ncy)
+__device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr,
+                                       const KParams &P, const KParams &Pm, int cxi, int cyi, int lane)
 {
     using R = typename Prec<S>::R;
-    const int wave = blockIdx.x * (S2_B / 64) + (threadIdx.x >> 6);
-    if (wave >= ncx * ncy) return;                       // wavefront-uniform
-    const int lane = threadIdx.x & 63;
-    const int cxi = wave % ncx, cyi = wave / ncx;
-    if (s2_lean(P, cxi, cyi) == FULL) return;            // the other instance's wavefront
     const int X0 = min(cxi * S2_OUT, P.nx - S2_OUT);
     int x = X0 - 1 + lane;                               // X0 < 0 when nx < 62
     bool xok = true;
@@ -217,14 +214,40 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KPa
     }
 }
 
+template <typename S, bool FULL>
+__global__ void __launch_bounds__(S2_B)
+k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KParams P, KParams Pm,
+        int ncx, int ncy)
+{
+    const int wave = blockIdx.x * (S2_B / 64) + (threadIdx.x >> 6);
+    if (wave >= ncx * ncy) return;                       // wavefront-uniform
+    const int cxi = wave % ncx, cyi = wave / ncx;
+    if (s2_lean(P, cxi, cyi) == FULL) return;            // the other instance's wavefront
+    march2<S, FULL>(src, dst, scr, P, Pm, cxi, cyi, threadIdx.x & 63);
+}
+
+// Batched: item (problem, wavefront index); the host sorts the wavefronts of every problem
+// into the lean and the full item lists.
+template <typename S, bool FULL>
+__global__ void __launch_bounds__(S2_B)
+k_batch_step2(const BatchProblem *__restrict__ probs, const int2 *__restrict__ items, int nitems, int parity)
+{
+    const int wi = blockIdx.x * (S2_B / 64) + (threadIdx.x >> 6);
+    if (wi >= nitems) return;                            // wavefront-uniform
+    const int2 it = items[wi];
+    const BatchProblem &B = probs[it.x];
+    const int ncx = (B.P.nx + S2_OUT - 1) / S2_OUT;
+    march2<S, FULL>(static_cast<const S *>(B.buf[parity]), static_cast<S *>(B.buf[parity ^ 1]),
+                    static_cast<S *>(B.scr), B.P, B.Pm, it.y % ncx, it.y / ncx, threadIdx.x & 63);
+}
+
 // Final step of the walled rows y = 0 and y = ny - 1 from the intermediate rows in the
 // scratch grid (rows 0-3 hold y = 0..3, rows 4-7 hold y = ny-4..ny-1).
 template <typename S>
-__global__ void __launch_bounds__(64)
-k_step2_rows(const S *__restrict__ scr, S *__restrict__ dst, KParams P, KParams Pm)
+__device__ __forceinline__ void rows2_node(const S *__restrict__ scr, S *__restrict__ dst, const KParams &P,
+                                           const KParams &Pm, int s)
 {
     using M = typename Prec<S>::M;
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= 2 * P.nx) return;
     const int x = s % P.nx;
     const bool top = s >= P.nx;
@@ -238,6 +261,24 @@ k_step2_rows(const S *__restrict__ scr, S *__restrict__ dst, KParams P, KParams 
     wall_from_ref<M>(P, k, x, y, eps_at<M>(P, x + w.dx, y + w.dy), eps_at<M>(P, x, y), ff, gf, Tdff, f, g);
     node_update<M, M>(f, g, P, x, y);
     store_node<S, M>(dst, P, x, y, f, g);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(64)
+k_step2_rows(const S *__restrict__ scr, S *__restrict__ dst, KParams P, KParams Pm)
+{
+    rows2_node<S>(scr, dst, P, Pm, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Batched: item (problem, block of 64 walled-row nodes).
+template <typename S>
+__global__ void __launch_bounds__(64)
+k_batch_step2_rows(const BatchProblem *__restrict__ probs, const int2 *__restrict__ items, int parity)
+{
+    const int2 it = items[blockIdx.x];
+    const BatchProblem &B = probs[it.x];
+    rows2_node<S>(static_cast<const S *>(B.scr), static_cast<S *>(B.buf[parity ^ 1]), B.P, B.Pm,
+                  it.y * 64 + threadIdx.x);
 }
 
 template <typename S, bool FULL>
@@ -308,6 +349,62 @@ hipError_t launch_step2_rows(int storage, void *dst, const void *scr, const KPar
     case 2: return step2_rows_t<__half>(dst, scr, P, Pm, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+// Wavefront indices (cyi * ncx + cxi) of a problem's lean and full wavefronts, and its
+// number of walled-row blocks of 64 nodes.
+void step2_wave_lists(const KParams &P, std::vector<int> &lean, std::vector<int> &full, int &row_blocks)
+{
+    const int ncx = (P.nx + S2_OUT - 1) / S2_OUT;
+    const int ncy = (P.ny + S2_TY - 1) / S2_TY;
+    lean.clear();
+    full.clear();
+    for (int cy = 0; cy < ncy; ++cy)
+        for (int cx = 0; cx < ncx; ++cx) (s2_lean(P, cx, cy) ? lean : full).push_back(cy * ncx + cx);
+    row_blocks = P.py ? 0 : (2 * P.nx + 63) / 64;
+}
+
+template <typename S>
+static hipError_t batch_step2_t(const BatchProblem *probs, const int2 *lean, int nlean, const int2 *full,
+                                int nfull, const int2 *rows, int nrows, int parity, hipStream_t st)
+{
+    constexpr int W = S2_B / 64;
+    if (nlean > 0)
+        hipLaunchKernelGGL((k_batch_step2<S, false>), dim3((nlean + W - 1) / W), dim3(S2_B), 0, st, probs, lean,
+                           nlean, parity);
+    if (nfull > 0)
+        hipLaunchKernelGGL((k_batch_step2<S, true>), dim3((nfull + W - 1) / W), dim3(S2_B), 0, st, probs, full,
+                           nfull, parity);
+    if (nrows > 0)
+        hipLaunchKernelGGL((k_batch_step2_rows<S>), dim3(nrows), dim3(64), 0, st, probs, rows, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step2(int storage, const BatchProblem *probs, const int2 *lean, int nlean,
+                              const int2 *full, int nfull, const int2 *rows, int nrows, int parity, hipStream_t st)
+{
+    switch (storage) {
+    case 0: return batch_step2_t<double>(probs, lean, nlean, full, nfull, rows, nrows, parity, st);
+    case 1: return batch_step2_t<float>(probs, lean, nlean, full, nfull, rows, nrows, parity, st);
+    case 2: return batch_step2_t<__half>(probs, lean, nlean, full, nfull, rows, nrows, parity, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+Batch2Kernels batch2_kernels(int storage)
+{
+    Batch2Kernels k;
+    switch (storage) {
+    case 0: k.lean = (const void *)k_batch_step2<double, false>; k.full = (const void *)k_batch_step2<double, true>;
+            k.rows = (const void *)k_batch_step2_rows<double>; break;
+    case 1: k.lean = (const void *)k_batch_step2<float, false>; k.full = (const void *)k_batch_step2<float, true>;
+            k.rows = (const void *)k_batch_step2_rows<float>; break;
+    default: k.lean = (const void *)k_batch_step2<__half, false>; k.full = (const void *)k_batch_step2<__half, true>;
+             k.rows = (const void *)k_batch_step2_rows<__half>; break;
+    }
+    k.threads = S2_B;
+    k.waves_per_block = S2_B / 64;
+    return k;
 }
 
 }  // namespace lbm

@@ -61,7 +61,7 @@ EXPORTS = ("lbm_derive", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_ste
            "lbm_set_state", "lbm_destroy", "lbm_last_error", "lbm_set_fusion", "lbm_fusion",
            "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_problem",
            "lbm_batch_check", "lbm_batch_destroy", "lbm_batch_autotune",
-           "lbm_batch_set_width",
+           "lbm_batch_set_width", "lbm_batch_set_fusion", "lbm_batch_fusion",
            "lbm_adjoint_workspace_bytes", "lbm_adjoint_forward", "lbm_adjoint_backward",
            "lbm_adjoint_destroy")
 
@@ -121,6 +121,10 @@ def lib():
     L.lbm_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     L.lbm_batch_set_width.restype = st
     L.lbm_batch_set_width.argtypes = [vp, C.c_int32]
+    L.lbm_batch_set_fusion.restype = st
+    L.lbm_batch_set_fusion.argtypes = [vp, C.c_int32]
+    L.lbm_batch_fusion.restype = C.c_int32
+    L.lbm_batch_fusion.argtypes = [vp]
     L.lbm_batch_destroy.restype = None
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_adjoint_workspace_bytes.restype = C.c_size_t
@@ -467,6 +471,15 @@ class Batch:
 
     def set_width(self, width: int):
         _check(lib().lbm_batch_set_width(self.h, int(width)))
+
+    @property
+    def fusion(self) -> int:
+        """Time steps per batched pass (1 or 2)."""
+        return int(lib().lbm_batch_fusion(self.h))
+
+    @fusion.setter
+    def fusion(self, steps_per_pass: int):
+        _check(lib().lbm_batch_set_fusion(self.h, int(steps_per_pass)))
 
     def check(self):
         """Per-problem non-finite flags (numpy int32 array)."""

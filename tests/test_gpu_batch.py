@@ -1,7 +1,7 @@
-"""Batched stepping of many problems (one bulk and one wall launch per step for all
-problems, replayed from a HIP graph of 64 steps) against the single-problem path and the
-oracle.  Graph replays are interleaved with eager work and synchronisations, and every
-replay is checked."""
+"""Batched stepping of many problems (the same launches per step, or per two-step pass,
+for all problems, replayed from a HIP graph of 64 steps) against the single-problem path
+and the oracle.  Graph replays are interleaved with eager work and synchronisations, and
+every replay is checked."""
 import numpy as np
 import pytest
 
@@ -123,3 +123,37 @@ def test_batch_block_widths_and_autotune(gpu, storage):
         assert bool((batch[k].get_state() == s.get_state()).all()), ("tuned", k)
     with pytest.raises(gpu.LbmError):
         batch.set_width(96)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_batch_two_step_passes_bitwise(gpu, storage):
+    """Two-step batched passes, graphs realigned after odd step counts and a switch of the
+    steps per pass mid-run all give bitwise the single-problem states."""
+    import torch
+    cfgs = _cases(storage) + [W.random_case(26, 4, 8, storage=storage),
+                              W.random_case(27, 70, 8, periodic_x=1, storage=storage)]
+    _say(f"case: batch of {len(cfgs)} {storage} problems, two-step passes, chunks 1/65/64/3/130")
+    batch = gpu.Batch(cfgs)
+    assert batch.fusion == 2
+    singles = [gpu.Sim(c) for c in cfgs]
+    total = 0
+    for chunk, fuse in ((1, 2), (65, 2), (64, 2), (3, 2), (130, 2), (66, 1), (64, 2)):
+        batch.fusion = fuse
+        batch.step(chunk)
+        _ = batch[0].fields()
+        for s in singles:
+            s.step(chunk)
+        total += chunk
+        torch.cuda.synchronize()
+        for k, s in enumerate(singles):
+            a, b = batch[k].get_state(), s.get_state()
+            assert bool((a == b).all()), (chunk, fuse, k, float((a - b).abs().max()))
+        assert batch[0].time == total
+    assert not batch.check().any()
+
+
+def test_batch_fp16_has_one_step_passes(gpu):
+    batch = gpu.Batch(_cases("f16")[:2])
+    assert batch.fusion == 1
+    with pytest.raises(gpu.LbmError):
+        batch.fusion = 2
