@@ -222,6 +222,7 @@ struct lbm_ctx {
     int cur;             // buffer holding the current populations (0: a, 1: b)
     int fuse;            // time steps per pass over the populations (1 or 2)
     lbm::KParams kpm;    // parameters of the eight-row scratch grid of the two-step pass
+    bool s2has[lbm::STEP2_MODES];   // which instances of the two-step pass have wavefronts
     // Second stream of the two-step pass: the wavefronts next to walls (few, long) run
     // there beside the lean launch; events order each launch after both of the previous pass.
     hipStream_t side;
@@ -301,6 +302,7 @@ static lbm_status init_ctx(const lbm_params *params, void *workspace, size_t wor
     // two-step passes by default where they are faster: FP32 and FP64 storage, whose tiles
     // match the two-step wavefronts (see lbm_step2.hip)
     c->fuse = (params->storage != LBM_F16 && lbm::step2_supported(kp)) ? 2 : 1;
+    for (int m = 0; m < lbm::STEP2_MODES; ++m) c->s2has[m] = lbm::step2_supported(kp) && lbm::step2_has(kp, m);
     e = hipMemsetAsync(c->ws + lay.off_b, 0, lay.pop_bytes, c->stream);
     if (e == hipSuccess)
         e = lbm::launch_init(params->storage, cur_buf(c), c->kp, params->T_init, params->p_init,
@@ -336,10 +338,10 @@ hipError_t ensure_side(lbm_ctx *c)
     return e;
 }
 
-// npass two-step passes.  The lean launch goes to the context's stream, the full launch and
-// the walled rows to the side stream; pass p's lean launch waits for the side stream's
-// pass p - 1, its full launch for the lean launch of pass p - 1 (both read the source and
-// write disjoint nodes of the destination).  Every wait names an event recorded earlier in
+// npass two-step passes.  The lean launch goes to the context's stream, the xwall and full
+// launches and the walled rows to the side stream; pass p's lean launch waits for the side
+// stream's pass p - 1, its xwall launch for the lean launch of pass p - 1 (the main launches
+// all read the source and write disjoint nodes of the destination).  Every wait names an event recorded earlier in
 // host order; the side stream first waits for the caller's stream and the caller's stream
 // finally waits for the side stream, so the call is ordered like launches on the caller's
 // stream.
@@ -364,11 +366,15 @@ hipError_t run_passes(lbm_ctx *c, int64_t npass, const StepEvents *tev, int ever
             if (e == hipSuccess) e = hipStreamWaitEvent(side, c->ev_main, 0);
         }
         if (e == hipSuccess && t) e = hipEventRecord(t->i0, c->stream);
-        if (e == hipSuccess) e = lbm::launch_step2_main(sto, false, src, dst, scr, c->kp, c->kpm, c->stream);
+        if (e == hipSuccess && c->s2has[lbm::STEP2_LEAN])
+            e = lbm::launch_step2_main(sto, lbm::STEP2_LEAN, src, dst, scr, c->kp, c->kpm, c->stream);
         if (e == hipSuccess && t) e = hipEventRecord(t->i1, c->stream);
         if (e == hipSuccess && LBM_STEP2_STREAMS == 2) e = hipEventRecord(c->ev_main, c->stream);
         if (e == hipSuccess && t) e = hipEventRecord(t->e0, side);
-        if (e == hipSuccess) e = lbm::launch_step2_main(sto, true, src, dst, scr, c->kp, c->kpm, side);
+        if (e == hipSuccess && c->s2has[lbm::STEP2_XWALL])
+            e = lbm::launch_step2_main(sto, lbm::STEP2_XWALL, src, dst, scr, c->kp, c->kpm, side);
+        if (e == hipSuccess && c->s2has[lbm::STEP2_FULL])
+            e = lbm::launch_step2_main(sto, lbm::STEP2_FULL, src, dst, scr, c->kp, c->kpm, side);
         if (e == hipSuccess) e = lbm::launch_step2_rows(sto, dst, scr, c->kp, c->kpm, side);
         if (e == hipSuccess && t) e = hipEventRecord(t->e1, side);
         if (e == hipSuccess && LBM_STEP2_STREAMS == 2) e = hipEventRecord(c->ev_side, side);
@@ -789,8 +795,9 @@ struct lbm_batch {
     int cur;                    // buffer (0/1) of every problem that holds the current state
     int fuse;                   // time steps per batched pass (1, or 2: two-step passes)
     int can_fuse;               // 1 if every problem admits the two-step pass
-    int2 *lean2, *full2, *rows2;   // item tables of the batched two-step pass
-    int nlean2, nfull2, nrows2;
+    int2 *items2[lbm::STEP2_MODES];   // item tables of the batched two-step pass per instance
+    int2 *rows2;
+    int nitems2[lbm::STEP2_MODES], nrows2;
     hipGraph_t graph;
     hipGraphExec_t exec;
     int graph_steps;
@@ -805,8 +812,8 @@ namespace {
 
 struct BatchLayout {
     std::vector<size_t> off;    // workspace offset of each problem
-    size_t off_probs, off_bulk, off_edge, off_wall, off_all, off_flags, off_lean2, off_full2, off_rows2, total;
-    std::vector<int2> bulk, edge, wall, all, lean2, full2, rows2;
+    size_t off_probs, off_bulk, off_edge, off_wall, off_all, off_flags, off_items2[lbm::STEP2_MODES], off_rows2, total;
+    std::vector<int2> bulk, edge, wall, all, items2[lbm::STEP2_MODES], rows2;
     bool two;
     std::vector<lbm::KParams> kp;
     std::vector<int> tiles_x;
@@ -823,8 +830,7 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
     B.edge.clear();
     B.wall.clear();
     B.all.clear();
-    B.lean2.clear();
-    B.full2.clear();
+    for (auto &v : B.items2) v.clear();
     B.rows2.clear();
     B.two = params[0].storage != LBM_F16;
     for (int k = 0; k < n; ++k) {
@@ -855,19 +861,18 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
         const int wb = lbm::wall_block_size();
         for (int b = 0; b < (kp.nwall_rows + wb - 1) / wb; ++b) B.wall.push_back(make_int2(k, b));
         if (B.two && lbm::step2_supported(kp)) {
-            std::vector<int> lean, full;
+            std::vector<int> lists[lbm::STEP2_MODES];
             int rb = 0;
-            lbm::step2_wave_lists(kp, lean, full, rb);
-            for (int w : lean) B.lean2.push_back(make_int2(k, w));
-            for (int w : full) B.full2.push_back(make_int2(k, w));
+            lbm::step2_wave_lists(kp, lists, rb);
+            for (int m = 0; m < lbm::STEP2_MODES; ++m)
+                for (int w : lists[m]) B.items2[m].push_back(make_int2(k, w));
             for (int r = 0; r < rb; ++r) B.rows2.push_back(make_int2(k, r));
         } else {
             B.two = false;
         }
     }
     if (!B.two) {
-        B.lean2.clear();
-        B.full2.clear();
+        for (auto &v : B.items2) v.clear();
         B.rows2.clear();
     }
     B.off_probs = o; o += align_up((size_t)n * sizeof(lbm::BatchProblem), 256);
@@ -876,11 +881,13 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
     B.off_wall = o; o += align_up(B.wall.size() * sizeof(int2) + 8, 256);
     B.off_all = o; o += align_up(B.all.size() * sizeof(int2), 256);
     B.off_flags = o; o += align_up((size_t)n * sizeof(int), 256);
-    B.off_lean2 = o; o += align_up(B.lean2.size() * sizeof(int2), 256);
-    B.off_full2 = o; o += align_up(B.full2.size() * sizeof(int2), 256);
+    for (int m = 0; m < lbm::STEP2_MODES; ++m) {
+        B.off_items2[m] = o;
+        o += align_up(B.items2[m].size() * sizeof(int2), 256);
+    }
     B.off_rows2 = o; o += align_up(B.rows2.size() * sizeof(int2), 256);
     B.total = o;
-    if (B.all.size() > 0x7fffffff || B.lean2.size() > 0x7fffffff)
+    if (B.all.size() > 0x7fffffff || B.items2[lbm::STEP2_LEAN].size() > 0x7fffffff)
         return fail(LBM_ERR_INVALID, "batch too large");
     return LBM_OK;
 }
@@ -902,7 +909,7 @@ hipError_t add_kernel_node(hipGraph_t g, const void *func, int grid, int threads
 
 // GRAPH_STEPS steps of every problem as one graph, starting from buffer b->cur.  One-step
 // mode: per step the bulk and the wall launches, both after the previous step.  Two-step
-// mode: per pass the lean and the full launches after the previous pass, the walled-row
+// mode: per pass the lean, xwall and full launches after the previous pass, the walled-row
 // launch after the full one (it reads the scratch rows the full launch writes).
 lbm_status batch_build_graph(lbm_batch *b)
 {
@@ -917,19 +924,22 @@ lbm_status batch_build_graph(lbm_batch *b)
             int parity = (b->cur + s) & 1;
             std::vector<hipGraphNode_t> cur;
             hipGraphNode_t full = nullptr, node;
-            const int2 *lean = b->lean2, *fullv = b->full2, *rows = b->rows2;
-            int nlean = b->nlean2, nfull = b->nfull2;
-            void *al[4] = {(void *)&probs, (void *)&lean, (void *)&nlean, (void *)&parity};
-            void *af[4] = {(void *)&probs, (void *)&fullv, (void *)&nfull, (void *)&parity};
-            void *ar[3] = {(void *)&probs, (void *)&rows, (void *)&parity};
-            if (nlean > 0) {
-                e = add_kernel_node(b->graph, K.lean, (nlean + W - 1) / W, K.threads, al, prev, &node);
+            const int2 *items[lbm::STEP2_MODES], *rows = b->rows2;
+            int nitems[lbm::STEP2_MODES];
+            void *args[lbm::STEP2_MODES][4];
+            for (int m = 0; m < lbm::STEP2_MODES && e == hipSuccess; ++m) {
+                items[m] = b->items2[m];
+                nitems[m] = b->nitems2[m];
+                if (nitems[m] == 0) continue;
+                args[m][0] = (void *)&probs;
+                args[m][1] = (void *)&items[m];
+                args[m][2] = (void *)&nitems[m];
+                args[m][3] = (void *)&parity;
+                e = add_kernel_node(b->graph, K.main[m], (nitems[m] + W - 1) / W, K.threads, args[m], prev, &node);
                 if (e == hipSuccess) cur.push_back(node);
+                if (m == lbm::STEP2_FULL) full = node;
             }
-            if (e == hipSuccess && nfull > 0) {
-                e = add_kernel_node(b->graph, K.full, (nfull + W - 1) / W, K.threads, af, prev, &full);
-                if (e == hipSuccess) cur.push_back(full);
-            }
+            void *ar[3] = {(void *)&probs, (void *)&rows, (void *)&parity};
             if (e == hipSuccess && b->nrows2 > 0) {
                 std::vector<hipGraphNode_t> dep = full ? std::vector<hipGraphNode_t>{full} : prev;
                 e = add_kernel_node(b->graph, K.rows, b->nrows2, 64, ar, dep, &node);
@@ -1070,11 +1080,11 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
     b->flags = reinterpret_cast<int *>(ws + B.off_flags);
     b->nbulk = (int)B.bulk.size();
     b->nwall = (int)B.wall.size();
-    b->lean2 = reinterpret_cast<int2 *>(ws + B.off_lean2);
-    b->full2 = reinterpret_cast<int2 *>(ws + B.off_full2);
+    for (int m = 0; m < lbm::STEP2_MODES; ++m) {
+        b->items2[m] = reinterpret_cast<int2 *>(ws + B.off_items2[m]);
+        b->nitems2[m] = (int)B.items2[m].size();
+    }
     b->rows2 = reinterpret_cast<int2 *>(ws + B.off_rows2);
-    b->nlean2 = (int)B.lean2.size();
-    b->nfull2 = (int)B.full2.size();
     b->nrows2 = (int)B.rows2.size();
     hipError_t e = hipMemcpyAsync(b->probs, hp.data(), n * sizeof(lbm::BatchProblem), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && b->nbulk)
@@ -1085,10 +1095,10 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
         e = hipMemcpyAsync(b->wall_items, B.wall.data(), B.wall.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && b->nall)
         e = hipMemcpyAsync(b->all_items, B.all.data(), B.all.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess && b->nlean2)
-        e = hipMemcpyAsync(b->lean2, B.lean2.data(), B.lean2.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess && b->nfull2)
-        e = hipMemcpyAsync(b->full2, B.full2.data(), B.full2.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
+    for (int m = 0; m < lbm::STEP2_MODES; ++m)
+        if (e == hipSuccess && b->nitems2[m])
+            e = hipMemcpyAsync(b->items2[m], B.items2[m].data(), B.items2[m].size() * sizeof(int2),
+                               hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && b->nrows2)
         e = hipMemcpyAsync(b->rows2, B.rows2.data(), B.rows2.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
     // the layout's host vectors are released on return: wait for the copies
@@ -1120,8 +1130,8 @@ hipError_t batch_single(lbm_batch *b)
 // in the other buffer).
 hipError_t batch_pass(lbm_batch *b)
 {
-    hipError_t e = lbm::launch_batch_step2(b->storage, b->probs, b->lean2, b->nlean2, b->full2, b->nfull2,
-                                           b->rows2, b->nrows2, b->cur, b->stream);
+    hipError_t e = lbm::launch_batch_step2(b->storage, b->probs, b->items2, b->nitems2, b->rows2, b->nrows2,
+                                           b->cur, b->stream);
     if (e == hipSuccess) {
         b->t += 2;
         b->cur ^= 1;

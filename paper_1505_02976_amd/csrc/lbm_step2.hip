@@ -23,10 +23,13 @@
 // bitwise identical to two one-step launches (FP16 storage rounds P1 to the stored format
 // before it is used, as the one-step path does by storing it).
 //
-// The 62-column outputs are not aligned to cache lines, which costs write bandwidth (a
-// copy with such writes runs at 3.3 TB/s against 5.4 aligned); the pass pays off where
-// the one-step kernel is furthest from its arithmetic limit, FP64 storage, and is the
-// default there only.
+// FP32 and FP64 storage use tiles of 62 columns, so every wavefront's 62 outputs fill one
+// tile segment per direction (unaligned 62-lane writes into wider tiles ran at 3.3 TB/s
+// against 5.4 aligned).  Each pass reads about 1.3 times the populations it writes (the two
+// halo columns and the two halo rows of intermediate state are recomputed) and issues
+// about 2.3 node updates per output node, so it sits near both the memory and the vector
+// issue limit; it pays off against one step per pass for FP32 and FP64 storage, not for
+// FP16, whose one-step kernel is already bound by vector issue.
 #include <vector>
 
 #include "lbm_kernels.h"
@@ -86,32 +89,85 @@ __device__ __forceinline__ void p1_node(const S *__restrict__ src, const KParams
     node_update<R, typename Prec<S>::M>(f, g, P, x, y);
 }
 
-// Whether the wavefront (column chunk cxi, row band cyi) touches no wall node, no node
-// whose intermediate state goes to the scratch grid and no row outside the grid: then it
-// runs the lean instance of the kernel, without the boundary-scheme code.
-__host__ __device__ __forceinline__ bool s2_lean(const KParams &P, int cxi, int cyi)
+// Instance that runs the wavefront of column chunk cxi and row band cyi: lean (no wall
+// node, no node whose intermediate state goes to the scratch grid, no row outside the
+// grid: no boundary-scheme code), xwall (walls x = 0 or x = nx - 1 only: the wall column's
+// intermediate rows are computed lane-parallel before the walk and its final rows after
+// it), full (everything else).
+// First output column of column chunk cxi.  Walls in x: chunks start on the 62-column
+// tiles, so that their loads and stores fill whole tile segments; the last one may reach
+// past x = nx - 1 (those lanes idle) and starts at least three columns before the wall, so
+// that the wall node's reference nodes x_f, x_ff are output lanes.  Periodic x: the last
+// chunk ends at x = nx - 1 (it may overlap its neighbour; grids narrower than 62 wrap).
+__host__ __device__ __forceinline__ int s2_x0(const KParams &P, int cxi)
 {
-    const int X0 = min(cxi * S2_OUT, P.nx - S2_OUT);
+    return P.px ? min(cxi * S2_OUT, P.nx - S2_OUT) : min(cxi * S2_OUT, P.nx - 3);
+}
+
+__host__ __device__ __forceinline__ int s2_kind(const KParams &P, int cxi, int cyi)
+{
+    const int X0 = s2_x0(P, cxi);
     const int Y0 = cyi * S2_TY, Y1 = min(Y0 + S2_TY, P.ny);
     const bool xin = P.px || (X0 - 1 >= 1 && X0 + S2_OUT <= P.nx - 2);
     const bool yin = P.py || (Y0 - 1 >= 4 && Y1 <= P.ny - 5);
-    return xin && yin;
+    return yin ? (xin ? STEP2_LEAN : STEP2_XWALL) : STEP2_FULL;
 }
 
-// One wavefront's walk: column chunk cxi, row band cyi.
-template <typename S, bool FULL>
+// LDS of one xwall wavefront: intermediate populations of the (up to two) wall columns for
+// the band's S2_TY + 2 intermediate rows, then per output row the pulled populations of
+// the wall node's reference node x_f and Td of x_ff.
+constexpr int S2_LDS_P1 = 2 * (S2_TY + 2) * 18;
+constexpr int S2_LDS = S2_LDS_P1 + 2 * S2_TY * 19;
+template <int MODE> struct S2Lds { static constexpr int n = 1; };
+template <> struct S2Lds<STEP2_XWALL> { static constexpr int n = S2_LDS; };
+
+// LDS writes of some lanes made visible to the other lanes of the wavefront.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wavefront's walk: column chunk cxi, row band cyi.  lds: S2_LDS values of the
+// wavefront's own (xwall instance only).
+template <typename S, int MODE>
 __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr,
-                                       const KParams &P, const KParams &Pm, int cxi, int cyi, int lane)
+                                       const KParams &P, const KParams &Pm, int cxi, int cyi, int lane,
+                                       typename Prec<S>::R *lds)
 {
     using R = typename Prec<S>::R;
-    const int X0 = min(cxi * S2_OUT, P.nx - S2_OUT);
-    int x = X0 - 1 + lane;                               // X0 < 0 when nx < 62
+    using M = typename Prec<S>::M;
+    constexpr bool FULL = MODE == STEP2_FULL, XW = MODE == STEP2_XWALL;
+    const int X0 = s2_x0(P, cxi);
+    int x = X0 - 1 + lane;                               // X0 < 0 when x is periodic, nx < 62
     bool xok = true;
     if (P.px) x = ((x % P.nx) + P.nx) % P.nx;
     else xok = x >= 0 && x < P.nx;
     const bool xout = lane >= 1 && lane <= S2_OUT && xok;
     const bool vwall = xok && !P.px && (x == 0 || x == P.nx - 1);
     const int Y0 = cyi * S2_TY, Y1 = min(Y0 + S2_TY, P.ny);
+    // xwall: lanes outside the grid compute on the nearest column (results unused); wl[0],
+    // wl[1] = lanes of the columns x = 0 and x = nx - 1, -1 when not in this wavefront
+    const int xs = XW ? min(max(x, 0), P.nx - 1) : x;
+    const int wl0 = XW && X0 <= 1 ? 1 - X0 : -1;
+    const int wl1 = XW && P.nx - X0 <= 63 ? P.nx - X0 : -1;
+    R *const P1w = lds, *const REF = lds + S2_LDS_P1;
+    if constexpr (XW) {
+        // intermediate populations of the wall nodes for rows Y0 - 1 .. Y1, one per lane
+        const int side = lane / (S2_TY + 2), r = lane % (S2_TY + 2);
+        const int wl = side == 0 ? wl0 : wl1;
+        const int yy = Y0 - 1 + r;
+        if (side < 2 && wl >= 0 && yy <= Y1) {
+            const int yr = P.py ? (yy + P.ny) % P.ny : yy;
+            R f[9], g[9];
+            p1_node<S, R>(src, P, side == 0 ? 0 : P.nx - 1, yr, f, g);
+            R *q = P1w + (side * (S2_TY + 2) + r) * 18;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) { q[i] = as_stored<S, R>(f[i], P); q[9 + i] = as_stored<S, R>(g[i], P); }
+        }
+        wave_sync();
+    }
 
     // kept values: U2 = (2,5,6) of P1(yy-2), U1 = (2,5,6) and C1 = (0,1,3) of P1(yy-1),
     // already shifted in x to where the final step pulls them
@@ -119,9 +175,9 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
 #pragma unroll
     for (int k = 0; k < 3; ++k) fU2[k] = gU2[k] = fU1[k] = gU1[k] = fC1[k] = gC1[k] = R(0);
 
-    constexpr bool PF = !FULL && S2Prefetch<S>::v;
+    constexpr bool PF = !FULL && S2Prefetch<S>::v;   // lean and xwall
     R nf[9], ng[9];                                      // next row, gathered ahead
-    if constexpr (PF) gather<S, R>(src, P, x, P.py ? (Y0 - 1 + P.ny) % P.ny : Y0 - 1, nf, ng);
+    if constexpr (PF) gather<S, R>(src, P, xs, P.py ? (Y0 - 1 + P.ny) % P.ny : Y0 - 1, nf, ng);
 
     for (int yy = Y0 - 1; yy <= Y1; ++yy) {
         int yr = yy;
@@ -133,13 +189,18 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
             if constexpr (PF) {
 #pragma unroll
                 for (int i = 0; i < 9; ++i) { f[i] = nf[i]; g[i] = ng[i]; }
-                if (yy < Y1) gather<S, R>(src, P, x, P.py ? (yy + 1) % P.ny : yy + 1, nf, ng);
+                if (yy < Y1) gather<S, R>(src, P, xs, P.py ? (yy + 1) % P.ny : yy + 1, nf, ng);
             } else {
-                gather<S, R>(src, P, x, yr, f, g);
+                gather<S, R>(src, P, xs, yr, f, g);
             }
-            node_update<R, typename Prec<S>::M>(f, g, P, x, yr);
+            node_update<R, M>(f, g, P, xs, yr);
 #pragma unroll
             for (int i = 0; i < 9; ++i) { f[i] = as_stored<S, R>(f[i], P); g[i] = as_stored<S, R>(g[i], P); }
+            if (XW && (lane == wl0 || lane == wl1)) {
+                const R *q = P1w + ((lane == wl0 ? 0 : 1) * (S2_TY + 2) + (yy - (Y0 - 1))) * 18;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) { f[i] = q[i]; g[i] = q[9 + i]; }
+            }
         } else if (xok && yok) {
             p1_node<S, R>(src, P, x, yr, f, g);
 #pragma unroll
@@ -197,8 +258,30 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
                                      ff, gf, Tn, pf, pg);
                 }
             }
-            if (xout) {
-                node_update<R, typename Prec<S>::M>(pf, pg, P, x, orow);
+            if constexpr (XW) {
+                // what the deferred update of the wall node needs: the pulled populations of
+                // its reference node x_f and Td of x_ff (as the full instance takes them)
+                const int r = o - Y0;
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    const int wl = side == 0 ? wl0 : wl1, dx = side == 0 ? 1 : -1;
+                    if (wl < 1 || wl > S2_OUT) continue;                  // wavefront-uniform
+                    R *q = REF + (side * S2_TY + r) * 19;
+                    if (lane == wl + dx) {
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) { q[i] = pf[i]; q[9 + i] = pg[i]; }
+                    }
+                    if (lane == wl + 2 * dx) {
+                        const Cst<R> &c = make_cst<R>(P);
+                        R sg = R(0);
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) sg += pg[i];
+                        q[18] = (sg + c.halfQ) * c.isig;
+                    }
+                }
+            }
+            if (xout && !(XW && vwall)) {
+                node_update<R, M>(pf, pg, P, x, orow);
                 store_node<S, R>(dst, P, x, orow, pf, pg);
             }
         }
@@ -212,33 +295,74 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
         fC1[1] = f[1]; gC1[1] = g[1];
         fC1[2] = f[3]; gC1[2] = g[3];
     }
+    if constexpr (XW) {
+        // final step of the wall nodes of the output rows, one per lane
+        wave_sync();
+        const int side = lane / S2_TY, r = lane % S2_TY;
+        const int wl = side == 0 ? wl0 : wl1;
+        const int o = Y0 + r;
+        if (side < 2 && wl >= 1 && wl <= S2_OUT && o < Y1) {
+            const int orow = P.py ? (o + P.ny) % P.ny : o;
+            const int xw = side == 0 ? 0 : P.nx - 1, dx = side == 0 ? 1 : -1;
+            const R *q = REF + (side * S2_TY + r) * 19;
+            R ff[9], gf[9], pf[9], pg[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) { ff[i] = q[i]; gf[i] = q[9 + i]; }
+            const Cst<R> &c = make_cst<R>(P);
+            const R Tn = thermal_dirichlet_wall(P, wall_info(P, xw, orow)) < 0 ? q[18] : R(0);
+            wall_from_ref<R>(P, c, xw, orow, eps_at<R>(P, xw + dx, orow), eps_at<R>(P, xw, orow), ff, gf, Tn,
+                             pf, pg);
+            node_update<R, M>(pf, pg, P, xw, orow);
+            store_node<S, R>(dst, P, xw, orow, pf, pg);
+        }
+    }
 }
 
-template <typename S, bool FULL>
+#ifndef LBM_STEP2_XCD
+#define LBM_STEP2_XCD 1
+#endif
+// Logical block of dispatched block b out of nb: blocks are dealt round-robin to the eight
+// XCDs, each with its own L2; this hands every XCD one contiguous range of logical blocks,
+// so that the neighbouring wavefronts whose halo columns and rows overlap share an L2.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    if (!LBM_STEP2_XCD) return b;
+    constexpr int X = 8;
+    const int per = nb / X, rem = nb % X;
+    const int x = b % X, i = b / X;
+    return x * per + min(x, rem) + i;
+}
+
+template <typename S, int MODE>
 __global__ void __launch_bounds__(S2_B)
 k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KParams P, KParams Pm,
         int ncx, int ncy)
 {
-    const int wave = blockIdx.x * (S2_B / 64) + (threadIdx.x >> 6);
+    using R = typename Prec<S>::R;
+    __shared__ R lds[S2_B / 64][S2Lds<MODE>::n];
+    const int wave = xcd_block(blockIdx.x, gridDim.x) * (S2_B / 64) + (threadIdx.x >> 6);
     if (wave >= ncx * ncy) return;                       // wavefront-uniform
     const int cxi = wave % ncx, cyi = wave / ncx;
-    if (s2_lean(P, cxi, cyi) == FULL) return;            // the other instance's wavefront
-    march2<S, FULL>(src, dst, scr, P, Pm, cxi, cyi, threadIdx.x & 63);
+    if (s2_kind(P, cxi, cyi) != MODE) return;            // another instance's wavefront
+    march2<S, MODE>(src, dst, scr, P, Pm, cxi, cyi, threadIdx.x & 63, lds[threadIdx.x >> 6]);
 }
 
 // Batched: item (problem, wavefront index); the host sorts the wavefronts of every problem
-// into the lean and the full item lists.
-template <typename S, bool FULL>
+// into one item list per instance.
+template <typename S, int MODE>
 __global__ void __launch_bounds__(S2_B)
 k_batch_step2(const BatchProblem *__restrict__ probs, const int2 *__restrict__ items, int nitems, int parity)
 {
-    const int wi = blockIdx.x * (S2_B / 64) + (threadIdx.x >> 6);
+    using R = typename Prec<S>::R;
+    __shared__ R lds[S2_B / 64][S2Lds<MODE>::n];
+    const int wi = xcd_block(blockIdx.x, gridDim.x) * (S2_B / 64) + (threadIdx.x >> 6);
     if (wi >= nitems) return;                            // wavefront-uniform
     const int2 it = items[wi];
     const BatchProblem &B = probs[it.x];
     const int ncx = (B.P.nx + S2_OUT - 1) / S2_OUT;
-    march2<S, FULL>(static_cast<const S *>(B.buf[parity]), static_cast<S *>(B.buf[parity ^ 1]),
-                    static_cast<S *>(B.scr), B.P, B.Pm, it.y % ncx, it.y / ncx, threadIdx.x & 63);
+    march2<S, MODE>(static_cast<const S *>(B.buf[parity]), static_cast<S *>(B.buf[parity ^ 1]),
+                    static_cast<S *>(B.scr), B.P, B.Pm, it.y % ncx, it.y / ncx, threadIdx.x & 63,
+                    lds[threadIdx.x >> 6]);
 }
 
 // Final step of the walled rows y = 0 and y = ny - 1 from the intermediate rows in the
@@ -281,7 +405,7 @@ k_batch_step2_rows(const BatchProblem *__restrict__ probs, const int2 *__restric
                   it.y * 64 + threadIdx.x);
 }
 
-template <typename S, bool FULL>
+template <typename S, int MODE>
 static hipError_t step2_main_t(const void *src, void *dst, void *scr, const KParams &P, const KParams &Pm,
                                hipStream_t st)
 {
@@ -289,7 +413,7 @@ static hipError_t step2_main_t(const void *src, void *dst, void *scr, const KPar
     const int ncy = (P.ny + S2_TY - 1) / S2_TY;
     const long long waves = (long long)ncx * ncy;
     const int blocks = (int)((waves + S2_B / 64 - 1) / (S2_B / 64));
-    hipLaunchKernelGGL((k_step2<S, FULL>), dim3(blocks), dim3(S2_B), 0, st, (const S *)src, (S *)dst, (S *)scr,
+    hipLaunchKernelGGL((k_step2<S, MODE>), dim3(blocks), dim3(S2_B), 0, st, (const S *)src, (S *)dst, (S *)scr,
                        P, Pm, ncx, ncy);
     return hipGetLastError();
 }
@@ -304,8 +428,9 @@ static hipError_t step2_rows_t(void *dst, const void *scr, const KParams &P, con
 }
 
 // nx >= 4 (a wall column needs its two inner neighbours), ny >= 8 (the scratch grid holds
-// rows 0-3 and ny-4..ny-1 without overlap).  Grids narrower than a wavefront start their
-// only column chunk left of x = 0 (those lanes idle, or wrapped when x is periodic).
+// rows 0-3 and ny-4..ny-1 without overlap).  Grids narrower than a wavefront have one
+// column chunk: from x = 0 with lanes past the wall x = nx - 1 idle, or, periodic in x,
+// starting left of x = 0 with the lanes wrapped.
 bool step2_supported(const KParams &P) { return P.nx >= 4 && P.ny >= 8; }
 
 long long step2_nodes(const KParams &P) { return (long long)P.nx * (P.py ? P.ny : P.ny - 2); }
@@ -318,24 +443,43 @@ long long step2_lean_nodes(const KParams &P)
     long long n = 0;
     for (int cy = 0; cy < ncy; ++cy)
         for (int cx = 0; cx < ncx; ++cx)
-            if (s2_lean(P, cx, cy)) {
+            if (s2_kind(P, cx, cy) == STEP2_LEAN) {
                 const int Y0 = cy * S2_TY, Y1 = min(Y0 + S2_TY, P.ny);
                 n += (long long)S2_OUT * (Y1 - Y0);
             }
     return n;
 }
 
-hipError_t launch_step2_main(int storage, bool full, const void *src, void *dst, void *scr, const KParams &P,
+template <typename S>
+static hipError_t step2_main_s(int mode, const void *src, void *dst, void *scr, const KParams &P,
+                               const KParams &Pm, hipStream_t st)
+{
+    switch (mode) {
+    case STEP2_LEAN: return step2_main_t<S, STEP2_LEAN>(src, dst, scr, P, Pm, st);
+    case STEP2_FULL: return step2_main_t<S, STEP2_FULL>(src, dst, scr, P, Pm, st);
+    case STEP2_XWALL: return step2_main_t<S, STEP2_XWALL>(src, dst, scr, P, Pm, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+bool step2_has(const KParams &P, int mode)
+{
+    const int ncx = (P.nx + S2_OUT - 1) / S2_OUT;
+    const int ncy = (P.ny + S2_TY - 1) / S2_TY;
+    for (int cy = 0; cy < ncy; ++cy)
+        for (int cx = 0; cx < ncx; ++cx)
+            if (s2_kind(P, cx, cy) == mode) return true;
+    return false;
+}
+
+hipError_t launch_step2_main(int storage, int mode, const void *src, void *dst, void *scr, const KParams &P,
                              const KParams &Pm, hipStream_t st)
 {
     if (!step2_supported(P)) return hipErrorInvalidValue;
     switch (storage) {
-    case 0: return full ? step2_main_t<double, true>(src, dst, scr, P, Pm, st)
-                        : step2_main_t<double, false>(src, dst, scr, P, Pm, st);
-    case 1: return full ? step2_main_t<float, true>(src, dst, scr, P, Pm, st)
-                        : step2_main_t<float, false>(src, dst, scr, P, Pm, st);
-    case 2: return full ? step2_main_t<__half, true>(src, dst, scr, P, Pm, st)
-                        : step2_main_t<__half, false>(src, dst, scr, P, Pm, st);
+    case 0: return step2_main_s<double>(mode, src, dst, scr, P, Pm, st);
+    case 1: return step2_main_s<float>(mode, src, dst, scr, P, Pm, st);
+    case 2: return step2_main_s<__half>(mode, src, dst, scr, P, Pm, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -351,60 +495,67 @@ hipError_t launch_step2_rows(int storage, void *dst, const void *scr, const KPar
     }
 }
 
-// Wavefront indices (cyi * ncx + cxi) of a problem's lean and full wavefronts, and its
-// number of walled-row blocks of 64 nodes.
-void step2_wave_lists(const KParams &P, std::vector<int> &lean, std::vector<int> &full, int &row_blocks)
+// Wavefront indices (cyi * ncx + cxi) of a problem's wavefronts per instance (lean, full,
+// xwall), and its number of walled-row blocks of 64 nodes.
+void step2_wave_lists(const KParams &P, std::vector<int> (&lists)[3], int &row_blocks)
 {
     const int ncx = (P.nx + S2_OUT - 1) / S2_OUT;
     const int ncy = (P.ny + S2_TY - 1) / S2_TY;
-    lean.clear();
-    full.clear();
+    for (auto &l : lists) l.clear();
     for (int cy = 0; cy < ncy; ++cy)
-        for (int cx = 0; cx < ncx; ++cx) (s2_lean(P, cx, cy) ? lean : full).push_back(cy * ncx + cx);
+        for (int cx = 0; cx < ncx; ++cx) lists[s2_kind(P, cx, cy)].push_back(cy * ncx + cx);
     row_blocks = P.py ? 0 : (2 * P.nx + 63) / 64;
 }
 
 template <typename S>
-static hipError_t batch_step2_t(const BatchProblem *probs, const int2 *lean, int nlean, const int2 *full,
-                                int nfull, const int2 *rows, int nrows, int parity, hipStream_t st)
+static hipError_t batch_step2_t(const BatchProblem *probs, const int2 *const *items, const int *nitems,
+                                const int2 *rows, int nrows, int parity, hipStream_t st)
 {
     constexpr int W = S2_B / 64;
-    if (nlean > 0)
-        hipLaunchKernelGGL((k_batch_step2<S, false>), dim3((nlean + W - 1) / W), dim3(S2_B), 0, st, probs, lean,
-                           nlean, parity);
-    if (nfull > 0)
-        hipLaunchKernelGGL((k_batch_step2<S, true>), dim3((nfull + W - 1) / W), dim3(S2_B), 0, st, probs, full,
-                           nfull, parity);
+    if (nitems[STEP2_LEAN] > 0)
+        hipLaunchKernelGGL((k_batch_step2<S, STEP2_LEAN>), dim3((nitems[STEP2_LEAN] + W - 1) / W), dim3(S2_B), 0, st,
+                           probs, items[STEP2_LEAN], nitems[STEP2_LEAN], parity);
+    if (nitems[STEP2_XWALL] > 0)
+        hipLaunchKernelGGL((k_batch_step2<S, STEP2_XWALL>), dim3((nitems[STEP2_XWALL] + W - 1) / W), dim3(S2_B), 0, st,
+                           probs, items[STEP2_XWALL], nitems[STEP2_XWALL], parity);
+    if (nitems[STEP2_FULL] > 0)
+        hipLaunchKernelGGL((k_batch_step2<S, STEP2_FULL>), dim3((nitems[STEP2_FULL] + W - 1) / W), dim3(S2_B), 0, st,
+                           probs, items[STEP2_FULL], nitems[STEP2_FULL], parity);
     if (nrows > 0)
         hipLaunchKernelGGL((k_batch_step2_rows<S>), dim3(nrows), dim3(64), 0, st, probs, rows, parity);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_step2(int storage, const BatchProblem *probs, const int2 *lean, int nlean,
-                              const int2 *full, int nfull, const int2 *rows, int nrows, int parity, hipStream_t st)
+hipError_t launch_batch_step2(int storage, const BatchProblem *probs, const int2 *const *items, const int *nitems,
+                              const int2 *rows, int nrows, int parity, hipStream_t st)
 {
     switch (storage) {
-    case 0: return batch_step2_t<double>(probs, lean, nlean, full, nfull, rows, nrows, parity, st);
-    case 1: return batch_step2_t<float>(probs, lean, nlean, full, nfull, rows, nrows, parity, st);
-    case 2: return batch_step2_t<__half>(probs, lean, nlean, full, nfull, rows, nrows, parity, st);
+    case 0: return batch_step2_t<double>(probs, items, nitems, rows, nrows, parity, st);
+    case 1: return batch_step2_t<float>(probs, items, nitems, rows, nrows, parity, st);
+    case 2: return batch_step2_t<__half>(probs, items, nitems, rows, nrows, parity, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-Batch2Kernels batch2_kernels(int storage)
+template <typename S> static Batch2Kernels batch2_kernels_t()
 {
     Batch2Kernels k;
-    switch (storage) {
-    case 0: k.lean = (const void *)k_batch_step2<double, false>; k.full = (const void *)k_batch_step2<double, true>;
-            k.rows = (const void *)k_batch_step2_rows<double>; break;
-    case 1: k.lean = (const void *)k_batch_step2<float, false>; k.full = (const void *)k_batch_step2<float, true>;
-            k.rows = (const void *)k_batch_step2_rows<float>; break;
-    default: k.lean = (const void *)k_batch_step2<__half, false>; k.full = (const void *)k_batch_step2<__half, true>;
-             k.rows = (const void *)k_batch_step2_rows<__half>; break;
-    }
+    k.main[STEP2_LEAN] = (const void *)k_batch_step2<S, STEP2_LEAN>;
+    k.main[STEP2_FULL] = (const void *)k_batch_step2<S, STEP2_FULL>;
+    k.main[STEP2_XWALL] = (const void *)k_batch_step2<S, STEP2_XWALL>;
+    k.rows = (const void *)k_batch_step2_rows<S>;
     k.threads = S2_B;
     k.waves_per_block = S2_B / 64;
     return k;
+}
+
+Batch2Kernels batch2_kernels(int storage)
+{
+    switch (storage) {
+    case 0: return batch2_kernels_t<double>();
+    case 1: return batch2_kernels_t<float>();
+    default: return batch2_kernels_t<__half>();
+    }
 }
 
 }  // namespace lbm
