@@ -89,7 +89,7 @@ struct Layout {
     int pitch, ntx;
     long long plane;
     size_t pop_bytes;     // one population buffer
-    size_t off_a, off_b, off_eps, off_snap, off_part, off_scalar, off_scr, total;
+    size_t off_a, off_b, off_eps, off_snap, off_part, off_scalar, off_scr, off_items, total;
     long long plane_scr;  // plane size of the eight-row scratch grid (plane layout)
     long long nparts;
 };
@@ -132,6 +132,8 @@ Layout layout(const lbm_params *p, const lbm::KParams &kp)
         scr = align_up((size_t)L.plane_scr * 18 * es, 256);
     }
     L.off_scr = o; o += scr;
+    // wavefront lists of the two-step pass's launches
+    L.off_items = o; o += align_up(lbm::step2_supported(kp) ? (size_t)lbm::step2_waves(kp) * sizeof(int) : 0, 256);
     L.total = o;
     return L;
 }
@@ -222,7 +224,8 @@ struct lbm_ctx {
     int cur;             // buffer holding the current populations (0: a, 1: b)
     int fuse;            // time steps per pass over the populations (1 or 2)
     lbm::KParams kpm;    // parameters of the eight-row scratch grid of the two-step pass
-    bool s2has[lbm::STEP2_MODES];   // which instances of the two-step pass have wavefronts
+    int n_main2, n_full2;       // wavefronts of the two-step pass's main and full launches
+    long long main_nodes2;      // output nodes of the main launch
     // Second stream of the two-step pass: the wavefronts next to walls (few, long) run
     // there beside the lean launch; events order each launch after both of the previous pass.
     hipStream_t side;
@@ -302,7 +305,21 @@ static lbm_status init_ctx(const lbm_params *params, void *workspace, size_t wor
     // two-step passes by default where they are faster: FP32 and FP64 storage, whose tiles
     // match the two-step wavefronts (see lbm_step2.hip)
     c->fuse = (params->storage != LBM_F16 && lbm::step2_supported(kp)) ? 2 : 1;
-    for (int m = 0; m < lbm::STEP2_MODES; ++m) c->s2has[m] = lbm::step2_supported(kp) && lbm::step2_has(kp, m);
+    c->n_main2 = c->n_full2 = 0;
+    c->main_nodes2 = 0;
+    if (lbm::step2_supported(kp)) {
+        std::vector<int> mainv, fullv;
+        int rb = 0;
+        lbm::step2_lists(kp, mainv, fullv, rb, c->main_nodes2);
+        c->n_main2 = (int)mainv.size();
+        c->n_full2 = (int)fullv.size();
+        mainv.insert(mainv.end(), fullv.begin(), fullv.end());
+        e = hipMemcpyAsync(c->ws + lay.off_items, mainv.data(), mainv.size() * sizeof(int), hipMemcpyHostToDevice,
+                           c->stream);
+        // the host list is released on return
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) { delete c; return hip_fail(e, "two-step wavefront lists"); }
+    }
     e = hipMemsetAsync(c->ws + lay.off_b, 0, lay.pop_bytes, c->stream);
     if (e == hipSuccess)
         e = lbm::launch_init(params->storage, cur_buf(c), c->kp, params->T_init, params->p_init,
@@ -338,10 +355,11 @@ hipError_t ensure_side(lbm_ctx *c)
     return e;
 }
 
-// npass two-step passes.  The lean launch goes to the context's stream, the xwall and full
-// launches and the walled rows to the side stream; pass p's lean launch waits for the side
-// stream's pass p - 1, its xwall launch for the lean launch of pass p - 1 (the main launches
-// all read the source and write disjoint nodes of the destination).  Every wait names an event recorded earlier in
+// npass two-step passes.  The main launch (lean and xwall wavefronts) goes to the context's
+// stream; the full launch and the walled rows (which read the scratch rows the full launch
+// writes) go to the side stream; pass p's main launch waits for the side stream's pass
+// p - 1, its full launch for the main launch of pass p - 1 (both read the source and write
+// disjoint nodes of the destination).  Every wait names an event recorded earlier in
 // host order; the side stream first waits for the caller's stream and the caller's stream
 // finally waits for the side stream, so the call is ordered like launches on the caller's
 // stream.
@@ -349,6 +367,7 @@ hipError_t run_passes(lbm_ctx *c, int64_t npass, const StepEvents *tev, int ever
 {
     const int sto = c->prm.storage;
     void *scr = c->ws + c->lay.off_scr;
+    const int *items = reinterpret_cast<const int *>(c->ws + c->lay.off_items);
     hipStream_t side = LBM_STEP2_STREAMS == 2 ? c->side : c->stream;
     hipError_t e = hipSuccess;
     if (LBM_STEP2_STREAMS == 2) {
@@ -365,19 +384,21 @@ hipError_t run_passes(lbm_ctx *c, int64_t npass, const StepEvents *tev, int ever
             e = hipStreamWaitEvent(c->stream, c->ev_side, 0);
             if (e == hipSuccess) e = hipStreamWaitEvent(side, c->ev_main, 0);
         }
-        if (e == hipSuccess && t) e = hipEventRecord(t->i0, c->stream);
-        if (e == hipSuccess && c->s2has[lbm::STEP2_LEAN])
-            e = lbm::launch_step2_main(sto, lbm::STEP2_LEAN, src, dst, scr, c->kp, c->kpm, c->stream);
-        if (e == hipSuccess && t) e = hipEventRecord(t->i1, c->stream);
-        if (e == hipSuccess && LBM_STEP2_STREAMS == 2) e = hipEventRecord(c->ev_main, c->stream);
+        // the side stream's launches are issued first so that their few wavefronts are
+        // dispatched beside the main launch's first ones rather than after its last ones
         if (e == hipSuccess && t) e = hipEventRecord(t->e0, side);
-        if (e == hipSuccess && c->s2has[lbm::STEP2_XWALL])
-            e = lbm::launch_step2_main(sto, lbm::STEP2_XWALL, src, dst, scr, c->kp, c->kpm, side);
-        if (e == hipSuccess && c->s2has[lbm::STEP2_FULL])
-            e = lbm::launch_step2_main(sto, lbm::STEP2_FULL, src, dst, scr, c->kp, c->kpm, side);
+        if (e == hipSuccess)
+            e = lbm::launch_step2_main(sto, lbm::STEP2_FULL, src, dst, scr, c->kp, c->kpm, items + c->n_main2,
+                                       c->n_full2, side);
         if (e == hipSuccess) e = lbm::launch_step2_rows(sto, dst, scr, c->kp, c->kpm, side);
         if (e == hipSuccess && t) e = hipEventRecord(t->e1, side);
         if (e == hipSuccess && LBM_STEP2_STREAMS == 2) e = hipEventRecord(c->ev_side, side);
+        if (e == hipSuccess && t) e = hipEventRecord(t->i0, c->stream);
+        if (e == hipSuccess)
+            e = lbm::launch_step2_main(sto, lbm::STEP2_MAIN, src, dst, scr, c->kp, c->kpm, items, c->n_main2,
+                                       c->stream);
+        if (e == hipSuccess && t) e = hipEventRecord(t->i1, c->stream);
+        if (e == hipSuccess && LBM_STEP2_STREAMS == 2) e = hipEventRecord(c->ev_main, c->stream);
         if (e == hipSuccess) {
             c->t += 2;
             c->cur ^= 1;
@@ -487,7 +508,7 @@ lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, int32_t every, double *mai
     if (main_ms) *main_ms = tb / (double)sampled;
     if (rest_ms) *rest_ms = tw / (double)sampled;
     if (main_nodes)
-        *main_nodes = c->fuse == 2 ? lbm::step2_lean_nodes(c->kp) : lbm::interior_nodes(c->prm.storage, c->kp);
+        *main_nodes = c->fuse == 2 ? c->main_nodes2 : lbm::interior_nodes(c->prm.storage, c->kp);
     if (steps_per_launch) *steps_per_launch = c->fuse;
     return LBM_OK;
 }
@@ -795,9 +816,9 @@ struct lbm_batch {
     int cur;                    // buffer (0/1) of every problem that holds the current state
     int fuse;                   // time steps per batched pass (1, or 2: two-step passes)
     int can_fuse;               // 1 if every problem admits the two-step pass
-    int2 *items2[lbm::STEP2_MODES];   // item tables of the batched two-step pass per instance
+    int2 *items2[lbm::STEP2_LAUNCHES];   // item tables of the batched two-step pass per launch
     int2 *rows2;
-    int nitems2[lbm::STEP2_MODES], nrows2;
+    int nitems2[lbm::STEP2_LAUNCHES], nrows2;
     hipGraph_t graph;
     hipGraphExec_t exec;
     int graph_steps;
@@ -812,8 +833,8 @@ namespace {
 
 struct BatchLayout {
     std::vector<size_t> off;    // workspace offset of each problem
-    size_t off_probs, off_bulk, off_edge, off_wall, off_all, off_flags, off_items2[lbm::STEP2_MODES], off_rows2, total;
-    std::vector<int2> bulk, edge, wall, all, items2[lbm::STEP2_MODES], rows2;
+    size_t off_probs, off_bulk, off_edge, off_wall, off_all, off_flags, off_items2[lbm::STEP2_LAUNCHES], off_rows2, total;
+    std::vector<int2> bulk, edge, wall, all, items2[lbm::STEP2_LAUNCHES], rows2;
     bool two;
     std::vector<lbm::KParams> kp;
     std::vector<int> tiles_x;
@@ -861,11 +882,12 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
         const int wb = lbm::wall_block_size();
         for (int b = 0; b < (kp.nwall_rows + wb - 1) / wb; ++b) B.wall.push_back(make_int2(k, b));
         if (B.two && lbm::step2_supported(kp)) {
-            std::vector<int> lists[lbm::STEP2_MODES];
+            std::vector<int> lists[lbm::STEP2_LAUNCHES];
             int rb = 0;
-            lbm::step2_wave_lists(kp, lists, rb);
-            for (int m = 0; m < lbm::STEP2_MODES; ++m)
-                for (int w : lists[m]) B.items2[m].push_back(make_int2(k, w));
+            long long mn = 0;
+            lbm::step2_lists(kp, lists[lbm::STEP2_MAIN], lists[lbm::STEP2_FULL], rb, mn);
+            for (int l = 0; l < lbm::STEP2_LAUNCHES; ++l)
+                for (int w : lists[l]) B.items2[l].push_back(make_int2(k, w));
             for (int r = 0; r < rb; ++r) B.rows2.push_back(make_int2(k, r));
         } else {
             B.two = false;
@@ -881,13 +903,13 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
     B.off_wall = o; o += align_up(B.wall.size() * sizeof(int2) + 8, 256);
     B.off_all = o; o += align_up(B.all.size() * sizeof(int2), 256);
     B.off_flags = o; o += align_up((size_t)n * sizeof(int), 256);
-    for (int m = 0; m < lbm::STEP2_MODES; ++m) {
-        B.off_items2[m] = o;
-        o += align_up(B.items2[m].size() * sizeof(int2), 256);
+    for (int l = 0; l < lbm::STEP2_LAUNCHES; ++l) {
+        B.off_items2[l] = o;
+        o += align_up(B.items2[l].size() * sizeof(int2), 256);
     }
     B.off_rows2 = o; o += align_up(B.rows2.size() * sizeof(int2), 256);
     B.total = o;
-    if (B.all.size() > 0x7fffffff || B.items2[lbm::STEP2_LEAN].size() > 0x7fffffff)
+    if (B.all.size() > 0x7fffffff || B.items2[lbm::STEP2_MAIN].size() > 0x7fffffff)
         return fail(LBM_ERR_INVALID, "batch too large");
     return LBM_OK;
 }
@@ -909,7 +931,7 @@ hipError_t add_kernel_node(hipGraph_t g, const void *func, int grid, int threads
 
 // GRAPH_STEPS steps of every problem as one graph, starting from buffer b->cur.  One-step
 // mode: per step the bulk and the wall launches, both after the previous step.  Two-step
-// mode: per pass the lean, xwall and full launches after the previous pass, the walled-row
+// mode: per pass the full and main launches after the previous pass, the walled-row
 // launch after the full one (it reads the scratch rows the full launch writes).
 lbm_status batch_build_graph(lbm_batch *b)
 {
@@ -924,10 +946,13 @@ lbm_status batch_build_graph(lbm_batch *b)
             int parity = (b->cur + s) & 1;
             std::vector<hipGraphNode_t> cur;
             hipGraphNode_t full = nullptr, node;
-            const int2 *items[lbm::STEP2_MODES], *rows = b->rows2;
-            int nitems[lbm::STEP2_MODES];
-            void *args[lbm::STEP2_MODES][4];
-            for (int m = 0; m < lbm::STEP2_MODES && e == hipSuccess; ++m) {
+            const int2 *items[lbm::STEP2_LAUNCHES], *rows = b->rows2;
+            int nitems[lbm::STEP2_LAUNCHES];
+            void *args[lbm::STEP2_LAUNCHES][4];
+            // the full launch first: its few wavefronts then start beside the main ones
+            const int order[lbm::STEP2_LAUNCHES] = {lbm::STEP2_FULL, lbm::STEP2_MAIN};
+            for (int m : order) {
+                if (e != hipSuccess) break;
                 items[m] = b->items2[m];
                 nitems[m] = b->nitems2[m];
                 if (nitems[m] == 0) continue;
@@ -1080,9 +1105,9 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
     b->flags = reinterpret_cast<int *>(ws + B.off_flags);
     b->nbulk = (int)B.bulk.size();
     b->nwall = (int)B.wall.size();
-    for (int m = 0; m < lbm::STEP2_MODES; ++m) {
-        b->items2[m] = reinterpret_cast<int2 *>(ws + B.off_items2[m]);
-        b->nitems2[m] = (int)B.items2[m].size();
+    for (int l = 0; l < lbm::STEP2_LAUNCHES; ++l) {
+        b->items2[l] = reinterpret_cast<int2 *>(ws + B.off_items2[l]);
+        b->nitems2[l] = (int)B.items2[l].size();
     }
     b->rows2 = reinterpret_cast<int2 *>(ws + B.off_rows2);
     b->nrows2 = (int)B.rows2.size();
@@ -1095,9 +1120,9 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
         e = hipMemcpyAsync(b->wall_items, B.wall.data(), B.wall.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && b->nall)
         e = hipMemcpyAsync(b->all_items, B.all.data(), B.all.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
-    for (int m = 0; m < lbm::STEP2_MODES; ++m)
-        if (e == hipSuccess && b->nitems2[m])
-            e = hipMemcpyAsync(b->items2[m], B.items2[m].data(), B.items2[m].size() * sizeof(int2),
+    for (int l = 0; l < lbm::STEP2_LAUNCHES; ++l)
+        if (e == hipSuccess && b->nitems2[l])
+            e = hipMemcpyAsync(b->items2[l], B.items2[l].data(), B.items2[l].size() * sizeof(int2),
                                hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && b->nrows2)
         e = hipMemcpyAsync(b->rows2, B.rows2.data(), B.rows2.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);

@@ -17,11 +17,12 @@ struct BatchProblem {
 };
 
 // Instances of the two-step pass: lean (no wall in reach), full, xwall (walls x = 0 and
-// x = nx - 1 only).
-enum : int { STEP2_LEAN = 0, STEP2_FULL = 1, STEP2_XWALL = 2, STEP2_MODES = 3 };
+// x = nx - 1 only).  Launches: main (the xwall and lean wavefronts) and full.
+enum : int { STEP2_LEAN = 0, STEP2_FULL = 1, STEP2_XWALL = 2 };
+enum : int { STEP2_MAIN = 0, STEP2_LAUNCHES = 2 };
 
 struct Batch2Kernels {
-    const void *main[STEP2_MODES];   // k_batch_step2 per instance
+    const void *main[STEP2_LAUNCHES];   // k_batch_step2 per launch (STEP2_MAIN, STEP2_FULL)
     const void *rows;
     int threads, waves_per_block;
 };
@@ -58,24 +59,23 @@ hipError_t launch_nusselt(int storage, const void *src, const KParams &P, int wa
 hipError_t launch_state(int storage, void *buf, const KParams &P, double *io, bool get, hipStream_t st);
 long long residual_partials(const KParams &P);
 
-// Two time steps per pass: the main launches (lean, xwall and full instances; together
-// every node outside the walled rows y = 0, y = ny - 1; the full one also writes the
-// intermediate populations of rows 0-3 and ny-4..ny-1 to the eight-row scratch grid
-// described by Pm), then the walled rows from the scratch grid.
+// Two time steps per pass: the main launch (lean and xwall wavefronts) and the full launch
+// (together every node outside the walled rows y = 0, y = ny - 1; the full one also writes
+// the intermediate populations of rows 0-3 and ny-4..ny-1 to the eight-row scratch grid
+// described by Pm), then the walled rows from the scratch grid.  Each launch reads its
+// wavefront indices from a device list built by step2_lists.
 bool step2_supported(const KParams &P);
 long long step2_nodes(const KParams &P);
-long long step2_lean_nodes(const KParams &P);   // output nodes of the lean launch
-// mode: STEP2_LEAN, STEP2_FULL or STEP2_XWALL; step2_has tells whether a grid has
-// wavefronts of that instance.
-bool step2_has(const KParams &P, int mode);
-hipError_t launch_step2_main(int storage, int mode, const void *src, void *dst, void *scr, const KParams &P,
-                             const KParams &Pm, hipStream_t st);
+int step2_waves(const KParams &P);   // wavefronts of both launches together
+void step2_lists(const KParams &P, std::vector<int> &main, std::vector<int> &full, int &row_blocks,
+                 long long &main_nodes);
+hipError_t launch_step2_main(int storage, int launch, const void *src, void *dst, void *scr, const KParams &P,
+                             const KParams &Pm, const int *items, int nitems, hipStream_t st);
 hipError_t launch_step2_rows(int storage, void *dst, const void *scr, const KParams &P, const KParams &Pm,
                              hipStream_t st);
 
-// Batched two-step passes: items[m] (problem, wavefront index) for instance m, nitems[m]
-// of them; rows: (problem, block of 64 walled-row nodes).
-void step2_wave_lists(const KParams &P, std::vector<int> (&lists)[STEP2_MODES], int &row_blocks);
+// Batched two-step passes: items[l] (problem, wavefront index) for launch l, nitems[l] of
+// them; rows: (problem, block of 64 walled-row nodes).
 hipError_t launch_batch_step2(int storage, const BatchProblem *probs, const int2 *const *items, const int *nitems,
                               const int2 *rows, int nrows, int parity, hipStream_t st);
 Batch2Kernels batch2_kernels(int storage);

@@ -118,8 +118,6 @@ __host__ __device__ __forceinline__ int s2_kind(const KParams &P, int cxi, int c
 // the wall node's reference node x_f and Td of x_ff.
 constexpr int S2_LDS_P1 = 2 * (S2_TY + 2) * 18;
 constexpr int S2_LDS = S2_LDS_P1 + 2 * S2_TY * 19;
-template <int MODE> struct S2Lds { static constexpr int n = 1; };
-template <> struct S2Lds<STEP2_XWALL> { static constexpr int n = S2_LDS; };
 
 // LDS writes of some lanes made visible to the other lanes of the wavefront.
 __device__ __forceinline__ void wave_sync()
@@ -333,36 +331,51 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return x * per + min(x, rem) + i;
 }
 
-template <typename S, int MODE>
-__global__ void __launch_bounds__(S2_B)
-k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KParams P, KParams Pm,
-        int ncx, int ncy)
+// One wavefront's walk with the instance chosen at run time: the main launch runs the lean
+// and the xwall wavefronts (both about 135 VGPRs), the full launch the full ones.
+template <typename S, int LAUNCH>
+__device__ __forceinline__ void march2_any(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr,
+                                           const KParams &P, const KParams &Pm, int cxi, int cyi, int lane,
+                                           typename Prec<S>::R *lds)
 {
-    using R = typename Prec<S>::R;
-    __shared__ R lds[S2_B / 64][S2Lds<MODE>::n];
-    const int wave = xcd_block(blockIdx.x, gridDim.x) * (S2_B / 64) + (threadIdx.x >> 6);
-    if (wave >= ncx * ncy) return;                       // wavefront-uniform
-    const int cxi = wave % ncx, cyi = wave / ncx;
-    if (s2_kind(P, cxi, cyi) != MODE) return;            // another instance's wavefront
-    march2<S, MODE>(src, dst, scr, P, Pm, cxi, cyi, threadIdx.x & 63, lds[threadIdx.x >> 6]);
+    if constexpr (LAUNCH == STEP2_FULL)
+        march2<S, STEP2_FULL>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
+    else if (s2_kind(P, cxi, cyi) == STEP2_XWALL)     // wavefront-uniform
+        march2<S, STEP2_XWALL>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
+    else
+        march2<S, STEP2_LEAN>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
 }
 
-// Batched: item (problem, wavefront index); the host sorts the wavefronts of every problem
-// into one item list per instance.
-template <typename S, int MODE>
+// items: wavefront indices cyi * ncx + cxi of this launch (the main launch lists the xwall
+// wavefronts first, so that they start beside the first lean ones rather than at the tail).
+template <typename S, int LAUNCH>
+__global__ void __launch_bounds__(S2_B)
+k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KParams P, KParams Pm,
+        const int *__restrict__ items, int nitems, int ncx)
+{
+    using R = typename Prec<S>::R;
+    __shared__ R lds[S2_B / 64][LAUNCH == STEP2_FULL ? 1 : S2_LDS];
+    const int wi = xcd_block(blockIdx.x, gridDim.x) * (S2_B / 64) + (threadIdx.x >> 6);
+    if (wi >= nitems) return;                            // wavefront-uniform
+    const int w = items[wi];
+    march2_any<S, LAUNCH>(src, dst, scr, P, Pm, w % ncx, w / ncx, threadIdx.x & 63, lds[threadIdx.x >> 6]);
+}
+
+// Batched: item (problem, wavefront index); one item list per launch.
+template <typename S, int LAUNCH>
 __global__ void __launch_bounds__(S2_B)
 k_batch_step2(const BatchProblem *__restrict__ probs, const int2 *__restrict__ items, int nitems, int parity)
 {
     using R = typename Prec<S>::R;
-    __shared__ R lds[S2_B / 64][S2Lds<MODE>::n];
+    __shared__ R lds[S2_B / 64][LAUNCH == STEP2_FULL ? 1 : S2_LDS];
     const int wi = xcd_block(blockIdx.x, gridDim.x) * (S2_B / 64) + (threadIdx.x >> 6);
     if (wi >= nitems) return;                            // wavefront-uniform
     const int2 it = items[wi];
     const BatchProblem &B = probs[it.x];
     const int ncx = (B.P.nx + S2_OUT - 1) / S2_OUT;
-    march2<S, MODE>(static_cast<const S *>(B.buf[parity]), static_cast<S *>(B.buf[parity ^ 1]),
-                    static_cast<S *>(B.scr), B.P, B.Pm, it.y % ncx, it.y / ncx, threadIdx.x & 63,
-                    lds[threadIdx.x >> 6]);
+    march2_any<S, LAUNCH>(static_cast<const S *>(B.buf[parity]), static_cast<S *>(B.buf[parity ^ 1]),
+                          static_cast<S *>(B.scr), B.P, B.Pm, it.y % ncx, it.y / ncx, threadIdx.x & 63,
+                          lds[threadIdx.x >> 6]);
 }
 
 // Final step of the walled rows y = 0 and y = ny - 1 from the intermediate rows in the
@@ -405,16 +418,15 @@ k_batch_step2_rows(const BatchProblem *__restrict__ probs, const int2 *__restric
                   it.y * 64 + threadIdx.x);
 }
 
-template <typename S, int MODE>
+template <typename S, int LAUNCH>
 static hipError_t step2_main_t(const void *src, void *dst, void *scr, const KParams &P, const KParams &Pm,
-                               hipStream_t st)
+                               const int *items, int nitems, hipStream_t st)
 {
     const int ncx = (P.nx + S2_OUT - 1) / S2_OUT;
-    const int ncy = (P.ny + S2_TY - 1) / S2_TY;
-    const long long waves = (long long)ncx * ncy;
-    const int blocks = (int)((waves + S2_B / 64 - 1) / (S2_B / 64));
-    hipLaunchKernelGGL((k_step2<S, MODE>), dim3(blocks), dim3(S2_B), 0, st, (const S *)src, (S *)dst, (S *)scr,
-                       P, Pm, ncx, ncy);
+    const int blocks = (nitems + S2_B / 64 - 1) / (S2_B / 64);
+    if (nitems > 0)
+        hipLaunchKernelGGL((k_step2<S, LAUNCH>), dim3(blocks), dim3(S2_B), 0, st, (const S *)src, (S *)dst, (S *)scr,
+                           P, Pm, items, nitems, ncx);
     return hipGetLastError();
 }
 
@@ -435,51 +447,56 @@ bool step2_supported(const KParams &P) { return P.nx >= 4 && P.ny >= 8; }
 
 long long step2_nodes(const KParams &P) { return (long long)P.nx * (P.py ? P.ny : P.ny - 2); }
 
-// Output nodes of the lean launch (column chunks and row bands away from walls).
-long long step2_lean_nodes(const KParams &P)
+int step2_waves(const KParams &P)
+{
+    return ((P.nx + S2_OUT - 1) / S2_OUT) * ((P.ny + S2_TY - 1) / S2_TY);
+}
+
+// Wavefront lists of the two launches: main (the xwall wavefronts, then the lean ones) and
+// full; the number of walled-row blocks of 64 nodes; the output nodes of the main launch.
+void step2_lists(const KParams &P, std::vector<int> &main, std::vector<int> &full, int &row_blocks,
+                 long long &main_nodes)
 {
     const int ncx = (P.nx + S2_OUT - 1) / S2_OUT;
     const int ncy = (P.ny + S2_TY - 1) / S2_TY;
-    long long n = 0;
+    std::vector<int> lean;
+    main.clear();
+    full.clear();
+    main_nodes = 0;
     for (int cy = 0; cy < ncy; ++cy)
-        for (int cx = 0; cx < ncx; ++cx)
-            if (s2_kind(P, cx, cy) == STEP2_LEAN) {
-                const int Y0 = cy * S2_TY, Y1 = min(Y0 + S2_TY, P.ny);
-                n += (long long)S2_OUT * (Y1 - Y0);
+        for (int cx = 0; cx < ncx; ++cx) {
+            const int w = cy * ncx + cx, kind = s2_kind(P, cx, cy);
+            if (kind == STEP2_FULL) {
+                full.push_back(w);
+                continue;
             }
-    return n;
+            (kind == STEP2_XWALL ? main : lean).push_back(w);
+            const int X0 = s2_x0(P, cx);
+            const int Y0 = cy * S2_TY, Y1 = min(Y0 + S2_TY, P.ny);
+            int cols = 0;
+            for (int l = 1; l <= S2_OUT; ++l) cols += P.px || (X0 - 1 + l >= 0 && X0 - 1 + l < P.nx);
+            main_nodes += (long long)cols * (Y1 - Y0);
+        }
+    main.insert(main.end(), lean.begin(), lean.end());
+    row_blocks = P.py ? 0 : (2 * P.nx + 63) / 64;
 }
 
 template <typename S>
-static hipError_t step2_main_s(int mode, const void *src, void *dst, void *scr, const KParams &P,
-                               const KParams &Pm, hipStream_t st)
+static hipError_t step2_main_s(int launch, const void *src, void *dst, void *scr, const KParams &P,
+                               const KParams &Pm, const int *items, int nitems, hipStream_t st)
 {
-    switch (mode) {
-    case STEP2_LEAN: return step2_main_t<S, STEP2_LEAN>(src, dst, scr, P, Pm, st);
-    case STEP2_FULL: return step2_main_t<S, STEP2_FULL>(src, dst, scr, P, Pm, st);
-    case STEP2_XWALL: return step2_main_t<S, STEP2_XWALL>(src, dst, scr, P, Pm, st);
-    default: return hipErrorInvalidValue;
-    }
+    if (launch == STEP2_FULL) return step2_main_t<S, STEP2_FULL>(src, dst, scr, P, Pm, items, nitems, st);
+    return step2_main_t<S, STEP2_MAIN>(src, dst, scr, P, Pm, items, nitems, st);
 }
 
-bool step2_has(const KParams &P, int mode)
-{
-    const int ncx = (P.nx + S2_OUT - 1) / S2_OUT;
-    const int ncy = (P.ny + S2_TY - 1) / S2_TY;
-    for (int cy = 0; cy < ncy; ++cy)
-        for (int cx = 0; cx < ncx; ++cx)
-            if (s2_kind(P, cx, cy) == mode) return true;
-    return false;
-}
-
-hipError_t launch_step2_main(int storage, int mode, const void *src, void *dst, void *scr, const KParams &P,
-                             const KParams &Pm, hipStream_t st)
+hipError_t launch_step2_main(int storage, int launch, const void *src, void *dst, void *scr, const KParams &P,
+                             const KParams &Pm, const int *items, int nitems, hipStream_t st)
 {
     if (!step2_supported(P)) return hipErrorInvalidValue;
     switch (storage) {
-    case 0: return step2_main_s<double>(mode, src, dst, scr, P, Pm, st);
-    case 1: return step2_main_s<float>(mode, src, dst, scr, P, Pm, st);
-    case 2: return step2_main_s<__half>(mode, src, dst, scr, P, Pm, st);
+    case 0: return step2_main_s<double>(launch, src, dst, scr, P, Pm, items, nitems, st);
+    case 1: return step2_main_s<float>(launch, src, dst, scr, P, Pm, items, nitems, st);
+    case 2: return step2_main_s<__half>(launch, src, dst, scr, P, Pm, items, nitems, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -495,34 +512,19 @@ hipError_t launch_step2_rows(int storage, void *dst, const void *scr, const KPar
     }
 }
 
-// Wavefront indices (cyi * ncx + cxi) of a problem's wavefronts per instance (lean, full,
-// xwall), and its number of walled-row blocks of 64 nodes.
-void step2_wave_lists(const KParams &P, std::vector<int> (&lists)[3], int &row_blocks)
-{
-    const int ncx = (P.nx + S2_OUT - 1) / S2_OUT;
-    const int ncy = (P.ny + S2_TY - 1) / S2_TY;
-    for (auto &l : lists) l.clear();
-    for (int cy = 0; cy < ncy; ++cy)
-        for (int cx = 0; cx < ncx; ++cx) lists[s2_kind(P, cx, cy)].push_back(cy * ncx + cx);
-    row_blocks = P.py ? 0 : (2 * P.nx + 63) / 64;
-}
-
 template <typename S>
 static hipError_t batch_step2_t(const BatchProblem *probs, const int2 *const *items, const int *nitems,
                                 const int2 *rows, int nrows, int parity, hipStream_t st)
 {
     constexpr int W = S2_B / 64;
-    if (nitems[STEP2_LEAN] > 0)
-        hipLaunchKernelGGL((k_batch_step2<S, STEP2_LEAN>), dim3((nitems[STEP2_LEAN] + W - 1) / W), dim3(S2_B), 0, st,
-                           probs, items[STEP2_LEAN], nitems[STEP2_LEAN], parity);
-    if (nitems[STEP2_XWALL] > 0)
-        hipLaunchKernelGGL((k_batch_step2<S, STEP2_XWALL>), dim3((nitems[STEP2_XWALL] + W - 1) / W), dim3(S2_B), 0, st,
-                           probs, items[STEP2_XWALL], nitems[STEP2_XWALL], parity);
     if (nitems[STEP2_FULL] > 0)
         hipLaunchKernelGGL((k_batch_step2<S, STEP2_FULL>), dim3((nitems[STEP2_FULL] + W - 1) / W), dim3(S2_B), 0, st,
                            probs, items[STEP2_FULL], nitems[STEP2_FULL], parity);
-    if (nrows > 0)
+    if (nrows > 0)   // after the full launch, whose scratch rows it reads
         hipLaunchKernelGGL((k_batch_step2_rows<S>), dim3(nrows), dim3(64), 0, st, probs, rows, parity);
+    if (nitems[STEP2_MAIN] > 0)
+        hipLaunchKernelGGL((k_batch_step2<S, STEP2_MAIN>), dim3((nitems[STEP2_MAIN] + W - 1) / W), dim3(S2_B), 0, st,
+                           probs, items[STEP2_MAIN], nitems[STEP2_MAIN], parity);
     return hipGetLastError();
 }
 
@@ -540,9 +542,8 @@ hipError_t launch_batch_step2(int storage, const BatchProblem *probs, const int2
 template <typename S> static Batch2Kernels batch2_kernels_t()
 {
     Batch2Kernels k;
-    k.main[STEP2_LEAN] = (const void *)k_batch_step2<S, STEP2_LEAN>;
+    k.main[STEP2_MAIN] = (const void *)k_batch_step2<S, STEP2_MAIN>;
     k.main[STEP2_FULL] = (const void *)k_batch_step2<S, STEP2_FULL>;
-    k.main[STEP2_XWALL] = (const void *)k_batch_step2<S, STEP2_XWALL>;
     k.rows = (const void *)k_batch_step2_rows<S>;
     k.threads = S2_B;
     k.waves_per_block = S2_B / 64;

@@ -1,8 +1,10 @@
 """The two-step pass against single steps, bit for bit: every node update of the pass is
 the one-step node code with the same inputs (FP16 storage rounds the intermediate state
 to the stored format), so any difference is an indexing, shift or boundary error.  Grids
-cover all wall combinations, ragged sizes (the last column chunk overlaps the previous
-one, the last row band is short), porosity fields, moving walls and a heat source, an odd
+cover all wall combinations and the three instances of the pass (lean, vertical walls
+only, full), ragged sizes (the last column chunk partly past the wall, or, for one or two
+leftover columns, overlapping the previous one; periodic grids whose last chunk overlaps
+or wraps; a short last row band), porosity fields, moving walls and a heat source, an odd
 number of steps (the last one single) and both layouts (planes for FP64, tiles for
 FP32/FP16)."""
 import pytest
@@ -37,6 +39,8 @@ CASES = [
     (52, 33, 33, 1, 1, {"with_Q": True}),
     (53, 61, 20, 0, 0, {"eps_field": True, "moving_walls": True}),
     (54, 63, 21, 1, 0, {}),
+    (55, 126, 24, 0, 0, {"moving_walls": True}),
+    (56, 250, 19, 0, 1, {"eps_field": True}),
 ]
 
 
