@@ -89,6 +89,7 @@ template <typename R> struct Cst {
     R aM0;             // cs^2 sigma (B - tau_T)
     R w1, w5;          // lattice weights 1/9, 1/36
     R w3a, w3d;        // 3 omega of axis / diagonal directions with 2 w3a + 4 w3d = 1 in R
+
 };
 
 // Porosity-dependent coefficients in R (uniform porosity: computed on the host).
@@ -397,6 +398,18 @@ __device__ __forceinline__ R geq_i(int i, R Td, R T, R ux, R uy, R ieps, R ep, R
                        + R(3) * T * ep + k.sigB * cg);
 }
 
+// Per-node coefficients of the pair updates (collide_pair).
+template <typename R> struct PairC {
+    R b0;     // even part of f^eq / omega apart from the (c.u)^2 and c.S.c terms
+    R k45;    // 4.5 / eps
+    R c9;     // 9 (1 - 1/(2 tau_f)) / eps
+    R m3b5;   // -3 (1 - 1/(2 tau_f)) (u.F) / eps
+    R b1;     // even part of g^eq / omega apart from the (c.u)^2 term
+    R T45;    // 4.5 T / eps
+    R s;      // T / tau_T + (1 - 1/(2 tau_T)) ((1/eps - 1/sigma) u.grad T + Q / sigma), the
+              // coefficient of 3 omega (c.u) in the odd part of g*
+};
+
 // BGK collision with forcing and sources, in place (Eqs. LBEeq, FtermF, TEqColli,
 // Eq:Tforce):  f* = f - (f - f^eq)/tau_f + F_i,  g* = g - (g - g^eq)/tau_T + P_i + Q_i.
 //
@@ -405,38 +418,39 @@ __device__ __forceinline__ R geq_i(int i, R Td, R T, R ux, R uy, R ieps, R ep, R
 // and u.F terms; g^eq: sigma T, u u and pressure terms; Q_i: the constant part) and a part
 // odd in c (the c.u, c.F, c.grad T, P_i and (c.u) Q terms), so each pair is updated as
 //   f*_i = (1 - 1/tau) f_i + E + O,   f*_i' = (1 - 1/tau) f_i' + E - O.
-// E collects 1/tau times the even part of the equilibrium plus the even part of the source.
+// E collects 1/tau times the even part of the equilibrium plus the even part of the source;
+// the terms are grouped around the per-node coefficients q so that a pair costs few
+// multiply-adds.
 //
 // The odd parts carry 3 omega_i (c_i . u) and friends, whose first moment over the lattice
 // must be exactly u: 3 omega is taken as w3a (axes) and w3d (diagonals) with
 // 2 w3a + 4 w3d = 1 in the arithmetic type, otherwise the rounded weights would scale the
 // momentum by a fixed factor every step.
+//
+// c = class of the pair (0 axes, 1 diagonals); cu = c.u, cF = c.F, cSc = c.S.c,
+// cg = c.grad T, cv = c.(T F + eps p grad T / rho0).
 template <typename R>
-__device__ __forceinline__ void collide_pair(R &fa, R &fb, R &ga, R &gb, R w, R w3, R cu, R cF,
-                                             R cSc, R cg, R cv, const R (&b)[8], const Cst<R> &k,
-                                             R &Ef_sum, R &Eg_sum)
+__device__ __forceinline__ void collide_pair(R &fa, R &fb, R &ga, R &gb, int c, R cu, R cF, R cSc, R cg, R cv,
+                                             const PairC<R> &q, const Cst<R> &k, R &Ef_sum, R &Eg_sum)
 {
-    // b: 0 eps p-u u-tr S base of f^eq, 1 base of g^eq, 2 1/eps, 3 A, 4 T, 5 fF (uF)/eps,
-    //    6 (1/eps - 1/sigma) u.grad T, 7 Q / sigma
+    const R w = c == 0 ? k.w1 : k.w5, w3 = c == 0 ? k.w3a : k.w3d;
+    // products of launch constants (the compiler keeps them out of the row loops)
+    const R witf = w * k.itf, witT = w * k.itT, wQ = w * k.fT * k.Q, bsg = k.itT * w * k.sigB;
+    const R w3fT = w3 * k.fT, w3fF = w3 * k.fF, A15 = R(1.5) * k.A;
     const R cu2 = cu * cu;
-    const R ieps = b[2];
-    const R fe_even = w * (b[0] + R(4.5) * cu2 * ieps + R(1.5) * b[3] * cSc);
-    const R fe_odd = w3 * cu;
-    const R F_even = w * (k.fF * R(9) * cu * cF * ieps - R(3) * b[5]);
-    const R F_odd = w3 * k.fF * cF;
-    const R Ef = k.itf * fe_even + F_even;
-    const R Of = k.itf * fe_odd + F_odd;
+    // f: E = omega [(b0 + 4.5 (c.u)^2 / eps + 1.5 A c.S.c) / tau_f + fF (9 (c.u)(c.F) - 3 u.F) / eps],
+    //    O = 3 omega [(c.u) / tau_f + fF c.F]
+    const R Ee = A15 * cSc + (q.k45 * cu2 + q.b0);
+    const R Es = q.c9 * (cu * cF) + q.m3b5;
+    const R Ef = witf * Ee + w * Es;
+    const R Of = k.itf * (w3 * cu) + w3fF * cF;
     fa = k.of * fa + (Ef + Of);
     fb = k.of * fb + (Ef - Of);
 
-    const R T = b[4];
-    const R ge_even = w * (b[1] + R(4.5) * T * cu2 * ieps);
-    const R ge_odd = w3 * T * cu + w * k.sigB * cg;
-    const R P_odd = w3 * k.fT * (cv + b[6] * cu);
-    const R Q_even = w * k.fT * k.Q;
-    const R Q_odd = w3 * k.fT * b[7] * cu;   // omega fT 3 (c.u) Q / sigma
-    const R Eg = k.itT * ge_even + Q_even;
-    const R Og = k.itT * ge_odd + P_odd + Q_odd;
+    // g: E = omega [(b1 + 4.5 T (c.u)^2 / eps) / tau_T + fT Q],
+    //    O = 3 omega (c.u) s + omega sigma B c.grad T / tau_T + 3 omega fT c.v
+    const R Eg = witT * (q.T45 * cu2 + q.b1) + wQ;
+    const R Og = (w3 * q.s) * cu + (bsg * cg + w3fT * cv);
     ga = k.og * ga + (Eg + Og);
     gb = k.og * gb + (Eg - Og);
     Ef_sum += Ef;
@@ -462,27 +476,25 @@ __device__ __forceinline__ void node_collide(R *f, R *g, const Macro<R> &m, R T0
     const R vx = T * m.Fx + ep * m.gx;   // T F + eps p grad T / rho0
     const R vy = T * m.Fy + ep * m.gy;
 
-    R b[8];
-    b[0] = R(3) * ep - R(1.5) * uu * e.ieps - R(0.5) * k.A * trS;
-    b[1] = k.sig * m.Td - R(1.5) * T * uu * e.ieps + R(3) * T * ep;
-    b[2] = e.ieps;
-    b[3] = k.A;
-    b[4] = T;
-    b[5] = k.fF * uF * e.ieps;
-    b[6] = (e.ieps - k.isig) * ugT;
-    b[7] = k.Q * k.isig;
-    const R w1 = k.w1, w5 = k.w5;
+    PairC<R> q;
+    q.b0 = R(3) * ep - R(1.5) * uu * e.ieps - R(0.5) * k.A * trS;
+    q.b1 = k.sig * m.Td - R(1.5) * T * uu * e.ieps + R(3) * T * ep;
+    q.k45 = R(4.5) * e.ieps;
+    q.c9 = R(9) * k.fF * e.ieps;
+    q.m3b5 = R(-3) * (k.fF * uF * e.ieps);
+    q.T45 = q.k45 * T;
+    q.s = k.itT * T + k.fT * ((e.ieps - k.isig) * ugT + k.Q * k.isig);
     R Ef = R(0), Eg = R(0);
     // (1, 3): c = (1, 0)
-    collide_pair<R>(f[1], f[3], g[1], g[3], w1, k.w3a, m.ux, m.Fx, m.Sxx, m.gx, vx, b, k, Ef, Eg);
+    collide_pair<R>(f[1], f[3], g[1], g[3], 0, m.ux, m.Fx, m.Sxx, m.gx, vx, q, k, Ef, Eg);
     // (2, 4): c = (0, 1)
-    collide_pair<R>(f[2], f[4], g[2], g[4], w1, k.w3a, m.uy, m.Fy, m.Syy, m.gy, vy, b, k, Ef, Eg);
+    collide_pair<R>(f[2], f[4], g[2], g[4], 0, m.uy, m.Fy, m.Syy, m.gy, vy, q, k, Ef, Eg);
     // (5, 7): c = (1, 1)
-    collide_pair<R>(f[5], f[7], g[5], g[7], w5, k.w3d, m.ux + m.uy, m.Fx + m.Fy,
-                    m.Sxx + R(2) * m.Sxy + m.Syy, m.gx + m.gy, vx + vy, b, k, Ef, Eg);
+    collide_pair<R>(f[5], f[7], g[5], g[7], 1, m.ux + m.uy, m.Fx + m.Fy, m.Sxx + R(2) * m.Sxy + m.Syy,
+                    m.gx + m.gy, vx + vy, q, k, Ef, Eg);
     // (6, 8): c = (-1, 1)
-    collide_pair<R>(f[6], f[8], g[6], g[8], w5, k.w3d, m.uy - m.ux, m.Fy - m.Fx,
-                    m.Sxx - R(2) * m.Sxy + m.Syy, m.gy - m.gx, vy - vx, b, k, Ef, Eg);
+    collide_pair<R>(f[6], f[8], g[6], g[8], 1, m.uy - m.ux, m.Fy - m.Fx, m.Sxx - R(2) * m.Sxy + m.Syy,
+                    m.gy - m.gx, vy - vx, q, k, Ef, Eg);
     // rest direction: f^eq_0 + tau_f F_0 and g^eq_0 + tau_T Q_0 from the zeroth moments
     f[0] = k.of * f[0] - R(2) * Ef;
     g[0] = k.og * g[0] + (k.itT * k.sig * m.Td + k.fT * k.Q) - R(2) * Eg;
