@@ -308,9 +308,10 @@ static lbm_status init_ctx(const lbm_params *params, void *workspace, size_t wor
     c->n_main2 = c->n_full2 = 0;
     c->main_nodes2 = 0;
     if (lbm::step2_supported(kp)) {
-        std::vector<int> mainv, fullv;
+        std::vector<int> xw, lean, fullv;
         int rb = 0;
-        lbm::step2_lists(kp, mainv, fullv, rb, c->main_nodes2);
+        lbm::step2_lists(kp, xw, lean, fullv, rb, c->main_nodes2);
+        std::vector<int> mainv = lbm::xcd_balanced(xw, lean);
         c->n_main2 = (int)mainv.size();
         c->n_full2 = (int)fullv.size();
         mainv.insert(mainv.end(), fullv.begin(), fullv.end());
@@ -882,12 +883,16 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
         const int wb = lbm::wall_block_size();
         for (int b = 0; b < (kp.nwall_rows + wb - 1) / wb; ++b) B.wall.push_back(make_int2(k, b));
         if (B.two && lbm::step2_supported(kp)) {
-            std::vector<int> lists[lbm::STEP2_LAUNCHES];
+            std::vector<int> xw, lean, fullv;
             int rb = 0;
             long long mn = 0;
-            lbm::step2_lists(kp, lists[lbm::STEP2_MAIN], lists[lbm::STEP2_FULL], rb, mn);
-            for (int l = 0; l < lbm::STEP2_LAUNCHES; ++l)
-                for (int w : lists[l]) B.items2[l].push_back(make_int2(k, w));
+            lbm::step2_lists(kp, xw, lean, fullv, rb, mn);
+            // per problem its xwall then its lean wavefronts: the XCD ranges of logical blocks
+            // then hold whole problems (their halos stay in one L2) and share the heavier
+            // xwall wavefronts about evenly
+            for (int w : xw) B.items2[lbm::STEP2_MAIN].push_back(make_int2(k, w));
+            for (int w : lean) B.items2[lbm::STEP2_MAIN].push_back(make_int2(k, w));
+            for (int w : fullv) B.items2[lbm::STEP2_FULL].push_back(make_int2(k, w));
             for (int r = 0; r < rb; ++r) B.rows2.push_back(make_int2(k, r));
         } else {
             B.two = false;

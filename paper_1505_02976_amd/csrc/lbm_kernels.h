@@ -1,6 +1,7 @@
 // Launchers of the HIP kernels (host side).  storage: 0 = FP64, 1 = FP32, 2 = FP16.
 #pragma once
 
+#include <algorithm>
 #include <vector>
 
 #include "lbm_device.h"
@@ -67,8 +68,40 @@ long long residual_partials(const KParams &P);
 bool step2_supported(const KParams &P);
 long long step2_nodes(const KParams &P);
 int step2_waves(const KParams &P);   // wavefronts of both launches together
-void step2_lists(const KParams &P, std::vector<int> &main, std::vector<int> &full, int &row_blocks,
-                 long long &main_nodes);
+void step2_lists(const KParams &P, std::vector<int> &xwall, std::vector<int> &lean, std::vector<int> &full,
+                 int &row_blocks, long long &main_nodes);
+
+// The two-step kernels run STEP2_WAVES_PER_BLOCK independent wavefronts per block.  The
+// hardware deals consecutive blocks round-robin to the eight XCDs; the kernels map
+// dispatched block b to a logical block so that XCD x runs the x-th contiguous range of
+// logical blocks (first block of that range below), whose wavefronts share that XCD's L2.
+constexpr int STEP2_WAVES_PER_BLOCK = 4;
+inline int xcd_range_start(int x, int nblocks)
+{
+    const int per = nblocks / 8, rem = nblocks % 8;
+    return x * per + std::min(x, rem);
+}
+
+// Item list of a launch of heavy and light wavefronts in which every XCD's range starts
+// with its proportional share of the heavy ones (so that no XCD gets more work than the
+// others, and the heavy wavefronts are not left for the end).
+template <typename T>
+std::vector<T> xcd_balanced(const std::vector<T> &heavy, const std::vector<T> &light)
+{
+    const long long H = (long long)heavy.size(), n = H + (long long)light.size();
+    std::vector<T> out;
+    out.reserve(n);
+    if (n == 0) return out;
+    const int nb = (int)((n + STEP2_WAVES_PER_BLOCK - 1) / STEP2_WAVES_PER_BLOCK);
+    size_t ih = 0, il = 0;
+    for (int x = 0; x < 8; ++x) {
+        const long long w0 = std::min(n, (long long)STEP2_WAVES_PER_BLOCK * xcd_range_start(x, nb));
+        const long long w1 = std::min(n, (long long)STEP2_WAVES_PER_BLOCK * xcd_range_start(x + 1, nb));
+        const size_t h1 = (size_t)(H * w1 / n);
+        for (long long w = w0; w < w1; ++w) out.push_back(ih < h1 ? heavy[ih++] : light[il++]);
+    }
+    return out;
+}
 hipError_t launch_step2_main(int storage, int launch, const void *src, void *dst, void *scr, const KParams &P,
                              const KParams &Pm, const int *items, int nitems, hipStream_t st);
 hipError_t launch_step2_rows(int storage, void *dst, const void *scr, const KParams &P, const KParams &Pm,

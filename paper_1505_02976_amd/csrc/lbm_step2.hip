@@ -43,6 +43,7 @@ constexpr int S2_TY = LBM_STEP2_TY;   // output rows per wavefront
 
 constexpr int S2_OUT = 62;            // output columns per wavefront
 constexpr int S2_B = 256;             // threads per block (independent wavefronts)
+static_assert(S2_B / 64 == STEP2_WAVES_PER_BLOCK, "wavefronts per block");
 
 // The lean instance gathers the next row's populations while it updates the current one
 // (one more set of 18 registers); FP64 has no registers to spare for it.
@@ -452,15 +453,15 @@ int step2_waves(const KParams &P)
     return ((P.nx + S2_OUT - 1) / S2_OUT) * ((P.ny + S2_TY - 1) / S2_TY);
 }
 
-// Wavefront lists of the two launches: main (the xwall wavefronts, then the lean ones) and
-// full; the number of walled-row blocks of 64 nodes; the output nodes of the main launch.
-void step2_lists(const KParams &P, std::vector<int> &main, std::vector<int> &full, int &row_blocks,
-                 long long &main_nodes)
+// Wavefront indices of the xwall, lean and full instances (the main launch runs the first
+// two); the number of walled-row blocks of 64 nodes; the output nodes of the main launch.
+void step2_lists(const KParams &P, std::vector<int> &xwall, std::vector<int> &lean, std::vector<int> &full,
+                 int &row_blocks, long long &main_nodes)
 {
     const int ncx = (P.nx + S2_OUT - 1) / S2_OUT;
     const int ncy = (P.ny + S2_TY - 1) / S2_TY;
-    std::vector<int> lean;
-    main.clear();
+    xwall.clear();
+    lean.clear();
     full.clear();
     main_nodes = 0;
     for (int cy = 0; cy < ncy; ++cy)
@@ -470,14 +471,13 @@ void step2_lists(const KParams &P, std::vector<int> &main, std::vector<int> &ful
                 full.push_back(w);
                 continue;
             }
-            (kind == STEP2_XWALL ? main : lean).push_back(w);
+            (kind == STEP2_XWALL ? xwall : lean).push_back(w);
             const int X0 = s2_x0(P, cx);
             const int Y0 = cy * S2_TY, Y1 = min(Y0 + S2_TY, P.ny);
             int cols = 0;
             for (int l = 1; l <= S2_OUT; ++l) cols += P.px || (X0 - 1 + l >= 0 && X0 - 1 + l < P.nx);
             main_nodes += (long long)cols * (Y1 - Y0);
         }
-    main.insert(main.end(), lean.begin(), lean.end());
     row_blocks = P.py ? 0 : (2 * P.nx + 63) / 64;
 }
 
