@@ -117,6 +117,7 @@ __host__ __device__ __forceinline__ int s2_kind(const KParams &P, int cxi, int c
 // LDS of one xwall wavefront: intermediate populations of the (up to two) wall columns for
 // the band's S2_TY + 2 intermediate rows, then per output row the pulled populations of
 // the wall node's reference node x_f and Td of x_ff.
+static_assert(2 * (S2_TY + 2) <= 64, "xwall: one lane per intermediate row of each wall column");
 constexpr int S2_LDS_P1 = 2 * (S2_TY + 2) * 18;
 constexpr int S2_LDS = S2_LDS_P1 + 2 * S2_TY * 19;
 
