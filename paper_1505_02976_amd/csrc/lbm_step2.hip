@@ -13,11 +13,17 @@
 // c_y = 0 (0, 1, 3) and c_y = +1 (2, 5, 6), from P1(yy - 2) the directions with c_y = +1;
 // directions with c_y = -1 (4, 7, 8) are used as soon as their row is computed.
 //
-// Nodes on the walls x = 0 and x = nx - 1 take the boundary scheme from the neighbouring
-// lanes' pulled populations, as in the one-step kernel.  The walled rows y = 0 and
-// y = ny - 1 need the intermediate populations of three more rows for their reference
-// nodes, so the pass writes P1 of rows 0-3 and ny-4..ny-1 to a small scratch grid and a
-// second launch finishes those two rows.
+// Three instances of the walk, by what lies in a wavefront's reach: lean (no wall, no
+// boundary-scheme code), xwall (the vertical walls x = 0, x = nx - 1 only: the wall
+// column's intermediate rows are computed before the walk, one lane per row, and its final
+// rows after it, from values the reference lanes leave in LDS) and full (everything else:
+// the boundary scheme inline, with the wall node taking its reference node's pulled
+// populations from the neighbouring lanes, as in the one-step kernel).  The walled rows
+// y = 0 and y = ny - 1 need the intermediate populations of three more rows for their
+// reference nodes, so the full instance writes P1 of rows 0-3 and ny-4..ny-1 to a small
+// scratch grid and a last launch finishes those two rows.  A pass is two launches over
+// wavefront lists built on the host: the main one (xwall and lean wavefronts, the instance
+// chosen per wavefront) and the full one, then the walled rows.
 //
 // Every node update is the one-step node code with the same inputs, so two steps here are
 // bitwise identical to two one-step launches (FP16 storage rounds P1 to the stored format
