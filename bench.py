@@ -42,17 +42,29 @@ BULK_SOURCES = ("lbm_device.h", "lbm_kernels.h", "lbm_kernels.hip", "lbm_step2.h
 def measured_traffic(kernel, storage, n):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it
     was taken on this workload and on the kernel sources as they are now (else None)."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_{storage}_cavity{n}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    csrc = os.path.join(ROOT, "paper_1505_02976_amd", "csrc")
-    src = b"".join(open(os.path.join(csrc, p), "rb").read() for p in BULK_SOURCES)
-    if hashlib.sha256(src).hexdigest() != rec.get("csrc_sha256"):
+    if kernel_sources_hash() != rec.get("csrc_sha256"):
         return None
     return rec["traffic_bytes_per_launch"]
+
+
+def kernel_sources_hash():
+    """SHA-256 of the kernel sources with comments and blank lines removed (a change of
+    wording in a comment does not make the recorded counters stale)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1505_02976_amd", "csrc")
+    lines = []
+    for p in BULK_SOURCES:
+        with open(os.path.join(csrc, p)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    lines.append(code)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
 def timed_run(lbm, torch, cfg, warmup, steps, every=8, fusion=None):
