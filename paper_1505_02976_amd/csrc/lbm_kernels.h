@@ -66,7 +66,6 @@ long long residual_partials(const KParams &P);
 // described by Pm), then the walled rows from the scratch grid.  Each launch reads its
 // wavefront indices from a device list built by step2_lists.
 bool step2_supported(const KParams &P);
-long long step2_nodes(const KParams &P);
 int step2_waves(const KParams &P);   // wavefronts of both launches together
 void step2_lists(const KParams &P, std::vector<int> &xwall, std::vector<int> &lean, std::vector<int> &full,
                  int &row_blocks, long long &main_nodes);

@@ -453,7 +453,6 @@ static hipError_t step2_rows_t(void *dst, const void *scr, const KParams &P, con
 // starting left of x = 0 with the lanes wrapped.
 bool step2_supported(const KParams &P) { return P.nx >= 4 && P.ny >= 8; }
 
-long long step2_nodes(const KParams &P) { return (long long)P.nx * (P.py ? P.ny : P.ny - 2); }
 
 int step2_waves(const KParams &P)
 {

@@ -63,6 +63,21 @@ def test_two_step_pass_is_bitwise_two_steps(gpu, storage, seed, nx, ny, px, py, 
         assert a.nusselt(2) == b.nusselt(2)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_two_step_pass_full_width(gpu, storage):
+    """The bench's grid width with walls in x (67 column chunks of 62, the last one four
+    columns wide) and a porosity field: passes equal single steps bit for bit."""
+    cfg = W.random_case(57, 4096, 264, storage=storage, eps_field=True, moving_walls=True)
+    print(f"case: {storage} 4096x264 walled, 9 steps", flush=True)
+    a = gpu.Sim(cfg)
+    b = gpu.Sim(cfg)
+    b.fusion = 1
+    a.step(9)
+    b.step(9)
+    sa, sb = a.get_state(), b.get_state()
+    assert bool((sa == sb).all()), float((sa - sb).abs().max())
+
+
 def test_fusion_setting(gpu):
     small = gpu.Sim(W.random_case(48, 100, 7))
     assert small.fusion == 1
