@@ -18,6 +18,15 @@
 namespace lbm {
 
 constexpr int ADJ_B = 128;
+// The Jacobian columns of a node are split over ADJ_SPLIT blocks (blockIdx.y): column j
+// goes to block j % ADJ_SPLIT.  At 256 VGPRs a SIMD holds two wavefronts; one thread per
+// node would leave a 256^2 grid with one wavefront per SIMD and its memory latency exposed
+// (backward sweep of the 256^2 cavity over 5000 steps: 1.84 s with one thread per node,
+// 1.44 / 1.24 / 1.11 s with 2 / 4 / 8 column groups).
+#ifndef LBM_ADJ_SPLIT
+#define LBM_ADJ_SPLIT 8
+#endif
+constexpr int ADJ_SPLIT = LBM_ADJ_SPLIT;
 
 __device__ __forceinline__ Cst<Dual> dual_cst(const Cst<double> &c)
 {
@@ -39,13 +48,15 @@ __device__ __forceinline__ void dual_update(Dual *f, Dual *g, const KParams &P, 
     node_collide<Dual>(f, g, m, Dual(P.T0), k, e);
 }
 
-// Step 1 at every node.
+// Step 1 at every node, Jacobian columns j = blockIdx.y, blockIdx.y + ADJ_SPLIT, ...  Every
+// output (mu[j], grad via column 18 or 19, wt, we, wf[j]) has one writer.
 template <typename S>
 __global__ void __launch_bounds__(ADJ_B)
 k_adj_node(const S *__restrict__ src, KParams P, AdjBufs A)
 {
     const long long N = (long long)P.nx * P.ny;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j0 = blockIdx.y;
     if (n >= N) return;
     const int x = int(n % P.nx), y = int(n / P.nx);
     double lam[18];
@@ -57,7 +68,7 @@ k_adj_node(const S *__restrict__ src, KParams P, AdjBufs A)
         gather<S, double>(src, P, x, y, pre, pre + 9);
         const double eps = eps_value(P, x, y);
 #pragma unroll 1
-        for (int j = 0; j < 19; ++j) {
+        for (int j = j0; j < 19; j += ADJ_SPLIT) {
             Dual f[9], g[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
@@ -81,7 +92,7 @@ k_adj_node(const S *__restrict__ src, KParams P, AdjBufs A)
         const double Tdff = neumann ? gather_Td<S, double>(src, P, P.cd, x + 2 * w.dx, y + 2 * w.dy) : 0.0;
         const double eb = eps_value(P, x, y), ef = eps_value(P, xf, yf);
 #pragma unroll 1
-        for (int j = 0; j < 21; ++j) {
+        for (int j = j0; j < 21; j += ADJ_SPLIT) {
             Dual ff[9], gf[9], f[9], g[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
@@ -101,8 +112,10 @@ k_adj_node(const S *__restrict__ src, KParams P, AdjBufs A)
             else if (j == 19) A.grad[n] += acc;
             else A.we[n] = acc;
         }
+        if (j0 == 0) {
 #pragma unroll
-        for (int q = 0; q < 18; ++q) A.mu[q * N + n] = 0.0;   // own gathered values unused
+            for (int q = 0; q < 18; ++q) A.mu[q * N + n] = 0.0;   // own gathered values unused
+        }
     }
 }
 
@@ -183,7 +196,7 @@ static hipError_t adj_step_t(const void *state, const KParams &P, const AdjBufs 
 {
     const long long N = (long long)P.nx * P.ny;
     const int nb = int((N + ADJ_B - 1) / ADJ_B);
-    hipLaunchKernelGGL((k_adj_node<S>), dim3(nb), dim3(ADJ_B), 0, st, (const S *)state, P, A);
+    hipLaunchKernelGGL((k_adj_node<S>), dim3(nb, ADJ_SPLIT), dim3(ADJ_B), 0, st, (const S *)state, P, A);
     hipLaunchKernelGGL(k_adj_pull, dim3(nb), dim3(ADJ_B), 0, st, P, A);
     return hipGetLastError();
 }
