@@ -325,10 +325,10 @@ __device__ __forceinline__ void node_macro(const R *f, const R *g, const Cst<R> 
     const R uu = m.ux * m.ux + m.uy * m.uy;
     const R uF = m.ux * m.Fx + m.uy * m.Fy;
     const R s18 = ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
-    // s_0 = -omega_0 |u|^2 / (2 eps cs^2),  F_0 = -omega_0 fF (u.F) / (eps cs^2)
-    const R s0 = R(-2.0 / 3.0) * uu * e.ieps;
-    const R F0 = R(-4.0 / 3.0) * k.fF * uF * e.ieps;
-    m.p = R(0.6) * e.ieps * (s18 + k.tau_f * F0 + s0);
+    // rho0 s_0 = -omega_0 |u|^2 / (2 eps cs^2),  tau_f F_0 = -omega_0 tau_f fF (u.F) / (eps cs^2);
+    // their coefficients depend only on the porosity and the launch constants
+    const R cuu = R(-2.0 / 3.0) * e.ieps, cuF = R(-4.0 / 3.0) * k.fF * k.tau_f * e.ieps;
+    m.p = (R(0.6) * e.ieps) * (s18 + cuu * uu + cuF * uF);
 
     const R ep = e.eps * m.p;
     const R Pxx = ((f[1] + f[3]) + (f[5] + f[6])) + (f[7] + f[8]);
@@ -352,8 +352,11 @@ __device__ __forceinline__ void node_gradT(Macro<R> &m, R T0, const Cst<R> &k, c
     const R a = k.aM0 - R(0.5) * e.eps * m.p;
     const R uu = m.ux * m.ux + m.uy * m.uy;
     const R uN = m.ux * Nx + m.uy * Ny;
-    const R c = e.bM * uN * rcp(a - e.bM * uu);
-    const R ia = rcp(a);
+    // one reciprocal for both factors: 1 / (a (a - b |u|^2))
+    const R d = a - e.bM * uu;
+    const R r = rcp(a * d);
+    const R c = (e.bM * uN) * (a * r);
+    const R ia = d * r;
     m.gx = (Nx + c * m.ux) * ia;
     m.gy = (Ny + c * m.uy) * ia;
 }
