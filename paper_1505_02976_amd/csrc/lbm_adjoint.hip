@@ -138,18 +138,20 @@ __device__ __forceinline__ double sum_wall_refs(const KParams &P, const double *
     return s;
 }
 
-// Step 2 at every node y: lambda_t(y, q) and the eps contributions routed through x_f.
+// Step 2 at every node y, one direction q = blockIdx.y per thread: lambda_t(y, q), and for
+// q = 0 the eps contributions routed through x_f.
 __global__ void __launch_bounds__(ADJ_B) k_adj_pull(KParams P, AdjBufs A)
 {
     const long long N = (long long)P.nx * P.ny;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
     if (n >= N) return;
     const int x = int(n % P.nx), y = int(n / P.nx);
     const double isig = 1.0 / P.sigma;
     // only nodes within three nodes of a wall can be (or neighbour) a reference node x_f
     // or x_ff of a wall node
     const bool near = (!P.px && (x < 4 || x >= P.nx - 4)) || (!P.py && (y < 4 || y >= P.ny - 4));
-    for (int q = 0; q < 18; ++q) {
+    {
         const int i = q < 9 ? q : q - 9;
         int zx = x + CXd[i], zy = y + CYd[i];
         if (P.px) zx = (zx + P.nx) % P.nx;
@@ -165,7 +167,7 @@ __global__ void __launch_bounds__(ADJ_B) k_adj_pull(KParams P, AdjBufs A)
         }
         A.lam[q * N + n] = v;
     }
-    if (near && !on_wall(P, x, y)) A.grad[n] += sum_wall_refs(P, A.we, N, 0, x, y, 1, false);
+    if (q == 0 && near && !on_wall(P, x, y)) A.grad[n] += sum_wall_refs(P, A.we, N, 0, x, y, 1, false);
 }
 
 // Seed lambda_N = dJ/ds_N for J depending on T at interior nodes with weights wtj
@@ -197,7 +199,7 @@ static hipError_t adj_step_t(const void *state, const KParams &P, const AdjBufs 
     const long long N = (long long)P.nx * P.ny;
     const int nb = int((N + ADJ_B - 1) / ADJ_B);
     hipLaunchKernelGGL((k_adj_node<S>), dim3(nb, ADJ_SPLIT), dim3(ADJ_B), 0, st, (const S *)state, P, A);
-    hipLaunchKernelGGL(k_adj_pull, dim3(nb), dim3(ADJ_B), 0, st, P, A);
+    hipLaunchKernelGGL(k_adj_pull, dim3(nb, 18), dim3(ADJ_B), 0, st, P, A);
     return hipGetLastError();
 }
 
