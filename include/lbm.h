@@ -135,9 +135,11 @@ lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_
  * lbm_set_fusion) pairs of steps run as one pass over the populations: the intermediate
  * state of every node is computed from the source buffer in registers and the final
  * state written once, so each pair reads and writes the populations once instead of
- * twice; the results are bitwise those of single steps.  A single step is two launches:
- * the interior columns, then the columns next to the walls x = 0, x = nx - 1 together
- * with the walled rows. */
+ * twice; the results are bitwise those of single steps.  A pass is a main launch on the
+ * context's stream and, on a second stream created by the library (default priority,
+ * ordered with the caller's stream by events), the launches next to the walled rows.  A
+ * single step is two launches: the interior columns, then the columns next to the walls
+ * x = 0, x = nx - 1 together with the walled rows. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
 /* Time steps per pass, 1 or 2.  The default is 2 for FP64 and FP32 storage when nx >= 4
@@ -148,11 +150,11 @@ int32_t lbm_fusion(const lbm_ctx *ctx);
 
 /* As lbm_step (nsteps >= the steps per pass), with HIP events around the launches of every
  * `every`-th pass (every >= 1); returns the mean duration in milliseconds of the main
- * launch of a pass (the interior launch of a single step; the launch of the wavefronts
- * away from walls of a two-step pass) and of the remaining launches of the pass (for
- * two-step passes these run on a second stream, beside the main launch), the number of
- * nodes the main launch updates, and the steps one pass advances (host outputs; any may
- * be NULL).  An odd last step of a two-step schedule runs untimed.  Used for measurement;
+ * launch of a pass (the interior launch of a single step; for a two-step pass the launch
+ * of the wavefronts whose reach holds no wall or only the walls x = 0, x = nx - 1) and of
+ * the remaining launches of the pass (for two-step passes these run on a second stream,
+ * beside the main launch), the number of nodes the main launch writes, and the steps one
+ * pass advances (host outputs; any may be NULL).  An odd last step of a two-step schedule runs untimed.  Used for measurement;
  * events between launches cost a few microseconds per bracketed pass.  Synchronizes on
  * the events, not on the stream. */
 lbm_status lbm_step_timed(lbm_ctx *ctx, int64_t nsteps, int32_t every, double *main_ms_host,
