@@ -121,3 +121,34 @@ def test_shear_wave_decay_clear_fluid(gpu, storage, A):
     rate = np.log(a1 / a2) / (t2 - t1) / (nu_e * k * k)
     _say(f"  {storage} A {A}: decay rate / nu_e k^2 = {rate:.6f}")
     assert abs(rate - 1) < 2e-3
+
+
+def test_internal_heat_generation_table(gpu):
+    """Sidewall-heated porous cavity with an internal heat source (Sec. 4.4): Ra = 1e5,
+    Pr = 0.7, eps = 0.4, 150 x 150, Q = Ra_I alpha_e dT / (Ra L^2), Da in {1e-2, 1e-4},
+    Ra_I in {1e3, 1e5, 1e7}, the six cavities advanced together as one FP64 batch for
+    600k steps.  The hot-wall Nusselt number and theta_max = max (T - T0) / dT against the
+    paper's own values (Table Tab:NatualHG, context): within 1.5 % and 1 %."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table_natual_hg.json")) as fh:
+        rows = json.load(fh)["rows"]
+    cfgs = []
+    for r in rows:
+        cfg = W.cavity(n=150, eps=0.4, Da=r["Da"], Ra=1e5, Pr=0.7, storage="f64")
+        d = gpu.derived(cfg)
+        cfg["Q"] = r["Ra_I"] * d["alpha_e"] * d["dT"] / (1e5 * d["L"] ** 2)
+        cfgs.append(cfg)
+    _say(f"case: {len(cfgs)} heat-generating cavities 150x150 (FP64 batch), 600000 steps")
+    batch = gpu.Batch(cfgs)
+    for k in range(6):
+        batch.step(100000)
+        _say(f"  {(k + 1) * 100000} steps")
+    assert not batch.check().any()
+    for r, p in zip(rows, batch.problems):
+        nu = p.nusselt(0)
+        theta = float(p.fields(gradients=False)["T"].max()) - 0.5
+        _say(f"  Da {r['Da']:g} Ra_I {r['Ra_I']:g}: Nu {nu:.4f} (paper {r['Nu']}), "
+             f"theta_max {theta:.4f} (paper {r['theta_max']})")
+        assert abs(nu - r["Nu"]) <= 0.015 * abs(r["Nu"]), (r, nu)
+        assert abs(theta - r["theta_max"]) <= 0.01 * r["theta_max"], (r, theta)
