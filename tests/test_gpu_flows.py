@@ -152,3 +152,47 @@ def test_internal_heat_generation_table(gpu):
              f"theta_max {theta:.4f} (paper {r['theta_max']})")
         assert abs(nu - r["Nu"]) <= 0.015 * abs(r["Nu"]), (r, nu)
         assert abs(theta - r["theta_max"]) <= 0.01 * r["theta_max"], (r, theta)
+
+
+def test_heat_generating_cavity_cooled_walls(gpu):
+    """Heat-generating fluid in a cavity with all walls isothermal at T_c (Sec. 4.3):
+    Ra_I = 6.4e5, Pr = 7, eps = 1, F_eps = 0, Da in {inf, 1e-2, 1e-4}, 120 x 120,
+    dT = Q L^2 / alpha_e = 10 with T0 = T_c, A and B from Ra_I.  The three cavities run as
+    one FP64 batch for 1.2M steps; theta_max and psi_max (stream function from the x
+    velocity, normalised by L sqrt(g beta dT L) = L Ma c_s) against the paper's own values
+    (Table Tab:SquareIHG, context): within 1.5 % and 4 %."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table_square_ihg.json")) as fh:
+        rows = json.load(fh)["rows"]
+    n = 120
+    cfgs, ds = [], []
+    for r in rows:
+        # Ra carries Ra_I: it sets A, B through the same relation; K infinite for Da = inf
+        cfg = W.cavity(n=n, eps=1.0, Da=1e30 if r["Da"] is None else r["Da"], Ra=6.4e5, Pr=7.0,
+                       storage="f64")
+        cfg["walls"] = [{"kind": "T", "T": 0.0} for _ in range(4)]
+        cfg["T_hot"], cfg["T_cold"] = 5.0, -5.0      # dT = 10 about T0 = T_c = 0
+        cfg["F_eps"] = 0.0
+        cfg["T_init"] = np.zeros((n, n))
+        d = gpu.derived(cfg)
+        cfg["Q"] = 10.0 * d["alpha_e"] / d["L"] ** 2
+        cfgs.append(cfg)
+        ds.append(d)
+    _say(f"case: {len(cfgs)} heat-generating cavities {n}x{n} with cooled walls (FP64 batch), 1200000 steps")
+    batch = gpu.Batch(cfgs)
+    for k in range(4):
+        batch.step(300000)
+        _say(f"  {(k + 1) * 300000} steps")
+    assert not batch.check().any()
+    U = 0.1 / np.sqrt(3.0)
+    for r, p, d in zip(rows, batch.problems, ds):
+        f = p.fields(gradients=False)
+        T, ux = f["T"].cpu().numpy(), f["ux"].cpu().numpy()
+        psi = np.concatenate([np.zeros((1, n)), np.cumsum(0.5 * (ux[1:] + ux[:-1]), axis=0)])
+        psi_max = float(np.abs(psi).max()) / (d["L"] * U)
+        theta = float(T.max()) / 10.0
+        _say(f"  Da {r['Da']}: theta_max {theta:.5f} (paper {r['theta_max']}), "
+             f"psi_max {psi_max:.4e} (paper {r['psi_max']})")
+        assert abs(theta - r["theta_max"]) <= 0.015 * r["theta_max"], (r, theta)
+        assert abs(psi_max - r["psi_max"]) <= 0.04 * r["psi_max"], (r, psi_max)
