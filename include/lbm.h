@@ -44,7 +44,7 @@ typedef enum {
     LBM_ERR_INVALID = 1,      /* a parameter or buffer is unusable; nothing was enqueued    */
     LBM_ERR_DEVICE = 2,       /* a HIP call failed (launch, copy, synchronisation)          */
     LBM_ERR_NONFINITE = 3,    /* a population or field became NaN or infinite               */
-    LBM_ERR_UNSUPPORTED = 4   /* valid request this build does not provide                  */
+    LBM_ERR_UNSUPPORTED = 4   /* valid request the library does not support for this problem */
 } lbm_status;
 
 /* Storage precision of the populations.  F32 and F16 store deviations from the rest
