@@ -196,3 +196,25 @@ def test_heat_generating_cavity_cooled_walls(gpu):
              f"psi_max {psi_max:.4e} (paper {r['psi_max']})")
         assert abs(theta - r["theta_max"]) <= 0.015 * r["theta_max"], (r, theta)
         assert abs(psi_max - r["psi_max"]) <= 0.04 * r["psi_max"], (r, psi_max)
+
+
+def test_cavity_nusselt_table_square1(gpu):
+    """Natural convection in the porous cavity (Sec. 4.2) on the paper's own 120 x 120 grid:
+    the hot-wall Nusselt numbers of the nine Da = 1e-2 cases of Table Tab:Square1 (Ra 1e3-1e5,
+    eps 0.4-0.9, Pr 1), one FP64 batch of 200k steps (steady to 1e-4 by then), within 0.5 %
+    of the paper's own values."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table_square1_nusselt.json")) as fh:
+        rows = [r for r in json.load(fh)["rows"] if r["Da"] == 1e-2]
+    cfgs = [W.cavity(n=r["grid"], eps=r["eps"], Da=r["Da"], Ra=r["Ra"], Pr=1.0, storage="f64") for r in rows]
+    _say(f"case: {len(cfgs)} porous cavities 120x120 (FP64 batch), 200000 steps")
+    batch = gpu.Batch(cfgs)
+    batch.step(100000)
+    _say("  100000 steps")
+    batch.step(100000)
+    assert not batch.check().any()
+    for r, p in zip(rows, batch.problems):
+        nu = p.nusselt(0)
+        _say(f"  Ra {r['Ra']:g} eps {r['eps']}: Nu {nu:.4f} (paper {r['Nu']})")
+        assert abs(nu - r["Nu"]) <= 0.005 * r["Nu"], (r, nu)
