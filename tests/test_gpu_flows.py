@@ -218,3 +218,24 @@ def test_cavity_nusselt_table_square1(gpu):
         nu = p.nusselt(0)
         _say(f"  Ra {r['Ra']:g} eps {r['eps']}: Nu {nu:.4f} (paper {r['Nu']})")
         assert abs(nu - r["Nu"]) <= 0.005 * r["Nu"], (r, nu)
+
+
+def test_clear_fluid_cavity_table(gpu):
+    """Clear-fluid limit of the cavity (eps 0.9999, Da 1e8, Pr 0.71; Sec. 4.2, Table
+    Tab:Square, grids 100-200 as in the paper): the cold-wall Nusselt numbers for
+    Ra 1e3-1e6 from one FP64 batch of 300k steps, within 0.5 % of the paper's own values."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table_square_clear_fluid.json")) as fh:
+        rows = json.load(fh)["rows"]
+    cfgs = [W.cavity(n=r["grid"], eps=0.9999, Da=1e8, Ra=r["Ra"], Pr=0.71, storage="f64") for r in rows]
+    _say(f"case: {len(cfgs)} clear-fluid cavities (FP64 batch), 300000 steps")
+    batch = gpu.Batch(cfgs)
+    for k in range(3):
+        batch.step(100000)
+        _say(f"  {(k + 1) * 100000} steps")
+    assert not batch.check().any()
+    for r, p in zip(rows, batch.problems):
+        nu = p.nusselt(1)           # cold wall x = nx - 1 (heat leaving through it counts positive)
+        _say(f"  Ra {r['Ra']:g} ({r['grid']}^2): cold-wall Nu {nu:.4f} (paper {r['Nu']})")
+        assert abs(nu - r["Nu"]) <= 0.005 * r["Nu"], (r, nu)
