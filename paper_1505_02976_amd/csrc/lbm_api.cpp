@@ -19,10 +19,13 @@ thread_local char g_err[512] = "";
 
 lbm_status fail(lbm_status st, const char *fmt, ...)
 {
+    // formatted into a local buffer first: callers may pass the previous message as an argument
+    char msg[sizeof(g_err)];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    vsnprintf(msg, sizeof(msg), fmt, ap);
     va_end(ap);
+    memcpy(g_err, msg, sizeof(g_err));
     return st;
 }
 

@@ -107,3 +107,14 @@ def test_batch_rejects_mixed_storage(lbm):
     arr[1] = lbm.make_params(cfgs[1])
     single = lbm.workspace_bytes(cfgs[0]) + lbm.workspace_bytes(cfgs[1])
     assert lbm.lib().lbm_batch_workspace_bytes(arr, 2) >= single
+
+
+def test_batch_error_names_problem_and_reason(lbm):
+    # the per-problem message is formatted from the previous message: it must come through intact
+    cfgs = [W.cavity(32, storage="f32"), W.cavity(40, storage="f32")]
+    arr = (lbm._Params * 2)()
+    for k, c in enumerate(cfgs):
+        arr[k] = lbm.make_params(c)
+    arr[1].tau_f = 0.5
+    assert lbm.lib().lbm_batch_workspace_bytes(arr, 2) == 0
+    assert lbm.lib().lbm_last_error().decode() == "problem 1: tau_f and tau_T must exceed 1/2"
