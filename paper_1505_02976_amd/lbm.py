@@ -73,6 +73,10 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1505_02976_amd.build.build()")
+    # torch first: it loads its own HIP and HSA runtimes (same sonames as the system's), and the
+    # library must bind to those.  Loaded the other way round the process holds two of each,
+    # and device memory from torch is not valid in the library's runtime.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, st = C.c_void_p, C.c_int
     L.lbm_last_error.restype = C.c_char_p

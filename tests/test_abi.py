@@ -118,3 +118,17 @@ def test_batch_error_names_problem_and_reason(lbm):
     arr[1].tau_f = 0.5
     assert lbm.lib().lbm_batch_workspace_bytes(arr, 2) == 0
     assert lbm.lib().lbm_last_error().decode() == "problem 1: tau_f and tau_T must exceed 1/2"
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    # loading the library before torch must not bring a second HIP/HSA runtime into the process
+    code = ("from paper_1505_02976_amd import lbm; lbm.lib(); import torch; "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') "
+            "if 'libamdhip64' in l or 'libhsa-runtime64' in l}))")
+    import subprocess, sys
+    out = subprocess.run([sys.executable, "-c", code], cwd=os.path.dirname(os.path.dirname(__file__)),
+                         capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert sum("libamdhip64" in p for p in libs) == 1, libs
+    assert sum("libhsa-runtime64" in p for p in libs) == 1, libs
