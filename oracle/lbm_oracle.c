@@ -24,7 +24,11 @@
  *       applying the boundary scheme.
  *   R3  r_0 is kept in f_0^eq with the full discrete S; the pressure formula has no r_0.
  *   R5  wall nodes: the boundary scheme rebuilds their pre-collision populations, and
- *       they then collide like every other node.
+ *       the node's macroscopic state is the one the scheme assigns: T_b, u_b, p(x_f),
+ *       S(x_f), grad T_b (the force follows from u_b and T_b).  The node collides with
+ *       the equilibrium of that state, which makes its post-collision populations
+ *       f^eq(x_b) + (1 - 1/tau) f^neq(x_f) plus the source terms (the post-collision form
+ *       of the non-equilibrium extrapolation); its reported fields are that state.
  *   R6  Neumann walls use p(x_f) in the boundary equilibrium.
  *   R7  Neumann walls: normal component of grad T prescribed, tangential from x_f.
  *   R8  corners: x_f is the inward diagonal neighbour, u_b = 0; an isothermal wall
@@ -121,9 +125,10 @@ typedef struct {
     double *u_prev, *T_prev;   /* residual snapshot: ux, uy per node; T per node */
     int have_prev;
     int64_t t;
+    struct orc_macro_s *mb;   /* per node: the boundary state of wall nodes (R5) */
 } orc_sim;
 
-typedef struct {
+typedef struct orc_macro_s {
     real eps, T, Gx, Gy, vx, vy, ux, uy, Fx, Fy, p;
     real Sxx, Sxy, Syy, dTx, dTy;
 } orc_macro;
@@ -363,15 +368,15 @@ static void thermal_sources(const orc_sim *s, const orc_macro *m, real Pout[9], 
     }
 }
 
-/* Collision at one node (Eqs. LBEeq and TEqColli). */
-static void collide_node(const orc_sim *s, real eps, const real *f, const real *g,
-                         real *fo, real *go)
+/* Collision of populations f, g with the equilibria and sources of the macroscopic
+ * state m (Eqs. LBEeq and TEqColli). */
+static void collide_state(const orc_sim *s, const orc_macro *mm, const real *f, const real *g,
+                          real *fo, real *go)
 {
-    orc_macro m;
-    node_macro(s, eps, f, g, &m);
+    const orc_macro m = *mm;
     real fe[9], ge[9], Fi[9], Pi[9], Qi[9];
-    feq_full(s, eps, m.p, m.ux, m.uy, m.Sxx, m.Sxy, m.Syy, fe);
-    geq_full(s, eps, m.T, m.ux, m.uy, m.p, m.dTx, m.dTy, ge);
+    feq_full(s, m.eps, m.p, m.ux, m.uy, m.Sxx, m.Sxy, m.Syy, fe);
+    geq_full(s, m.eps, m.T, m.ux, m.uy, m.p, m.dTx, m.dTy, ge);
     force_terms(s, &m, Fi);
     thermal_sources(s, &m, Pi, Qi);
     const double tf = s->prm.tau_f, tT = s->prm.tau_T;
@@ -379,6 +384,15 @@ static void collide_node(const orc_sim *s, real eps, const real *f, const real *
         fo[i] = f[i] - (f[i] - fe[i]) / tf + Fi[i];
         go[i] = g[i] - (g[i] - ge[i]) / tT + Pi[i] + Qi[i];
     }
+}
+
+/* Collision at an interior node: its state from its own populations. */
+static void collide_node(const orc_sim *s, real eps, const real *f, const real *g,
+                         real *fo, real *go)
+{
+    orc_macro m;
+    node_macro(s, eps, f, g, &m);
+    collide_state(s, &m, f, g, fo, go);
 }
 
 /* ------------------------------------------------------------------------------ */
@@ -395,11 +409,29 @@ static void wall_of(const orc_sim *s, int x, int y, int *xw, int *yw)
     if (!P->periodic_y) { if (y == 0) *yw = 2; else if (y == P->ny - 1) *yw = 3; }
 }
 
+static int is_wall_node(const orc_sim *s, int k)
+{
+    int xw, yw;
+    wall_of(s, k % s->prm.nx, k / s->prm.nx, &xw, &yw);
+    return xw >= 0 || yw >= 0;
+}
+
+/* Macroscopic state of node k at the current time: R5 for wall nodes. */
+static void state_of(const orc_sim *s, int k, orc_macro *m)
+{
+    if (is_wall_node(s, k)) *m = s->mb[k];
+    else node_macro(s, s->eps[k], s->f + 9 * k, s->g + 9 * k, m);
+}
+
 static void collide_all(orc_sim *s)
 {
 #pragma omp parallel for schedule(static)
-    for (int k = 0; k < s->n; ++k)
-        collide_node(s, s->eps[k], s->f + 9 * k, s->g + 9 * k, s->fs + 9 * k, s->gs + 9 * k);
+    for (int k = 0; k < s->n; ++k) {
+        if (is_wall_node(s, k))
+            collide_state(s, &s->mb[k], s->f + 9 * k, s->g + 9 * k, s->fs + 9 * k, s->gs + 9 * k);
+        else
+            collide_node(s, s->eps[k], s->f + 9 * k, s->g + 9 * k, s->fs + 9 * k, s->gs + 9 * k);
+    }
 }
 
 /* Streaming (push): f_i(x + c_i, t + 1) = f*_i(x, t); periodic directions wrap,
@@ -472,6 +504,24 @@ static void nees_node(orc_sim *s, int x, int y, int xw, int yw)
     real ge_b[9];
     geq_full(s, eb, Tb, ubx, uby, mf.p, gbx, gby, ge_b);
     for (int i = 0; i < 9; ++i) s->g[9 * kb + i] = ge_b[i] + (gf[i] - ge_f[i]);
+
+    /* the node's state (R5): the boundary values, with G and F (Eq. ForceEq) at u_b, T_b */
+    const orc_derived *D = &s->d;
+    orc_macro *m = &s->mb[kb];
+    real Feps, c0, c1;
+    porous_coeffs(s, eb, &Feps, &c0, &c1);
+    m->eps = eb;
+    m->T = Tb;
+    m->Gx = P->ax;
+    m->Gy = P->ay + D->gbeta * (Tb - D->T0);
+    m->vx = ubx; m->vy = uby;
+    m->ux = ubx; m->uy = uby;
+    real umag = R_SQRT(ubx * ubx + uby * uby);
+    m->Fx = -eb * D->nu / D->K * ubx - eb * Feps / sqrt(D->K) * umag * ubx + eb * m->Gx;
+    m->Fy = -eb * D->nu / D->K * uby - eb * Feps / sqrt(D->K) * umag * uby + eb * m->Gy;
+    m->p = mf.p;
+    m->Sxx = mf.Sxx; m->Sxy = mf.Sxy; m->Syy = mf.Syy;
+    m->dTx = gbx; m->dTy = gby;
 }
 
 static void boundary_all(orc_sim *s)
@@ -522,6 +572,7 @@ orc_sim *orc_create(const orc_params *p, const real *eps_field, const real *T_in
     s->gs = (real *)malloc(sizeof(real) * 9 * s->n);
     s->u_prev = (double *)calloc(2 * (size_t)s->n, sizeof(double));
     s->T_prev = (double *)calloc((size_t)s->n, sizeof(double));
+    s->mb = (orc_macro *)calloc((size_t)s->n, sizeof(orc_macro));
     for (int k = 0; k < s->n; ++k) s->eps[k] = eps_field ? eps_field[k] : (real)p->eps;
     for (int y = 0; y < p->ny; ++y)
         for (int x = 0; x < p->nx; ++x) {
@@ -552,7 +603,7 @@ void orc_destroy(orc_sim *s)
 {
     if (!s) return;
     free(s->eps); free(s->f); free(s->g); free(s->fs); free(s->gs);
-    free(s->u_prev); free(s->T_prev);
+    free(s->u_prev); free(s->T_prev); free(s->mb);
     free(s);
 }
 
@@ -569,14 +620,15 @@ void orc_step(orc_sim *s, int64_t nsteps)
 
 int64_t orc_time(const orc_sim *s) { return s->t; }
 
-/* Macroscopic fields at the current time; any output may be NULL. */
+/* Macroscopic fields at the current time (wall nodes: their boundary state, R5); any
+ * output may be NULL. */
 void orc_macro_fields(const orc_sim *s, real *p, real *ux, real *uy, real *T,
                       real *Sxx, real *Sxy, real *Syy, real *dTx, real *dTy)
 {
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < s->n; ++k) {
         orc_macro m;
-        node_macro(s, s->eps[k], s->f + 9 * k, s->g + 9 * k, &m);
+        state_of(s, k, &m);
         if (p) p[k] = m.p;
         if (ux) ux[k] = m.ux;
         if (uy) uy[k] = m.uy;
@@ -650,7 +702,7 @@ int orc_residual(orc_sim *s, double *r_u, double *r_T)
     int first = !s->have_prev;
     for (int k = 0; k < s->n; ++k) {
         orc_macro m;
-        node_macro(s, s->eps[k], s->f + 9 * k, s->g + 9 * k, &m);
+        state_of(s, k, &m);
         double ux = R_RE(m.ux), uy = R_RE(m.uy), T = R_RE(m.T);
         double dux = ux - s->u_prev[2 * k], duy = uy - s->u_prev[2 * k + 1];
         num_u += sqrt(dux * dux + duy * duy);
