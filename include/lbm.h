@@ -54,7 +54,10 @@ typedef enum {
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 } lbm_storage;
 
 /* Thermal wall condition (Sec. 3.4): isothermal (Eqs. TeEBounDFEQ, TNEESAp) or prescribed
- * normal temperature derivative (Eq. TNEESApGra). */
+ * normal temperature derivative (Eq. TNEESApGra).  A wall node's macroscopic state is the
+ * one the boundary scheme assigns to it (T_b, the wall velocity, p and S of the reference
+ * node x_f, the boundary temperature gradient); the node collides with that state and
+ * lbm_moments / lbm_gradients report it. */
 typedef enum { LBM_T_DIRICHLET = 0, LBM_T_NEUMANN = 1 } lbm_twall;
 
 /* One wall.  The velocity condition is always a prescribed wall velocity (ux, uy).

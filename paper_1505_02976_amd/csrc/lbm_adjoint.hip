@@ -102,8 +102,9 @@ k_adj_node(const S *__restrict__ src, KParams P, AdjBufs A)
             const Dual td(Tdff, j == 18 ? 1.0 : 0.0);
             const EpsC<Dual> cb = eps_coeffs<Dual>(P, Dual(eb, j == 19 ? 1.0 : 0.0));
             const EpsC<Dual> cf = eps_coeffs<Dual>(P, Dual(ef, j == 20 ? 1.0 : 0.0));
-            wall_from_ref<Dual>(P, k, x, y, cf, cb, ff, gf, td, f, g);
-            dual_update(f, g, P, k, cb);
+            Macro<Dual> mb;
+            wall_from_ref<Dual>(P, k, x, y, cf, cb, ff, gf, td, f, g, mb);
+            node_collide<Dual>(f, g, mb, Dual(P.T0), k, cb);   // the state the boundary scheme assigns
             double acc = 0.0;
 #pragma unroll
             for (int i = 0; i < 9; ++i) acc += lam[i] * f[i].d + lam[9 + i] * g[i].d;

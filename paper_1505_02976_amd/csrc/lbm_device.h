@@ -664,11 +664,16 @@ __device__ __forceinline__ R gather_Td(const S *__restrict__ src, const KParams 
 // Non-equilibrium extrapolation (Sec. 3.4, Eqs. FNEESEQFIN, NEESVel, TeEBounDFEQ,
 // TNEESAp, TNEESApGra): pre-collision populations of wall node (x, y) from the streamed
 // populations ff, gf of its reference node x_f and, on prescribed-gradient walls, Td of
-// the next node x_ff.  f, g may alias ff, gf.
+// the next node x_ff.  f, g may alias ff, gf.  mb receives the node's macroscopic state,
+// the one the scheme assigns to x_b: T_b, u_b, p and S of x_f, the boundary grad T, and
+// G and F (Eq. ForceEq) at u_b and T_b.  The node collides with that state (wall_collide),
+// which gives the post-collision form of the extrapolation,
+// f^eq(x_b) + (1 - 1/tau) f^neq(x_f) plus the source terms.
 template <typename R>
 __device__ __forceinline__ void wall_from_ref(const KParams &P, const Cst<R> &k, int x, int y,
                                               const EpsC<R> &ef, const EpsC<R> &eb,
-                                              const R *ff, const R *gf, R Tdff, R *f, R *g)
+                                              const R *ff, const R *gf, R Tdff, R *f, R *g,
+                                              Macro<R> &mb)
 {
     const WallInfo w = wall_info(P, x, y);
     Macro<R> mf;
@@ -678,8 +683,13 @@ __device__ __forceinline__ void wall_from_ref(const KParams &P, const Cst<R> &k,
     const R epf = ef.eps * mf.p;
 
     R ubx = R(0), uby = R(0);
-    if (w.xw >= 0 && w.yw < 0) { ubx = R(P.wall_ux[w.xw]); uby = R(P.wall_uy[w.xw]); }
-    if (w.yw >= 0 && w.xw < 0) { ubx = R(P.wall_ux[w.yw]); uby = R(P.wall_uy[w.yw]); }
+    double ubm = 0.0;              // |u_b|, a constant of the wall
+    const int vw = (w.xw >= 0 && w.yw < 0) ? w.xw : (w.yw >= 0 && w.xw < 0) ? w.yw : -1;
+    if (vw >= 0) {
+        ubx = R(P.wall_ux[vw]);
+        uby = R(P.wall_uy[vw]);
+        ubm = sqrt(P.wall_ux[vw] * P.wall_ux[vw] + P.wall_uy[vw] * P.wall_uy[vw]);
+    }
     const R epb = eb.eps * mf.p;   // eps at the wall node, pressure of x_f
 
 #pragma unroll
@@ -707,19 +717,40 @@ __device__ __forceinline__ void wall_from_ref(const KParams &P, const Cst<R> &k,
         const R gef = geq_i<R>(i, mf.Td, Tf, mf.ux, mf.uy, ef.ieps, epf, mf.gx, mf.gy, k);
         g[i] = geb + (gf[i] - gef);
     }
+
+    mb.Td = Tdb;
+    mb.ux = ubx;
+    mb.uy = uby;
+    const R dl = eb.dlin + eb.dquad * R(ubm);
+    mb.Fx = eb.eps * k.ax - dl * ubx;
+    mb.Fy = eb.eps * (k.ay + k.gb * Tdb) - dl * uby;
+    mb.p = mf.p;
+    mb.Sxx = mf.Sxx;
+    mb.Sxy = mf.Sxy;
+    mb.Syy = mf.Syy;
+    mb.gx = gbx;
+    mb.gy = gby;
+}
+
+// Collision of wall node (x, y) with the state mb the boundary scheme assigned to it.
+template <typename R>
+__device__ __forceinline__ void wall_collide(R *f, R *g, const Macro<R> &mb, const KParams &P, int x, int y)
+{
+    node_collide<R>(f, g, mb, R(P.T0), cst<R>(P), eps_at<R>(P, x, y));
 }
 
 // The boundary scheme with the reference nodes' populations gathered from memory.
 template <typename S, typename R>
 __device__ __forceinline__ void wall_populations(const S *__restrict__ src, const KParams &P,
-                                                 const Cst<R> &k, int x, int y, R *f, R *g)
+                                                 const Cst<R> &k, int x, int y, R *f, R *g,
+                                                 Macro<R> &mb)
 {
     const WallInfo w = wall_info(P, x, y);
     R ff[9], gf[9];
     gather<S, R>(src, P, x + w.dx, y + w.dy, ff, gf);
     R Tdff = R(0);
     if (thermal_dirichlet_wall(P, w) < 0) Tdff = gather_Td<S, R>(src, P, k, x + 2 * w.dx, y + 2 * w.dy);
-    wall_from_ref<R>(P, k, x, y, eps_at<R>(P, x + w.dx, y + w.dy), eps_at<R>(P, x, y), ff, gf, Tdff, f, g);
+    wall_from_ref<R>(P, k, x, y, eps_at<R>(P, x + w.dx, y + w.dy), eps_at<R>(P, x, y), ff, gf, Tdff, f, g, mb);
 }
 
 // Wall-node slot s -> (x, y); returns false for slots that are not wall nodes of this

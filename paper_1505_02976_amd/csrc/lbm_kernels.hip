@@ -141,9 +141,11 @@ __device__ __forceinline__ void bulk_tile(const S *__restrict__ src, S *__restri
                 if (!in1) gather<S, RC>(src, P, x + dx, y, f[k], g[k]);
                 if (!in2 && thermal_dirichlet_wall(P, wall_info(P, x, y)) < 0)
                     Tdff = gather_Td<S, RC>(src, P, c, x + 2 * dx, y);
+                Macro<RC> mb;
                 wall_from_ref<RC>(P, c, x, y, eps_at<RC>(P, x + dx, y), eps_at<RC>(P, x, y),
-                                  f[k], g[k], Tdff, f[k], g[k]);
-                act[k] = true;
+                                  f[k], g[k], Tdff, f[k], g[k], mb);
+                wall_collide<RC>(f[k], g[k], mb, P, x, y);
+                store_node<S, RC>(dst, P, x, y, f[k], g[k]);
             }
         }
     }
@@ -157,7 +159,7 @@ __device__ __forceinline__ void bulk_tile(const S *__restrict__ src, S *__restri
 }
 
 // One node of the walled rows y = 0 and y = ny - 1 (slot s < nwall_rows): boundary scheme
-// -> moments -> collide -> store.
+// -> collision with the state it assigns -> store.
 template <typename S>
 __device__ __forceinline__ void wall_node(const S *__restrict__ src, S *__restrict__ dst,
                                           const KParams &P, int s)
@@ -166,8 +168,9 @@ __device__ __forceinline__ void wall_node(const S *__restrict__ src, S *__restri
     if (s >= P.nwall_rows || !wall_slot(P, s, x, y)) return;
     using M = typename Prec<S>::M;
     M f[9], g[9];
-    wall_populations<S, M>(src, P, make_cst<M>(P), x, y, f, g);
-    node_update<M, M>(f, g, P, x, y);
+    Macro<M> mb;
+    wall_populations<S, M>(src, P, make_cst<M>(P), x, y, f, g, mb);
+    wall_collide<M>(f, g, mb, P, x, y);
     store_node<S, M>(dst, P, x, y, f, g);
 }
 
@@ -346,10 +349,9 @@ k_fields_wall(const S *__restrict__ src, KParams P, FieldOut o)
     if (s >= P.nwall || !wall_slot(P, s, x, y)) return;
     using M = typename Prec<S>::M;
     M f[9], g[9];
-    wall_populations<S, M>(src, P, make_cst<M>(P), x, y, f, g);
-    Macro<M> m;
-    node_macro_full<M>(f, g, M(P.T0), make_cst<M>(P), eps_at<M>(P, x, y), m);
-    write_fields<M>(o, P, x, y, m);
+    Macro<M> mb;   // a wall node's fields are the state the boundary scheme assigns
+    wall_populations<S, M>(src, P, make_cst<M>(P), x, y, f, g, mb);
+    write_fields<M>(o, P, x, y, mb);
 }
 
 // ---------------------------------------------------------------------------------
@@ -426,10 +428,9 @@ k_resid_wall(const S *__restrict__ src, KParams P, double *snap, double *partial
     if (s < P.nwall && wall_slot(P, s, x, y)) {
         using M = typename Prec<S>::M;
         M f[9], g[9];
-        wall_populations<S, M>(src, P, make_cst<M>(P), x, y, f, g);
-        Macro<M> m;
-        node_macro_full<M>(f, g, M(P.T0), make_cst<M>(P), eps_at<M>(P, x, y), m);
-        resid_node<M>(P, x, y, f, g, m, snap, v);
+        Macro<M> mb;
+        wall_populations<S, M>(src, P, make_cst<M>(P), x, y, f, g, mb);
+        resid_node<M>(P, x, y, f, g, mb, snap, v);
     }
     block_sum5(v, partial + 5 * (long long)blockIdx.x);
 }

@@ -90,11 +90,14 @@ template <> __device__ __forceinline__ float as_stored<__half, float>(float v, c
 template <typename S, typename R>
 __device__ __forceinline__ void p1_node(const S *__restrict__ src, const KParams &P, int x, int y, R *f, R *g)
 {
-    if (on_wall(P, x, y))
-        wall_populations<S, R>(src, P, make_cst<R>(P), x, y, f, g);
-    else
+    if (on_wall(P, x, y)) {
+        Macro<R> mb;
+        wall_populations<S, R>(src, P, make_cst<R>(P), x, y, f, g, mb);
+        wall_collide<R>(f, g, mb, P, x, y);
+    } else {
         gather<S, R>(src, P, x, y, f, g);
-    node_update<R, typename Prec<S>::M>(f, g, P, x, y);
+        node_update<R, typename Prec<S>::M>(f, g, P, x, y);
+    }
 }
 
 // Instance that runs the wavefront of column chunk cxi and row band cyi: lean (no wall
@@ -261,8 +264,11 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
                 const R Tdff = __shfl(Td_own, s2);
                 if (vwall && xout) {
                     const R Tn = thermal_dirichlet_wall(P, wall_info(P, x, orow)) < 0 ? Tdff : R(0);
+                    Macro<R> mb;
                     wall_from_ref<R>(P, c, x, orow, eps_at<R>(P, x + dx, orow), eps_at<R>(P, x, orow),
-                                     ff, gf, Tn, pf, pg);
+                                     ff, gf, Tn, pf, pg, mb);
+                    wall_collide<R>(pf, pg, mb, P, x, orow);
+                    store_node<S, R>(dst, P, x, orow, pf, pg);
                 }
             }
             if constexpr (XW) {
@@ -287,7 +293,7 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
                     }
                 }
             }
-            if (xout && !(XW && vwall)) {
+            if (xout && !((XW || FULL) && vwall)) {     // wall nodes: above, or after the walk
                 node_update<R, M>(pf, pg, P, x, orow);
                 store_node<S, R>(dst, P, x, orow, pf, pg);
             }
@@ -317,9 +323,10 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
             for (int i = 0; i < 9; ++i) { ff[i] = q[i]; gf[i] = q[9 + i]; }
             const Cst<R> &c = make_cst<R>(P);
             const R Tn = thermal_dirichlet_wall(P, wall_info(P, xw, orow)) < 0 ? q[18] : R(0);
+            Macro<R> mb;
             wall_from_ref<R>(P, c, xw, orow, eps_at<R>(P, xw + dx, orow), eps_at<R>(P, xw, orow), ff, gf, Tn,
-                             pf, pg);
-            node_update<R, M>(pf, pg, P, xw, orow);
+                             pf, pg, mb);
+            wall_collide<R>(pf, pg, mb, P, xw, orow);
             store_node<S, R>(dst, P, xw, orow, pf, pg);
         }
     }
@@ -357,8 +364,11 @@ __device__ __forceinline__ void march2_any(const S *__restrict__ src, S *__restr
 
 // items: wavefront indices cyi * ncx + cxi of this launch (the main launch lists the xwall
 // wavefronts first, so that they start beside the first lean ones rather than at the tail).
+// The FP64 full launch is held to two waves per SIMD (256 registers, a few spilled): it runs
+// beside the main launch, whose FP64 waves take 217 of a SIMD's 512 registers per lane, and
+// a full wave of more than 295 would wait for a SIMD with no main wave on it.
 template <typename S, int LAUNCH>
-__global__ void __launch_bounds__(S2_B)
+__global__ void __launch_bounds__(S2_B, (LAUNCH == STEP2_FULL && sizeof(S) == 8) ? 2 : 1)
 k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KParams P, KParams Pm,
         const int *__restrict__ items, int nitems, int ncx)
 {
@@ -404,8 +414,9 @@ __device__ __forceinline__ void rows2_node(const S *__restrict__ scr, S *__restr
     gather<S, M>(scr, Pm, x + w.dx, ym + w.dy, ff, gf);
     M Tdff = M(0);
     if (thermal_dirichlet_wall(P, w) < 0) Tdff = gather_Td<S, M>(scr, Pm, k, x + 2 * w.dx, ym + 2 * w.dy);
-    wall_from_ref<M>(P, k, x, y, eps_at<M>(P, x + w.dx, y + w.dy), eps_at<M>(P, x, y), ff, gf, Tdff, f, g);
-    node_update<M, M>(f, g, P, x, y);
+    Macro<M> mb;
+    wall_from_ref<M>(P, k, x, y, eps_at<M>(P, x + w.dx, y + w.dy), eps_at<M>(P, x, y), ff, gf, Tdff, f, g, mb);
+    wall_collide<M>(f, g, mb, P, x, y);
     store_node<S, M>(dst, P, x, y, f, g);
 }
 
