@@ -61,9 +61,18 @@ def test_porous_poiseuille_with_conduction(gpu):
     assert max(e32) < 1e-4
 
 
-@pytest.mark.parametrize("tau", [0.8, 1.0])
+@pytest.mark.parametrize("tau", [0.55, 0.8, 1.0, 1.2, 2.0])
 def test_mixed_convection_channel(gpu, tau):
+    """Mixed convection in the porous channel (Sec. 4.1) at the five relaxation times of the
+    paper's accuracy study, A and B from Re and Pr as the section gives them: second-order
+    convergence of u_x, T and their gradients against the closed forms.  The errors grow away
+    from tau = 1 (as the paper's own accuracy figure shows); at tau = 2 the finest grid's
+    shear-rate error is 1.1e-2 and the normal-velocity error 1.1e-3."""
     ns = (17, 33, 65)
+    e_max, v_max = (1.5e-2, 2e-3) if tau > 1.5 else (1e-2, 1e-3)
+    # FP32 storage against FP64: over the 192k steps of the finest grid it moves E(T) by
+    # about 6 % at tau = 0.8-1.0, and E(T) and E(dT/dy) by 12 % and 15 % at tau = 0.55
+    f32_rel = 0.25 if tau < 0.6 else 0.1
     res, res32 = [], []
     for ny in ns:
         cfg, steps, exact = mixed_convection_cfg(ny, tau)
@@ -76,12 +85,10 @@ def test_mixed_convection_channel(gpu, tau):
         _say(f"  tau {tau} ny {ny}: {steps} steps, FP64 E = {np.round(res[-1], 7)}, FP32 E = {np.round(res32[-1], 7)}")
     for k, lo in zip(range(4), (1.5, 1.75, 1.75, 1.75)):
         e1, e2 = res[1][k], res[2][k]
-        assert e2 < 1e-2, (k, res)
+        assert e2 < e_max, (k, res)
         assert order(e1, e2, ns[1], ns[2]) > lo, (k, res)
-        # FP32 storage stays well below the discretisation error (over 192k steps it adds
-        # about 6 % to E(T) on the finest grid)
-        assert abs(res32[2][k] - e2) < 0.1 * e2, (k, res32)
-    assert res[-1][4] < 1e-3
+        assert abs(res32[2][k] - e2) < f32_rel * e2, (k, res32)
+    assert res[-1][4] < v_max
 
 
 @pytest.mark.parametrize("kind", ["dirichlet", "neumann"])
