@@ -68,7 +68,7 @@ def forchheimer_bvp(c, Feps, npts=20001):
 
 
 
-def mixed_convection_cfg(ny, tau, Re=5.0):
+def mixed_convection_cfg(ny, tau, Re=5.0, A=None):
     """Sec. 4.1: porous channel with a moving hot top wall and injection through the
     walls; eps 0.6, Ra 100, Pr 1, Da 0.01, F_eps = 0, u0 = v0.  Returns (cfg, steps,
     exact) with exact = (u_x, T, du_x/dy, dT/dy, v0) on the nodes.
@@ -76,13 +76,20 @@ def mixed_convection_cfg(ny, tau, Re=5.0):
     The boundary scheme does not balance the normal mass flux exactly, so the pressure
     level drifts slowly (at a rate that falls roughly 15-fold per grid doubling) and the
     residual never settles to round-off; the run therefore stops at a fixed diffusive
-    time 3 H^2 / nu, after which the slowest transient has decayed by e^-30."""
+    time 3 H^2 / nu, after which the slowest transient has decayed by e^-30.
+
+    With A given (the accuracy study at fixed tau, Sec. 4.1), B = A, the viscosity is
+    cs^2 (tau - A - 1/2) and the injection speed v0 = Re nu / H keeps Re."""
     H = ny - 1
     eps, Da, Pr, J = 0.6, 1e-2, 1.0, 1.0
-    v0 = 0.01 * 32.0 / H
+    if A is None:
+        v0 = 0.01 * 32.0 / H
+        nu = H * v0 / Re
+        A = tau - 0.5 - nu / CS2
+    else:
+        nu = CS2 * (tau - A - 0.5)
+        v0 = Re * nu / H
     u0 = v0
-    nu = H * v0 / Re
-    A = tau - 0.5 - nu / CS2
     B = tau - 0.5 - nu / Pr / CS2
     K = Da * H * H
     cfg = W.channel(ny=ny, A=A, B=B, tau=tau, eps=eps, Da=Da, F_eps=0.0, ax=0.0,

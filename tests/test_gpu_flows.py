@@ -91,6 +91,32 @@ def test_mixed_convection_channel(gpu, tau):
     assert res[-1][4] < v_max
 
 
+def test_mixed_convection_channel_A_sweep(gpu):
+    """The other half of the accuracy study of Sec. 4.1: tau_f = tau_T = 1 with A = B in
+    {-0.2, 0, 0.2, 0.4} at Re 5, Pr 1 (viscosity cs^2 (1/2 - A), injection speed Re nu / H).
+    Second-order convergence of u_x, T and their gradients against the closed forms for every
+    A, and the paper's finding on the velocity: its error is smallest near A = 0 and grows on
+    both sides (finest grid: 6.5e-3, 1.0e-3, 4.5e-3, 9.7e-3)."""
+    ns = (17, 33, 65)
+    As = (-0.2, 0.0, 0.2, 0.4)
+    finest = []
+    for A in As:
+        res = []
+        for ny in ns:
+            cfg, steps, exact = mixed_convection_cfg(ny, 1.0, A=A)
+            sim = gpu.Sim(dict(cfg, storage="f64"))
+            sim.step(steps)
+            res.append(mixed_convection_errors(_fields(sim), exact))
+        _say(f"  A = B = {A}: finest E = {np.round(res[-1], 7)}, orders "
+             f"{[round(float(order(res[1][k], res[2][k], ns[1], ns[2])), 3) for k in range(4)]}")
+        for k, lo in zip(range(4), (1.5, 1.75, 1.75, 1.75)):
+            assert res[2][k] < 1.5e-2, (A, k, res)
+            assert order(res[1][k], res[2][k], ns[1], ns[2]) > lo, (A, k, res)
+        assert res[2][4] < 1e-3, (A, res)
+        finest.append(res[2][0])
+    assert finest[1] < finest[0] and finest[1] < finest[2] < finest[3], finest
+
+
 @pytest.mark.parametrize("kind", ["dirichlet", "neumann"])
 def test_conduction_fixed_point(gpu, kind):
     ny, slope = 24, 0.8 / 23
