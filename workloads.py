@@ -189,3 +189,58 @@ def ensemble(count=256, seed=0, side_lo=64, side_hi=512, storage="f32", max_cell
         cfg = cavity(n=n, eps=eps, Da=Da, Ra=Ra, Pr=1.0, seed=seed * 100003 + k, storage=storage)
         out.append(cfg)
     return out
+
+
+# ------------------------------------------------------------------------------------
+# Three dimensions (D3Q19): periodic in x and y, walls at z = 0 and z = nz - 1 (or z
+# periodic too).  Walls are listed bottom (z = 0) then top; "u" is the wall velocity.
+# ------------------------------------------------------------------------------------
+def layer3d(nx=64, ny=64, nz=32, eps=0.6, Da=1e-2, Ra=1e4, Pr=1.0, seed=0, storage="f64", amp=1e-3,
+            tau=1.0, Ma=0.1):
+    """Porous layer heated from below: isothermal walls, T_hot at z = 0 and T_cold at the
+    top, buoyancy along +z, a conduction profile plus uniform noise of +-amp inside."""
+    rng = np.random.default_rng(seed)
+    z = np.arange(nz, dtype=np.float64) / (nz - 1)
+    T = np.broadcast_to((1.0 - z)[:, None, None], (nz, ny, nx)).copy()
+    T[1:-1] += rng.uniform(-amp, amp, size=(nz - 2, ny, nx))
+    return {
+        "nx": nx, "ny": ny, "nz": nz, "periodic_z": 0,
+        "walls": [{"kind": "T", "T": 1.0}, {"kind": "T", "T": 0.0}],
+        "Da": Da, "Ra": Ra, "Pr": Pr, "J": 1.0, "Ma": Ma, "sigma": 1.0, "Q": 0.0,
+        "tau_f": tau, "tau_T": tau, "A": None, "B": None, "eps": eps, "a": (0.0, 0.0, 0.0),
+        "T_hot": 1.0, "T_cold": 0.0, "F_eps": None, "T_init": T, "storage": storage,
+    }
+
+
+def random_case3d(seed, nx, ny, nz, periodic_z=0, storage="f64"):
+    """A randomised 3-D problem with a non-trivial initial flow and temperature for parity
+    tests: random Da, Ra in [1e2, 1e3], Pr, tau, A, B, eps, forcing and heat source, wall
+    kinds and wall velocities, smooth random initial u and T."""
+    rng = np.random.default_rng(seed)
+    tau_f, tau_T = rng.uniform(0.7, 1.3), rng.uniform(0.7, 1.3)
+    walls = []
+    for k in range(2):
+        kind = "T" if rng.uniform() < 0.6 else "dTdn"
+        walls.append({"kind": kind, "T": float(rng.uniform(0.0, 1.0)), "dTdn": float(rng.uniform(-0.01, 0.01)),
+                      "u": tuple(float(v) for v in rng.uniform(-0.02, 0.02, size=3) * np.array([1.0, 1.0, 0.0]))})
+    shape = (nz, ny, nx)
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    def smooth(amp):
+        f = np.zeros(shape)
+        for _ in range(3):
+            kx, ky, kz = rng.integers(0, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi, size=3)
+            f += np.cos(2 * np.pi * kx * xx / nx + ph[0]) * np.cos(2 * np.pi * ky * yy / ny + ph[1]) \
+                * np.cos(np.pi * kz * zz / max(nz - 1, 1) + ph[2])
+        return amp * f / max(np.abs(f).max(), 1e-30)
+    u = np.stack([smooth(0.02), smooth(0.02), smooth(0.01)])
+    T = 0.5 + smooth(0.3)
+    return {
+        "nx": nx, "ny": ny, "nz": nz, "periodic_z": periodic_z, "walls": walls,
+        "L": 200.0, "Da": float(10 ** rng.uniform(-3, -1)), "Ra": float(10 ** rng.uniform(2, 3)),
+        "Pr": float(rng.uniform(0.7, 2.0)), "J": 1.0, "Ma": 0.1, "sigma": float(rng.uniform(0.8, 1.2)),
+        "Q": float(rng.uniform(0.0, 1e-5)), "tau_f": tau_f, "tau_T": tau_T,
+        "A": float(rng.uniform(-0.1, tau_f - 0.55)), "B": float(rng.uniform(-0.1, tau_T - 0.55)),
+        "eps": float(rng.uniform(0.4, 0.95)), "a": tuple(float(v) for v in rng.uniform(-1e-5, 1e-5, size=3)),
+        "T_hot": 1.0, "T_cold": 0.0, "F_eps": None, "T_init": T, "u_init": u, "storage": storage,
+    }
