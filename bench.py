@@ -175,6 +175,34 @@ def adjoint_run(lbm, torch, W, n=256, steps=5000, storage="f32"):
     return res
 
 
+def three_d_run(torch, W, shape=(192, 192, 96), steps=200, warmup=20):
+    """The 3-D (D3Q19) path on a porous layer heated from below (Ra 1e4, Da 1e-2, eps 0.6),
+    FP64 and FP32 storage: one launch per step, each reading and writing 2 x 19 populations
+    per node, timed with events on the stream the launches go to."""
+    from paper_1505_02976_amd import lbm3d
+    nx, ny, nz = shape
+    nodes = nx * ny * nz
+    out = {"workload": f"porous layer heated from below {nx}x{ny}x{nz}, Ra 1e4, Da 1e-2, eps 0.6, D3Q19",
+           "nodes": nodes}
+    for storage, es in (("f64", 8), ("f32", 4)):
+        sim = lbm3d.Sim3(W.layer3d(nx, ny, nz, Ra=1e4, Da=1e-2, storage=storage))
+        sim.step(warmup)
+        st = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st.synchronize()
+        a.record(st)
+        sim.step(steps)
+        b.record(st)
+        b.synchronize()
+        ms = a.elapsed_time(b) / steps
+        bytes_step = nodes * 2 * 38 * es
+        out[storage] = {"mlups": nodes / (ms * 1e3), "ms_per_step": ms, "bytes_per_step": bytes_step,
+                        "GBps": bytes_step / (ms * 1e6), "frac": bytes_step / (ms * 1e6) / HBM_PEAK_GBS}
+        sim.close()
+        del sim
+    return out
+
+
 def accuracy(lbm, W, n=128, tol=1e-9, max_steps=200000):
     """Steady average Nusselt number of the hot wall on the n x n cavity per precision."""
     out = {}
@@ -233,6 +261,7 @@ def main():
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--fusion", type=int, default=None, choices=(1, 2),
                     help="time steps per pass (default: the library's choice, 2 on large grids)")
     ap.add_argument("--ensemble-steps", type=int, default=10000)
@@ -291,6 +320,11 @@ def main():
         adj = adjoint_run(lbm, torch, W)
         log(f"bench: adjoint forward {adj['forward_s']:.2f} s, backward {adj['backward_s']:.2f} s "
             f"({adj['backward_us_per_step']:.0f} us per step)")
+    td = None
+    if not args.no_3d:
+        td = three_d_run(torch, W)
+        log(f"bench: 3-D f64 {td['f64']['mlups']:.0f} MLUPS ({td['f64']['GBps']:.0f} GB/s), "
+            f"f32 {td['f32']['mlups']:.0f} MLUPS ({td['f32']['GBps']:.0f} GB/s)")
     acc = None if args.no_accuracy else accuracy(lbm, W)
     cpu = None if args.no_cpu else cpu_baseline(W, n)
 
@@ -321,6 +355,7 @@ def main():
         "one_step_per_pass": one_step,
         "ensemble": ens,
         "adjoint": adj,
+        "three_d": td,
         "accuracy": acc,
         "cpu_baseline": cpu,
     }

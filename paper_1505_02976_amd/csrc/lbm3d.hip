@@ -1,0 +1,505 @@
+// Three-dimensional path: the modified lattice-BGK model (Secs. 2-3) on the D3Q19 lattice
+// for the flow and the temperature populations, periodic in x and y, with z periodic or
+// bounded by walls under the non-equilibrium extrapolation (Sec. 3.4).  One thread per
+// node: pull streaming from the previous step's post-collision buffer, the node's
+// macroscopic state, BGK collision with forcing and sources, store.  Populations are kept
+// as 38 planes [q][z][y][x] (flow 0-18, temperature 19-37) in deviation form (f_0 - rho0,
+// g_i - omega_i sigma T0), FP64 or FP32; all arithmetic is FP64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/lbm3d.h"
+#include "lbm_error.h"
+
+namespace lbm3 {
+
+constexpr int NQ = 19;
+// rest, the six axis directions, the twelve edge directions; opposite velocities adjacent
+__device__ constexpr int CX[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__device__ constexpr int CY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__device__ constexpr int CZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+__host__ __device__ constexpr double W(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+// Launch constants (host-computed, passed by value).
+struct K3 {
+    int nx, ny, nz, pz;
+    long long n;
+    double tau_f, tau_T, A, B, sigma, Q, eps, T0, gbeta;
+    double a[3];
+    double c0, c1, dlin, dquad;      // drag solve: c0, c1; force: eps nu / K, eps F_eps / sqrt(K)
+    int wkind[2];
+    double wu[2][3], wT[2], wdTdn[2];
+};
+
+// Macroscopic state; S as xx, xy, xz, yy, yz, zz.
+struct Mac {
+    double T, u[3], F[3], p, S[6], gT[3];
+};
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Pre-collision populations of node (x, y, z): pulled from the post-collision buffer
+// (rest state added back).
+template <typename S>
+__device__ __forceinline__ void pull(const S *__restrict__ src, const K3 &K, int x, int y, int z,
+                                     double *f, double *g)
+{
+    const double gT0 = K.sigma * K.T0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int xs = wrap(x - CX[q], K.nx), ys = wrap(y - CY[q], K.ny);
+        const int zs = K.pz ? wrap(z - CZ[q], K.nz) : z - CZ[q];
+        const size_t k = ((size_t)zs * K.ny + ys) * K.nx + xs;
+        f[q] = double(src[(size_t)q * K.n + k]) + (q == 0 ? 1.0 : 0.0);
+        g[q] = double(src[(size_t)(NQ + q) * K.n + k]) + W(q) * gT0;
+    }
+}
+
+// G and F (Eq. ForceEq) at velocity u and temperature T.
+__device__ __forceinline__ void force(const K3 &K, const double *u, double T, double *F)
+{
+    const double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const double dl = K.dlin + K.dquad * um;
+    F[0] = K.eps * K.a[0] - dl * u[0];
+    F[1] = K.eps * K.a[1] - dl * u[1];
+    F[2] = K.eps * (K.a[2] + K.gbeta * (T - K.T0)) - dl * u[2];
+}
+
+// State of an interior node from its populations: T (Sec. 3.2), v and u (drag solve,
+// Sec. 3.1), F, p (Sec. 3.1 with omega_0 = 1/3 in the closed forms of App. A), S from the
+// non-equilibrium second moment (Eq. ShearEqCom; the D3Q19 equilibrium's second moment is
+// eps p I + u u / eps), grad T = <M>^-1 <N> by the Sherman-Morrison form of <M> = a I - b u u.
+__device__ __forceinline__ void macro3(const double *f, const double *g, const K3 &K, Mac &m)
+{
+    double sg = 0.0, s18 = 0.0, j[3] = {0.0, 0.0, 0.0}, P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double h[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double cx = CX[q], cy = CY[q], cz = CZ[q];
+        sg += g[q];
+        if (q) s18 += f[q];
+        j[0] += cx * f[q]; j[1] += cy * f[q]; j[2] += cz * f[q];
+        P[0] += cx * cx * f[q]; P[1] += cx * cy * f[q]; P[2] += cx * cz * f[q];
+        P[3] += cy * cy * f[q]; P[4] += cy * cz * f[q]; P[5] += cz * cz * f[q];
+        h[0] += cx * g[q]; h[1] += cy * g[q]; h[2] += cz * g[q];
+    }
+    const double eps = K.eps, ieps = 1.0 / eps;
+    m.T = (sg + 0.5 * K.Q) / K.sigma;
+    const double G[3] = {K.a[0], K.a[1], K.a[2] + K.gbeta * (m.T - K.T0)};
+    double v[3];
+    for (int a = 0; a < 3; ++a) v[a] = j[a] + 0.5 * eps * G[a];
+    const double vm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const double iden = 1.0 / (K.c0 + sqrt(K.c0 * K.c0 + K.c1 * vm));
+    for (int a = 0; a < 3; ++a) m.u[a] = v[a] * iden;
+    force(K, m.u, m.T, m.F);
+    const double uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+    const double uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
+    // rho0 s_0 = -omega_0 |u|^2 / (2 eps cs^2) = -|u|^2 / (2 eps); tau_f F_0 = -tau_f (1 - 1/(2 tau_f)) u.F / eps
+    const double s0 = -0.5 * uu * ieps, tF0 = -(K.tau_f - 0.5) * uF * ieps;
+    m.p = 0.5 * ieps * (s18 + tF0 + s0);               // cs^2 / (eps (1 - omega_0)) = 1 / (2 eps)
+    const double ep = eps * m.p;
+    const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
+    const double Sden = 1.0 / ((K.A - K.tau_f) / 3.0);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const double neq = P[c] - (ia[c] == ib[c] ? ep : 0.0) - m.u[ia[c]] * m.u[ib[c]] * ieps;
+        m.S[c] = (neq + 0.5 * (m.u[ia[c]] * m.F[ib[c]] + m.F[ia[c]] * m.u[ib[c]]) * ieps) * Sden;
+    }
+    double N[3];
+    for (int a = 0; a < 3; ++a) N[a] = h[a] - m.T * m.u[a] + 0.5 * (m.T * m.F[a] + m.u[a] * K.Q / K.sigma);
+    const double am = K.sigma * (K.B - K.tau_T) / 3.0 - 0.5 * ep;
+    const double bm = 0.5 * (ieps - 1.0 / K.sigma);
+    const double uN = m.u[0] * N[0] + m.u[1] * N[1] + m.u[2] * N[2];
+    const double c = bm * uN / (am - bm * uu);
+    for (int a = 0; a < 3; ++a) m.gT[a] = (N[a] + c * m.u[a]) / am;
+}
+
+// Equilibria (Eqs. EQFIN, EQTSHIN, TeEDFEQ) of direction q for pressure term ep = eps p.
+__device__ __forceinline__ double feq(int q, const K3 &K, double ep, const double *u, const double *S)
+{
+    const double cx = CX[q], cy = CY[q], cz = CZ[q], w = W(q);
+    const double cu = cx * u[0] + cy * u[1] + cz * u[2];
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double cSc = cx * cx * S[0] + 2.0 * cx * cy * S[1] + 2.0 * cx * cz * S[2] + cy * cy * S[3]
+                     + 2.0 * cy * cz * S[4] + cz * cz * S[5];
+    const double trS = S[0] + S[3] + S[5];
+    const double base = q == 0 ? 1.0 - 2.0 * ep : 3.0 * w * ep;   // rho0 - (1 - omega_0) eps p / cs^2
+    return base + w * (3.0 * cu + 4.5 * (cu * cu - uu / 3.0) / K.eps) + w * 1.5 * K.A * (cSc - trS / 3.0);
+}
+
+__device__ __forceinline__ double geq(int q, const K3 &K, double T, double ep, const double *u, const double *gT)
+{
+    const double cx = CX[q], cy = CY[q], cz = CZ[q], w = W(q);
+    const double cu = cx * u[0] + cy * u[1] + cz * u[2];
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double cg = cx * gT[0] + cy * gT[1] + cz * gT[2];
+    const double pres = q == 0 ? -2.0 * T * ep : 3.0 * w * T * ep;  // varpi_q T eps p / (cs^2 rho0)
+    return w * T * (K.sigma + 3.0 * cu + 4.5 * (cu * cu - uu / 3.0) / K.eps) + pres + K.sigma * w * K.B * cg;
+}
+
+// BGK collision with forcing and sources (Eqs. LBEeq, FtermF, TEqColli, Eq:Tforce).
+__device__ __forceinline__ void collide(double *f, double *g, const Mac &m, const K3 &K)
+{
+    const double ep = K.eps * m.p, ieps = 1.0 / K.eps;
+    const double fF = 1.0 - 0.5 / K.tau_f, fT = 1.0 - 0.5 / K.tau_T;
+    const double uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
+    const double ugT = m.u[0] * m.gT[0] + m.u[1] * m.gT[1] + m.u[2] * m.gT[2];
+    const double V[3] = {m.T * m.F[0] + ep * m.gT[0], m.T * m.F[1] + ep * m.gT[1], m.T * m.F[2] + ep * m.gT[2]};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double cx = CX[q], cy = CY[q], cz = CZ[q], w = W(q);
+        const double cu = cx * m.u[0] + cy * m.u[1] + cz * m.u[2];
+        const double cF = cx * m.F[0] + cy * m.F[1] + cz * m.F[2];
+        const double cV = cx * V[0] + cy * V[1] + cz * V[2];
+        const double Fi = w * fF * (3.0 * cF + 4.5 * ieps * (2.0 * cu * cF - 2.0 * uF / 3.0));
+        const double Pi = w * fT * (3.0 * cV + 3.0 * (ieps - 1.0 / K.sigma) * cu * ugT);
+        const double Qi = w * fT * (1.0 + 3.0 * cu / K.sigma) * K.Q;
+        f[q] += (feq(q, K, ep, m.u, m.S) - f[q]) / K.tau_f + Fi;
+        g[q] += (geq(q, K, m.T, ep, m.u, m.gT) - g[q]) / K.tau_T + Pi + Qi;
+    }
+}
+
+// Pre-collision populations and state of node (x, y, z).  Interior: pulled populations
+// and their moments.  Wall (walled z, z = 0 or nz - 1): the non-equilibrium extrapolation
+// from x_f = (x, y, z +- 1) (and T of x_ff on prescribed-gradient walls), whose state is
+// the one the scheme assigns (T_b, u_b, p and S of x_f, the boundary grad T).
+template <typename S>
+__device__ __forceinline__ void node_state(const S *__restrict__ src, const K3 &K, int x, int y, int z,
+                                           double *f, double *g, Mac &m)
+{
+    if (K.pz || (z > 0 && z < K.nz - 1)) {
+        pull<S>(src, K, x, y, z, f, g);
+        macro3(f, g, K, m);
+        return;
+    }
+    const int w = z == 0 ? 0 : 1, dz = z == 0 ? 1 : -1;
+    double ff[NQ], gf[NQ];
+    pull<S>(src, K, x, y, z + dz, ff, gf);
+    Mac mf;
+    macro3(ff, gf, K, mf);
+    double Tb, gb[3] = {mf.gT[0], mf.gT[1], mf.gT[2]};
+    if (K.wkind[w] == 0) {
+        Tb = K.wT[w];
+    } else {
+        double f2[NQ], g2[NQ];
+        pull<S>(src, K, x, y, z + 2 * dz, f2, g2);
+        double sg = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sg += g2[q];
+        const double Tff = (sg + 0.5 * K.Q) / K.sigma;
+        gb[2] = dz * K.wdTdn[w];
+        Tb = (4.0 * mf.T - Tff - 2.0 * dz * gb[2]) / 3.0;
+    }
+    m.T = Tb;
+    for (int a = 0; a < 3; ++a) { m.u[a] = K.wu[w][a]; m.gT[a] = gb[a]; }
+    force(K, m.u, m.T, m.F);
+    m.p = mf.p;
+    for (int c = 0; c < 6; ++c) m.S[c] = mf.S[c];
+    const double ep = K.eps * mf.p;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        f[q] = feq(q, K, ep, m.u, mf.S) + (ff[q] - feq(q, K, ep, mf.u, mf.S));
+        g[q] = geq(q, K, Tb, ep, m.u, gb) + (gf[q] - geq(q, K, mf.T, ep, mf.u, mf.gT));
+    }
+}
+
+__device__ __forceinline__ bool node_xyz(const K3 &K, int &x, int &y, int &z)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K.n) return false;
+    x = (int)(k % K.nx);
+    y = (int)((k / K.nx) % K.ny);
+    z = (int)(k / ((long long)K.nx * K.ny));
+    return true;
+}
+
+template <typename S>
+__device__ __forceinline__ void store(S *__restrict__ dst, const K3 &K, size_t k, const double *f, const double *g)
+{
+    const double gT0 = K.sigma * K.T0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        dst[(size_t)q * K.n + k] = S(f[q] - (q == 0 ? 1.0 : 0.0));
+        dst[(size_t)(NQ + q) * K.n + k] = S(g[q] - W(q) * gT0);
+    }
+}
+
+constexpr int B3 = 256;
+
+// One time step: pull, state, collide, store.
+template <typename S>
+__global__ void __launch_bounds__(B3) k3_step(const S *__restrict__ src, S *__restrict__ dst, K3 K)
+{
+    int x, y, z;
+    if (!node_xyz(K, x, y, z)) return;
+    double f[NQ], g[NQ];
+    Mac m;
+    node_state<S>(src, K, x, y, z, f, g, m);
+    collide(f, g, m, K);
+    store<S>(dst, K, ((size_t)z * K.ny + y) * K.nx + x, f, g);
+}
+
+// Initial post-collision populations: the equilibria of the initial fields (S = 0,
+// grad T = 0, p = 0).
+template <typename S>
+__global__ void __launch_bounds__(B3) k3_init(S *__restrict__ dst, K3 K, const double *T_init, const double *u_init)
+{
+    int x, y, z;
+    if (!node_xyz(K, x, y, z)) return;
+    const size_t k = ((size_t)z * K.ny + y) * K.nx + x;
+    double T = K.T0;
+    if (T_init) T = T_init[k];
+    else if (!K.pz && z == 0 && K.wkind[0] == 0) T = K.wT[0];
+    else if (!K.pz && z == K.nz - 1 && K.wkind[1] == 0) T = K.wT[1];
+    double u[3] = {0.0, 0.0, 0.0};
+    if (u_init)
+        for (int a = 0; a < 3; ++a) u[a] = u_init[(size_t)a * K.n + k];
+    const double S0[6] = {0, 0, 0, 0, 0, 0}, g0[3] = {0, 0, 0};
+    double f[NQ], g[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        f[q] = feq(q, K, 0.0, u, S0);
+        g[q] = geq(q, K, T, 0.0, u, g0);
+    }
+    store<S>(dst, K, k, f, g);
+}
+
+struct FieldOut3 { double *p, *u, *T, *S, *gT; };
+
+template <typename S>
+__global__ void __launch_bounds__(B3) k3_fields(const S *__restrict__ src, K3 K, FieldOut3 o)
+{
+    int x, y, z;
+    if (!node_xyz(K, x, y, z)) return;
+    double f[NQ], g[NQ];
+    Mac m;
+    node_state<S>(src, K, x, y, z, f, g, m);
+    const size_t k = ((size_t)z * K.ny + y) * K.nx + x, n = (size_t)K.n;
+    if (o.p) o.p[k] = m.p;
+    if (o.T) o.T[k] = m.T;
+    for (int a = 0; a < 3; ++a) {
+        if (o.u) o.u[a * n + k] = m.u[a];
+        if (o.gT) o.gT[a * n + k] = m.gT[a];
+    }
+    if (o.S)
+        for (int c = 0; c < 6; ++c) o.S[c * n + k] = m.S[c];
+}
+
+template <typename S>
+__global__ void __launch_bounds__(B3) k3_populations(const S *__restrict__ src, K3 K, double *fo, double *go)
+{
+    int x, y, z;
+    if (!node_xyz(K, x, y, z)) return;
+    double f[NQ], g[NQ];
+    Mac m;
+    node_state<S>(src, K, x, y, z, f, g, m);
+    const size_t k = ((size_t)z * K.ny + y) * K.nx + x;
+    for (int q = 0; q < NQ; ++q) {
+        if (fo) fo[(size_t)q * K.n + k] = f[q];
+        if (go) go[(size_t)q * K.n + k] = g[q];
+    }
+}
+
+}  // namespace lbm3
+
+using namespace lbm3;
+
+struct lbm3_ctx {
+    K3 K;
+    int storage;
+    char *buf[2];
+    int cur;
+    hipStream_t stream;
+    int64_t t;
+};
+
+namespace {
+
+lbm_status fail3(lbm_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+lbm_status fail3(lbm_status st, const char *fmt, ...)
+{
+    char msg[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(msg, sizeof(msg), fmt, ap);
+    va_end(ap);
+    return lbm::set_error(st, msg);
+}
+
+size_t elem3(int storage) { return storage == LBM_F64 ? 8 : 4; }
+
+size_t buffer_bytes(const lbm3_params *p)
+{
+    const size_t n = (size_t)p->nx * p->ny * p->nz;
+    return (2 * NQ * n * elem3(p->storage) + 255) / 256 * 256;
+}
+
+// Derived lattice constants, as for two dimensions (Sec. 2, Sec. 3.1, Eq. Therdiff,
+// Eq. EQA&B, Eq. ForceEq with the Ergun relation).
+lbm_status make_constants(const lbm3_params *p, K3 &K)
+{
+    if (!p) return fail3(LBM_ERR_INVALID, "params is NULL");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail3(LBM_ERR_INVALID, "grid must be at least 1 x 1 x 1");
+    if (!p->periodic_z && p->nz < 4) return fail3(LBM_ERR_INVALID, "walled z needs nz >= 4 (got %d)", p->nz);
+    if (p->storage != LBM_F64 && p->storage != LBM_F32) return fail3(LBM_ERR_INVALID, "storage must be LBM_F64 or LBM_F32");
+    if ((double)p->nx * p->ny * p->nz * 2 * NQ > 9.0e18) return fail3(LBM_ERR_INVALID, "grid too large");
+    if (!(p->tau_f > 0.5) || !(p->tau_T > 0.5)) return fail3(LBM_ERR_INVALID, "tau_f and tau_T must exceed 1/2");
+    if (!(p->eps > 0.0) || !(p->eps <= 1.0) || !(p->sigma > 0.0) || !(p->J > 0.0))
+        return fail3(LBM_ERR_INVALID, "eps must lie in (0, 1]; sigma and J must be positive");
+    const double L = p->L > 0 ? p->L : (p->periodic_z ? p->nz : p->nz - 1);
+    double A = p->A, B = p->B;
+    if (std::isnan(A) || std::isnan(B)) {
+        if (!(p->Ra > 0) || !(p->Pr > 0)) return fail3(LBM_ERR_INVALID, "A, B from Ma need Ra > 0 and Pr > 0");
+        A = p->tau_f - 0.5 - p->J * p->Ma * L * sqrt(3.0 * p->Pr / p->Ra);
+        B = p->tau_T - 0.5 - (p->Ma / p->sigma) * L * sqrt(3.0 / (p->Pr * p->Ra));
+    }
+    const double nu_e = (p->tau_f - A - 0.5) / 3.0, nu = nu_e / p->J;
+    const double alpha = p->sigma * (p->tau_T - B - 0.5) / 3.0;
+    const double Kp = p->Da * L * L;
+    if (!(nu_e > 0)) return fail3(LBM_ERR_INVALID, "nu_e <= 0 (A = %g >= tau_f - 1/2)", A);
+    if (!(alpha > 0)) return fail3(LBM_ERR_INVALID, "alpha_e <= 0 (B = %g >= tau_T - 1/2)", B);
+    if (!(Kp > 0)) return fail3(LBM_ERR_INVALID, "K = Da L^2 must be positive");
+    const double dT = p->T_hot - p->T_cold;
+    const double Feps = std::isnan(p->F_eps) ? 1.75 / sqrt(150.0 * p->eps * p->eps * p->eps) : p->F_eps;
+    K.nx = p->nx; K.ny = p->ny; K.nz = p->nz; K.pz = p->periodic_z ? 1 : 0;
+    K.n = (long long)p->nx * p->ny * p->nz;
+    K.tau_f = p->tau_f; K.tau_T = p->tau_T; K.A = A; K.B = B; K.sigma = p->sigma; K.Q = p->Q; K.eps = p->eps;
+    K.T0 = 0.5 * (p->T_hot + p->T_cold);
+    K.gbeta = (p->Ra > 0 && dT != 0.0) ? p->Ra * nu * alpha / (dT * L * L * L) : 0.0;
+    for (int a = 0; a < 3; ++a) K.a[a] = p->a[a];
+    K.c0 = 0.5 * (1.0 + p->eps * 0.5 * nu / Kp);
+    K.c1 = p->eps * 0.5 * Feps / sqrt(Kp);
+    K.dlin = p->eps * nu / Kp;
+    K.dquad = p->eps * Feps / sqrt(Kp);
+    for (int w = 0; w < 2; ++w) {
+        K.wkind[w] = p->wall[w].t_kind == LBM_T_NEUMANN ? 1 : 0;
+        for (int a = 0; a < 3; ++a) K.wu[w][a] = p->wall[w].u[a];
+        K.wT[w] = p->wall[w].T;
+        K.wdTdn[w] = p->wall[w].dTdn;
+    }
+    return LBM_OK;
+}
+
+unsigned blocks_for(long long n) { return (unsigned)((n + B3 - 1) / B3); }
+
+lbm_status launched(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LBM_OK : fail3(LBM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm3_workspace_bytes(const lbm3_params *params)
+{
+    K3 K;
+    if (make_constants(params, K) != LBM_OK) return 0;
+    return 2 * buffer_bytes(params);
+}
+
+lbm_status lbm3_init(const lbm3_params *params, void *workspace, size_t workspace_bytes, void *hip_stream,
+                     lbm3_ctx **out)
+{
+    if (!out) return fail3(LBM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    K3 K;
+    lbm_status st = make_constants(params, K);
+    if (st != LBM_OK) return st;
+    if (!workspace || ((uintptr_t)workspace) % 256) return fail3(LBM_ERR_INVALID, "workspace must be non-NULL and 256-byte aligned");
+    const size_t need = 2 * buffer_bytes(params);
+    if (workspace_bytes < need) return fail3(LBM_ERR_INVALID, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+    lbm3_ctx *c = new (std::nothrow) lbm3_ctx;
+    if (!c) return fail3(LBM_ERR_DEVICE, "out of host memory");
+    c->K = K;
+    c->storage = params->storage;
+    c->buf[0] = static_cast<char *>(workspace);
+    c->buf[1] = c->buf[0] + buffer_bytes(params);
+    c->cur = 0;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->t = 0;
+    if (c->storage == LBM_F64)
+        hipLaunchKernelGGL((k3_init<double>), dim3(blocks_for(K.n)), dim3(B3), 0, c->stream,
+                           reinterpret_cast<double *>(c->buf[0]), K, params->T_init, params->u_init);
+    else
+        hipLaunchKernelGGL((k3_init<float>), dim3(blocks_for(K.n)), dim3(B3), 0, c->stream,
+                           reinterpret_cast<float *>(c->buf[0]), K, params->T_init, params->u_init);
+    st = launched("initial populations");
+    if (st == LBM_OK) {
+        const hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) st = fail3(LBM_ERR_DEVICE, "initial populations: %s", hipGetErrorString(e));
+    }
+    if (st != LBM_OK) { delete c; return st; }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm3_step(lbm3_ctx *c, int64_t nsteps)
+{
+    if (!c) return fail3(LBM_ERR_INVALID, "ctx is NULL");
+    if (nsteps < 0) return fail3(LBM_ERR_INVALID, "nsteps must be >= 0");
+    const unsigned nb = blocks_for(c->K.n);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (c->storage == LBM_F64)
+            hipLaunchKernelGGL((k3_step<double>), dim3(nb), dim3(B3), 0, c->stream,
+                               reinterpret_cast<const double *>(c->buf[c->cur]), reinterpret_cast<double *>(c->buf[c->cur ^ 1]), c->K);
+        else
+            hipLaunchKernelGGL((k3_step<float>), dim3(nb), dim3(B3), 0, c->stream,
+                               reinterpret_cast<const float *>(c->buf[c->cur]), reinterpret_cast<float *>(c->buf[c->cur ^ 1]), c->K);
+        c->cur ^= 1;
+        c->t += 1;
+    }
+    return launched("3-D step");
+}
+
+lbm_status lbm3_fields(lbm3_ctx *c, double *p, double *u, double *T, double *S, double *gradT)
+{
+    if (!c) return fail3(LBM_ERR_INVALID, "ctx is NULL");
+    const FieldOut3 o{p, u, T, S, gradT};
+    if (c->storage == LBM_F64)
+        hipLaunchKernelGGL((k3_fields<double>), dim3(blocks_for(c->K.n)), dim3(B3), 0, c->stream,
+                           reinterpret_cast<const double *>(c->buf[c->cur]), c->K, o);
+    else
+        hipLaunchKernelGGL((k3_fields<float>), dim3(blocks_for(c->K.n)), dim3(B3), 0, c->stream,
+                           reinterpret_cast<const float *>(c->buf[c->cur]), c->K, o);
+    return launched("3-D fields");
+}
+
+lbm_status lbm3_populations(lbm3_ctx *c, double *f, double *g)
+{
+    if (!c) return fail3(LBM_ERR_INVALID, "ctx is NULL");
+    if (c->storage == LBM_F64)
+        hipLaunchKernelGGL((k3_populations<double>), dim3(blocks_for(c->K.n)), dim3(B3), 0, c->stream,
+                           reinterpret_cast<const double *>(c->buf[c->cur]), c->K, f, g);
+    else
+        hipLaunchKernelGGL((k3_populations<float>), dim3(blocks_for(c->K.n)), dim3(B3), 0, c->stream,
+                           reinterpret_cast<const float *>(c->buf[c->cur]), c->K, f, g);
+    return launched("3-D populations");
+}
+
+int32_t lbm3_lattice(int32_t *c)
+{
+    static const int32_t v[NQ][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+                                     {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1}, {-1, 0, -1},
+                                     {1, 0, -1}, {-1, 0, 1}, {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    if (c) memcpy(c, v, sizeof(v));
+    return NQ;
+}
+
+int64_t lbm3_time(const lbm3_ctx *c) { return c ? c->t : -1; }
+
+void lbm3_destroy(lbm3_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+}  // extern "C"

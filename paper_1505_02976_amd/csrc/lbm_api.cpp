@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "lbm_error.h"
 #include "lbm_kernels.h"
 
 namespace {
@@ -33,6 +34,13 @@ lbm_status hip_fail(hipError_t e, const char *what)
 {
     return fail(LBM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace
+
+// The message lbm_last_error reports, for the three-dimensional entry points.
+lbm_status lbm::set_error(lbm_status st, const char *msg) { return fail(st, "%s", msg); }
+
+namespace {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

@@ -132,3 +132,33 @@ def test_one_hip_runtime_whatever_the_import_order():
     libs = eval(out.stdout.strip().splitlines()[-1])
     assert sum("libamdhip64" in p for p in libs) == 1, libs
     assert sum("libhsa-runtime64" in p for p in libs) == 1, libs
+
+
+def test_exports_every_declared_3d_symbol(lbm):
+    with open(os.path.join(ROOT, "include", "lbm3d.h")) as fh:
+        names = sorted(set(re.findall(r"\b(lbm3_[a-z_]+)\s*\(", fh.read())))
+    assert len(names) == 8, names
+    lib = C.CDLL(lbm.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_3d_struct_sizes_and_validation(lbm):
+    import workloads as W
+    from paper_1505_02976_amd import lbm3d as L3
+    # lbm3_wall: 3 doubles, 2 int32, 2 doubles; lbm3_params: 4 int32, 2 walls, 19 doubles, 2 int32, 2 pointers
+    assert C.sizeof(L3._Wall3) == 48
+    assert C.sizeof(L3._Params3) == 16 + 2 * 48 + 19 * 8 + 8 + 16
+    cfg = W.layer3d(16, 8, 12)
+    n = 16 * 8 * 12
+    assert L3.workspace_bytes(cfg) == 2 * ((2 * 19 * n * 8 + 255) // 256 * 256)
+    assert L3.workspace_bytes(dict(cfg, storage="f32")) == 2 * ((2 * 19 * n * 4 + 255) // 256 * 256)
+    assert L3.workspace_bytes(dict(cfg, nz=3)) == 0
+    assert "nz >= 4" in lbm.lib().lbm_last_error().decode()
+    assert L3.workspace_bytes(dict(cfg, nz=3, periodic_z=1)) > 0
+    assert L3.workspace_bytes(dict(cfg, tau_f=0.5)) == 0
+    assert L3.workspace_bytes(dict(cfg, A=0.6, B=0.1)) == 0
+    assert "nu_e" in lbm.lib().lbm_last_error().decode()
+    c = L3.lattice()
+    assert len(set(c)) == 19 and (0, 0, 0) in c
+    assert sorted(sum(abs(v) for v in ci) for ci in c) == [0] + [1] * 6 + [2] * 12
