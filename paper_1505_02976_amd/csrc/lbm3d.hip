@@ -169,11 +169,11 @@ __device__ __forceinline__ void collide(double *f, double *g, const Mac &m, cons
 // and their moments.  Wall (walled z, z = 0 or nz - 1): the non-equilibrium extrapolation
 // from x_f = (x, y, z +- 1) (and T of x_ff on prescribed-gradient walls), whose state is
 // the one the scheme assigns (T_b, u_b, p and S of x_f, the boundary grad T).
-template <typename S>
+template <typename S, bool WALLS = true>
 __device__ __forceinline__ void node_state(const S *__restrict__ src, const K3 &K, int x, int y, int z,
                                            double *f, double *g, Mac &m)
 {
-    if (K.pz || (z > 0 && z < K.nz - 1)) {
+    if (!WALLS || K.pz || (z > 0 && z < K.nz - 1)) {
         pull<S>(src, K, x, y, z, f, g);
         macro3(f, g, K, m);
         return;
@@ -232,17 +232,36 @@ __device__ __forceinline__ void store(S *__restrict__ dst, const K3 &K, size_t k
 
 constexpr int B3 = 256;
 
-// One time step: pull, state, collide, store.
+// One time step, pull, state, collide, store, in two launches: the interior nodes (no
+// boundary-scheme code, so fewer registers and more waves per SIMD) and the two wall planes.
 template <typename S>
-__global__ void __launch_bounds__(B3) k3_step(const S *__restrict__ src, S *__restrict__ dst, K3 K)
+__global__ void __launch_bounds__(B3) k3_step_interior(const S *__restrict__ src, S *__restrict__ dst, K3 K)
 {
-    int x, y, z;
-    if (!node_xyz(K, x, y, z)) return;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long plane = (long long)K.nx * K.ny;
+    const long long k = K.pz ? i : i + plane;            // walled: planes 1 .. nz - 2
+    if (k >= (K.pz ? K.n : K.n - plane)) return;
+    const int x = (int)(k % K.nx), y = (int)((k / K.nx) % K.ny), z = (int)(k / plane);
+    double f[NQ], g[NQ];
+    Mac m;
+    node_state<S, false>(src, K, x, y, z, f, g, m);
+    collide(f, g, m, K);
+    store<S>(dst, K, (size_t)k, f, g);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(B3) k3_step_walls(const S *__restrict__ src, S *__restrict__ dst, K3 K)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long plane = (long long)K.nx * K.ny;
+    if (i >= 2 * plane) return;
+    const long long k = i < plane ? i : (long long)(K.nz - 1) * plane + (i - plane);
+    const int x = (int)(k % K.nx), y = (int)((k / K.nx) % K.ny), z = (int)(k / plane);
     double f[NQ], g[NQ];
     Mac m;
     node_state<S>(src, K, x, y, z, f, g, m);
     collide(f, g, m, K);
-    store<S>(dst, K, ((size_t)z * K.ny + y) * K.nx + x, f, g);
+    store<S>(dst, K, (size_t)k, f, g);
 }
 
 // Initial post-collision populations: the equilibria of the initial fields (S = 0,
@@ -445,14 +464,20 @@ lbm_status lbm3_step(lbm3_ctx *c, int64_t nsteps)
 {
     if (!c) return fail3(LBM_ERR_INVALID, "ctx is NULL");
     if (nsteps < 0) return fail3(LBM_ERR_INVALID, "nsteps must be >= 0");
-    const unsigned nb = blocks_for(c->K.n);
+    const long long plane = (long long)c->K.nx * c->K.ny;
+    const unsigned nb_in = blocks_for(c->K.pz ? c->K.n : c->K.n - 2 * plane), nb_w = blocks_for(2 * plane);
     for (int64_t s = 0; s < nsteps; ++s) {
-        if (c->storage == LBM_F64)
-            hipLaunchKernelGGL((k3_step<double>), dim3(nb), dim3(B3), 0, c->stream,
-                               reinterpret_cast<const double *>(c->buf[c->cur]), reinterpret_cast<double *>(c->buf[c->cur ^ 1]), c->K);
-        else
-            hipLaunchKernelGGL((k3_step<float>), dim3(nb), dim3(B3), 0, c->stream,
-                               reinterpret_cast<const float *>(c->buf[c->cur]), reinterpret_cast<float *>(c->buf[c->cur ^ 1]), c->K);
+        if (c->storage == LBM_F64) {
+            const double *src = reinterpret_cast<const double *>(c->buf[c->cur]);
+            double *dst = reinterpret_cast<double *>(c->buf[c->cur ^ 1]);
+            hipLaunchKernelGGL((k3_step_interior<double>), dim3(nb_in), dim3(B3), 0, c->stream, src, dst, c->K);
+            if (!c->K.pz) hipLaunchKernelGGL((k3_step_walls<double>), dim3(nb_w), dim3(B3), 0, c->stream, src, dst, c->K);
+        } else {
+            const float *src = reinterpret_cast<const float *>(c->buf[c->cur]);
+            float *dst = reinterpret_cast<float *>(c->buf[c->cur ^ 1]);
+            hipLaunchKernelGGL((k3_step_interior<float>), dim3(nb_in), dim3(B3), 0, c->stream, src, dst, c->K);
+            if (!c->K.pz) hipLaunchKernelGGL((k3_step_walls<float>), dim3(nb_w), dim3(B3), 0, c->stream, src, dst, c->K);
+        }
         c->cur ^= 1;
         c->t += 1;
     }
