@@ -110,3 +110,51 @@ def test_heated_layer_against_oracle(gpu3):
     _say(f"  max |populations| diff {dpop:.2e}; fields {max(dfield.values()):.2e}")
     assert dpop < 1e-10
     assert all(v < 1e-10 for v in dfield.values()), dfield
+
+
+def test_brinkman_between_plates(gpu3):
+    """The 3-D path against the Brinkman closed form between plates at rest (eps 0.5,
+    Da 1e-2, tau 0.8, A = B = 0.1, F_eps = 0, force along x), second order in the plate
+    distance, FP64."""
+    from closed_forms import E, brinkman_profile, order, poiseuille_cfg
+    ns = (17, 33, 65)
+    errs = []
+    for nz in ns:
+        cfg2, c = poiseuille_cfg(nz, 0.1, F_eps=0.0)
+        cfg = {"nx": 4, "ny": 4, "nz": nz, "periodic_z": 0,
+               "walls": [{"kind": "T", "T": 0.0}, {"kind": "T", "T": 0.0}],
+               "Da": cfg2["Da"], "Ra": 0.0, "Pr": 1.0, "J": 1.0, "Ma": 0.1, "sigma": 1.0, "Q": 0.0,
+               "tau_f": cfg2["tau_f"], "tau_T": cfg2["tau_T"], "A": cfg2["A"], "B": cfg2["B"],
+               "eps": cfg2["eps"], "a": (c["a"], 0.0, 0.0), "T_hot": 0.0, "T_cold": 0.0, "F_eps": 0.0,
+               "storage": "f64"}
+        sim = gpu3.Sim3(cfg)
+        sim.step(int(6 * (nz - 1) ** 2 / c["nu"]))
+        ua, _ = brinkman_profile(np.arange(nz, dtype=float), c)
+        errs.append(E(ua, sim.fields()["ux"].cpu().numpy()[:, 1, 1]))
+    _say(f"  Brinkman between plates, E(u) at nz {ns}: {[f'{e:.3e}' for e in errs]}")
+    assert errs[-1] < 2e-3, errs
+    assert order(errs[1], errs[2], ns[1], ns[2]) > 1.7, errs
+
+
+@pytest.mark.parametrize("storage,A", [("f64", 0.3), ("f32", -0.2)])
+def test_shear_wave_decay(gpu3, storage, A):
+    """A shear wave u_x = u0 sin(k y) in a periodic 4 x 64 x 4 box decays at nu_e k^2,
+    nu_e = cs^2 (tau_f - A - 1/2) (Sec. 3.1)."""
+    n = 64
+    k = 2 * np.pi / n
+    y = np.arange(n, dtype=float)
+    u = np.zeros((3, 4, n, 4))
+    u[0] = (1e-3 * np.sin(k * y))[None, :, None]
+    cfg = {"nx": 4, "ny": n, "nz": 4, "periodic_z": 1, "walls": [{}, {}], "Da": 1e30, "Ra": 0.0, "Pr": 1.0,
+           "J": 1.0, "Ma": 0.1, "sigma": 1.0, "Q": 0.0, "tau_f": 1.0, "tau_T": 1.0, "A": A, "B": 0.0, "eps": 1.0,
+           "a": (0.0, 0.0, 0.0), "T_hot": 1.0, "T_cold": 0.0, "F_eps": 0.0, "u_init": u, "storage": storage}
+    sim = gpu3.Sim3(cfg)
+    nu_e = (1.0 - A - 0.5) / 3.0
+    t1, t2 = int(0.1 / (nu_e * k * k)), int(0.6 / (nu_e * k * k))
+    sim.step(t1)
+    a1 = 2 / n * (sim.fields()["ux"].cpu().numpy()[0, :, 0] * np.sin(k * y)).sum()
+    sim.step(t2 - t1)
+    a2 = 2 / n * (sim.fields()["ux"].cpu().numpy()[0, :, 0] * np.sin(k * y)).sum()
+    rate = np.log(a1 / a2) / (t2 - t1) / (nu_e * k * k)
+    _say(f"  {storage} A {A}: decay rate / nu_e k^2 = {rate:.6f}")
+    assert abs(rate - 1) < 2e-3
