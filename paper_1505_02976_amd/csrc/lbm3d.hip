@@ -4,7 +4,8 @@
 // node: pull streaming from the previous step's post-collision buffer, the node's
 // macroscopic state, BGK collision with forcing and sources, store.  Populations are kept
 // as 38 planes [q][z][y][x] (flow 0-18, temperature 19-37) in deviation form (f_0 - rho0,
-// g_i - omega_i sigma T0), FP64 or FP32; all arithmetic is FP64.
+// g_i - omega_i sigma T0), FP64 or FP32, with arithmetic in the storage precision (the drag
+// solve in FP64).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -37,18 +38,21 @@ struct K3 {
     double wu[2][3], wT[2], wdTdn[2];
 };
 
-// Macroscopic state; S as xx, xy, xz, yy, yz, zz.
-struct Mac {
-    double T, u[3], F[3], p, S[6], gT[3];
-};
-
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// Pre-collision populations of node (x, y, z): pulled from the post-collision buffer
-// (rest state added back).
-template <typename S>
-__device__ __forceinline__ void pull(const S *__restrict__ src, const K3 &K, int x, int y, int z,
-                                     double *f, double *g)
+// Arithmetic type of a storage type: FP64 storage computes in FP64, FP32 storage in FP32
+// (the drag solve in FP64 for both).  The flow populations are handled as deviations
+// throughout: the rest state is f_0 = rho0 and f_i = 0 otherwise, so the moments the node
+// needs (sum over i > 0, first and second moments) involve only small values, and f_0
+// enters as f_0 - rho0.
+template <typename S> struct Arith;
+template <> struct Arith<double> { using R = double; };
+template <> struct Arith<float> { using R = float; };
+
+// Pre-collision populations of node (x, y, z) pulled from the post-collision buffer: f in
+// deviation form, g with the rest state omega_i sigma T0 added back.
+template <typename S, typename R>
+__device__ __forceinline__ void pull(const S *__restrict__ src, const K3 &K, int x, int y, int z, R *f, R *g)
 {
     const double gT0 = K.sigma * K.T0;
 #pragma unroll
@@ -56,32 +60,40 @@ __device__ __forceinline__ void pull(const S *__restrict__ src, const K3 &K, int
         const int xs = wrap(x - CX[q], K.nx), ys = wrap(y - CY[q], K.ny);
         const int zs = K.pz ? wrap(z - CZ[q], K.nz) : z - CZ[q];
         const size_t k = ((size_t)zs * K.ny + ys) * K.nx + xs;
-        f[q] = double(src[(size_t)q * K.n + k]) + (q == 0 ? 1.0 : 0.0);
-        g[q] = double(src[(size_t)(NQ + q) * K.n + k]) + W(q) * gT0;
+        f[q] = R(src[(size_t)q * K.n + k]);
+        g[q] = R(src[(size_t)(NQ + q) * K.n + k]) + R(W(q) * gT0);
     }
 }
 
 // G and F (Eq. ForceEq) at velocity u and temperature T.
-__device__ __forceinline__ void force(const K3 &K, const double *u, double T, double *F)
+template <typename R>
+__device__ __forceinline__ void force(const K3 &K, const R *u, R T, R *F)
 {
-    const double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    const double dl = K.dlin + K.dquad * um;
-    F[0] = K.eps * K.a[0] - dl * u[0];
-    F[1] = K.eps * K.a[1] - dl * u[1];
-    F[2] = K.eps * (K.a[2] + K.gbeta * (T - K.T0)) - dl * u[2];
+    const R um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const R dl = R(K.dlin) + R(K.dquad) * um, eps = R(K.eps);
+    F[0] = eps * R(K.a[0]) - dl * u[0];
+    F[1] = eps * R(K.a[1]) - dl * u[1];
+    F[2] = eps * (R(K.a[2]) + R(K.gbeta) * (T - R(K.T0))) - dl * u[2];
 }
 
-// State of an interior node from its populations: T (Sec. 3.2), v and u (drag solve,
-// Sec. 3.1), F, p (Sec. 3.1 with omega_0 = 1/3 in the closed forms of App. A), S from the
-// non-equilibrium second moment (Eq. ShearEqCom; the D3Q19 equilibrium's second moment is
-// eps p I + u u / eps), grad T = <M>^-1 <N> by the Sherman-Morrison form of <M> = a I - b u u.
-__device__ __forceinline__ void macro3(const double *f, const double *g, const K3 &K, Mac &m)
+// Macroscopic state; S as xx, xy, xz, yy, yz, zz.
+template <typename R> struct Mac {
+    R T, u[3], F[3], p, S[6], gT[3];
+};
+
+// State of an interior node from its populations: T (Sec. 3.2), v and u (drag solve in
+// FP64, Sec. 3.1), F, p (Sec. 3.1 with omega_0 = 1/3 in the closed forms of App. A), S from
+// the non-equilibrium second moment (Eq. ShearEqCom; the D3Q19 equilibrium's second moment
+// is eps p I + u u / eps), grad T = <M>^-1 <N> by the Sherman-Morrison form of
+// <M> = a I - b u u.
+template <typename R>
+__device__ __forceinline__ void macro3(const R *f, const R *g, const K3 &K, Mac<R> &m)
 {
-    double sg = 0.0, s18 = 0.0, j[3] = {0.0, 0.0, 0.0}, P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double h[3] = {0.0, 0.0, 0.0};
+    R sg = R(0), s18 = R(0), j[3] = {R(0), R(0), R(0)}, P[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    R h[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const double cx = CX[q], cy = CY[q], cz = CZ[q];
+        const R cx = R(CX[q]), cy = R(CY[q]), cz = R(CZ[q]);
         sg += g[q];
         if (q) s18 += f[q];
         j[0] += cx * f[q]; j[1] += cy * f[q]; j[2] += cz * f[q];
@@ -89,79 +101,86 @@ __device__ __forceinline__ void macro3(const double *f, const double *g, const K
         P[3] += cy * cy * f[q]; P[4] += cy * cz * f[q]; P[5] += cz * cz * f[q];
         h[0] += cx * g[q]; h[1] += cy * g[q]; h[2] += cz * g[q];
     }
-    const double eps = K.eps, ieps = 1.0 / eps;
-    m.T = (sg + 0.5 * K.Q) / K.sigma;
-    const double G[3] = {K.a[0], K.a[1], K.a[2] + K.gbeta * (m.T - K.T0)};
+    const R eps = R(K.eps), ieps = R(1.0 / K.eps), isig = R(1.0 / K.sigma), Q = R(K.Q);
+    m.T = (sg + R(0.5) * Q) * isig;
+    const R G[3] = {R(K.a[0]), R(K.a[1]), R(K.a[2]) + R(K.gbeta) * (m.T - R(K.T0))};
     double v[3];
-    for (int a = 0; a < 3; ++a) v[a] = j[a] + 0.5 * eps * G[a];
+    for (int a = 0; a < 3; ++a) v[a] = double(j[a] + R(0.5) * eps * G[a]);
     const double vm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     const double iden = 1.0 / (K.c0 + sqrt(K.c0 * K.c0 + K.c1 * vm));
-    for (int a = 0; a < 3; ++a) m.u[a] = v[a] * iden;
-    force(K, m.u, m.T, m.F);
-    const double uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
-    const double uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
+    for (int a = 0; a < 3; ++a) m.u[a] = R(v[a] * iden);
+    force<R>(K, m.u, m.T, m.F);
+    const R uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+    const R uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
     // rho0 s_0 = -omega_0 |u|^2 / (2 eps cs^2) = -|u|^2 / (2 eps); tau_f F_0 = -tau_f (1 - 1/(2 tau_f)) u.F / eps
-    const double s0 = -0.5 * uu * ieps, tF0 = -(K.tau_f - 0.5) * uF * ieps;
-    m.p = 0.5 * ieps * (s18 + tF0 + s0);               // cs^2 / (eps (1 - omega_0)) = 1 / (2 eps)
-    const double ep = eps * m.p;
+    const R s0 = R(-0.5) * uu * ieps, tF0 = -R(K.tau_f - 0.5) * uF * ieps;
+    m.p = R(0.5) * ieps * (s18 + tF0 + s0);            // cs^2 / (eps (1 - omega_0)) = 1 / (2 eps)
+    const R ep = eps * m.p;
     const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
-    const double Sden = 1.0 / ((K.A - K.tau_f) / 3.0);
+    const R Sden = R(3.0 / (K.A - K.tau_f));
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        const double neq = P[c] - (ia[c] == ib[c] ? ep : 0.0) - m.u[ia[c]] * m.u[ib[c]] * ieps;
-        m.S[c] = (neq + 0.5 * (m.u[ia[c]] * m.F[ib[c]] + m.F[ia[c]] * m.u[ib[c]]) * ieps) * Sden;
+        const R neq = P[c] - (ia[c] == ib[c] ? ep : R(0)) - m.u[ia[c]] * m.u[ib[c]] * ieps;
+        m.S[c] = (neq + R(0.5) * (m.u[ia[c]] * m.F[ib[c]] + m.F[ia[c]] * m.u[ib[c]]) * ieps) * Sden;
     }
-    double N[3];
-    for (int a = 0; a < 3; ++a) N[a] = h[a] - m.T * m.u[a] + 0.5 * (m.T * m.F[a] + m.u[a] * K.Q / K.sigma);
-    const double am = K.sigma * (K.B - K.tau_T) / 3.0 - 0.5 * ep;
-    const double bm = 0.5 * (ieps - 1.0 / K.sigma);
-    const double uN = m.u[0] * N[0] + m.u[1] * N[1] + m.u[2] * N[2];
-    const double c = bm * uN / (am - bm * uu);
+    R N[3];
+    for (int a = 0; a < 3; ++a) N[a] = h[a] - m.T * m.u[a] + R(0.5) * (m.T * m.F[a] + m.u[a] * Q * isig);
+    const R am = R(K.sigma * (K.B - K.tau_T) / 3.0) - R(0.5) * ep;
+    const R bm = R(0.5 * (1.0 / K.eps - 1.0 / K.sigma));
+    const R uN = m.u[0] * N[0] + m.u[1] * N[1] + m.u[2] * N[2];
+    const R c = bm * uN / (am - bm * uu);
     for (int a = 0; a < 3; ++a) m.gT[a] = (N[a] + c * m.u[a]) / am;
 }
 
-// Equilibria (Eqs. EQFIN, EQTSHIN, TeEDFEQ) of direction q for pressure term ep = eps p.
-__device__ __forceinline__ double feq(int q, const K3 &K, double ep, const double *u, const double *S)
+// Equilibria (Eqs. EQFIN, EQTSHIN, TeEDFEQ) of direction q for pressure term ep = eps p;
+// the flow equilibrium as a deviation (f_0^eq - rho0 for q = 0).
+template <typename R>
+__device__ __forceinline__ R feq(int q, const K3 &K, R ep, const R *u, const R *S)
 {
-    const double cx = CX[q], cy = CY[q], cz = CZ[q], w = W(q);
-    const double cu = cx * u[0] + cy * u[1] + cz * u[2];
-    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const double cSc = cx * cx * S[0] + 2.0 * cx * cy * S[1] + 2.0 * cx * cz * S[2] + cy * cy * S[3]
-                     + 2.0 * cy * cz * S[4] + cz * cz * S[5];
-    const double trS = S[0] + S[3] + S[5];
-    const double base = q == 0 ? 1.0 - 2.0 * ep : 3.0 * w * ep;   // rho0 - (1 - omega_0) eps p / cs^2
-    return base + w * (3.0 * cu + 4.5 * (cu * cu - uu / 3.0) / K.eps) + w * 1.5 * K.A * (cSc - trS / 3.0);
+    const R cx = R(CX[q]), cy = R(CY[q]), cz = R(CZ[q]), w = R(W(q));
+    const R cu = cx * u[0] + cy * u[1] + cz * u[2];
+    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const R cSc = cx * cx * S[0] + R(2) * cx * cy * S[1] + R(2) * cx * cz * S[2] + cy * cy * S[3]
+                + R(2) * cy * cz * S[4] + cz * cz * S[5];
+    const R trS = S[0] + S[3] + S[5];
+    const R base = q == 0 ? R(-2) * ep : R(3) * w * ep;      // -(1 - omega_0) eps p / cs^2; omega_q eps p / cs^2
+    return base + w * (R(3) * cu + R(4.5) * (cu * cu - uu * R(1.0 / 3.0)) * R(1.0 / K.eps))
+         + w * R(1.5 * K.A) * (cSc - trS * R(1.0 / 3.0));
 }
 
-__device__ __forceinline__ double geq(int q, const K3 &K, double T, double ep, const double *u, const double *gT)
+template <typename R>
+__device__ __forceinline__ R geq(int q, const K3 &K, R T, R ep, const R *u, const R *gT)
 {
-    const double cx = CX[q], cy = CY[q], cz = CZ[q], w = W(q);
-    const double cu = cx * u[0] + cy * u[1] + cz * u[2];
-    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const double cg = cx * gT[0] + cy * gT[1] + cz * gT[2];
-    const double pres = q == 0 ? -2.0 * T * ep : 3.0 * w * T * ep;  // varpi_q T eps p / (cs^2 rho0)
-    return w * T * (K.sigma + 3.0 * cu + 4.5 * (cu * cu - uu / 3.0) / K.eps) + pres + K.sigma * w * K.B * cg;
+    const R cx = R(CX[q]), cy = R(CY[q]), cz = R(CZ[q]), w = R(W(q));
+    const R cu = cx * u[0] + cy * u[1] + cz * u[2];
+    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const R cg = cx * gT[0] + cy * gT[1] + cz * gT[2];
+    const R pres = q == 0 ? R(-2) * T * ep : R(3) * w * T * ep;   // varpi_q T eps p / (cs^2 rho0)
+    return w * T * (R(K.sigma) + R(3) * cu + R(4.5) * (cu * cu - uu * R(1.0 / 3.0)) * R(1.0 / K.eps)) + pres
+         + R(K.sigma * K.B) * w * cg;
 }
 
 // BGK collision with forcing and sources (Eqs. LBEeq, FtermF, TEqColli, Eq:Tforce).
-__device__ __forceinline__ void collide(double *f, double *g, const Mac &m, const K3 &K)
+template <typename R>
+__device__ __forceinline__ void collide(R *f, R *g, const Mac<R> &m, const K3 &K)
 {
-    const double ep = K.eps * m.p, ieps = 1.0 / K.eps;
-    const double fF = 1.0 - 0.5 / K.tau_f, fT = 1.0 - 0.5 / K.tau_T;
-    const double uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
-    const double ugT = m.u[0] * m.gT[0] + m.u[1] * m.gT[1] + m.u[2] * m.gT[2];
-    const double V[3] = {m.T * m.F[0] + ep * m.gT[0], m.T * m.F[1] + ep * m.gT[1], m.T * m.F[2] + ep * m.gT[2]};
+    const R ep = R(K.eps) * m.p, ieps = R(1.0 / K.eps), isig = R(1.0 / K.sigma);
+    const R fF = R(1.0 - 0.5 / K.tau_f), fT = R(1.0 - 0.5 / K.tau_T);
+    const R itf = R(1.0 / K.tau_f), itT = R(1.0 / K.tau_T), Q = R(K.Q);
+    const R uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
+    const R ugT = m.u[0] * m.gT[0] + m.u[1] * m.gT[1] + m.u[2] * m.gT[2];
+    const R V[3] = {m.T * m.F[0] + ep * m.gT[0], m.T * m.F[1] + ep * m.gT[1], m.T * m.F[2] + ep * m.gT[2]};
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const double cx = CX[q], cy = CY[q], cz = CZ[q], w = W(q);
-        const double cu = cx * m.u[0] + cy * m.u[1] + cz * m.u[2];
-        const double cF = cx * m.F[0] + cy * m.F[1] + cz * m.F[2];
-        const double cV = cx * V[0] + cy * V[1] + cz * V[2];
-        const double Fi = w * fF * (3.0 * cF + 4.5 * ieps * (2.0 * cu * cF - 2.0 * uF / 3.0));
-        const double Pi = w * fT * (3.0 * cV + 3.0 * (ieps - 1.0 / K.sigma) * cu * ugT);
-        const double Qi = w * fT * (1.0 + 3.0 * cu / K.sigma) * K.Q;
-        f[q] += (feq(q, K, ep, m.u, m.S) - f[q]) / K.tau_f + Fi;
-        g[q] += (geq(q, K, m.T, ep, m.u, m.gT) - g[q]) / K.tau_T + Pi + Qi;
+        const R cx = R(CX[q]), cy = R(CY[q]), cz = R(CZ[q]), w = R(W(q));
+        const R cu = cx * m.u[0] + cy * m.u[1] + cz * m.u[2];
+        const R cF = cx * m.F[0] + cy * m.F[1] + cz * m.F[2];
+        const R cV = cx * V[0] + cy * V[1] + cz * V[2];
+        const R Fi = w * fF * (R(3) * cF + R(4.5) * ieps * (R(2) * cu * cF - R(2.0 / 3.0) * uF));
+        const R Pi = w * fT * (R(3) * cV + R(3) * (ieps - isig) * cu * ugT);
+        const R Qi = w * fT * (R(1) + R(3) * cu * isig) * Q;
+        f[q] += (feq<R>(q, K, ep, m.u, m.S) - f[q]) * itf + Fi;
+        g[q] += (geq<R>(q, K, m.T, ep, m.u, m.gT) - g[q]) * itT + Pi + Qi;
     }
 }
 
@@ -169,43 +188,43 @@ __device__ __forceinline__ void collide(double *f, double *g, const Mac &m, cons
 // and their moments.  Wall (walled z, z = 0 or nz - 1): the non-equilibrium extrapolation
 // from x_f = (x, y, z +- 1) (and T of x_ff on prescribed-gradient walls), whose state is
 // the one the scheme assigns (T_b, u_b, p and S of x_f, the boundary grad T).
-template <typename S, bool WALLS = true>
+template <typename S, typename R, bool WALLS = true>
 __device__ __forceinline__ void node_state(const S *__restrict__ src, const K3 &K, int x, int y, int z,
-                                           double *f, double *g, Mac &m)
+                                           R *f, R *g, Mac<R> &m)
 {
     if (!WALLS || K.pz || (z > 0 && z < K.nz - 1)) {
-        pull<S>(src, K, x, y, z, f, g);
-        macro3(f, g, K, m);
+        pull<S, R>(src, K, x, y, z, f, g);
+        macro3<R>(f, g, K, m);
         return;
     }
     const int w = z == 0 ? 0 : 1, dz = z == 0 ? 1 : -1;
-    double ff[NQ], gf[NQ];
-    pull<S>(src, K, x, y, z + dz, ff, gf);
-    Mac mf;
-    macro3(ff, gf, K, mf);
-    double Tb, gb[3] = {mf.gT[0], mf.gT[1], mf.gT[2]};
+    R ff[NQ], gf[NQ];
+    pull<S, R>(src, K, x, y, z + dz, ff, gf);
+    Mac<R> mf;
+    macro3<R>(ff, gf, K, mf);
+    R Tb, gb[3] = {mf.gT[0], mf.gT[1], mf.gT[2]};
     if (K.wkind[w] == 0) {
-        Tb = K.wT[w];
+        Tb = R(K.wT[w]);
     } else {
-        double f2[NQ], g2[NQ];
-        pull<S>(src, K, x, y, z + 2 * dz, f2, g2);
-        double sg = 0.0;
+        R f2[NQ], g2[NQ];
+        pull<S, R>(src, K, x, y, z + 2 * dz, f2, g2);
+        R sg = R(0);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) sg += g2[q];
-        const double Tff = (sg + 0.5 * K.Q) / K.sigma;
-        gb[2] = dz * K.wdTdn[w];
-        Tb = (4.0 * mf.T - Tff - 2.0 * dz * gb[2]) / 3.0;
+        const R Tff = (sg + R(0.5 * K.Q)) * R(1.0 / K.sigma);
+        gb[2] = R(dz * K.wdTdn[w]);
+        Tb = (R(4) * mf.T - Tff - R(2 * dz) * gb[2]) * R(1.0 / 3.0);
     }
     m.T = Tb;
-    for (int a = 0; a < 3; ++a) { m.u[a] = K.wu[w][a]; m.gT[a] = gb[a]; }
-    force(K, m.u, m.T, m.F);
+    for (int a = 0; a < 3; ++a) { m.u[a] = R(K.wu[w][a]); m.gT[a] = gb[a]; }
+    force<R>(K, m.u, m.T, m.F);
     m.p = mf.p;
     for (int c = 0; c < 6; ++c) m.S[c] = mf.S[c];
-    const double ep = K.eps * mf.p;
+    const R ep = R(K.eps) * mf.p;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        f[q] = feq(q, K, ep, m.u, mf.S) + (ff[q] - feq(q, K, ep, mf.u, mf.S));
-        g[q] = geq(q, K, Tb, ep, m.u, gb) + (gf[q] - geq(q, K, mf.T, ep, mf.u, mf.gT));
+        f[q] = feq<R>(q, K, ep, m.u, mf.S) + (ff[q] - feq<R>(q, K, ep, mf.u, mf.S));
+        g[q] = geq<R>(q, K, Tb, ep, m.u, gb) + (gf[q] - geq<R>(q, K, mf.T, ep, mf.u, mf.gT));
     }
 }
 
@@ -219,14 +238,15 @@ __device__ __forceinline__ bool node_xyz(const K3 &K, int &x, int &y, int &z)
     return true;
 }
 
-template <typename S>
-__device__ __forceinline__ void store(S *__restrict__ dst, const K3 &K, size_t k, const double *f, const double *g)
+// Post-collision populations into the buffer: f as deviations already, g less its rest state.
+template <typename S, typename R>
+__device__ __forceinline__ void store(S *__restrict__ dst, const K3 &K, size_t k, const R *f, const R *g)
 {
     const double gT0 = K.sigma * K.T0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        dst[(size_t)q * K.n + k] = S(f[q] - (q == 0 ? 1.0 : 0.0));
-        dst[(size_t)(NQ + q) * K.n + k] = S(g[q] - W(q) * gT0);
+        dst[(size_t)q * K.n + k] = S(f[q]);
+        dst[(size_t)(NQ + q) * K.n + k] = S(g[q] - R(W(q) * gT0));
     }
 }
 
@@ -237,35 +257,37 @@ constexpr int B3 = 256;
 template <typename S>
 __global__ void __launch_bounds__(B3) k3_step_interior(const S *__restrict__ src, S *__restrict__ dst, K3 K)
 {
+    using R = typename Arith<S>::R;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long plane = (long long)K.nx * K.ny;
     const long long k = K.pz ? i : i + plane;            // walled: planes 1 .. nz - 2
     if (k >= (K.pz ? K.n : K.n - plane)) return;
     const int x = (int)(k % K.nx), y = (int)((k / K.nx) % K.ny), z = (int)(k / plane);
-    double f[NQ], g[NQ];
-    Mac m;
-    node_state<S, false>(src, K, x, y, z, f, g, m);
-    collide(f, g, m, K);
-    store<S>(dst, K, (size_t)k, f, g);
+    R f[NQ], g[NQ];
+    Mac<R> m;
+    node_state<S, R, false>(src, K, x, y, z, f, g, m);
+    collide<R>(f, g, m, K);
+    store<S, R>(dst, K, (size_t)k, f, g);
 }
 
 template <typename S>
 __global__ void __launch_bounds__(B3) k3_step_walls(const S *__restrict__ src, S *__restrict__ dst, K3 K)
 {
+    using R = typename Arith<S>::R;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long plane = (long long)K.nx * K.ny;
     if (i >= 2 * plane) return;
     const long long k = i < plane ? i : (long long)(K.nz - 1) * plane + (i - plane);
     const int x = (int)(k % K.nx), y = (int)((k / K.nx) % K.ny), z = (int)(k / plane);
-    double f[NQ], g[NQ];
-    Mac m;
-    node_state<S>(src, K, x, y, z, f, g, m);
-    collide(f, g, m, K);
-    store<S>(dst, K, (size_t)k, f, g);
+    R f[NQ], g[NQ];
+    Mac<R> m;
+    node_state<S, R>(src, K, x, y, z, f, g, m);
+    collide<R>(f, g, m, K);
+    store<S, R>(dst, K, (size_t)k, f, g);
 }
 
 // Initial post-collision populations: the equilibria of the initial fields (S = 0,
-// grad T = 0, p = 0).
+// grad T = 0, p = 0), computed in FP64.
 template <typename S>
 __global__ void __launch_bounds__(B3) k3_init(S *__restrict__ dst, K3 K, const double *T_init, const double *u_init)
 {
@@ -283,10 +305,10 @@ __global__ void __launch_bounds__(B3) k3_init(S *__restrict__ dst, K3 K, const d
     double f[NQ], g[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        f[q] = feq(q, K, 0.0, u, S0);
-        g[q] = geq(q, K, T, 0.0, u, g0);
+        f[q] = feq<double>(q, K, 0.0, u, S0);
+        g[q] = geq<double>(q, K, T, 0.0, u, g0);
     }
-    store<S>(dst, K, k, f, g);
+    store<S, double>(dst, K, k, f, g);
 }
 
 struct FieldOut3 { double *p, *u, *T, *S, *gT; };
@@ -294,34 +316,37 @@ struct FieldOut3 { double *p, *u, *T, *S, *gT; };
 template <typename S>
 __global__ void __launch_bounds__(B3) k3_fields(const S *__restrict__ src, K3 K, FieldOut3 o)
 {
+    using R = typename Arith<S>::R;
     int x, y, z;
     if (!node_xyz(K, x, y, z)) return;
-    double f[NQ], g[NQ];
-    Mac m;
-    node_state<S>(src, K, x, y, z, f, g, m);
+    R f[NQ], g[NQ];
+    Mac<R> m;
+    node_state<S, R>(src, K, x, y, z, f, g, m);
     const size_t k = ((size_t)z * K.ny + y) * K.nx + x, n = (size_t)K.n;
-    if (o.p) o.p[k] = m.p;
-    if (o.T) o.T[k] = m.T;
+    if (o.p) o.p[k] = double(m.p);
+    if (o.T) o.T[k] = double(m.T);
     for (int a = 0; a < 3; ++a) {
-        if (o.u) o.u[a * n + k] = m.u[a];
-        if (o.gT) o.gT[a * n + k] = m.gT[a];
+        if (o.u) o.u[a * n + k] = double(m.u[a]);
+        if (o.gT) o.gT[a * n + k] = double(m.gT[a]);
     }
     if (o.S)
-        for (int c = 0; c < 6; ++c) o.S[c * n + k] = m.S[c];
+        for (int c = 0; c < 6; ++c) o.S[c * n + k] = double(m.S[c]);
 }
 
+// Pre-collision populations with the rest state added back (f_0 + rho0).
 template <typename S>
 __global__ void __launch_bounds__(B3) k3_populations(const S *__restrict__ src, K3 K, double *fo, double *go)
 {
+    using R = typename Arith<S>::R;
     int x, y, z;
     if (!node_xyz(K, x, y, z)) return;
-    double f[NQ], g[NQ];
-    Mac m;
-    node_state<S>(src, K, x, y, z, f, g, m);
+    R f[NQ], g[NQ];
+    Mac<R> m;
+    node_state<S, R>(src, K, x, y, z, f, g, m);
     const size_t k = ((size_t)z * K.ny + y) * K.nx + x;
     for (int q = 0; q < NQ; ++q) {
-        if (fo) fo[(size_t)q * K.n + k] = f[q];
-        if (go) go[(size_t)q * K.n + k] = g[q];
+        if (fo) fo[(size_t)q * K.n + k] = double(f[q]) + (q == 0 ? 1.0 : 0.0);
+        if (go) go[(size_t)q * K.n + k] = double(g[q]);
     }
 }
 

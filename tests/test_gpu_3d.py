@@ -1,7 +1,7 @@
 """The 3-D (D3Q19) HIP path through the C interface against the 3-D oracle: populations and
 every field of seeded random problems (walled and periodic z, isothermal and
 prescribed-gradient walls, moving walls, ragged sizes, the smallest walled nz), FP64 within
-1e-10 and FP32 within 1e-5 relative L2, the exact conduction fixed point, and a larger
+1e-10 and FP32 within 1e-5 relative L2, the exact conduction fixed point, a larger
 layer heated from below."""
 import numpy as np
 import pytest
