@@ -17,8 +17,8 @@
  * Units, status codes, storage types and thread rules are those of lbm.h.  Arrays are
  * [z][y][x] with x fastest; vector fields are consecutive planes (x, y, z components).
  * The populations live in a caller-provided device workspace as two buffers of 2 x 19
- * planes (flow, temperature), in deviation form as in two dimensions; the arithmetic is
- * FP64 for both storage types.
+ * planes (flow, temperature), in deviation form as in two dimensions; the arithmetic is in
+ * the storage precision (FP64 or FP32), with the drag solve in FP64.
  */
 #pragma once
 
