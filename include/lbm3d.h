@@ -76,8 +76,9 @@ size_t lbm3_workspace_bytes(const lbm3_params *params);
 lbm_status lbm3_init(const lbm3_params *params, void *workspace, size_t workspace_bytes,
                      void *hip_stream, lbm3_ctx **out);
 
-/* Enqueues nsteps time steps (collide, stream, boundary scheme; one launch per step).
- * Asynchronous; nsteps < 0 is LBM_ERR_INVALID. */
+/* Enqueues nsteps time steps (collide, stream, boundary scheme; per step one launch over
+ * the interior nodes and, with walls, one over the two wall planes).  Asynchronous;
+ * nsteps < 0 is LBM_ERR_INVALID. */
 lbm_status lbm3_step(lbm3_ctx *ctx, int64_t nsteps);
 
 /* Macroscopic fields at the current time into FP64 device arrays (any may be NULL):
