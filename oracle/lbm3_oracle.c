@@ -75,7 +75,7 @@ typedef struct {
     double L;                      /* characteristic length; 0 => nz - 1 */
     double Da, Ra, Pr, J, Ma, sigma, Q;
     double tau_f, tau_T, A, B;     /* A, B: NaN => from Ma, Ra, Pr (Eq. EQA&B) */
-    double eps;                    /* uniform porosity */
+    double eps;                    /* porosity when no field is given */
     double a[3];                   /* external acceleration */
     double T_hot, T_cold;
     double F_eps;                  /* NaN => Ergun relation */
@@ -95,6 +95,7 @@ typedef struct {
     o3_params prm;
     o3_derived d;
     int n;
+    double *eps;                   /* porosity per node */
     double *f, *g, *fs, *gs;       /* pre- and post-collision populations, [node][19] */
     o3_macro *mb;                  /* per node: the boundary state of wall nodes (R5) */
     int64_t t;
@@ -208,11 +209,11 @@ static double det3(double M[3][3])
 /* Macroscopic state of a node from its pre-collision populations, in the order of the
  * 2-D model: T, G, v and u (drag solve), F, p, S (Eq. ShearEqCom), grad T (Eqs. MatrM,
  * MatrN, TeEqCom). */
-static void node_macro(const o3_sim *s, const double *f, const double *g, o3_macro *m)
+static void node_macro(const o3_sim *s, double eps, const double *f, const double *g, o3_macro *m)
 {
     const o3_params *P = &s->prm;
     const o3_derived *D = &s->d;
-    const double eps = P->eps, sigma = P->sigma, Q = P->Q, tf = P->tau_f, tT = P->tau_T;
+    const double sigma = P->sigma, Q = P->Q, tf = P->tau_f, tT = P->tau_T;
     m->eps = eps;
     double sg = 0.0;
     for (int i = 0; i < Q19; ++i) sg += g[i];
@@ -320,7 +321,7 @@ static void collide_all(o3_sim *s)
     for (int k = 0; k < s->n; ++k) {
         o3_macro m;
         if (is_wall(s, k)) m = s->mb[k];
-        else node_macro(s, s->f + Q19 * k, s->g + Q19 * k, &m);
+        else node_macro(s, s->eps[k], s->f + Q19 * k, s->g + Q19 * k, &m);
         collide_state(s, &m, s->f + Q19 * k, s->g + Q19 * k, s->fs + Q19 * k, s->gs + Q19 * k);
     }
 }
@@ -354,12 +355,13 @@ static void nees_node(o3_sim *s, int x, int y, int z)
     const int kb = idx(s, x, y, z), kf = idx(s, x, y, z + dz), kff = idx(s, x, y, z + 2 * dz);
     const double *ff = s->f + Q19 * kf, *gf = s->g + Q19 * kf;
     o3_macro mf;
-    node_macro(s, ff, gf, &mf);
+    node_macro(s, s->eps[kf], ff, gf, &mf);
+    const double eb = s->eps[kb];
     double fe_f[Q19], ge_f[Q19], fe_b[Q19], ge_b[Q19];
     feq_full(s, mf.eps, mf.p, mf.u, mf.S, fe_f);
     geq_full(s, mf.eps, mf.T, mf.u, mf.p, mf.dT, ge_f);
     const double *ub = P->wall_u[w];
-    feq_full(s, P->eps, mf.p, ub, mf.S, fe_b);
+    feq_full(s, eb, mf.p, ub, mf.S, fe_b);
     for (int i = 0; i < Q19; ++i) s->f[Q19 * kb + i] = fe_b[i] + (ff[i] - fe_f[i]);
 
     double Tb, gb[3] = {mf.dT[0], mf.dT[1], mf.dT[2]};
@@ -372,15 +374,15 @@ static void nees_node(o3_sim *s, int x, int y, int z)
         double Tff = (sgff + 0.5 * P->Q) / P->sigma;
         Tb = (4.0 * mf.T - Tff - 2.0 * dz * gb[2]) / 3.0;
     }
-    geq_full(s, P->eps, Tb, ub, mf.p, gb, ge_b);
+    geq_full(s, eb, Tb, ub, mf.p, gb, ge_b);
     for (int i = 0; i < Q19; ++i) s->g[Q19 * kb + i] = ge_b[i] + (gf[i] - ge_f[i]);
 
     o3_macro *m = &s->mb[kb];
-    m->eps = P->eps;
+    m->eps = eb;
     m->T = Tb;
     for (int a = 0; a < 3; ++a) { m->u[a] = ub[a]; m->G[a] = P->a[a]; m->dT[a] = gb[a]; }
     m->G[2] += s->d.gbeta * (Tb - s->d.T0);
-    force_of(s, P->eps, m->u, m->G, m->F);
+    force_of(s, eb, m->u, m->G, m->F);
     m->p = mf.p;
     memcpy(m->S, mf.S, sizeof(m->S));
 }
@@ -418,9 +420,10 @@ int o3_derive(const o3_params *p, double *out /* 10 */)
     return r;
 }
 
-/* Initial fields (R1, R2): optional T, u per node ([z][y][x], u as three planes); NULL
- * means u = 0 and T = T0 inside, T_wall on isothermal wall nodes.  p = 0. */
-o3_sim *o3_create(const o3_params *p, const double *T_init, const double *u_init)
+/* Initial fields (R1, R2): optional porosity, T, u per node ([z][y][x], u as three planes);
+ * NULL means the uniform eps, u = 0 and T = T0 inside, T_wall on isothermal wall nodes.
+ * p = 0. */
+o3_sim *o3_create(const o3_params *p, const double *eps_field, const double *T_init, const double *u_init)
 {
     build_lattice();
     o3_sim *s = (o3_sim *)calloc(1, sizeof(o3_sim));
@@ -432,6 +435,8 @@ o3_sim *o3_create(const o3_params *p, const double *T_init, const double *u_init
     s->fs = (double *)malloc(sizeof(double) * Q19 * s->n);
     s->gs = (double *)malloc(sizeof(double) * Q19 * s->n);
     s->mb = (o3_macro *)calloc((size_t)s->n, sizeof(o3_macro));
+    s->eps = (double *)malloc(sizeof(double) * s->n);
+    for (int k = 0; k < s->n; ++k) s->eps[k] = eps_field ? eps_field[k] : p->eps;
     double S0[3][3] = {{0}}, g0[3] = {0, 0, 0};
     for (int k = 0; k < s->n; ++k) {
         int z = k / (p->nx * p->ny);
@@ -442,8 +447,8 @@ o3_sim *o3_create(const o3_params *p, const double *T_init, const double *u_init
         double u[3] = {0, 0, 0};
         if (u_init)
             for (int a = 0; a < 3; ++a) u[a] = u_init[(size_t)a * s->n + k];
-        feq_full(s, p->eps, 0.0, u, S0, s->fs + Q19 * k);
-        geq_full(s, p->eps, T, u, 0.0, g0, s->gs + Q19 * k);
+        feq_full(s, s->eps[k], 0.0, u, S0, s->fs + Q19 * k);
+        geq_full(s, s->eps[k], T, u, 0.0, g0, s->gs + Q19 * k);
     }
     memcpy(s->f, s->fs, sizeof(double) * Q19 * s->n);
     memcpy(s->g, s->gs, sizeof(double) * Q19 * s->n);
@@ -456,7 +461,7 @@ o3_sim *o3_create(const o3_params *p, const double *T_init, const double *u_init
 void o3_destroy(o3_sim *s)
 {
     if (!s) return;
-    free(s->f); free(s->g); free(s->fs); free(s->gs); free(s->mb);
+    free(s->eps); free(s->f); free(s->g); free(s->fs); free(s->gs); free(s->mb);
     free(s);
 }
 
@@ -478,7 +483,7 @@ void o3_fields(const o3_sim *s, double *p, double *u, double *T, double *S, doub
     for (int k = 0; k < s->n; ++k) {
         o3_macro m;
         if (is_wall(s, k)) m = s->mb[k];
-        else node_macro(s, s->f + Q19 * k, s->g + Q19 * k, &m);
+        else node_macro(s, s->eps[k], s->f + Q19 * k, s->g + Q19 * k, &m);
         if (p) p[k] = m.p;
         if (T) T[k] = m.T;
         for (int a = 0; a < 3; ++a) {

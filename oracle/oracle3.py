@@ -78,7 +78,7 @@ def _lib():
     L = C.CDLL(LIB)
     vp = C.c_void_p
     L.o3_create.restype = vp
-    L.o3_create.argtypes = [C.POINTER(_Params), vp, vp]
+    L.o3_create.argtypes = [C.POINTER(_Params), vp, vp, vp]
     L.o3_destroy.argtypes = [vp]
     L.o3_step.argtypes = [vp, C.c_int64]
     L.o3_fields.argtypes = [vp] * 6
@@ -121,9 +121,11 @@ class Oracle3:
         self.shape = (int(cfg["nz"]), int(cfg["ny"]), int(cfg["nx"]))
         self.n = int(np.prod(self.shape))
         self._p = params_from_dict(cfg)
+        e = cfg.get("eps_field")
         T = cfg.get("T_init")
         u = cfg.get("u_init")
-        self._keep = [None if T is None else np.ascontiguousarray(np.asarray(T, np.float64).reshape(self.shape)),
+        self._keep = [None if e is None else np.ascontiguousarray(np.asarray(e, np.float64).reshape(self.shape)),
+                      None if T is None else np.ascontiguousarray(np.asarray(T, np.float64).reshape(self.shape)),
                       None if u is None else np.ascontiguousarray(np.asarray(u, np.float64).reshape((3,) + self.shape))]
         h = self.lib.o3_create(C.byref(self._p), *[_ptr(a) for a in self._keep])
         if not h:

@@ -130,3 +130,29 @@ def test_mass_conservation():
     f1, g1 = o.populations()
     assert abs(f1.sum() - f0.sum()) < 1e-10 * f0.size
     assert abs(g1.sum() - g0.sum()) < 1e-10 * g0.size
+
+
+def test_rest_state_with_porosity_field():
+    """Fluid at rest at uniform temperature is an exact steady state for any porosity field
+    (no force, no source): populations unchanged after 100 steps."""
+    import workloads as W
+    cfg = W.random_case3d(6, 6, 5, 7, eps_field=True)
+    cfg.update({"Q": 0.0, "a": (0.0, 0.0, 0.0), "Ra": 0.0, "T_init": None, "u_init": None,
+                "walls": [{"kind": "T", "T": 0.5}, {"kind": "T", "T": 0.5}], "T_hot": 0.5, "T_cold": 0.5})
+    o = O3.Oracle3(cfg)
+    f0, g0 = o.populations()
+    o.step(100)
+    f1, g1 = o.populations()
+    assert np.abs(f1 - f0).max() < 1e-14 and np.abs(g1 - g0).max() < 1e-14
+
+
+def test_mass_conservation_with_porosity_field():
+    import workloads as W
+    cfg = W.random_case3d(7, 6, 5, 7, periodic_z=1, eps_field=True)
+    cfg.update({"Q": 0.0, "a": (0.0, 0.0, 0.0), "Ra": 0.0})
+    o = O3.Oracle3(cfg)
+    f0, g0 = o.populations()
+    o.step(50)
+    f1, g1 = o.populations()
+    assert abs(f1.sum() - f0.sum()) < 1e-10 * f0.size
+    assert abs(g1.sum() - g0.sum()) < 1e-10 * g0.size

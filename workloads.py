@@ -212,10 +212,11 @@ def layer3d(nx=64, ny=64, nz=32, eps=0.6, Da=1e-2, Ra=1e4, Pr=1.0, seed=0, stora
     }
 
 
-def random_case3d(seed, nx, ny, nz, periodic_z=0, storage="f64"):
+def random_case3d(seed, nx, ny, nz, periodic_z=0, storage="f64", eps_field=False):
     """A randomised 3-D problem with a non-trivial initial flow and temperature for parity
     tests: random Da, Ra in [1e2, 1e3], Pr, tau, A, B, eps, forcing and heat source, wall
-    kinds and wall velocities, smooth random initial u and T."""
+    kinds and wall velocities, smooth random initial u and T; with eps_field, a smooth
+    random porosity field in [0.4, 0.9] (drawn after everything else)."""
     rng = np.random.default_rng(seed)
     tau_f, tau_T = rng.uniform(0.7, 1.3), rng.uniform(0.7, 1.3)
     walls = []
@@ -235,7 +236,7 @@ def random_case3d(seed, nx, ny, nz, periodic_z=0, storage="f64"):
         return amp * f / max(np.abs(f).max(), 1e-30)
     u = np.stack([smooth(0.02), smooth(0.02), smooth(0.01)])
     T = 0.5 + smooth(0.3)
-    return {
+    cfg = {
         "nx": nx, "ny": ny, "nz": nz, "periodic_z": periodic_z, "walls": walls,
         "L": 200.0, "Da": float(10 ** rng.uniform(-3, -1)), "Ra": float(10 ** rng.uniform(2, 3)),
         "Pr": float(rng.uniform(0.7, 2.0)), "J": 1.0, "Ma": 0.1, "sigma": float(rng.uniform(0.8, 1.2)),
@@ -244,3 +245,6 @@ def random_case3d(seed, nx, ny, nz, periodic_z=0, storage="f64"):
         "eps": float(rng.uniform(0.4, 0.95)), "a": tuple(float(v) for v in rng.uniform(-1e-5, 1e-5, size=3)),
         "T_hot": 1.0, "T_cold": 0.0, "F_eps": None, "T_init": T, "u_init": u, "storage": storage,
     }
+    if eps_field:
+        cfg["eps_field"] = 0.65 + smooth(0.25)
+    return cfg
