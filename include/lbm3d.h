@@ -44,10 +44,12 @@ typedef struct {
 
 /* Problem description.  L = characteristic length: L if > 0, else nz - 1 (walled z) or nz
  * (periodic z).  A, B given, or if either is NaN from Ma, Ra, Pr (Eq. EQA&B).  nu_e, alpha_e,
- * g beta, K, T0 and dT follow as in two dimensions (lbm.h).  Porosity uniform (eps).
- * T_init ([nz][ny][nx]) and u_init (3 planes) are optional FP64 device arrays read during
- * lbm3_init only; NULL means T = T0 (T_wall on isothermal wall nodes) and u = 0; p starts
- * at 0 (gauge pressure). */
+ * g beta, K, T0 and dT follow as in two dimensions (lbm.h).  eps_field ([nz][ny][nx], FP64,
+ * device, values in (0, 1]) gives the porosity per node and must stay valid until
+ * lbm3_destroy (the kernels read it every step; K = Da L^2 stays uniform, F_eps follows the
+ * Ergun relation per node unless given); NULL means the uniform eps.  T_init ([nz][ny][nx])
+ * and u_init (3 planes) are optional FP64 device arrays read during lbm3_init only; NULL
+ * means T = T0 (T_wall on isothermal wall nodes) and u = 0; p starts at 0 (gauge pressure). */
 typedef struct {
     int32_t nx, ny, nz, periodic_z;
     lbm3_wall wall[2];
@@ -61,6 +63,7 @@ typedef struct {
     int32_t reserved;
     const double *T_init;
     const double *u_init;
+    const double *eps_field;
 } lbm3_params;
 
 /* Workspace bytes lbm3_init needs for this problem (0 if it is invalid; lbm_last_error

@@ -34,11 +34,37 @@ struct K3 {
     double tau_f, tau_T, A, B, sigma, Q, eps, T0, gbeta;
     double a[3];
     double c0, c1, dlin, dquad;      // drag solve: c0, c1; force: eps nu / K, eps F_eps / sqrt(K)
+    const double *eps_field;         // porosity per node, or NULL for the uniform eps
+    double nuK, isqK, Feps;          // nu / K, 1 / sqrt(K), F_eps (if not from the Ergun relation)
+    int ergun;
     int wkind[2];
     double wu[2][3], wT[2], wdTdn[2];
 };
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Porosity-dependent coefficients of one node (Sec. 2, Eq. ForceEq; Sec. 3.1 drag solve).
+struct Por {
+    double eps, ieps, c0, c1, dlin, dquad;
+};
+
+__device__ __forceinline__ Por por_of(const K3 &K, size_t k)
+{
+    Por e;
+    if (!K.eps_field) {
+        e.eps = K.eps; e.c0 = K.c0; e.c1 = K.c1; e.dlin = K.dlin; e.dquad = K.dquad;
+    } else {
+        const double eps = K.eps_field[k];
+        const double Feps = K.ergun ? 1.75 / sqrt(150.0 * eps * eps * eps) : K.Feps;
+        e.eps = eps;
+        e.c0 = 0.5 * (1.0 + eps * 0.5 * K.nuK);
+        e.c1 = eps * 0.5 * Feps * K.isqK;
+        e.dlin = eps * K.nuK;
+        e.dquad = eps * Feps * K.isqK;
+    }
+    e.ieps = 1.0 / e.eps;
+    return e;
+}
 
 // Arithmetic type of a storage type: FP64 storage computes in FP64, FP32 storage in FP32
 // (the drag solve in FP64 for both).  The flow populations are handled as deviations
@@ -67,10 +93,10 @@ __device__ __forceinline__ void pull(const S *__restrict__ src, const K3 &K, int
 
 // G and F (Eq. ForceEq) at velocity u and temperature T.
 template <typename R>
-__device__ __forceinline__ void force(const K3 &K, const R *u, R T, R *F)
+__device__ __forceinline__ void force(const K3 &K, const Por &e, const R *u, R T, R *F)
 {
     const R um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    const R dl = R(K.dlin) + R(K.dquad) * um, eps = R(K.eps);
+    const R dl = R(e.dlin) + R(e.dquad) * um, eps = R(e.eps);
     F[0] = eps * R(K.a[0]) - dl * u[0];
     F[1] = eps * R(K.a[1]) - dl * u[1];
     F[2] = eps * (R(K.a[2]) + R(K.gbeta) * (T - R(K.T0))) - dl * u[2];
@@ -87,7 +113,7 @@ template <typename R> struct Mac {
 // is eps p I + u u / eps), grad T = <M>^-1 <N> by the Sherman-Morrison form of
 // <M> = a I - b u u.
 template <typename R>
-__device__ __forceinline__ void macro3(const R *f, const R *g, const K3 &K, Mac<R> &m)
+__device__ __forceinline__ void macro3(const R *f, const R *g, const K3 &K, const Por &e, Mac<R> &m)
 {
     R sg = R(0), s18 = R(0), j[3] = {R(0), R(0), R(0)}, P[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     R h[3] = {R(0), R(0), R(0)};
@@ -101,15 +127,15 @@ __device__ __forceinline__ void macro3(const R *f, const R *g, const K3 &K, Mac<
         P[3] += cy * cy * f[q]; P[4] += cy * cz * f[q]; P[5] += cz * cz * f[q];
         h[0] += cx * g[q]; h[1] += cy * g[q]; h[2] += cz * g[q];
     }
-    const R eps = R(K.eps), ieps = R(1.0 / K.eps), isig = R(1.0 / K.sigma), Q = R(K.Q);
+    const R eps = R(e.eps), ieps = R(e.ieps), isig = R(1.0 / K.sigma), Q = R(K.Q);
     m.T = (sg + R(0.5) * Q) * isig;
     const R G[3] = {R(K.a[0]), R(K.a[1]), R(K.a[2]) + R(K.gbeta) * (m.T - R(K.T0))};
     double v[3];
     for (int a = 0; a < 3; ++a) v[a] = double(j[a] + R(0.5) * eps * G[a]);
     const double vm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    const double iden = 1.0 / (K.c0 + sqrt(K.c0 * K.c0 + K.c1 * vm));
+    const double iden = 1.0 / (e.c0 + sqrt(e.c0 * e.c0 + e.c1 * vm));
     for (int a = 0; a < 3; ++a) m.u[a] = R(v[a] * iden);
-    force<R>(K, m.u, m.T, m.F);
+    force<R>(K, e, m.u, m.T, m.F);
     const R uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
     const R uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
     // rho0 s_0 = -omega_0 |u|^2 / (2 eps cs^2) = -|u|^2 / (2 eps); tau_f F_0 = -tau_f (1 - 1/(2 tau_f)) u.F / eps
@@ -126,7 +152,7 @@ __device__ __forceinline__ void macro3(const R *f, const R *g, const K3 &K, Mac<
     R N[3];
     for (int a = 0; a < 3; ++a) N[a] = h[a] - m.T * m.u[a] + R(0.5) * (m.T * m.F[a] + m.u[a] * Q * isig);
     const R am = R(K.sigma * (K.B - K.tau_T) / 3.0) - R(0.5) * ep;
-    const R bm = R(0.5 * (1.0 / K.eps - 1.0 / K.sigma));
+    const R bm = R(0.5 * (e.ieps - 1.0 / K.sigma));
     const R uN = m.u[0] * N[0] + m.u[1] * N[1] + m.u[2] * N[2];
     const R c = bm * uN / (am - bm * uu);
     for (int a = 0; a < 3; ++a) m.gT[a] = (N[a] + c * m.u[a]) / am;
@@ -135,7 +161,7 @@ __device__ __forceinline__ void macro3(const R *f, const R *g, const K3 &K, Mac<
 // Equilibria (Eqs. EQFIN, EQTSHIN, TeEDFEQ) of direction q for pressure term ep = eps p;
 // the flow equilibrium as a deviation (f_0^eq - rho0 for q = 0).
 template <typename R>
-__device__ __forceinline__ R feq(int q, const K3 &K, R ep, const R *u, const R *S)
+__device__ __forceinline__ R feq(int q, const K3 &K, const Por &e, R ep, const R *u, const R *S)
 {
     const R cx = R(CX[q]), cy = R(CY[q]), cz = R(CZ[q]), w = R(W(q));
     const R cu = cx * u[0] + cy * u[1] + cz * u[2];
@@ -144,27 +170,27 @@ __device__ __forceinline__ R feq(int q, const K3 &K, R ep, const R *u, const R *
                 + R(2) * cy * cz * S[4] + cz * cz * S[5];
     const R trS = S[0] + S[3] + S[5];
     const R base = q == 0 ? R(-2) * ep : R(3) * w * ep;      // -(1 - omega_0) eps p / cs^2; omega_q eps p / cs^2
-    return base + w * (R(3) * cu + R(4.5) * (cu * cu - uu * R(1.0 / 3.0)) * R(1.0 / K.eps))
+    return base + w * (R(3) * cu + R(4.5) * (cu * cu - uu * R(1.0 / 3.0)) * R(e.ieps))
          + w * R(1.5 * K.A) * (cSc - trS * R(1.0 / 3.0));
 }
 
 template <typename R>
-__device__ __forceinline__ R geq(int q, const K3 &K, R T, R ep, const R *u, const R *gT)
+__device__ __forceinline__ R geq(int q, const K3 &K, const Por &e, R T, R ep, const R *u, const R *gT)
 {
     const R cx = R(CX[q]), cy = R(CY[q]), cz = R(CZ[q]), w = R(W(q));
     const R cu = cx * u[0] + cy * u[1] + cz * u[2];
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const R cg = cx * gT[0] + cy * gT[1] + cz * gT[2];
     const R pres = q == 0 ? R(-2) * T * ep : R(3) * w * T * ep;   // varpi_q T eps p / (cs^2 rho0)
-    return w * T * (R(K.sigma) + R(3) * cu + R(4.5) * (cu * cu - uu * R(1.0 / 3.0)) * R(1.0 / K.eps)) + pres
+    return w * T * (R(K.sigma) + R(3) * cu + R(4.5) * (cu * cu - uu * R(1.0 / 3.0)) * R(e.ieps)) + pres
          + R(K.sigma * K.B) * w * cg;
 }
 
 // BGK collision with forcing and sources (Eqs. LBEeq, FtermF, TEqColli, Eq:Tforce).
 template <typename R>
-__device__ __forceinline__ void collide(R *f, R *g, const Mac<R> &m, const K3 &K)
+__device__ __forceinline__ void collide(R *f, R *g, const Mac<R> &m, const K3 &K, const Por &e)
 {
-    const R ep = R(K.eps) * m.p, ieps = R(1.0 / K.eps), isig = R(1.0 / K.sigma);
+    const R ep = R(e.eps) * m.p, ieps = R(e.ieps), isig = R(1.0 / K.sigma);
     const R fF = R(1.0 - 0.5 / K.tau_f), fT = R(1.0 - 0.5 / K.tau_T);
     const R itf = R(1.0 / K.tau_f), itT = R(1.0 / K.tau_T), Q = R(K.Q);
     const R uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
@@ -179,8 +205,8 @@ __device__ __forceinline__ void collide(R *f, R *g, const Mac<R> &m, const K3 &K
         const R Fi = w * fF * (R(3) * cF + R(4.5) * ieps * (R(2) * cu * cF - R(2.0 / 3.0) * uF));
         const R Pi = w * fT * (R(3) * cV + R(3) * (ieps - isig) * cu * ugT);
         const R Qi = w * fT * (R(1) + R(3) * cu * isig) * Q;
-        f[q] += (feq<R>(q, K, ep, m.u, m.S) - f[q]) * itf + Fi;
-        g[q] += (geq<R>(q, K, m.T, ep, m.u, m.gT) - g[q]) * itT + Pi + Qi;
+        f[q] += (feq<R>(q, K, e, ep, m.u, m.S) - f[q]) * itf + Fi;
+        g[q] += (geq<R>(q, K, e, m.T, ep, m.u, m.gT) - g[q]) * itT + Pi + Qi;
     }
 }
 
@@ -190,18 +216,21 @@ __device__ __forceinline__ void collide(R *f, R *g, const Mac<R> &m, const K3 &K
 // the one the scheme assigns (T_b, u_b, p and S of x_f, the boundary grad T).
 template <typename S, typename R, bool WALLS = true>
 __device__ __forceinline__ void node_state(const S *__restrict__ src, const K3 &K, int x, int y, int z,
-                                           R *f, R *g, Mac<R> &m)
+                                           R *f, R *g, Mac<R> &m, Por &e)
 {
+    const size_t plane = (size_t)K.nx * K.ny, k = (size_t)z * plane + (size_t)y * K.nx + x;
+    e = por_of(K, k);
     if (!WALLS || K.pz || (z > 0 && z < K.nz - 1)) {
         pull<S, R>(src, K, x, y, z, f, g);
-        macro3<R>(f, g, K, m);
+        macro3<R>(f, g, K, e, m);
         return;
     }
     const int w = z == 0 ? 0 : 1, dz = z == 0 ? 1 : -1;
     R ff[NQ], gf[NQ];
     pull<S, R>(src, K, x, y, z + dz, ff, gf);
+    const Por ef = por_of(K, k + (dz > 0 ? plane : -plane));
     Mac<R> mf;
-    macro3<R>(ff, gf, K, mf);
+    macro3<R>(ff, gf, K, ef, mf);
     R Tb, gb[3] = {mf.gT[0], mf.gT[1], mf.gT[2]};
     if (K.wkind[w] == 0) {
         Tb = R(K.wT[w]);
@@ -217,14 +246,14 @@ __device__ __forceinline__ void node_state(const S *__restrict__ src, const K3 &
     }
     m.T = Tb;
     for (int a = 0; a < 3; ++a) { m.u[a] = R(K.wu[w][a]); m.gT[a] = gb[a]; }
-    force<R>(K, m.u, m.T, m.F);
+    force<R>(K, e, m.u, m.T, m.F);
     m.p = mf.p;
     for (int c = 0; c < 6; ++c) m.S[c] = mf.S[c];
-    const R ep = R(K.eps) * mf.p;
+    const R epb = R(e.eps) * mf.p, epf = R(ef.eps) * mf.p;   // the wall node's porosity, x_f's pressure
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        f[q] = feq<R>(q, K, ep, m.u, mf.S) + (ff[q] - feq<R>(q, K, ep, mf.u, mf.S));
-        g[q] = geq<R>(q, K, Tb, ep, m.u, gb) + (gf[q] - geq<R>(q, K, mf.T, ep, mf.u, mf.gT));
+        f[q] = feq<R>(q, K, e, epb, m.u, mf.S) + (ff[q] - feq<R>(q, K, ef, epf, mf.u, mf.S));
+        g[q] = geq<R>(q, K, e, Tb, epb, m.u, gb) + (gf[q] - geq<R>(q, K, ef, mf.T, epf, mf.u, mf.gT));
     }
 }
 
@@ -265,8 +294,9 @@ __global__ void __launch_bounds__(B3) k3_step_interior(const S *__restrict__ src
     const int x = (int)(k % K.nx), y = (int)((k / K.nx) % K.ny), z = (int)(k / plane);
     R f[NQ], g[NQ];
     Mac<R> m;
-    node_state<S, R, false>(src, K, x, y, z, f, g, m);
-    collide<R>(f, g, m, K);
+    Por e;
+    node_state<S, R, false>(src, K, x, y, z, f, g, m, e);
+    collide<R>(f, g, m, K, e);
     store<S, R>(dst, K, (size_t)k, f, g);
 }
 
@@ -281,8 +311,9 @@ __global__ void __launch_bounds__(B3) k3_step_walls(const S *__restrict__ src, S
     const int x = (int)(k % K.nx), y = (int)((k / K.nx) % K.ny), z = (int)(k / plane);
     R f[NQ], g[NQ];
     Mac<R> m;
-    node_state<S, R>(src, K, x, y, z, f, g, m);
-    collide<R>(f, g, m, K);
+    Por e;
+    node_state<S, R>(src, K, x, y, z, f, g, m, e);
+    collide<R>(f, g, m, K, e);
     store<S, R>(dst, K, (size_t)k, f, g);
 }
 
@@ -302,11 +333,12 @@ __global__ void __launch_bounds__(B3) k3_init(S *__restrict__ dst, K3 K, const d
     if (u_init)
         for (int a = 0; a < 3; ++a) u[a] = u_init[(size_t)a * K.n + k];
     const double S0[6] = {0, 0, 0, 0, 0, 0}, g0[3] = {0, 0, 0};
+    const Por e = por_of(K, k);
     double f[NQ], g[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        f[q] = feq<double>(q, K, 0.0, u, S0);
-        g[q] = geq<double>(q, K, T, 0.0, u, g0);
+        f[q] = feq<double>(q, K, e, 0.0, u, S0);
+        g[q] = geq<double>(q, K, e, T, 0.0, u, g0);
     }
     store<S, double>(dst, K, k, f, g);
 }
@@ -321,7 +353,8 @@ __global__ void __launch_bounds__(B3) k3_fields(const S *__restrict__ src, K3 K,
     if (!node_xyz(K, x, y, z)) return;
     R f[NQ], g[NQ];
     Mac<R> m;
-    node_state<S, R>(src, K, x, y, z, f, g, m);
+    Por e;
+    node_state<S, R>(src, K, x, y, z, f, g, m, e);
     const size_t k = ((size_t)z * K.ny + y) * K.nx + x, n = (size_t)K.n;
     if (o.p) o.p[k] = double(m.p);
     if (o.T) o.T[k] = double(m.T);
@@ -342,7 +375,8 @@ __global__ void __launch_bounds__(B3) k3_populations(const S *__restrict__ src, 
     if (!node_xyz(K, x, y, z)) return;
     R f[NQ], g[NQ];
     Mac<R> m;
-    node_state<S, R>(src, K, x, y, z, f, g, m);
+    Por e;
+    node_state<S, R>(src, K, x, y, z, f, g, m, e);
     const size_t k = ((size_t)z * K.ny + y) * K.nx + x;
     for (int q = 0; q < NQ; ++q) {
         if (fo) fo[(size_t)q * K.n + k] = double(f[q]) + (q == 0 ? 1.0 : 0.0);
@@ -396,6 +430,8 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
     if (!(p->tau_f > 0.5) || !(p->tau_T > 0.5)) return fail3(LBM_ERR_INVALID, "tau_f and tau_T must exceed 1/2");
     if (!(p->eps > 0.0) || !(p->eps <= 1.0) || !(p->sigma > 0.0) || !(p->J > 0.0))
         return fail3(LBM_ERR_INVALID, "eps must lie in (0, 1]; sigma and J must be positive");
+    if (p->eps_field && ((uintptr_t)p->eps_field) % 8)
+        return fail3(LBM_ERR_INVALID, "eps_field must be 8-byte aligned");
     const double L = p->L > 0 ? p->L : (p->periodic_z ? p->nz : p->nz - 1);
     double A = p->A, B = p->B;
     if (std::isnan(A) || std::isnan(B)) {
@@ -421,6 +457,11 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
     K.c1 = p->eps * 0.5 * Feps / sqrt(Kp);
     K.dlin = p->eps * nu / Kp;
     K.dquad = p->eps * Feps / sqrt(Kp);
+    K.eps_field = p->eps_field;
+    K.nuK = nu / Kp;
+    K.isqK = 1.0 / sqrt(Kp);
+    K.ergun = std::isnan(p->F_eps) ? 1 : 0;
+    K.Feps = K.ergun ? 0.0 : p->F_eps;
     for (int w = 0; w < 2; ++w) {
         K.wkind[w] = p->wall[w].t_kind == LBM_T_NEUMANN ? 1 : 0;
         for (int a = 0; a < 3; ++a) K.wu[w][a] = p->wall[w].u[a];

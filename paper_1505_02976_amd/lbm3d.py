@@ -27,7 +27,7 @@ class _Params3(C.Structure):
         ("eps", C.c_double), ("a", C.c_double * 3),
         ("T_hot", C.c_double), ("T_cold", C.c_double), ("F_eps", C.c_double),
         ("storage", C.c_int32), ("reserved", C.c_int32),
-        ("T_init", C.c_void_p), ("u_init", C.c_void_p),
+        ("T_init", C.c_void_p), ("u_init", C.c_void_p), ("eps_field", C.c_void_p),
     ]
 
 
@@ -63,7 +63,7 @@ def _f(v):
     return math.nan if v is None else float(v)
 
 
-def make_params(cfg: dict, T_init=0, u_init=0) -> _Params3:
+def make_params(cfg: dict, T_init=0, u_init=0, eps_field=0) -> _Params3:
     p = _Params3()
     p.nx, p.ny, p.nz = int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"])
     p.periodic_z = int(cfg.get("periodic_z", 0))
@@ -82,6 +82,7 @@ def make_params(cfg: dict, T_init=0, u_init=0) -> _Params3:
     p.storage = STORAGE3[cfg.get("storage", "f64")]
     p.T_init = T_init or None
     p.u_init = u_init or None
+    p.eps_field = eps_field or None
     return p
 
 
@@ -116,7 +117,13 @@ class Sim3:
                     t = torch.as_tensor(a, dtype=torch.float64).reshape(shp).contiguous().to(self.device)
                     keep.append(t)
                     ptrs[key] = t.data_ptr()
-            p = make_params(cfg, ptrs.get("T_init", 0), ptrs.get("u_init", 0))
+            # the porosity field is read by every step: it lives as long as the simulation
+            self.eps_field = None
+            if cfg.get("eps_field") is not None:
+                self.eps_field = torch.as_tensor(cfg["eps_field"], dtype=torch.float64).reshape(
+                    self.shape).contiguous().to(self.device)
+            p = make_params(cfg, ptrs.get("T_init", 0), ptrs.get("u_init", 0),
+                            self.eps_field.data_ptr() if self.eps_field is not None else 0)
             nbytes = int(L.lbm3_workspace_bytes(C.byref(p)))
             if nbytes == 0:
                 raise _lbm.LbmError(_lbm.ERR_INVALID, L.lbm_last_error().decode())

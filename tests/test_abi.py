@@ -146,9 +146,9 @@ def test_exports_every_declared_3d_symbol(lbm):
 def test_3d_struct_sizes_and_validation(lbm):
     import workloads as W
     from paper_1505_02976_amd import lbm3d as L3
-    # lbm3_wall: 3 doubles, 2 int32, 2 doubles; lbm3_params: 4 int32, 2 walls, 19 doubles, 2 int32, 2 pointers
+    # lbm3_wall: 3 doubles, 2 int32, 2 doubles; lbm3_params: 4 int32, 2 walls, 19 doubles, 2 int32, 3 pointers
     assert C.sizeof(L3._Wall3) == 48
-    assert C.sizeof(L3._Params3) == 16 + 2 * 48 + 19 * 8 + 8 + 16
+    assert C.sizeof(L3._Params3) == 16 + 2 * 48 + 19 * 8 + 8 + 24
     cfg = W.layer3d(16, 8, 12)
     n = 16 * 8 * 12
     assert L3.workspace_bytes(cfg) == 2 * ((2 * 19 * n * 8 + 255) // 256 * 256)

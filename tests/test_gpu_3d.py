@@ -1,6 +1,7 @@
 """The 3-D (D3Q19) HIP path through the C interface against the 3-D oracle: populations and
 every field of seeded random problems (walled and periodic z, isothermal and
-prescribed-gradient walls, moving walls, ragged sizes, the smallest walled nz), FP64 within
+prescribed-gradient walls, moving walls, porosity fields, ragged sizes, the smallest walled
+nz), FP64 within
 1e-10 and FP32 within 1e-5 relative L2, the exact conduction fixed point, a larger
 layer heated from below."""
 import numpy as np
@@ -50,18 +51,20 @@ def _compare(gpu3, cfg, steps, tol_pop, tol_field):
 
 
 CASES = [
-    # (seed, nx, ny, nz, periodic_z)
-    (1, 20, 12, 9, 0),
-    (2, 17, 5, 4, 0),       # smallest walled nz, ragged x
-    (3, 9, 14, 11, 1),      # periodic z
-    (4, 33, 3, 7, 0),
+    # (seed, nx, ny, nz, periodic_z, porosity field)
+    (1, 20, 12, 9, 0, False),
+    (2, 17, 5, 4, 0, False),       # smallest walled nz, ragged x
+    (3, 9, 14, 11, 1, False),      # periodic z
+    (4, 33, 3, 7, 0, False),
+    (5, 16, 9, 8, 0, True),        # porosity field, walls
+    (6, 11, 7, 10, 1, True),       # porosity field, periodic z
 ]
 
 
-@pytest.mark.parametrize("seed,nx,ny,nz,pz", CASES)
-def test_fp64_parity(gpu3, seed, nx, ny, nz, pz):
-    cfg = W.random_case3d(seed, nx, ny, nz, periodic_z=pz)
-    _say(f"case: 3-D FP64 seed {seed} {nx}x{ny}x{nz} periodic_z {pz}, walls "
+@pytest.mark.parametrize("seed,nx,ny,nz,pz,ef", CASES)
+def test_fp64_parity(gpu3, seed, nx, ny, nz, pz, ef):
+    cfg = W.random_case3d(seed, nx, ny, nz, periodic_z=pz, eps_field=ef)
+    _say(f"case: 3-D FP64 seed {seed} {nx}x{ny}x{nz} periodic_z {pz} porosity field {ef}, walls "
          f"{[w['kind'] for w in cfg['walls']]}, 200 steps")
     dpop, dfield, _, _ = _compare(gpu3, cfg, 200, 1e-10, 1e-10)
     _say(f"  max |populations| diff {dpop:.2e}; fields {max(dfield.values()):.2e}")
@@ -69,9 +72,9 @@ def test_fp64_parity(gpu3, seed, nx, ny, nz, pz):
     assert all(v < 1e-10 for v in dfield.values()), dfield
 
 
-@pytest.mark.parametrize("seed", [1, 3])
+@pytest.mark.parametrize("seed", [1, 3, 5])
 def test_fp32_parity(gpu3, seed):
-    cfg = W.random_case3d(seed, 20, 12, 9, periodic_z=1 if seed == 3 else 0, storage="f32")
+    cfg = W.random_case3d(seed, 20, 12, 9, periodic_z=1 if seed == 3 else 0, storage="f32", eps_field=seed == 5)
     _say(f"case: 3-D FP32 seed {seed}, 200 steps")
     _, _, a, b = _compare(gpu3, cfg, 200, None, None)
     # the velocity as one vector field (between walls u_z is small, and its own relative
