@@ -161,3 +161,22 @@ def test_shear_wave_decay(gpu3, storage, A):
     rate = np.log(a1 / a2) / (t2 - t1) / (nu_e * k * k)
     _say(f"  {storage} A {A}: decay rate / nu_e k^2 = {rate:.6f}")
     assert abs(rate - 1) < 2e-3
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_bench_size_against_oracle(gpu3, storage):
+    """The bench's 3-D workload at its full size (192 x 192 x 96 heated layer, the launches
+    the bench times), 5 steps: every field against the oracle (FP64 within 1e-10, FP32
+    within 1e-5 relative L2)."""
+    cfg = W.layer3d(192, 192, 96, Ra=1e4, Da=1e-2, storage=storage)
+    _say(f"case: 3-D {storage} bench layer 192x192x96, 5 steps")
+    _, dfield, a, b = _compare(gpu3, cfg, 5, None, None)
+    if storage == "f64":
+        _say(f"  max |fields| diff {max(dfield.values()):.2e}")
+        assert all(v < 1e-10 for v in dfield.values()), dfield
+    else:
+        rel = {k: float(np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k])) for k in ("T", "p")}
+        du = np.sqrt(sum(np.linalg.norm(a[k] - b[k]) ** 2 for k in ("ux", "uy", "uz")))
+        rel["u"] = float(du / np.sqrt(sum(np.linalg.norm(b[k]) ** 2 for k in ("ux", "uy", "uz"))))
+        _say(f"  rel L2 {rel}")
+        assert rel["u"] < 1e-5 and rel["T"] < 1e-5, rel
