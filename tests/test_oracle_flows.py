@@ -120,3 +120,19 @@ def test_mixed_convection_channel_second_order(oracle_mod, tau):
         assert order(e1, e2, ns[1], ns[2]) > lo, (k, res)
         assert order(res[0][k], e1, ns[0], ns[1]) < order(e1, e2, ns[1], ns[2]) + 0.3
     assert res[-1][4] < 1e-3
+
+
+def test_adiabatic_wall_nodes_take_the_prescribed_gradient(oracle_mod):
+    """Reading R5 (Sec. 3.4: on a prescribed-gradient wall grad T(x_b) is the known one): in a
+    convecting cavity the adiabatic wall nodes report and collide with dT/dy = 0 exactly,
+    while the next node inward carries a nonzero gradient.  Recomputing the wall node's
+    gradient from its rebuilt populations would give tau_T / (tau_T - B) times that of x_f."""
+    cfg = W.cavity(n=24, eps=0.6, Da=1e-2, Ra=1e4, Pr=1.0)
+    o = oracle_mod.Oracle(cfg)
+    o.step(3000)
+    f = o.fields()
+    inner = slice(1, -1)                 # the corners belong to the isothermal walls (R8)
+    assert np.abs(f["dTdy"][0, inner]).max() == 0.0
+    assert np.abs(f["dTdy"][-1, inner]).max() == 0.0
+    assert np.abs(f["dTdy"][1, inner]).max() > 1e-4
+    assert np.abs(f["dTdy"][-2, inner]).max() > 1e-4
