@@ -66,9 +66,10 @@ typedef struct {
     const double *eps_field;
 } lbm3_params;
 
-/* Workspace bytes lbm3_init needs for this problem (0 if it is invalid; lbm_last_error
- * says why).  Unusable: nx, ny < 1; nz < 1 (periodic) or < 4 (walled); storage other
- * than F64/F32; tau <= 1/2; nu_e, alpha_e or K not positive. */
+/* Workspace bytes lbm3_init needs for this problem: two population buffers and 256 bytes
+ * for reduction results (0 if the problem is invalid; lbm_last_error says why).  Unusable:
+ * nx, ny < 1; nz < 1 (periodic) or < 4 (walled); storage other than F64/F32; tau <= 1/2;
+ * nu_e, alpha_e or K not positive. */
 size_t lbm3_workspace_bytes(const lbm3_params *params);
 
 /* Creates a context on the current device.  workspace: device memory of at least
@@ -92,6 +93,13 @@ lbm_status lbm3_fields(lbm3_ctx *ctx, double *p, double *u, double *T, double *S
 /* Pre-collision populations at the current time as FP64 device arrays [19][nz][ny][nx]
  * (f and g; the rest state added back), in the order of lbm3_lattice.  Asynchronous. */
 lbm_status lbm3_populations(lbm3_ctx *ctx, double *f, double *g);
+
+/* Average Nusselt number of wall 0 (z = 0) or 1 (z = nz - 1) at the current time, as in two
+ * dimensions (Eq. AvNuss): Nu(x, y) = -L (dT/dz) / dT with dT/dz from the one-sided
+ * second-order difference into the fluid, averaged over the wall plane (a heat flux along
+ * +z counts positive at both walls).  FP64 arithmetic in a fixed summation order.  Needs
+ * walls in z and T_hot != T_cold.  *nu_host receives the value.  Synchronizes. */
+lbm_status lbm3_nusselt(lbm3_ctx *ctx, int32_t wall, double *nu_host);
 
 /* The library's D3Q19 velocities (c: 19 x 3 ints, host) in population order; returns 19. */
 int32_t lbm3_lattice(int32_t *c);

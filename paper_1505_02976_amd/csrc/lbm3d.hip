@@ -37,6 +37,7 @@ struct K3 {
     const double *eps_field;         // porosity per node, or NULL for the uniform eps
     double nuK, isqK, Feps;          // nu / K, 1 / sqrt(K), F_eps (if not from the Ergun relation)
     int ergun;
+    double L, dT;                    // characteristic length and temperature difference
     int wkind[2];
     double wu[2][3], wT[2], wdTdn[2];
 };
@@ -343,6 +344,40 @@ __global__ void __launch_bounds__(B3) k3_init(S *__restrict__ dst, K3 K, const d
     store<S, double>(dst, K, k, f, g);
 }
 
+// Average Nusselt number of wall w (0: z = 0, 1: z = nz - 1): -L dT/dz / dT by the
+// one-sided second-order difference at each (x, y), averaged over the plane, as in two
+// dimensions (Eq. AvNuss).  One block; every thread sums a fixed strided subset in order,
+// then a fixed-order tree: FP64 results do not depend on the launch.
+template <typename S>
+__global__ void __launch_bounds__(256) k3_nusselt(const S *__restrict__ src, K3 K, int w, double *out)
+{
+    using R = typename Arith<S>::R;
+    __shared__ double part[256];
+    const long long plane = (long long)K.nx * K.ny;
+    double acc = 0.0;
+    for (long long c = threadIdx.x; c < plane; c += 256) {
+        const int x = (int)(c % K.nx), y = (int)(c / K.nx);
+        double T[3];
+        for (int d = 0; d < 3; ++d) {
+            const int z = w == 0 ? d : K.nz - 1 - d;
+            R f[NQ], g[NQ];
+            Mac<R> m;
+            Por e;
+            node_state<S, R>(src, K, x, y, z, f, g, m, e);
+            T[d] = double(m.T);
+        }
+        const double d1 = (-3.0 * T[0] + 4.0 * T[1] - T[2]) / 2.0;   // along the inward normal
+        acc += -K.L * (w == 0 ? d1 : -d1) / K.dT;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = part[0] / double(plane);
+}
+
 struct FieldOut3 { double *p, *u, *T, *S, *gT; };
 
 template <typename S>
@@ -392,6 +427,7 @@ struct lbm3_ctx {
     K3 K;
     int storage;
     char *buf[2];
+    double *result;
     int cur;
     hipStream_t stream;
     int64_t t;
@@ -417,6 +453,8 @@ size_t buffer_bytes(const lbm3_params *p)
     const size_t n = (size_t)p->nx * p->ny * p->nz;
     return (2 * NQ * n * elem3(p->storage) + 255) / 256 * 256;
 }
+
+constexpr size_t RESULT_BYTES = 256;   // after the two buffers: the reduction's result
 
 // Derived lattice constants, as for two dimensions (Sec. 2, Sec. 3.1, Eq. Therdiff,
 // Eq. EQA&B, Eq. ForceEq with the Ergun relation).
@@ -458,6 +496,8 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
     K.dlin = p->eps * nu / Kp;
     K.dquad = p->eps * Feps / sqrt(Kp);
     K.eps_field = p->eps_field;
+    K.L = L;
+    K.dT = dT;
     K.nuK = nu / Kp;
     K.isqK = 1.0 / sqrt(Kp);
     K.ergun = std::isnan(p->F_eps) ? 1 : 0;
@@ -487,7 +527,7 @@ size_t lbm3_workspace_bytes(const lbm3_params *params)
 {
     K3 K;
     if (make_constants(params, K) != LBM_OK) return 0;
-    return 2 * buffer_bytes(params);
+    return 2 * buffer_bytes(params) + RESULT_BYTES;
 }
 
 lbm_status lbm3_init(const lbm3_params *params, void *workspace, size_t workspace_bytes, void *hip_stream,
@@ -499,7 +539,7 @@ lbm_status lbm3_init(const lbm3_params *params, void *workspace, size_t workspac
     lbm_status st = make_constants(params, K);
     if (st != LBM_OK) return st;
     if (!workspace || ((uintptr_t)workspace) % 256) return fail3(LBM_ERR_INVALID, "workspace must be non-NULL and 256-byte aligned");
-    const size_t need = 2 * buffer_bytes(params);
+    const size_t need = 2 * buffer_bytes(params) + RESULT_BYTES;
     if (workspace_bytes < need) return fail3(LBM_ERR_INVALID, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
     lbm3_ctx *c = new (std::nothrow) lbm3_ctx;
     if (!c) return fail3(LBM_ERR_DEVICE, "out of host memory");
@@ -507,6 +547,7 @@ lbm_status lbm3_init(const lbm3_params *params, void *workspace, size_t workspac
     c->storage = params->storage;
     c->buf[0] = static_cast<char *>(workspace);
     c->buf[1] = c->buf[0] + buffer_bytes(params);
+    c->result = reinterpret_cast<double *>(c->buf[1] + buffer_bytes(params));
     c->cur = 0;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->t = 0;
@@ -573,6 +614,26 @@ lbm_status lbm3_populations(lbm3_ctx *c, double *f, double *g)
         hipLaunchKernelGGL((k3_populations<float>), dim3(blocks_for(c->K.n)), dim3(B3), 0, c->stream,
                            reinterpret_cast<const float *>(c->buf[c->cur]), c->K, f, g);
     return launched("3-D populations");
+}
+
+lbm_status lbm3_nusselt(lbm3_ctx *c, int32_t wall, double *nu_host)
+{
+    if (!c || !nu_host) return fail3(LBM_ERR_INVALID, "ctx and nu_host must be non-NULL");
+    if (c->K.pz) return fail3(LBM_ERR_INVALID, "the Nusselt number needs walls in z");
+    if (wall != 0 && wall != 1) return fail3(LBM_ERR_INVALID, "wall must be 0 (z = 0) or 1 (z = nz - 1)");
+    if (!(c->K.dT != 0.0)) return fail3(LBM_ERR_INVALID, "T_hot - T_cold is zero");
+    if (c->storage == LBM_F64)
+        hipLaunchKernelGGL((k3_nusselt<double>), dim3(1), dim3(256), 0, c->stream,
+                           reinterpret_cast<const double *>(c->buf[c->cur]), c->K, (int)wall, c->result);
+    else
+        hipLaunchKernelGGL((k3_nusselt<float>), dim3(1), dim3(256), 0, c->stream,
+                           reinterpret_cast<const float *>(c->buf[c->cur]), c->K, (int)wall, c->result);
+    lbm_status st = launched("3-D Nusselt number");
+    if (st != LBM_OK) return st;
+    hipError_t e = hipMemcpyAsync(nu_host, c->result, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail3(LBM_ERR_DEVICE, "3-D Nusselt number: %s", hipGetErrorString(e));
+    return LBM_OK;
 }
 
 int32_t lbm3_lattice(int32_t *c)

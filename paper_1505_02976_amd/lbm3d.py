@@ -50,6 +50,8 @@ def lib():
         L.lbm3_fields.argtypes = [vp] * 6
         L.lbm3_populations.restype = C.c_int
         L.lbm3_populations.argtypes = [vp, vp, vp]
+        L.lbm3_nusselt.restype = C.c_int
+        L.lbm3_nusselt.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]
         L.lbm3_lattice.restype = C.c_int32
         L.lbm3_lattice.argtypes = [vp]
         L.lbm3_time.restype = C.c_int64
@@ -156,6 +158,12 @@ class Sim3:
         out.update({k: o["S"][c] for c, k in enumerate(("Sxx", "Sxy", "Sxz", "Syy", "Syz", "Szz"))})
         out.update({k: o["gT"][a] for a, k in enumerate(("dTdx", "dTdy", "dTdz"))})
         return out
+
+    def nusselt(self, wall: int = 0) -> float:
+        """Average Nusselt number of wall 0 (z = 0) or 1 (z = nz - 1), FP64."""
+        v = C.c_double()
+        _lbm._check(lib().lbm3_nusselt(self.h, int(wall), C.byref(v)))
+        return v.value
 
     def populations(self):
         """(f, g) pre-collision now, each [19, nz, ny, nx] in the order of lattice()."""

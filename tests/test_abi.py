@@ -137,7 +137,7 @@ def test_one_hip_runtime_whatever_the_import_order():
 def test_exports_every_declared_3d_symbol(lbm):
     with open(os.path.join(ROOT, "include", "lbm3d.h")) as fh:
         names = sorted(set(re.findall(r"\b(lbm3_[a-z_]+)\s*\(", fh.read())))
-    assert len(names) == 8, names
+    assert len(names) == 9, names
     lib = C.CDLL(lbm.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
@@ -151,8 +151,8 @@ def test_3d_struct_sizes_and_validation(lbm):
     assert C.sizeof(L3._Params3) == 16 + 2 * 48 + 19 * 8 + 8 + 24
     cfg = W.layer3d(16, 8, 12)
     n = 16 * 8 * 12
-    assert L3.workspace_bytes(cfg) == 2 * ((2 * 19 * n * 8 + 255) // 256 * 256)
-    assert L3.workspace_bytes(dict(cfg, storage="f32")) == 2 * ((2 * 19 * n * 4 + 255) // 256 * 256)
+    assert L3.workspace_bytes(cfg) == 2 * ((2 * 19 * n * 8 + 255) // 256 * 256) + 256
+    assert L3.workspace_bytes(dict(cfg, storage="f32")) == 2 * ((2 * 19 * n * 4 + 255) // 256 * 256) + 256
     assert L3.workspace_bytes(dict(cfg, nz=3)) == 0
     assert "nz >= 4" in lbm.lib().lbm_last_error().decode()
     assert L3.workspace_bytes(dict(cfg, nz=3, periodic_z=1)) > 0

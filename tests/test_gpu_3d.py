@@ -106,9 +106,19 @@ def test_conduction_fixed_point(gpu3, kind):
 
 
 def test_heated_layer_against_oracle(gpu3):
-    """A 64 x 64 x 32 porous layer heated from below (Ra 1e4, Da 1e-2), 20 steps, FP64."""
+    """A 64 x 64 x 32 porous layer heated from below (Ra 1e4, Da 1e-2), 20 steps, FP64;
+    with the average Nusselt numbers of both walls (FP64 reduction) against the oracle's."""
+    import oracle.oracle3 as O3
     cfg = W.layer3d(64, 64, 32, Ra=1e4, Da=1e-2)
     _say("case: 3-D FP64 heated layer 64x64x32, 20 steps")
+    sim = gpu3.Sim3(cfg)
+    sim.step(20)
+    ref = O3.Oracle3(cfg)
+    ref.step(20)
+    for w in (0, 1):
+        a, b = sim.nusselt(w), ref.nusselt(w)
+        _say(f"  Nusselt number of wall {w}: {a:.12f} (oracle {b:.12f})")
+        assert abs(a - b) < 1e-10 * max(1.0, abs(b))
     dpop, dfield, _, _ = _compare(gpu3, cfg, 20, 1e-10, 1e-10)
     _say(f"  max |populations| diff {dpop:.2e}; fields {max(dfield.values()):.2e}")
     assert dpop < 1e-10
