@@ -34,10 +34,11 @@ def build(verbose: bool = False) -> None:
 
 class _Params(C.Structure):
     _fields_ = [
-        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("periodic_z", C.c_int32),
-        ("wall_kind", C.c_int32 * 2),
-        ("wall_u", (C.c_double * 3) * 2),
-        ("wall_T", C.c_double * 2), ("wall_dTdn", C.c_double * 2),
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("periodic_x", C.c_int32),
+        ("periodic_z", C.c_int32), ("reserved0", C.c_int32),
+        ("wall_kind", C.c_int32 * 4),
+        ("wall_u", (C.c_double * 3) * 4),
+        ("wall_T", C.c_double * 4), ("wall_dTdn", C.c_double * 4),
         ("L", C.c_double), ("Da", C.c_double), ("Ra", C.c_double), ("Pr", C.c_double),
         ("J", C.c_double), ("Ma", C.c_double), ("sigma", C.c_double), ("Q", C.c_double),
         ("tau_f", C.c_double), ("tau_T", C.c_double), ("A", C.c_double), ("B", C.c_double),
@@ -54,6 +55,7 @@ def params_from_dict(d: dict) -> _Params:
     p = _Params()
     p.nx, p.ny, p.nz = int(d["nx"]), int(d["ny"]), int(d["nz"])
     p.periodic_z = int(d.get("periodic_z", 0))
+    p.periodic_x = int(d.get("periodic_x", 1))
     for k, w in enumerate(d["walls"]):
         p.wall_kind[k] = 1 if w.get("kind", "T") == "dTdn" else 0
         for a, v in enumerate(w.get("u", (0.0, 0.0, 0.0))):

@@ -248,3 +248,19 @@ def random_case3d(seed, nx, ny, nz, periodic_z=0, storage="f64", eps_field=False
     if eps_field:
         cfg["eps_field"] = 0.65 + smooth(0.25)
     return cfg
+
+
+def cavity3d(n=40, ny=2, eps=0.6, Da=1e-2, Ra=1e5, Pr=1.0, seed=0, storage="f64", tau=1.0, Ma=0.1):
+    """The porous cavity of Sec. 4.2 on the 3-D lattice: hot wall x = 0, cold wall x = n - 1,
+    adiabatic walls z = 0 and z = n - 1 (buoyancy along +z), periodic in y over ny nodes; the
+    2-D cavity's initial temperature repeated along y, so the flow stays uniform in y."""
+    T2 = cavity_T_init(n, n, seed)                  # [z][x]
+    T = np.repeat(T2[:, None, :], ny, axis=1)       # [z][y][x]
+    return {
+        "nx": n, "ny": ny, "nz": n, "periodic_x": 0, "periodic_z": 0,
+        "walls": [{"kind": "dTdn", "dTdn": 0.0}, {"kind": "dTdn", "dTdn": 0.0},
+                  {"kind": "T", "T": 1.0}, {"kind": "T", "T": 0.0}],
+        "Da": Da, "Ra": Ra, "Pr": Pr, "J": 1.0, "Ma": Ma, "sigma": 1.0, "Q": 0.0,
+        "tau_f": tau, "tau_T": tau, "A": None, "B": None, "eps": eps, "a": (0.0, 0.0, 0.0),
+        "T_hot": 1.0, "T_cold": 0.0, "F_eps": None, "T_init": T, "storage": storage,
+    }
