@@ -8,11 +8,15 @@
  * to three; the tensor expressions carry over unchanged, with omega_0 = 1/3 in the
  * pressure formula and in the closed forms of s_0 and F_0 (App. A).
  *
- * Geometry: periodic in x and y; z either periodic or bounded by walls at z = 0 and
- * z = nz - 1 (x_f is the next node inward along z).  Buoyancy acts along +z.  A wall
- * node's macroscopic state is the one the boundary scheme assigns to it (T_b, the wall
+ * Geometry: periodic in y; x and z each either periodic or bounded by walls at 0 and
+ * n - 1 (x_f is the next node inward along the wall normal).  Buoyancy acts along +z.  A
+ * wall node's macroscopic state is the one the boundary scheme assigns to it (T_b, the wall
  * velocity, p and S of x_f, the boundary temperature gradient); it collides with that
- * state, and lbm3_fields reports it.
+ * state, and lbm3_fields reports it.  On an edge where an x wall meets a z wall, x_f is the
+ * diagonal neighbour inward, the wall is at rest, an isothermal wall's temperature wins
+ * over a prescribed gradient (the x wall's over the z wall's when both are isothermal) and
+ * two prescribed gradients set both normal components of grad T, as at the corners of the
+ * two-dimensional path (Sec. 3.4 applied along each normal).
  *
  * Units, status codes, storage types and thread rules are those of lbm.h.  Arrays are
  * [z][y][x] with x fastest; vector fields are consecutive planes (x, y, z components).
@@ -33,8 +37,9 @@ extern "C" {
 
 typedef struct lbm3_ctx lbm3_ctx;
 
-/* One wall (index 0: z = 0, index 1: z = nz - 1).  dTdn is the derivative of T along the
- * inward normal; t_kind is lbm_twall. */
+/* One wall (index 0: z = 0, 1: z = nz - 1, 2: x = 0, 3: x = nx - 1; walls of a periodic
+ * direction are ignored).  dTdn is the derivative of T along the inward normal; t_kind is
+ * lbm_twall. */
 typedef struct {
     double u[3];
     int32_t t_kind;
@@ -42,17 +47,18 @@ typedef struct {
     double T, dTdn;
 } lbm3_wall;
 
-/* Problem description.  L = characteristic length: L if > 0, else nz - 1 (walled z) or nz
- * (periodic z).  A, B given, or if either is NaN from Ma, Ra, Pr (Eq. EQA&B).  nu_e, alpha_e,
+/* Problem description.  L = characteristic length: L if > 0, else nx - 1 (walled x), else
+ * nz - 1 (walled z) or nz (periodic z).  A, B given, or if either is NaN from Ma, Ra, Pr (Eq. EQA&B).  nu_e, alpha_e,
  * g beta, K, T0 and dT follow as in two dimensions (lbm.h).  eps_field ([nz][ny][nx], FP64,
  * device, values in (0, 1]) gives the porosity per node and must stay valid until
  * lbm3_destroy (the kernels read it every step; K = Da L^2 stays uniform, F_eps follows the
  * Ergun relation per node unless given); NULL means the uniform eps.  T_init ([nz][ny][nx])
  * and u_init (3 planes) are optional FP64 device arrays read during lbm3_init only; NULL
- * means T = T0 (T_wall on isothermal wall nodes) and u = 0; p starts at 0 (gauge pressure). */
+ * means T = T0 (T_wall on isothermal wall nodes, an x wall's on an edge) and u = 0; p starts
+ * at 0 (gauge pressure). */
 typedef struct {
-    int32_t nx, ny, nz, periodic_z;
-    lbm3_wall wall[2];
+    int32_t nx, ny, nz, periodic_x, periodic_z, reserved0;
+    lbm3_wall wall[4];
     double L, Da, Ra, Pr, J, Ma, sigma, Q;
     double tau_f, tau_T, A, B;
     double eps;
@@ -68,7 +74,7 @@ typedef struct {
 
 /* Workspace bytes lbm3_init needs for this problem: two population buffers and 256 bytes
  * for reduction results (0 if the problem is invalid; lbm_last_error says why).  Unusable:
- * nx, ny < 1; nz < 1 (periodic) or < 4 (walled); storage other than F64/F32; tau <= 1/2;
+ * ny < 1; nx, nz < 1 (periodic) or < 4 (walled); storage other than F64/F32; tau <= 1/2;
  * nu_e, alpha_e or K not positive. */
 size_t lbm3_workspace_bytes(const lbm3_params *params);
 
@@ -81,7 +87,7 @@ lbm_status lbm3_init(const lbm3_params *params, void *workspace, size_t workspac
                      void *hip_stream, lbm3_ctx **out);
 
 /* Enqueues nsteps time steps (collide, stream, boundary scheme; per step one launch over
- * the interior nodes and, with walls, one over the two wall planes).  Asynchronous;
+ * the interior nodes and, with walls, one over the wall nodes).  Asynchronous;
  * nsteps < 0 is LBM_ERR_INVALID. */
 lbm_status lbm3_step(lbm3_ctx *ctx, int64_t nsteps);
 
@@ -94,11 +100,14 @@ lbm_status lbm3_fields(lbm3_ctx *ctx, double *p, double *u, double *T, double *S
  * (f and g; the rest state added back), in the order of lbm3_lattice.  Asynchronous. */
 lbm_status lbm3_populations(lbm3_ctx *ctx, double *f, double *g);
 
-/* Average Nusselt number of wall 0 (z = 0) or 1 (z = nz - 1) at the current time, as in two
- * dimensions (Eq. AvNuss): Nu(x, y) = -L (dT/dz) / dT with dT/dz from the one-sided
- * second-order difference into the fluid, averaged over the wall plane (a heat flux along
- * +z counts positive at both walls).  FP64 arithmetic in a fixed summation order.  Needs
- * walls in z and T_hot != T_cold.  *nu_host receives the value.  Synchronizes. */
+/* Average Nusselt number of wall 0 (z = 0), 1 (z = nz - 1), 2 (x = 0) or 3 (x = nx - 1) at
+ * the current time, as in two dimensions (Eq. AvNuss): Nu = -L (dT/dn) / dT, n = +z for the
+ * z walls and +x for the x walls, with dT/dn from the one-sided second-order difference into
+ * the fluid, averaged over the wall plane (a plain mean along a periodic in-plane direction,
+ * the trapezoid rule along a walled one; a heat flux along +n counts positive at both walls
+ * of a pair).  FP64 arithmetic in a fixed summation order.  Needs that wall to exist
+ * (LBM_ERR_INVALID otherwise) and T_hot != T_cold.  *nu_host receives the value.
+ * Synchronizes. */
 lbm_status lbm3_nusselt(lbm3_ctx *ctx, int32_t wall, double *nu_host);
 
 /* The library's D3Q19 velocities (c: 19 x 3 ints, host) in population order; returns 19. */

@@ -1,7 +1,7 @@
 """Python handle on the 3-D C oracle (TEST INFRASTRUCTURE ONLY).
 
 The plain FP64 CPU implementation of the modified lattice-BGK model on the D3Q19 lattice
-(periodic in x and y, walls at z = 0 and z = nz - 1) that the GPU path's 3-D kernels are
+(periodic in y; x and z each periodic or walled) that the GPU path's 3-D kernels are
 checked against.  Only the test suite, the smoke check and the CPU-baseline leg of the
 benchmark may import this module; it never imports the GPU package.
 

@@ -1,5 +1,5 @@
 // Three-dimensional path: the modified lattice-BGK model (Secs. 2-3) on the D3Q19 lattice
-// for the flow and the temperature populations, periodic in x and y, with z periodic or
+// for the flow and the temperature populations, periodic in y, with x and z each periodic or
 // bounded by walls under the non-equilibrium extrapolation (Sec. 3.4).  One thread per
 // node: pull streaming from the previous step's post-collision buffer, the node's
 // macroscopic state, BGK collision with forcing and sources, store.  Populations are kept
@@ -29,7 +29,7 @@ __host__ __device__ constexpr double W(int i) { return i == 0 ? 1.0 / 3.0 : (i <
 
 // Launch constants (host-computed, passed by value).
 struct K3 {
-    int nx, ny, nz, pz;
+    int nx, ny, nz, px, pz;
     long long n;
     double tau_f, tau_T, A, B, sigma, Q, eps, T0, gbeta;
     double a[3];
@@ -38,9 +38,17 @@ struct K3 {
     double nuK, isqK, Feps;          // nu / K, 1 / sqrt(K), F_eps (if not from the Ergun relation)
     int ergun;
     double L, dT;                    // characteristic length and temperature difference
-    int wkind[2];
-    double wu[2][3], wT[2], wdTdn[2];
+    // walls: 0 z = 0, 1 z = nz - 1, 2 x = 0, 3 x = nx - 1
+    int wkind[4];
+    double wu[4][3], wT[4], wdTdn[4];
 };
+
+// The walls node (x, z) lies on: zw in {-1, 0, 1}, xw in {-1, 2, 3}.
+__device__ __forceinline__ void wall_of(const K3 &K, int x, int z, int &xw, int &zw)
+{
+    xw = K.px ? -1 : (x == 0 ? 2 : (x == K.nx - 1 ? 3 : -1));
+    zw = K.pz ? -1 : (z == 0 ? 0 : (z == K.nz - 1 ? 1 : -1));
+}
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -212,41 +220,50 @@ __device__ __forceinline__ void collide(R *f, R *g, const Mac<R> &m, const K3 &K
 }
 
 // Pre-collision populations and state of node (x, y, z).  Interior: pulled populations
-// and their moments.  Wall (walled z, z = 0 or nz - 1): the non-equilibrium extrapolation
-// from x_f = (x, y, z +- 1) (and T of x_ff on prescribed-gradient walls), whose state is
-// the one the scheme assigns (T_b, u_b, p and S of x_f, the boundary grad T).
+// and their moments.  Wall node: the non-equilibrium extrapolation from the next node
+// inward x_f (and T of x_ff on prescribed-gradient walls), whose state is the one the
+// scheme assigns (T_b, u_b, p and S of x_f, the boundary grad T).  On an edge of an x wall
+// and a z wall, x_f is the diagonal neighbour (x +- 1, y, z +- 1), the wall is at rest, an
+// isothermal wall's temperature wins over a prescribed gradient (the x wall's over the z
+// wall's if both are isothermal), and two prescribed gradients give the two normal
+// components of grad T, as at the corners in two dimensions.
 template <typename S, typename R, bool WALLS = true>
 __device__ __forceinline__ void node_state(const S *__restrict__ src, const K3 &K, int x, int y, int z,
                                            R *f, R *g, Mac<R> &m, Por &e)
 {
     const size_t plane = (size_t)K.nx * K.ny, k = (size_t)z * plane + (size_t)y * K.nx + x;
     e = por_of(K, k);
-    if (!WALLS || K.pz || (z > 0 && z < K.nz - 1)) {
+    int xw = -1, zw = -1;
+    if (WALLS) wall_of(K, x, z, xw, zw);
+    if (xw < 0 && zw < 0) {
         pull<S, R>(src, K, x, y, z, f, g);
         macro3<R>(f, g, K, e, m);
         return;
     }
-    const int w = z == 0 ? 0 : 1, dz = z == 0 ? 1 : -1;
+    const int dx = xw == 2 ? 1 : (xw == 3 ? -1 : 0), dz = zw == 0 ? 1 : (zw == 1 ? -1 : 0);
     R ff[NQ], gf[NQ];
-    pull<S, R>(src, K, x, y, z + dz, ff, gf);
-    const Por ef = por_of(K, k + (dz > 0 ? plane : -plane));
+    pull<S, R>(src, K, x + dx, y, z + dz, ff, gf);
+    const Por ef = por_of(K, (size_t)((long long)k + dz * (long long)plane + dx));
     Mac<R> mf;
     macro3<R>(ff, gf, K, ef, mf);
     R Tb, gb[3] = {mf.gT[0], mf.gT[1], mf.gT[2]};
-    if (K.wkind[w] == 0) {
-        Tb = R(K.wT[w]);
+    const int iso = (xw >= 0 && K.wkind[xw] == 0) ? xw : ((zw >= 0 && K.wkind[zw] == 0) ? zw : -1);
+    if (iso >= 0) {
+        Tb = R(K.wT[iso]);
     } else {
         R f2[NQ], g2[NQ];
-        pull<S, R>(src, K, x, y, z + 2 * dz, f2, g2);
+        pull<S, R>(src, K, x + 2 * dx, y, z + 2 * dz, f2, g2);
         R sg = R(0);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) sg += g2[q];
         const R Tff = (sg + R(0.5 * K.Q)) * R(1.0 / K.sigma);
-        gb[2] = R(dz * K.wdTdn[w]);
-        Tb = (R(4) * mf.T - Tff - R(2 * dz) * gb[2]) * R(1.0 / 3.0);
+        if (xw >= 0) gb[0] = R(dx * K.wdTdn[xw]);
+        if (zw >= 0) gb[2] = R(dz * K.wdTdn[zw]);
+        Tb = (R(4) * mf.T - Tff - R(2) * (R(dx) * gb[0] + R(dz) * gb[2])) * R(1.0 / 3.0);
     }
     m.T = Tb;
-    for (int a = 0; a < 3; ++a) { m.u[a] = R(K.wu[w][a]); m.gT[a] = gb[a]; }
+    const int wu = (xw >= 0 && zw >= 0) ? -1 : (xw >= 0 ? xw : zw);   // an edge is at rest
+    for (int a = 0; a < 3; ++a) { m.u[a] = wu < 0 ? R(0) : R(K.wu[wu][a]); m.gT[a] = gb[a]; }
     force<R>(K, e, m.u, m.T, m.F);
     m.p = mf.p;
     for (int c = 0; c < 6; ++c) m.S[c] = mf.S[c];
@@ -282,17 +299,23 @@ __device__ __forceinline__ void store(S *__restrict__ dst, const K3 &K, size_t k
 
 constexpr int B3 = 256;
 
+// Extent of the interior along x and z: all nodes of a periodic direction, all but the two
+// wall nodes of a walled one.
+__host__ __device__ __forceinline__ int inner_x(const K3 &K) { return K.px ? K.nx : K.nx - 2; }
+__host__ __device__ __forceinline__ int inner_z(const K3 &K) { return K.pz ? K.nz : K.nz - 2; }
+
 // One time step, pull, state, collide, store, in two launches: the interior nodes (no
-// boundary-scheme code, so fewer registers and more waves per SIMD) and the two wall planes.
+// boundary-scheme code, so fewer registers and more waves per SIMD) and the wall nodes.
 template <typename S>
 __global__ void __launch_bounds__(B3) k3_step_interior(const S *__restrict__ src, S *__restrict__ dst, K3 K)
 {
     using R = typename Arith<S>::R;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long plane = (long long)K.nx * K.ny;
-    const long long k = K.pz ? i : i + plane;            // walled: planes 1 .. nz - 2
-    if (k >= (K.pz ? K.n : K.n - plane)) return;
-    const int x = (int)(k % K.nx), y = (int)((k / K.nx) % K.ny), z = (int)(k / plane);
+    const int nxi = inner_x(K);
+    if (i >= (long long)nxi * K.ny * inner_z(K)) return;
+    const int x = (int)(i % nxi) + (K.px ? 0 : 1), y = (int)((i / nxi) % K.ny);
+    const int z = (int)(i / ((long long)nxi * K.ny)) + (K.pz ? 0 : 1);
+    const long long k = ((long long)z * K.ny + y) * K.nx + x;
     R f[NQ], g[NQ];
     Mac<R> m;
     Por e;
@@ -306,10 +329,20 @@ __global__ void __launch_bounds__(B3) k3_step_walls(const S *__restrict__ src, S
 {
     using R = typename Arith<S>::R;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long plane = (long long)K.nx * K.ny;
-    if (i >= 2 * plane) return;
-    const long long k = i < plane ? i : (long long)(K.nz - 1) * plane + (i - plane);
-    const int x = (int)(k % K.nx), y = (int)((k / K.nx) % K.ny), z = (int)(k / plane);
+    const long long plane = (long long)K.nx * K.ny, zn = K.pz ? 0 : 2 * plane;   // z wall planes first
+    const long long xside = K.px ? 0 : (long long)K.ny * inner_z(K);             // then the x wall planes less their z rows
+    if (i >= zn + 2 * xside) return;
+    int x, y, z;
+    if (i < zn) {
+        const long long k = i < plane ? i : (long long)(K.nz - 1) * plane + (i - plane);
+        x = (int)(k % K.nx); y = (int)((k / K.nx) % K.ny); z = (int)(k / plane);
+    } else {
+        const long long j = i - zn, r = j % xside;
+        x = j < xside ? 0 : K.nx - 1;
+        y = (int)(r % K.ny);
+        z = (int)(r / K.ny) + (K.pz ? 0 : 1);
+    }
+    const long long k = ((long long)z * K.ny + y) * K.nx + x;
     R f[NQ], g[NQ];
     Mac<R> m;
     Por e;
@@ -327,9 +360,11 @@ __global__ void __launch_bounds__(B3) k3_init(S *__restrict__ dst, K3 K, const d
     if (!node_xyz(K, x, y, z)) return;
     const size_t k = ((size_t)z * K.ny + y) * K.nx + x;
     double T = K.T0;
+    int xw, zw;
+    wall_of(K, x, z, xw, zw);
     if (T_init) T = T_init[k];
-    else if (!K.pz && z == 0 && K.wkind[0] == 0) T = K.wT[0];
-    else if (!K.pz && z == K.nz - 1 && K.wkind[1] == 0) T = K.wT[1];
+    else if (xw >= 0 && K.wkind[xw] == 0) T = K.wT[xw];
+    else if (zw >= 0 && K.wkind[zw] == 0) T = K.wT[zw];
     double u[3] = {0.0, 0.0, 0.0};
     if (u_init)
         for (int a = 0; a < 3; ++a) u[a] = u_init[(size_t)a * K.n + k];
@@ -344,22 +379,28 @@ __global__ void __launch_bounds__(B3) k3_init(S *__restrict__ dst, K3 K, const d
     store<S, double>(dst, K, k, f, g);
 }
 
-// Average Nusselt number of wall w (0: z = 0, 1: z = nz - 1): -L dT/dz / dT by the
-// one-sided second-order difference at each (x, y), averaged over the plane, as in two
-// dimensions (Eq. AvNuss).  One block; every thread sums a fixed strided subset in order,
-// then a fixed-order tree: FP64 results do not depend on the launch.
+// Average Nusselt number of wall w (0: z = 0, 1: z = nz - 1, 2: x = 0, 3: x = nx - 1):
+// -L dT/dn / dT (n = +z for z walls, +x for x walls) by the one-sided second-order
+// difference at each wall node, averaged over the wall plane, as in two dimensions
+// (Eq. AvNuss): a plain mean along a periodic in-plane direction, the trapezoid rule along a
+// walled one.  One block; every thread sums a fixed strided subset in order, then a
+// fixed-order tree: FP64 results do not depend on the launch.
 template <typename S>
 __global__ void __launch_bounds__(256) k3_nusselt(const S *__restrict__ src, K3 K, int w, double *out)
 {
     using R = typename Arith<S>::R;
     __shared__ double part[256];
-    const long long plane = (long long)K.nx * K.ny;
+    const bool zwall = w < 2;
+    const int na = zwall ? K.nx : K.nz, pa = zwall ? K.px : K.pz;   // the wall's in-plane axis other than y
+    const long long cells = (long long)na * K.ny;
     double acc = 0.0;
-    for (long long c = threadIdx.x; c < plane; c += 256) {
-        const int x = (int)(c % K.nx), y = (int)(c / K.nx);
+    for (long long c = threadIdx.x; c < cells; c += 256) {
+        const int a = (int)(c % na), y = (int)(c / na);
         double T[3];
         for (int d = 0; d < 3; ++d) {
-            const int z = w == 0 ? d : K.nz - 1 - d;
+            int x, z;
+            if (zwall) { x = a; z = w == 0 ? d : K.nz - 1 - d; }
+            else { z = a; x = w == 2 ? d : K.nx - 1 - d; }
             R f[NQ], g[NQ];
             Mac<R> m;
             Por e;
@@ -367,7 +408,8 @@ __global__ void __launch_bounds__(256) k3_nusselt(const S *__restrict__ src, K3 
             T[d] = double(m.T);
         }
         const double d1 = (-3.0 * T[0] + 4.0 * T[1] - T[2]) / 2.0;   // along the inward normal
-        acc += -K.L * (w == 0 ? d1 : -d1) / K.dT;
+        const double wt = (!pa && (a == 0 || a == na - 1)) ? 0.5 : 1.0;
+        acc += wt * (-K.L * ((w == 0 || w == 2) ? d1 : -d1) / K.dT);
     }
     part[threadIdx.x] = acc;
     __syncthreads();
@@ -375,7 +417,7 @@ __global__ void __launch_bounds__(256) k3_nusselt(const S *__restrict__ src, K3 
         if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = part[0] / double(plane);
+    if (threadIdx.x == 0) *out = part[0] / (double(K.ny) * (pa ? na : na - 1));
 }
 
 struct FieldOut3 { double *p, *u, *T, *S, *gT; };
@@ -463,6 +505,7 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
     if (!p) return fail3(LBM_ERR_INVALID, "params is NULL");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail3(LBM_ERR_INVALID, "grid must be at least 1 x 1 x 1");
     if (!p->periodic_z && p->nz < 4) return fail3(LBM_ERR_INVALID, "walled z needs nz >= 4 (got %d)", p->nz);
+    if (!p->periodic_x && p->nx < 4) return fail3(LBM_ERR_INVALID, "walled x needs nx >= 4 (got %d)", p->nx);
     if (p->storage != LBM_F64 && p->storage != LBM_F32) return fail3(LBM_ERR_INVALID, "storage must be LBM_F64 or LBM_F32");
     if ((double)p->nx * p->ny * p->nz * 2 * NQ > 9.0e18) return fail3(LBM_ERR_INVALID, "grid too large");
     if (!(p->tau_f > 0.5) || !(p->tau_T > 0.5)) return fail3(LBM_ERR_INVALID, "tau_f and tau_T must exceed 1/2");
@@ -470,7 +513,7 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
         return fail3(LBM_ERR_INVALID, "eps must lie in (0, 1]; sigma and J must be positive");
     if (p->eps_field && ((uintptr_t)p->eps_field) % 8)
         return fail3(LBM_ERR_INVALID, "eps_field must be 8-byte aligned");
-    const double L = p->L > 0 ? p->L : (p->periodic_z ? p->nz : p->nz - 1);
+    const double L = p->L > 0 ? p->L : (!p->periodic_x ? p->nx - 1 : (p->periodic_z ? p->nz : p->nz - 1));
     double A = p->A, B = p->B;
     if (std::isnan(A) || std::isnan(B)) {
         if (!(p->Ra > 0) || !(p->Pr > 0)) return fail3(LBM_ERR_INVALID, "A, B from Ma need Ra > 0 and Pr > 0");
@@ -485,7 +528,7 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
     if (!(Kp > 0)) return fail3(LBM_ERR_INVALID, "K = Da L^2 must be positive");
     const double dT = p->T_hot - p->T_cold;
     const double Feps = std::isnan(p->F_eps) ? 1.75 / sqrt(150.0 * p->eps * p->eps * p->eps) : p->F_eps;
-    K.nx = p->nx; K.ny = p->ny; K.nz = p->nz; K.pz = p->periodic_z ? 1 : 0;
+    K.nx = p->nx; K.ny = p->ny; K.nz = p->nz; K.px = p->periodic_x ? 1 : 0; K.pz = p->periodic_z ? 1 : 0;
     K.n = (long long)p->nx * p->ny * p->nz;
     K.tau_f = p->tau_f; K.tau_T = p->tau_T; K.A = A; K.B = B; K.sigma = p->sigma; K.Q = p->Q; K.eps = p->eps;
     K.T0 = 0.5 * (p->T_hot + p->T_cold);
@@ -502,7 +545,7 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
     K.isqK = 1.0 / sqrt(Kp);
     K.ergun = std::isnan(p->F_eps) ? 1 : 0;
     K.Feps = K.ergun ? 0.0 : p->F_eps;
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < 4; ++w) {
         K.wkind[w] = p->wall[w].t_kind == LBM_T_NEUMANN ? 1 : 0;
         for (int a = 0; a < 3; ++a) K.wu[w][a] = p->wall[w].u[a];
         K.wT[w] = p->wall[w].T;
@@ -571,19 +614,20 @@ lbm_status lbm3_step(lbm3_ctx *c, int64_t nsteps)
 {
     if (!c) return fail3(LBM_ERR_INVALID, "ctx is NULL");
     if (nsteps < 0) return fail3(LBM_ERR_INVALID, "nsteps must be >= 0");
-    const long long plane = (long long)c->K.nx * c->K.ny;
-    const unsigned nb_in = blocks_for(c->K.pz ? c->K.n : c->K.n - 2 * plane), nb_w = blocks_for(2 * plane);
+    const K3 &K = c->K;
+    const long long n_in = (long long)inner_x(K) * K.ny * inner_z(K), n_w = K.n - n_in;
+    const unsigned nb_in = blocks_for(n_in), nb_w = blocks_for(n_w);
     for (int64_t s = 0; s < nsteps; ++s) {
         if (c->storage == LBM_F64) {
             const double *src = reinterpret_cast<const double *>(c->buf[c->cur]);
             double *dst = reinterpret_cast<double *>(c->buf[c->cur ^ 1]);
             hipLaunchKernelGGL((k3_step_interior<double>), dim3(nb_in), dim3(B3), 0, c->stream, src, dst, c->K);
-            if (!c->K.pz) hipLaunchKernelGGL((k3_step_walls<double>), dim3(nb_w), dim3(B3), 0, c->stream, src, dst, c->K);
+            if (n_w) hipLaunchKernelGGL((k3_step_walls<double>), dim3(nb_w), dim3(B3), 0, c->stream, src, dst, c->K);
         } else {
             const float *src = reinterpret_cast<const float *>(c->buf[c->cur]);
             float *dst = reinterpret_cast<float *>(c->buf[c->cur ^ 1]);
             hipLaunchKernelGGL((k3_step_interior<float>), dim3(nb_in), dim3(B3), 0, c->stream, src, dst, c->K);
-            if (!c->K.pz) hipLaunchKernelGGL((k3_step_walls<float>), dim3(nb_w), dim3(B3), 0, c->stream, src, dst, c->K);
+            if (n_w) hipLaunchKernelGGL((k3_step_walls<float>), dim3(nb_w), dim3(B3), 0, c->stream, src, dst, c->K);
         }
         c->cur ^= 1;
         c->t += 1;
@@ -619,8 +663,8 @@ lbm_status lbm3_populations(lbm3_ctx *c, double *f, double *g)
 lbm_status lbm3_nusselt(lbm3_ctx *c, int32_t wall, double *nu_host)
 {
     if (!c || !nu_host) return fail3(LBM_ERR_INVALID, "ctx and nu_host must be non-NULL");
-    if (c->K.pz) return fail3(LBM_ERR_INVALID, "the Nusselt number needs walls in z");
-    if (wall != 0 && wall != 1) return fail3(LBM_ERR_INVALID, "wall must be 0 (z = 0) or 1 (z = nz - 1)");
+    if (wall < 0 || wall > 3) return fail3(LBM_ERR_INVALID, "wall must be 0 (z = 0), 1 (z = nz - 1), 2 (x = 0) or 3 (x = nx - 1)");
+    if (wall < 2 ? c->K.pz : c->K.px) return fail3(LBM_ERR_INVALID, "wall %d does not exist (periodic direction)", (int)wall);
     if (!(c->K.dT != 0.0)) return fail3(LBM_ERR_INVALID, "T_hot - T_cold is zero");
     if (c->storage == LBM_F64)
         hipLaunchKernelGGL((k3_nusselt<double>), dim3(1), dim3(256), 0, c->stream,

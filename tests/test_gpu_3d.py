@@ -1,9 +1,9 @@
 """The 3-D (D3Q19) HIP path through the C interface against the 3-D oracle: populations and
-every field of seeded random problems (walled and periodic z, isothermal and
-prescribed-gradient walls, moving walls, porosity fields, ragged sizes, the smallest walled
-nz), FP64 within
+every field of seeded random problems (walled and periodic z, walls in x with and without
+z walls, isothermal and prescribed-gradient walls, moving walls, porosity fields, ragged
+sizes, the smallest walled nx and nz), FP64 within
 1e-10 and FP32 within 1e-5 relative L2, the exact conduction fixed point, a larger
-layer heated from below."""
+layer heated from below, the porous cavity's wall Nusselt numbers."""
 import numpy as np
 import pytest
 
@@ -190,3 +190,57 @@ def test_bench_size_against_oracle(gpu3, storage):
         rel["u"] = float(du / np.sqrt(sum(np.linalg.norm(b[k]) ** 2 for k in ("ux", "uy", "uz"))))
         _say(f"  rel L2 {rel}")
         assert rel["u"] < 1e-5 and rel["T"] < 1e-5, rel
+
+
+XCASES = [
+    # (seed, nx, ny, nz, periodic_z, porosity field): walls at x = 0 and x = nx - 1
+    (11, 13, 5, 9, 0, False),      # x and z walls, edges
+    (12, 4, 6, 7, 1, False),       # smallest walled nx, periodic z
+    (13, 10, 3, 4, 0, True),       # smallest walled nz, porosity field
+    (14, 9, 7, 12, 0, True),
+]
+
+
+@pytest.mark.parametrize("seed,nx,ny,nz,pz,ef", XCASES)
+def test_fp64_parity_x_walls(gpu3, seed, nx, ny, nz, pz, ef):
+    cfg = W.random_case3d(seed, nx, ny, nz, periodic_z=pz, eps_field=ef, periodic_x=0)
+    _say(f"case: 3-D FP64 x walls seed {seed} {nx}x{ny}x{nz} periodic_z {pz} porosity field {ef}, walls "
+         f"{[w['kind'] for w in cfg['walls']]}, 200 steps")
+    dpop, dfield, _, _ = _compare(gpu3, cfg, 200, 1e-10, 1e-10)
+    _say(f"  max |populations| diff {dpop:.2e}; fields {max(dfield.values()):.2e}")
+    assert dpop < 1e-10
+    assert all(v < 1e-10 for v in dfield.values()), dfield
+
+
+def test_fp32_parity_x_walls(gpu3):
+    cfg = W.random_case3d(11, 13, 5, 9, storage="f32", periodic_x=0)
+    _say("case: 3-D FP32 x walls seed 11, 200 steps")
+    _, _, a, b = _compare(gpu3, cfg, 200, None, None)
+    du = np.sqrt(sum(np.linalg.norm(a[k] - b[k]) ** 2 for k in ("ux", "uy", "uz")))
+    nu = np.sqrt(sum(np.linalg.norm(b[k]) ** 2 for k in ("ux", "uy", "uz")))
+    rel = {"u": du / nu, "T": np.linalg.norm(a["T"] - b["T"]) / np.linalg.norm(b["T"])}
+    _say(f"  rel L2: u {rel['u']:.2e}, T {rel['T']:.2e}")
+    assert rel["u"] < 1e-5 and rel["T"] < 1e-5, rel
+
+
+def test_cavity_nusselt_against_oracle_and_paper(gpu3):
+    """The porous cavity of Sec. 4.2 on the 3-D lattice (hot x = 0, cold x = nx - 1,
+    adiabatic z walls, 40 x 2 x 40, Ra 1e3, Da 1e-2, eps 0.6): the four wall Nusselt numbers
+    after 300 steps against the oracle's (FP64), then the hot wall's at 12000 steps within
+    half a percent of Table Tab:Square1's 1.012."""
+    import oracle.oracle3 as O3
+    cfg = W.cavity3d(40, 2, eps=0.6, Da=1e-2, Ra=1e3)
+    _say("case: 3-D FP64 cavity 40x2x40 Ra 1e3, 300 then 12000 steps")
+    sim = gpu3.Sim3(cfg)
+    sim.step(300)
+    ref = O3.Oracle3(cfg)
+    ref.step(300)
+    for w in range(4):
+        a, b = sim.nusselt(w), ref.nusselt(w)
+        _say(f"  Nusselt number of wall {w}: {a:.12f} (oracle {b:.12f})")
+        assert abs(a - b) < 1e-10 * max(1.0, abs(b))
+    sim.step(12000 - 300)
+    nu = sim.nusselt(2)
+    _say(f"  hot wall at 12000 steps: {nu:.5f} (paper 1.012)")
+    assert abs(nu - 1.012) < 0.005 * 1.012
+    assert abs(sim.nusselt(3) - nu) < 0.002 * nu
