@@ -15,10 +15,11 @@
  * contractions are written out as sums over the three Cartesian indices; the temperature
  * gradient solves its 3 x 3 system <M> grad T = <N> (Eqs. MatrM, MatrN) by Cramer's rule.
  *
- * Geometry: periodic in y; in x and in z periodic, or walls at x = 0, nx - 1 and z = 0,
- * nz - 1 treated by the non-equilibrium extrapolation of Sec. 3.4 with x_f the next node
- * inward (on an edge where an x wall meets a z wall, the inward diagonal neighbour, with
- * the rules of the 2-D corners, R8).
+ * Geometry: each of x, y, z periodic, or walls at 0 and n - 1 treated by the
+ * non-equilibrium extrapolation of Sec. 3.4 with x_f the next node inward (on an edge or a
+ * vertex where two or three walls meet, the inward diagonal neighbour, with the rules of
+ * the 2-D corners, R8: at rest, an isothermal wall's temperature first, in the order x, y,
+ * z, and each prescribed gradient setting its own normal component of grad T).
  *
  * Readings (the 2-D readings R1-R3, R5-R7, R9, R10, R12-R14 carry over unchanged):
  *   R21 lattice: D3Q19 for the flow and the temperature populations (the temperature
@@ -70,10 +71,11 @@ static void build_lattice(void)
 static double varpi(int i) { return i == 0 ? -(1.0 - W3[0]) : W3[i]; }
 
 typedef struct {
-    int32_t nx, ny, nz, periodic_x, periodic_z, reserved0;
-    int32_t wall_kind[4];          /* z = 0, z = nz - 1, x = 0, x = nx - 1: 0 isothermal, 1 prescribed dT/dn */
-    double wall_u[4][3];           /* wall velocity */
-    double wall_T[4], wall_dTdn[4];/* dTdn: derivative along the inward normal */
+    int32_t nx, ny, nz, periodic_x, periodic_y, periodic_z;
+    int32_t wall_kind[6];          /* z = 0, z = nz - 1, x = 0, x = nx - 1, y = 0, y = ny - 1:
+                                      0 isothermal, 1 prescribed dT/dn */
+    double wall_u[6][3];           /* wall velocity */
+    double wall_T[6], wall_dTdn[6];/* dTdn: derivative along the inward normal */
     double L;                      /* characteristic length; 0 => nz - 1 */
     double Da, Ra, Pr, J, Ma, sigma, Q;
     double tau_f, tau_T, A, B;     /* A, B: NaN => from Ma, Ra, Pr (Eq. EQA&B) */
@@ -313,20 +315,21 @@ static void collide_state(const o3_sim *s, const o3_macro *m, const double *f, c
 static int idx(const o3_sim *s, int x, int y, int z) { return (z * s->prm.ny + y) * s->prm.nx + x; }
 
 /* The walls a node lies on: zw in {-1, 0 (z = 0), 1 (z = nz - 1)}, xw in {-1, 2 (x = 0),
- * 3 (x = nx - 1)}. */
-static void wall_of(const o3_sim *s, int x, int z, int *xw, int *zw)
+ * 3 (x = nx - 1)}, yw in {-1, 4 (y = 0), 5 (y = ny - 1)}. */
+static void wall_of(const o3_sim *s, int x, int y, int z, int *xw, int *yw, int *zw)
 {
     const o3_params *P = &s->prm;
-    *xw = -1; *zw = -1;
+    *xw = -1; *yw = -1; *zw = -1;
     if (!P->periodic_x) { if (x == 0) *xw = 2; else if (x == P->nx - 1) *xw = 3; }
+    if (!P->periodic_y) { if (y == 0) *yw = 4; else if (y == P->ny - 1) *yw = 5; }
     if (!P->periodic_z) { if (z == 0) *zw = 0; else if (z == P->nz - 1) *zw = 1; }
 }
 
 static int is_wall(const o3_sim *s, int k)
 {
-    int xw, zw;
-    wall_of(s, k % s->prm.nx, k / (s->prm.nx * s->prm.ny), &xw, &zw);
-    return xw >= 0 || zw >= 0;
+    int xw, yw, zw;
+    wall_of(s, k % s->prm.nx, (k / s->prm.nx) % s->prm.ny, k / (s->prm.nx * s->prm.ny), &xw, &yw, &zw);
+    return xw >= 0 || yw >= 0 || zw >= 0;
 }
 
 static void collide_all(o3_sim *s)
@@ -340,8 +343,7 @@ static void collide_all(o3_sim *s)
     }
 }
 
-/* Push streaming, periodic in y (and in x, z if so set); populations leaving through a wall
- * are dropped. */
+/* Push streaming, periodic where so set; populations leaving through a wall are dropped. */
 static void stream_all(o3_sim *s)
 {
     const int nx = s->prm.nx, ny = s->prm.ny, nz = s->prm.nz;
@@ -351,11 +353,12 @@ static void stream_all(o3_sim *s)
             for (int x = 0; x < nx; ++x) {
                 int k = idx(s, x, y, z);
                 for (int i = 0; i < Q19; ++i) {
-                    int zd = z + C3[i][2], xd = x + C3[i][0];
+                    int zd = z + C3[i][2], xd = x + C3[i][0], yd = y + C3[i][1];
                     if (s->prm.periodic_z) zd = (zd + nz) % nz;
                     if (s->prm.periodic_x) xd = (xd + nx) % nx;
-                    if (zd < 0 || zd >= nz || xd < 0 || xd >= nx) continue;
-                    int kd = idx(s, xd, (y + C3[i][1] + ny) % ny, zd);
+                    if (s->prm.periodic_y) yd = (yd + ny) % ny;
+                    if (zd < 0 || zd >= nz || xd < 0 || xd >= nx || yd < 0 || yd >= ny) continue;
+                    int kd = idx(s, xd, yd, zd);
                     s->f[Q19 * kd + i] = s->fs[Q19 * k + i];
                     s->g[Q19 * kd + i] = s->gs[Q19 * k + i];
                 }
@@ -366,10 +369,12 @@ static void stream_all(o3_sim *s)
 static void nees_node(o3_sim *s, int x, int y, int z)
 {
     const o3_params *P = &s->prm;
-    int xw, zw;
-    wall_of(s, x, z, &xw, &zw);
+    int xw, yw, zw;
+    wall_of(s, x, y, z, &xw, &yw, &zw);
     const int dx = xw == 2 ? 1 : (xw == 3 ? -1 : 0), dz = zw == 0 ? 1 : (zw == 1 ? -1 : 0);
-    const int kb = idx(s, x, y, z), kf = idx(s, x + dx, y, z + dz), kff = idx(s, x + 2 * dx, y, z + 2 * dz);
+    const int dy = yw == 4 ? 1 : (yw == 5 ? -1 : 0);
+    const int kb = idx(s, x, y, z), kf = idx(s, x + dx, y + dy, z + dz);
+    const int kff = idx(s, x + 2 * dx, y + 2 * dy, z + 2 * dz);
     const double *ff = s->f + Q19 * kf, *gf = s->g + Q19 * kf;
     o3_macro mf;
     node_macro(s, s->eps[kf], ff, gf, &mf);
@@ -377,24 +382,28 @@ static void nees_node(o3_sim *s, int x, int y, int z)
     double fe_f[Q19], ge_f[Q19], fe_b[Q19], ge_b[Q19];
     feq_full(s, mf.eps, mf.p, mf.u, mf.S, fe_f);
     geq_full(s, mf.eps, mf.T, mf.u, mf.p, mf.dT, ge_f);
-    /* an edge is at rest (R8) */
+    /* an edge or a vertex is at rest (R8) */
     const double zero[3] = {0.0, 0.0, 0.0};
-    const double *ub = (xw >= 0 && zw >= 0) ? zero : P->wall_u[xw >= 0 ? xw : zw];
+    const int nwalls = (xw >= 0) + (yw >= 0) + (zw >= 0);
+    const double *ub = nwalls > 1 ? zero : P->wall_u[xw >= 0 ? xw : (yw >= 0 ? yw : zw)];
     feq_full(s, eb, mf.p, ub, mf.S, fe_b);
     for (int i = 0; i < Q19; ++i) s->f[Q19 * kb + i] = fe_b[i] + (ff[i] - fe_f[i]);
 
-    /* an isothermal wall wins over a prescribed-gradient one, the x wall over the z wall (R8) */
-    const int dir = (xw >= 0 && P->wall_kind[xw] == 0) ? xw : ((zw >= 0 && P->wall_kind[zw] == 0) ? zw : -1);
+    /* an isothermal wall wins over a prescribed-gradient one; among isothermal walls x, then
+     * y, then z (R8) */
+    const int dir = (xw >= 0 && P->wall_kind[xw] == 0) ? xw
+                  : ((yw >= 0 && P->wall_kind[yw] == 0) ? yw : ((zw >= 0 && P->wall_kind[zw] == 0) ? zw : -1));
     double Tb, gb[3] = {mf.dT[0], mf.dT[1], mf.dT[2]};
     if (dir >= 0) {
         Tb = P->wall_T[dir];
     } else {
         if (xw >= 0) gb[0] = dx * P->wall_dTdn[xw];
+        if (yw >= 0) gb[1] = dy * P->wall_dTdn[yw];
         if (zw >= 0) gb[2] = dz * P->wall_dTdn[zw];
         double sgff = 0.0;
         for (int i = 0; i < Q19; ++i) sgff += s->g[Q19 * kff + i];
         double Tff = (sgff + 0.5 * P->Q) / P->sigma;
-        Tb = (4.0 * mf.T - Tff - 2.0 * (dx * gb[0] + dz * gb[2])) / 3.0;
+        Tb = (4.0 * mf.T - Tff - 2.0 * (dx * gb[0] + dy * gb[1] + dz * gb[2])) / 3.0;
     }
     geq_full(s, eb, Tb, ub, mf.p, gb, ge_b);
     for (int i = 0; i < Q19; ++i) s->g[Q19 * kb + i] = ge_b[i] + (gf[i] - ge_f[i]);
@@ -447,7 +456,8 @@ o3_sim *o3_create(const o3_params *p, const double *eps_field, const double *T_i
     build_lattice();
     o3_sim *s = (o3_sim *)calloc(1, sizeof(o3_sim));
     s->prm = *p;
-    if ((!p->periodic_z && p->nz < 4) || (!p->periodic_x && p->nx < 4) || derive(p, &s->d) != 0) { free(s); return NULL; }
+    if ((!p->periodic_z && p->nz < 4) || (!p->periodic_x && p->nx < 4) || (!p->periodic_y && p->ny < 4)
+        || derive(p, &s->d) != 0) { free(s); return NULL; }
     s->n = p->nx * p->ny * p->nz;
     s->f = (double *)malloc(sizeof(double) * Q19 * s->n);
     s->g = (double *)malloc(sizeof(double) * Q19 * s->n);
@@ -460,10 +470,11 @@ o3_sim *o3_create(const o3_params *p, const double *eps_field, const double *T_i
     for (int k = 0; k < s->n; ++k) {
         int z = k / (p->nx * p->ny);
         double T = s->d.T0;
-        int xw, zw;
-        wall_of(s, k % p->nx, z, &xw, &zw);
+        int xw, yw, zw;
+        wall_of(s, k % p->nx, (k / p->nx) % p->ny, z, &xw, &yw, &zw);
         if (T_init) T = T_init[k];
         else if (xw >= 0 && p->wall_kind[xw] == 0) T = p->wall_T[xw];
+        else if (yw >= 0 && p->wall_kind[yw] == 0) T = p->wall_T[yw];
         else if (zw >= 0 && p->wall_kind[zw] == 0) T = p->wall_T[zw];
         double u[3] = {0, 0, 0};
         if (u_init)
@@ -530,30 +541,37 @@ void o3_get_populations(const o3_sim *s, int which, double *f_out, double *g_out
         }
 }
 
-/* Average Nusselt number of wall w (0: z = 0, 1: z = nz - 1, 2: x = 0, 3: x = nx - 1) as in
- * two dimensions (R14): -L dT/dn_axis / dT by the one-sided second-order difference along
- * the wall's axis, averaged over the wall plane by the trapezoid rule along a walled
- * direction and a plain mean along a periodic one. */
+/* Average Nusselt number of wall w (0: z = 0, 1: z = nz - 1, 2: x = 0, 3: x = nx - 1,
+ * 4: y = 0, 5: y = ny - 1) as in two dimensions (R14): -L dT/dn / dT, n the wall's axis
+ * (+z, +x, +y), by the one-sided second-order difference into the fluid, averaged over the
+ * wall plane by the trapezoid rule along each walled in-plane direction and a plain mean
+ * along each periodic one. */
 double o3_nusselt(const o3_sim *s, int w)
 {
-    const int nx = s->prm.nx, ny = s->prm.ny, nz = s->prm.nz;
+    const int nn[3] = {s->prm.nx, s->prm.ny, s->prm.nz};
+    const int per[3] = {s->prm.periodic_x, s->prm.periodic_y, s->prm.periodic_z};
+    const int ax = w < 2 ? 2 : (w < 4 ? 0 : 1), hi = w & 1;
     double *T = (double *)malloc(sizeof(double) * s->n);
     o3_fields(s, NULL, NULL, T, NULL, NULL);
-    const int zwall = w < 2;
-    const int na = zwall ? nx : nz;                       /* the wall's in-plane walled-or-periodic axis */
-    const int pa = zwall ? s->prm.periodic_x : s->prm.periodic_z;
-    double acc = 0.0;
-    for (int y = 0; y < ny; ++y)
-        for (int a = 0; a < na; ++a) {
-            double T0v, T1v, T2v, sgn;
-            if (w == 0) { T0v = T[idx(s, a, y, 0)]; T1v = T[idx(s, a, y, 1)]; T2v = T[idx(s, a, y, 2)]; sgn = 1.0; }
-            else if (w == 1) { T0v = T[idx(s, a, y, nz - 1)]; T1v = T[idx(s, a, y, nz - 2)]; T2v = T[idx(s, a, y, nz - 3)]; sgn = -1.0; }
-            else if (w == 2) { T0v = T[idx(s, 0, y, a)]; T1v = T[idx(s, 1, y, a)]; T2v = T[idx(s, 2, y, a)]; sgn = 1.0; }
-            else { T0v = T[idx(s, nx - 1, y, a)]; T1v = T[idx(s, nx - 2, y, a)]; T2v = T[idx(s, nx - 3, y, a)]; sgn = -1.0; }
-            const double d = sgn * (-3.0 * T0v + 4.0 * T1v - T2v) / 2.0;
-            const double wt = (!pa && (a == 0 || a == na - 1)) ? 0.5 : 1.0;
-            acc += wt * (-s->d.L * d / s->d.dT);
-        }
+    double acc = 0.0, cells = 1.0;
+    for (int b = 0; b < 3; ++b)
+        if (b != ax) cells *= per[b] ? nn[b] : nn[b] - 1;
+    int c[3];
+    for (c[2] = 0; c[2] < nn[2]; ++c[2])
+        for (c[1] = 0; c[1] < nn[1]; ++c[1])
+            for (c[0] = 0; c[0] < nn[0]; ++c[0]) {
+                if (c[ax] != (hi ? nn[ax] - 1 : 0)) continue;
+                double Tv[3], wt = 1.0;
+                for (int d = 0; d < 3; ++d) {
+                    int e[3] = {c[0], c[1], c[2]};
+                    e[ax] = hi ? nn[ax] - 1 - d : d;
+                    Tv[d] = T[idx(s, e[0], e[1], e[2])];
+                }
+                for (int b = 0; b < 3; ++b)
+                    if (b != ax && !per[b] && (c[b] == 0 || c[b] == nn[b] - 1)) wt *= 0.5;
+                const double dn = (hi ? -1.0 : 1.0) * (-3.0 * Tv[0] + 4.0 * Tv[1] - Tv[2]) / 2.0;
+                acc += wt * (-s->d.L * dn / s->d.dT);
+            }
     free(T);
-    return acc / ((double)ny * (pa ? na : na - 1));
+    return acc / cells;
 }

@@ -1,7 +1,7 @@
 """Python handle on the 3-D C oracle (TEST INFRASTRUCTURE ONLY).
 
 The plain FP64 CPU implementation of the modified lattice-BGK model on the D3Q19 lattice
-(periodic in y; x and z each periodic or walled) that the GPU path's 3-D kernels are
+(x, y and z each periodic or walled) that the GPU path's 3-D kernels are
 checked against.  Only the test suite, the smoke check and the CPU-baseline leg of the
 benchmark may import this module; it never imports the GPU package.
 
@@ -35,10 +35,10 @@ def build(verbose: bool = False) -> None:
 class _Params(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("periodic_x", C.c_int32),
-        ("periodic_z", C.c_int32), ("reserved0", C.c_int32),
-        ("wall_kind", C.c_int32 * 4),
-        ("wall_u", (C.c_double * 3) * 4),
-        ("wall_T", C.c_double * 4), ("wall_dTdn", C.c_double * 4),
+        ("periodic_y", C.c_int32), ("periodic_z", C.c_int32),
+        ("wall_kind", C.c_int32 * 6),
+        ("wall_u", (C.c_double * 3) * 6),
+        ("wall_T", C.c_double * 6), ("wall_dTdn", C.c_double * 6),
         ("L", C.c_double), ("Da", C.c_double), ("Ra", C.c_double), ("Pr", C.c_double),
         ("J", C.c_double), ("Ma", C.c_double), ("sigma", C.c_double), ("Q", C.c_double),
         ("tau_f", C.c_double), ("tau_T", C.c_double), ("A", C.c_double), ("B", C.c_double),
@@ -56,6 +56,7 @@ def params_from_dict(d: dict) -> _Params:
     p.nx, p.ny, p.nz = int(d["nx"]), int(d["ny"]), int(d["nz"])
     p.periodic_z = int(d.get("periodic_z", 0))
     p.periodic_x = int(d.get("periodic_x", 1))
+    p.periodic_y = int(d.get("periodic_y", 1))
     for k, w in enumerate(d["walls"]):
         p.wall_kind[k] = 1 if w.get("kind", "T") == "dTdn" else 0
         for a, v in enumerate(w.get("u", (0.0, 0.0, 0.0))):

@@ -187,3 +187,45 @@ def test_cavity_between_x_walls_matches_the_paper():
     nu = o.nusselt(2)
     assert abs(nu - 1.012) < 0.005 * 1.012, nu
     assert abs(o.nusselt(3) - nu) < 0.002 * nu
+
+
+def test_walls_in_x_and_in_y_are_symmetric():
+    """D3Q19 is symmetric under swapping x and y: the cavity between x walls (periodic y)
+    and the same cavity between y walls (periodic x) give the same fields with x and y
+    exchanged, and the same hot-wall Nusselt number, to rounding."""
+    import workloads as W
+    cx = W.cavity3d(16, 2, eps=0.6, Da=1e-2, Ra=1e4)
+    cy = dict(cx, nx=2, ny=16, periodic_x=1, periodic_y=0,
+              walls=cx["walls"][:2] + [{}, {}] + cx["walls"][2:],
+              T_init=np.ascontiguousarray(np.swapaxes(cx["T_init"], 1, 2)))
+    a, b = O3.Oracle3(cx), O3.Oracle3(cy)
+    a.step(400)
+    b.step(400)
+    fa, fb = a.fields(), b.fields()
+    sw = lambda v: np.swapaxes(v, 1, 2)
+    assert np.abs(fa["ux"]).max() > 1e-4
+    for ka, kb in (("T", "T"), ("p", "p"), ("ux", "uy"), ("uy", "ux"), ("uz", "uz"), ("dTdx", "dTdy"),
+                   ("Sxx", "Syy"), ("Sxz", "Syz"), ("Szz", "Szz")):
+        assert np.abs(fa[ka] - sw(fb[kb])).max() < 1e-12, ka
+    for wa, wb in ((2, 4), (3, 5), (0, 0)):
+        assert abs(a.nusselt(wa) - b.nusselt(wb)) < 1e-12
+
+
+def test_conduction_fixed_point_in_a_closed_box():
+    """Walls on all six faces: isothermal z walls, adiabatic x and y walls (edges and
+    vertices by the corner rules, R8).  A linear temperature in z is an exact steady state
+    with the fluid at rest."""
+    nx, ny, nz = 6, 5, 16
+    slope = 0.8 / (nz - 1)
+    z = np.arange(nz, dtype=float)
+    T = np.broadcast_to((0.1 + slope * z)[:, None, None], (nz, ny, nx)).copy()
+    adiabatic = {"kind": "dTdn", "dTdn": 0.0}
+    cfg = _box(nx, ny, nz, 0, periodic_x=0, periodic_y=0,
+               walls=[{"kind": "T", "T": 0.1}, {"kind": "T", "T": 0.9}] + [adiabatic] * 4,
+               A=0.05, B=-0.1, tau_f=0.9, tau_T=0.9, Da=1e-2, eps=0.6, F_eps=None, T_init=T)
+    o = O3.Oracle3(cfg)
+    o.step(2000)
+    f = o.fields()
+    assert np.abs(f["T"] - (0.1 + slope * z)[:, None, None]).max() < 1e-12
+    assert np.abs(f["dTdz"] - slope).max() < 1e-12
+    assert max(np.abs(f[k]).max() for k in ("ux", "uy", "uz", "dTdx", "dTdy")) < 1e-12
