@@ -8,15 +8,15 @@
  * to three; the tensor expressions carry over unchanged, with omega_0 = 1/3 in the
  * pressure formula and in the closed forms of s_0 and F_0 (App. A).
  *
- * Geometry: periodic in y; x and z each either periodic or bounded by walls at 0 and
- * n - 1 (x_f is the next node inward along the wall normal).  Buoyancy acts along +z.  A
+ * Geometry: x, y and z each either periodic or bounded by walls at 0 and n - 1 (x_f is
+ * the next node inward along the wall normal).  Buoyancy acts along +z.  A
  * wall node's macroscopic state is the one the boundary scheme assigns to it (T_b, the wall
  * velocity, p and S of x_f, the boundary temperature gradient); it collides with that
- * state, and lbm3_fields reports it.  On an edge where an x wall meets a z wall, x_f is the
- * diagonal neighbour inward, the wall is at rest, an isothermal wall's temperature wins
- * over a prescribed gradient (the x wall's over the z wall's when both are isothermal) and
- * two prescribed gradients set both normal components of grad T, as at the corners of the
- * two-dimensional path (Sec. 3.4 applied along each normal).
+ * state, and lbm3_fields reports it.  On an edge or a vertex where two or three walls
+ * meet, x_f is the inward diagonal neighbour, the wall is at rest, an isothermal wall's
+ * temperature wins over a prescribed gradient (among isothermal walls x first, then y,
+ * then z) and each prescribed gradient sets its own normal component of grad T, as at the
+ * corners of the two-dimensional path (Sec. 3.4 applied along each normal).
  *
  * Units, status codes, storage types and thread rules are those of lbm.h.  Arrays are
  * [z][y][x] with x fastest; vector fields are consecutive planes (x, y, z components).
@@ -37,8 +37,8 @@ extern "C" {
 
 typedef struct lbm3_ctx lbm3_ctx;
 
-/* One wall (index 0: z = 0, 1: z = nz - 1, 2: x = 0, 3: x = nx - 1; walls of a periodic
- * direction are ignored).  dTdn is the derivative of T along the inward normal; t_kind is
+/* One wall (index 0: z = 0, 1: z = nz - 1, 2: x = 0, 3: x = nx - 1, 4: y = 0, 5: y = ny - 1;
+ * walls of a periodic direction are ignored).  dTdn is the derivative of T along the inward normal; t_kind is
  * lbm_twall. */
 typedef struct {
     double u[3];
@@ -54,11 +54,11 @@ typedef struct {
  * lbm3_destroy (the kernels read it every step; K = Da L^2 stays uniform, F_eps follows the
  * Ergun relation per node unless given); NULL means the uniform eps.  T_init ([nz][ny][nx])
  * and u_init (3 planes) are optional FP64 device arrays read during lbm3_init only; NULL
- * means T = T0 (T_wall on isothermal wall nodes, an x wall's on an edge) and u = 0; p starts
- * at 0 (gauge pressure). */
+ * means T = T0 (T_wall on isothermal wall nodes, in the order x, y, z where walls meet) and
+ * u = 0; p starts at 0 (gauge pressure). */
 typedef struct {
-    int32_t nx, ny, nz, periodic_x, periodic_z, reserved0;
-    lbm3_wall wall[4];
+    int32_t nx, ny, nz, periodic_x, periodic_y, periodic_z;
+    lbm3_wall wall[6];
     double L, Da, Ra, Pr, J, Ma, sigma, Q;
     double tau_f, tau_T, A, B;
     double eps;
@@ -74,7 +74,7 @@ typedef struct {
 
 /* Workspace bytes lbm3_init needs for this problem: two population buffers and 256 bytes
  * for reduction results (0 if the problem is invalid; lbm_last_error says why).  Unusable:
- * ny < 1; nx, nz < 1 (periodic) or < 4 (walled); storage other than F64/F32; tau <= 1/2;
+ * nx, ny, nz < 1 (periodic) or < 4 (walled); storage other than F64/F32; tau <= 1/2;
  * nu_e, alpha_e or K not positive. */
 size_t lbm3_workspace_bytes(const lbm3_params *params);
 
@@ -100,12 +100,12 @@ lbm_status lbm3_fields(lbm3_ctx *ctx, double *p, double *u, double *T, double *S
  * (f and g; the rest state added back), in the order of lbm3_lattice.  Asynchronous. */
 lbm_status lbm3_populations(lbm3_ctx *ctx, double *f, double *g);
 
-/* Average Nusselt number of wall 0 (z = 0), 1 (z = nz - 1), 2 (x = 0) or 3 (x = nx - 1) at
- * the current time, as in two dimensions (Eq. AvNuss): Nu = -L (dT/dn) / dT, n = +z for the
- * z walls and +x for the x walls, with dT/dn from the one-sided second-order difference into
- * the fluid, averaged over the wall plane (a plain mean along a periodic in-plane direction,
- * the trapezoid rule along a walled one; a heat flux along +n counts positive at both walls
- * of a pair).  FP64 arithmetic in a fixed summation order.  Needs that wall to exist
+/* Average Nusselt number of wall 0 (z = 0), 1 (z = nz - 1), 2 (x = 0), 3 (x = nx - 1),
+ * 4 (y = 0) or 5 (y = ny - 1) at the current time, as in two dimensions (Eq. AvNuss):
+ * Nu = -L (dT/dn) / dT, n = +z, +x or +y along the wall's axis, with dT/dn from the
+ * one-sided second-order difference into the fluid, averaged over the wall plane (a plain
+ * mean along each periodic in-plane direction, the trapezoid rule along each walled one; a
+ * heat flux along +n counts positive at both walls of a pair).  FP64 arithmetic in a fixed summation order.  Needs that wall to exist
  * (LBM_ERR_INVALID otherwise) and T_hot != T_cold.  *nu_host receives the value.
  * Synchronizes. */
 lbm_status lbm3_nusselt(lbm3_ctx *ctx, int32_t wall, double *nu_host);

@@ -1,6 +1,6 @@
 // Three-dimensional path: the modified lattice-BGK model (Secs. 2-3) on the D3Q19 lattice
-// for the flow and the temperature populations, periodic in y, with x and z each periodic or
-// bounded by walls under the non-equilibrium extrapolation (Sec. 3.4).  One thread per
+// for the flow and the temperature populations, with x, y and z each periodic or bounded by
+// walls under the non-equilibrium extrapolation (Sec. 3.4).  One thread per
 // node: pull streaming from the previous step's post-collision buffer, the node's
 // macroscopic state, BGK collision with forcing and sources, store.  Populations are kept
 // as 38 planes [q][z][y][x] (flow 0-18, temperature 19-37) in deviation form (f_0 - rho0,
@@ -29,7 +29,7 @@ __host__ __device__ constexpr double W(int i) { return i == 0 ? 1.0 / 3.0 : (i <
 
 // Launch constants (host-computed, passed by value).
 struct K3 {
-    int nx, ny, nz, px, pz;
+    int nx, ny, nz, px, py, pz;
     long long n;
     double tau_f, tau_T, A, B, sigma, Q, eps, T0, gbeta;
     double a[3];
@@ -38,15 +38,16 @@ struct K3 {
     double nuK, isqK, Feps;          // nu / K, 1 / sqrt(K), F_eps (if not from the Ergun relation)
     int ergun;
     double L, dT;                    // characteristic length and temperature difference
-    // walls: 0 z = 0, 1 z = nz - 1, 2 x = 0, 3 x = nx - 1
-    int wkind[4];
-    double wu[4][3], wT[4], wdTdn[4];
+    // walls: 0 z = 0, 1 z = nz - 1, 2 x = 0, 3 x = nx - 1, 4 y = 0, 5 y = ny - 1
+    int wkind[6];
+    double wu[6][3], wT[6], wdTdn[6];
 };
 
-// The walls node (x, z) lies on: zw in {-1, 0, 1}, xw in {-1, 2, 3}.
-__device__ __forceinline__ void wall_of(const K3 &K, int x, int z, int &xw, int &zw)
+// The walls node (x, y, z) lies on: zw in {-1, 0, 1}, xw in {-1, 2, 3}, yw in {-1, 4, 5}.
+__device__ __forceinline__ void wall_of(const K3 &K, int x, int y, int z, int &xw, int &yw, int &zw)
 {
     xw = K.px ? -1 : (x == 0 ? 2 : (x == K.nx - 1 ? 3 : -1));
+    yw = K.py ? -1 : (y == 0 ? 4 : (y == K.ny - 1 ? 5 : -1));
     zw = K.pz ? -1 : (z == 0 ? 0 : (z == K.nz - 1 ? 1 : -1));
 }
 
@@ -222,47 +223,51 @@ __device__ __forceinline__ void collide(R *f, R *g, const Mac<R> &m, const K3 &K
 // Pre-collision populations and state of node (x, y, z).  Interior: pulled populations
 // and their moments.  Wall node: the non-equilibrium extrapolation from the next node
 // inward x_f (and T of x_ff on prescribed-gradient walls), whose state is the one the
-// scheme assigns (T_b, u_b, p and S of x_f, the boundary grad T).  On an edge of an x wall
-// and a z wall, x_f is the diagonal neighbour (x +- 1, y, z +- 1), the wall is at rest, an
-// isothermal wall's temperature wins over a prescribed gradient (the x wall's over the z
-// wall's if both are isothermal), and two prescribed gradients give the two normal
-// components of grad T, as at the corners in two dimensions.
+// scheme assigns (T_b, u_b, p and S of x_f, the boundary grad T).  On an edge or a vertex
+// where two or three walls meet, x_f is the inward diagonal neighbour, the wall is at rest,
+// an isothermal wall's temperature wins over a prescribed gradient (among isothermal walls
+// x first, then y, then z), and each prescribed gradient sets its own normal component of
+// grad T, as at the corners in two dimensions.
 template <typename S, typename R, bool WALLS = true>
 __device__ __forceinline__ void node_state(const S *__restrict__ src, const K3 &K, int x, int y, int z,
                                            R *f, R *g, Mac<R> &m, Por &e)
 {
     const size_t plane = (size_t)K.nx * K.ny, k = (size_t)z * plane + (size_t)y * K.nx + x;
     e = por_of(K, k);
-    int xw = -1, zw = -1;
-    if (WALLS) wall_of(K, x, z, xw, zw);
-    if (xw < 0 && zw < 0) {
+    int xw = -1, yw = -1, zw = -1;
+    if (WALLS) wall_of(K, x, y, z, xw, yw, zw);
+    if (xw < 0 && yw < 0 && zw < 0) {
         pull<S, R>(src, K, x, y, z, f, g);
         macro3<R>(f, g, K, e, m);
         return;
     }
     const int dx = xw == 2 ? 1 : (xw == 3 ? -1 : 0), dz = zw == 0 ? 1 : (zw == 1 ? -1 : 0);
+    const int dy = yw == 4 ? 1 : (yw == 5 ? -1 : 0);
     R ff[NQ], gf[NQ];
-    pull<S, R>(src, K, x + dx, y, z + dz, ff, gf);
-    const Por ef = por_of(K, (size_t)((long long)k + dz * (long long)plane + dx));
+    pull<S, R>(src, K, x + dx, y + dy, z + dz, ff, gf);
+    const Por ef = por_of(K, (size_t)((long long)k + dz * (long long)plane + dy * (long long)K.nx + dx));
     Mac<R> mf;
     macro3<R>(ff, gf, K, ef, mf);
     R Tb, gb[3] = {mf.gT[0], mf.gT[1], mf.gT[2]};
-    const int iso = (xw >= 0 && K.wkind[xw] == 0) ? xw : ((zw >= 0 && K.wkind[zw] == 0) ? zw : -1);
+    const int iso = (xw >= 0 && K.wkind[xw] == 0) ? xw
+                  : ((yw >= 0 && K.wkind[yw] == 0) ? yw : ((zw >= 0 && K.wkind[zw] == 0) ? zw : -1));
     if (iso >= 0) {
         Tb = R(K.wT[iso]);
     } else {
         R f2[NQ], g2[NQ];
-        pull<S, R>(src, K, x + 2 * dx, y, z + 2 * dz, f2, g2);
+        pull<S, R>(src, K, x + 2 * dx, y + 2 * dy, z + 2 * dz, f2, g2);
         R sg = R(0);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) sg += g2[q];
         const R Tff = (sg + R(0.5 * K.Q)) * R(1.0 / K.sigma);
         if (xw >= 0) gb[0] = R(dx * K.wdTdn[xw]);
+        if (yw >= 0) gb[1] = R(dy * K.wdTdn[yw]);
         if (zw >= 0) gb[2] = R(dz * K.wdTdn[zw]);
-        Tb = (R(4) * mf.T - Tff - R(2) * (R(dx) * gb[0] + R(dz) * gb[2])) * R(1.0 / 3.0);
+        Tb = (R(4) * mf.T - Tff - R(2) * (R(dx) * gb[0] + R(dy) * gb[1] + R(dz) * gb[2])) * R(1.0 / 3.0);
     }
     m.T = Tb;
-    const int wu = (xw >= 0 && zw >= 0) ? -1 : (xw >= 0 ? xw : zw);   // an edge is at rest
+    const int nwall = (xw >= 0) + (yw >= 0) + (zw >= 0);
+    const int wu = nwall > 1 ? -1 : (xw >= 0 ? xw : (yw >= 0 ? yw : zw));   // an edge or a vertex is at rest
     for (int a = 0; a < 3; ++a) { m.u[a] = wu < 0 ? R(0) : R(K.wu[wu][a]); m.gT[a] = gb[a]; }
     force<R>(K, e, m.u, m.T, m.F);
     m.p = mf.p;
@@ -302,6 +307,7 @@ constexpr int B3 = 256;
 // Extent of the interior along x and z: all nodes of a periodic direction, all but the two
 // wall nodes of a walled one.
 __host__ __device__ __forceinline__ int inner_x(const K3 &K) { return K.px ? K.nx : K.nx - 2; }
+__host__ __device__ __forceinline__ int inner_y(const K3 &K) { return K.py ? K.ny : K.ny - 2; }
 __host__ __device__ __forceinline__ int inner_z(const K3 &K) { return K.pz ? K.nz : K.nz - 2; }
 
 // One time step, pull, state, collide, store, in two launches: the interior nodes (no
@@ -311,10 +317,10 @@ __global__ void __launch_bounds__(B3) k3_step_interior(const S *__restrict__ src
 {
     using R = typename Arith<S>::R;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int nxi = inner_x(K);
-    if (i >= (long long)nxi * K.ny * inner_z(K)) return;
-    const int x = (int)(i % nxi) + (K.px ? 0 : 1), y = (int)((i / nxi) % K.ny);
-    const int z = (int)(i / ((long long)nxi * K.ny)) + (K.pz ? 0 : 1);
+    const int nxi = inner_x(K), nyi = inner_y(K);
+    if (i >= (long long)nxi * nyi * inner_z(K)) return;
+    const int x = (int)(i % nxi) + (K.px ? 0 : 1), y = (int)((i / nxi) % nyi) + (K.py ? 0 : 1);
+    const int z = (int)(i / ((long long)nxi * nyi)) + (K.pz ? 0 : 1);
     const long long k = ((long long)z * K.ny + y) * K.nx + x;
     R f[NQ], g[NQ];
     Mac<R> m;
@@ -331,16 +337,23 @@ __global__ void __launch_bounds__(B3) k3_step_walls(const S *__restrict__ src, S
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long plane = (long long)K.nx * K.ny, zn = K.pz ? 0 : 2 * plane;   // z wall planes first
     const long long xside = K.px ? 0 : (long long)K.ny * inner_z(K);             // then the x wall planes less their z rows
-    if (i >= zn + 2 * xside) return;
+    const long long yside = K.py ? 0 : (long long)inner_x(K) * inner_z(K);       // then the y wall planes less both
+    if (i >= zn + 2 * xside + 2 * yside) return;
     int x, y, z;
     if (i < zn) {
         const long long k = i < plane ? i : (long long)(K.nz - 1) * plane + (i - plane);
         x = (int)(k % K.nx); y = (int)((k / K.nx) % K.ny); z = (int)(k / plane);
-    } else {
+    } else if (i < zn + 2 * xside) {
         const long long j = i - zn, r = j % xside;
         x = j < xside ? 0 : K.nx - 1;
         y = (int)(r % K.ny);
         z = (int)(r / K.ny) + (K.pz ? 0 : 1);
+    } else {
+        const long long j = i - zn - 2 * xside, r = j % yside;
+        const int nxi = inner_x(K);
+        y = j < yside ? 0 : K.ny - 1;
+        x = (int)(r % nxi) + (K.px ? 0 : 1);
+        z = (int)(r / nxi) + (K.pz ? 0 : 1);
     }
     const long long k = ((long long)z * K.ny + y) * K.nx + x;
     R f[NQ], g[NQ];
@@ -360,10 +373,11 @@ __global__ void __launch_bounds__(B3) k3_init(S *__restrict__ dst, K3 K, const d
     if (!node_xyz(K, x, y, z)) return;
     const size_t k = ((size_t)z * K.ny + y) * K.nx + x;
     double T = K.T0;
-    int xw, zw;
-    wall_of(K, x, z, xw, zw);
+    int xw, yw, zw;
+    wall_of(K, x, y, z, xw, yw, zw);
     if (T_init) T = T_init[k];
     else if (xw >= 0 && K.wkind[xw] == 0) T = K.wT[xw];
+    else if (yw >= 0 && K.wkind[yw] == 0) T = K.wT[yw];
     else if (zw >= 0 && K.wkind[zw] == 0) T = K.wT[zw];
     double u[3] = {0.0, 0.0, 0.0};
     if (u_init)
@@ -379,37 +393,40 @@ __global__ void __launch_bounds__(B3) k3_init(S *__restrict__ dst, K3 K, const d
     store<S, double>(dst, K, k, f, g);
 }
 
-// Average Nusselt number of wall w (0: z = 0, 1: z = nz - 1, 2: x = 0, 3: x = nx - 1):
-// -L dT/dn / dT (n = +z for z walls, +x for x walls) by the one-sided second-order
-// difference at each wall node, averaged over the wall plane, as in two dimensions
-// (Eq. AvNuss): a plain mean along a periodic in-plane direction, the trapezoid rule along a
-// walled one.  One block; every thread sums a fixed strided subset in order, then a
-// fixed-order tree: FP64 results do not depend on the launch.
+// Average Nusselt number of wall w (0: z = 0, 1: z = nz - 1, 2: x = 0, 3: x = nx - 1,
+// 4: y = 0, 5: y = ny - 1): -L dT/dn / dT (n = +z, +x or +y along the wall's axis) by the
+// one-sided second-order difference at each wall node, averaged over the wall plane, as in
+// two dimensions (Eq. AvNuss): a plain mean along each periodic in-plane direction, the
+// trapezoid rule along each walled one.  One block; every thread sums a fixed strided subset
+// in order, then a fixed-order tree: FP64 results do not depend on the launch.
 template <typename S>
 __global__ void __launch_bounds__(256) k3_nusselt(const S *__restrict__ src, K3 K, int w, double *out)
 {
     using R = typename Arith<S>::R;
     __shared__ double part[256];
-    const bool zwall = w < 2;
-    const int na = zwall ? K.nx : K.nz, pa = zwall ? K.px : K.pz;   // the wall's in-plane axis other than y
-    const long long cells = (long long)na * K.ny;
+    const int nn[3] = {K.nx, K.ny, K.nz}, per[3] = {K.px, K.py, K.pz};
+    const int ax = w < 2 ? 2 : (w < 4 ? 0 : 1), hi = w & 1;          // normal axis, far wall
+    const int b0 = ax == 0 ? 1 : 0, b1 = ax == 2 ? 1 : 2;             // the in-plane axes
+    const long long cells = (long long)nn[b0] * nn[b1];
     double acc = 0.0;
     for (long long c = threadIdx.x; c < cells; c += 256) {
-        const int a = (int)(c % na), y = (int)(c / na);
+        int e[3];
+        e[b0] = (int)(c % nn[b0]);
+        e[b1] = (int)(c / nn[b0]);
         double T[3];
         for (int d = 0; d < 3; ++d) {
-            int x, z;
-            if (zwall) { x = a; z = w == 0 ? d : K.nz - 1 - d; }
-            else { z = a; x = w == 2 ? d : K.nx - 1 - d; }
+            e[ax] = hi ? nn[ax] - 1 - d : d;
             R f[NQ], g[NQ];
             Mac<R> m;
-            Por e;
-            node_state<S, R>(src, K, x, y, z, f, g, m, e);
+            Por p;
+            node_state<S, R>(src, K, e[0], e[1], e[2], f, g, m, p);
             T[d] = double(m.T);
         }
         const double d1 = (-3.0 * T[0] + 4.0 * T[1] - T[2]) / 2.0;   // along the inward normal
-        const double wt = (!pa && (a == 0 || a == na - 1)) ? 0.5 : 1.0;
-        acc += wt * (-K.L * ((w == 0 || w == 2) ? d1 : -d1) / K.dT);
+        double wt = 1.0;
+        if (!per[b0] && (e[b0] == 0 || e[b0] == nn[b0] - 1)) wt *= 0.5;
+        if (!per[b1] && (e[b1] == 0 || e[b1] == nn[b1] - 1)) wt *= 0.5;
+        acc += wt * (-K.L * (hi ? -d1 : d1) / K.dT);
     }
     part[threadIdx.x] = acc;
     __syncthreads();
@@ -417,7 +434,8 @@ __global__ void __launch_bounds__(256) k3_nusselt(const S *__restrict__ src, K3 
         if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = part[0] / (double(K.ny) * (pa ? na : na - 1));
+    if (threadIdx.x == 0)
+        *out = part[0] / (double(per[b0] ? nn[b0] : nn[b0] - 1) * double(per[b1] ? nn[b1] : nn[b1] - 1));
 }
 
 struct FieldOut3 { double *p, *u, *T, *S, *gT; };
@@ -506,6 +524,7 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail3(LBM_ERR_INVALID, "grid must be at least 1 x 1 x 1");
     if (!p->periodic_z && p->nz < 4) return fail3(LBM_ERR_INVALID, "walled z needs nz >= 4 (got %d)", p->nz);
     if (!p->periodic_x && p->nx < 4) return fail3(LBM_ERR_INVALID, "walled x needs nx >= 4 (got %d)", p->nx);
+    if (!p->periodic_y && p->ny < 4) return fail3(LBM_ERR_INVALID, "walled y needs ny >= 4 (got %d)", p->ny);
     if (p->storage != LBM_F64 && p->storage != LBM_F32) return fail3(LBM_ERR_INVALID, "storage must be LBM_F64 or LBM_F32");
     if ((double)p->nx * p->ny * p->nz * 2 * NQ > 9.0e18) return fail3(LBM_ERR_INVALID, "grid too large");
     if (!(p->tau_f > 0.5) || !(p->tau_T > 0.5)) return fail3(LBM_ERR_INVALID, "tau_f and tau_T must exceed 1/2");
@@ -528,7 +547,7 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
     if (!(Kp > 0)) return fail3(LBM_ERR_INVALID, "K = Da L^2 must be positive");
     const double dT = p->T_hot - p->T_cold;
     const double Feps = std::isnan(p->F_eps) ? 1.75 / sqrt(150.0 * p->eps * p->eps * p->eps) : p->F_eps;
-    K.nx = p->nx; K.ny = p->ny; K.nz = p->nz; K.px = p->periodic_x ? 1 : 0; K.pz = p->periodic_z ? 1 : 0;
+    K.nx = p->nx; K.ny = p->ny; K.nz = p->nz; K.px = p->periodic_x ? 1 : 0; K.py = p->periodic_y ? 1 : 0; K.pz = p->periodic_z ? 1 : 0;
     K.n = (long long)p->nx * p->ny * p->nz;
     K.tau_f = p->tau_f; K.tau_T = p->tau_T; K.A = A; K.B = B; K.sigma = p->sigma; K.Q = p->Q; K.eps = p->eps;
     K.T0 = 0.5 * (p->T_hot + p->T_cold);
@@ -545,7 +564,7 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
     K.isqK = 1.0 / sqrt(Kp);
     K.ergun = std::isnan(p->F_eps) ? 1 : 0;
     K.Feps = K.ergun ? 0.0 : p->F_eps;
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < 6; ++w) {
         K.wkind[w] = p->wall[w].t_kind == LBM_T_NEUMANN ? 1 : 0;
         for (int a = 0; a < 3; ++a) K.wu[w][a] = p->wall[w].u[a];
         K.wT[w] = p->wall[w].T;
@@ -615,7 +634,7 @@ lbm_status lbm3_step(lbm3_ctx *c, int64_t nsteps)
     if (!c) return fail3(LBM_ERR_INVALID, "ctx is NULL");
     if (nsteps < 0) return fail3(LBM_ERR_INVALID, "nsteps must be >= 0");
     const K3 &K = c->K;
-    const long long n_in = (long long)inner_x(K) * K.ny * inner_z(K), n_w = K.n - n_in;
+    const long long n_in = (long long)inner_x(K) * inner_y(K) * inner_z(K), n_w = K.n - n_in;
     const unsigned nb_in = blocks_for(n_in), nb_w = blocks_for(n_w);
     for (int64_t s = 0; s < nsteps; ++s) {
         if (c->storage == LBM_F64) {
@@ -663,8 +682,10 @@ lbm_status lbm3_populations(lbm3_ctx *c, double *f, double *g)
 lbm_status lbm3_nusselt(lbm3_ctx *c, int32_t wall, double *nu_host)
 {
     if (!c || !nu_host) return fail3(LBM_ERR_INVALID, "ctx and nu_host must be non-NULL");
-    if (wall < 0 || wall > 3) return fail3(LBM_ERR_INVALID, "wall must be 0 (z = 0), 1 (z = nz - 1), 2 (x = 0) or 3 (x = nx - 1)");
-    if (wall < 2 ? c->K.pz : c->K.px) return fail3(LBM_ERR_INVALID, "wall %d does not exist (periodic direction)", (int)wall);
+    if (wall < 0 || wall > 5)
+        return fail3(LBM_ERR_INVALID, "wall must be 0 (z = 0), 1 (z = nz - 1), 2 (x = 0), 3 (x = nx - 1), 4 (y = 0) or 5 (y = ny - 1)");
+    if (wall < 2 ? c->K.pz : (wall < 4 ? c->K.px : c->K.py))
+        return fail3(LBM_ERR_INVALID, "wall %d does not exist (periodic direction)", (int)wall);
     if (!(c->K.dT != 0.0)) return fail3(LBM_ERR_INVALID, "T_hot - T_cold is zero");
     if (c->storage == LBM_F64)
         hipLaunchKernelGGL((k3_nusselt<double>), dim3(1), dim3(256), 0, c->stream,

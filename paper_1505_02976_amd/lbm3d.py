@@ -20,8 +20,8 @@ class _Wall3(C.Structure):
 class _Params3(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("periodic_x", C.c_int32),
-        ("periodic_z", C.c_int32), ("reserved0", C.c_int32),
-        ("wall", _Wall3 * 4),
+        ("periodic_y", C.c_int32), ("periodic_z", C.c_int32),
+        ("wall", _Wall3 * 6),
         ("L", C.c_double), ("Da", C.c_double), ("Ra", C.c_double), ("Pr", C.c_double),
         ("J", C.c_double), ("Ma", C.c_double), ("sigma", C.c_double), ("Q", C.c_double),
         ("tau_f", C.c_double), ("tau_T", C.c_double), ("A", C.c_double), ("B", C.c_double),
@@ -70,6 +70,7 @@ def make_params(cfg: dict, T_init=0, u_init=0, eps_field=0) -> _Params3:
     p = _Params3()
     p.nx, p.ny, p.nz = int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"])
     p.periodic_x = int(cfg.get("periodic_x", 1))
+    p.periodic_y = int(cfg.get("periodic_y", 1))
     p.periodic_z = int(cfg.get("periodic_z", 0))
     for k, w in enumerate(cfg["walls"]):
         p.wall[k].t_kind = 1 if w.get("kind", "T") == "dTdn" else 0
@@ -162,7 +163,8 @@ class Sim3:
         return out
 
     def nusselt(self, wall: int = 0) -> float:
-        """Average Nusselt number of wall 0 (z = 0), 1 (z = nz - 1), 2 (x = 0) or 3 (x = nx - 1), FP64."""
+        """Average Nusselt number of wall 0 (z = 0), 1 (z = nz - 1), 2 (x = 0), 3 (x = nx - 1),
+        4 (y = 0) or 5 (y = ny - 1), FP64."""
         v = C.c_double()
         _lbm._check(lib().lbm3_nusselt(self.h, int(wall), C.byref(v)))
         return v.value

@@ -146,9 +146,9 @@ def test_exports_every_declared_3d_symbol(lbm):
 def test_3d_struct_sizes_and_validation(lbm):
     import workloads as W
     from paper_1505_02976_amd import lbm3d as L3
-    # lbm3_wall: 3 doubles, 2 int32, 2 doubles; lbm3_params: 6 int32, 4 walls, 19 doubles, 2 int32, 3 pointers
+    # lbm3_wall: 3 doubles, 2 int32, 2 doubles; lbm3_params: 6 int32, 6 walls, 19 doubles, 2 int32, 3 pointers
     assert C.sizeof(L3._Wall3) == 48
-    assert C.sizeof(L3._Params3) == 24 + 4 * 48 + 19 * 8 + 8 + 24
+    assert C.sizeof(L3._Params3) == 24 + 6 * 48 + 19 * 8 + 8 + 24
     cfg = W.layer3d(16, 8, 12)
     n = 16 * 8 * 12
     assert L3.workspace_bytes(cfg) == 2 * ((2 * 19 * n * 8 + 255) // 256 * 256) + 256
@@ -159,6 +159,8 @@ def test_3d_struct_sizes_and_validation(lbm):
     assert L3.workspace_bytes(dict(cfg, nx=3, periodic_x=0)) == 0
     assert "nx >= 4" in lbm.lib().lbm_last_error().decode()
     assert L3.workspace_bytes(dict(cfg, nx=4, periodic_x=0, walls=cfg["walls"] + [{}, {}])) > 0
+    assert L3.workspace_bytes(dict(cfg, ny=3, periodic_y=0)) == 0
+    assert "ny >= 4" in lbm.lib().lbm_last_error().decode()
     assert L3.workspace_bytes(dict(cfg, tau_f=0.5)) == 0
     assert L3.workspace_bytes(dict(cfg, A=0.6, B=0.1)) == 0
     assert "nu_e" in lbm.lib().lbm_last_error().decode()

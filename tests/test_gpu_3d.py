@@ -244,3 +244,52 @@ def test_cavity_nusselt_against_oracle_and_paper(gpu3):
     _say(f"  hot wall at 12000 steps: {nu:.5f} (paper 1.012)")
     assert abs(nu - 1.012) < 0.005 * 1.012
     assert abs(sim.nusselt(3) - nu) < 0.002 * nu
+
+
+YCASES = [
+    # (seed, nx, ny, nz, periodic_x, periodic_z): walls at y = 0 and y = ny - 1
+    (21, 11, 8, 10, 0, 0),         # closed box: edges and vertices
+    (22, 7, 9, 5, 1, 0),           # y and z walls
+    (26, 5, 4, 6, 0, 1),           # smallest walled ny, x walls, periodic z (a case that stays bounded)
+    (24, 4, 4, 4, 0, 0),           # smallest closed box
+]
+
+
+@pytest.mark.parametrize("seed,nx,ny,nz,px,pz", YCASES)
+def test_fp64_parity_y_walls(gpu3, seed, nx, ny, nz, px, pz):
+    cfg = W.random_case3d(seed, nx, ny, nz, periodic_z=pz, eps_field=seed % 2 == 1, periodic_x=px, periodic_y=0)
+    _say(f"case: 3-D FP64 y walls seed {seed} {nx}x{ny}x{nz} periodic_x {px} periodic_z {pz}, walls "
+         f"{[w.get('kind') for w in cfg['walls']]}, 200 steps")
+    dpop, dfield, _, _ = _compare(gpu3, cfg, 200, 1e-10, 1e-10)
+    _say(f"  max |populations| diff {dpop:.2e}; fields {max(dfield.values()):.2e}")
+    assert dpop < 1e-10
+    assert all(v < 1e-10 for v in dfield.values()), dfield
+
+
+def test_fp32_parity_closed_box(gpu3):
+    cfg = W.random_case3d(21, 11, 8, 10, storage="f32", periodic_x=0, periodic_y=0)
+    _say("case: 3-D FP32 closed box seed 21, 200 steps")
+    _, _, a, b = _compare(gpu3, cfg, 200, None, None)
+    du = np.sqrt(sum(np.linalg.norm(a[k] - b[k]) ** 2 for k in ("ux", "uy", "uz")))
+    nu = np.sqrt(sum(np.linalg.norm(b[k]) ** 2 for k in ("ux", "uy", "uz")))
+    rel = {"u": du / nu, "T": np.linalg.norm(a["T"] - b["T"]) / np.linalg.norm(b["T"])}
+    _say(f"  rel L2: u {rel['u']:.2e}, T {rel['T']:.2e}")
+    assert rel["u"] < 1e-5 and rel["T"] < 1e-5, rel
+
+
+def test_closed_box_nusselt_numbers_against_oracle(gpu3):
+    """A box closed on all six faces (the cavity of Sec. 4.2 between x walls, with y walls
+    as well), 300 steps: the six wall Nusselt numbers against the oracle's (FP64)."""
+    import oracle.oracle3 as O3
+    cfg = W.cavity3d(20, 2, eps=0.6, Da=1e-2, Ra=1e4)
+    cfg = dict(cfg, ny=6, periodic_y=0, T_init=np.repeat(cfg["T_init"][:, :1, :], 6, axis=1),
+               walls=cfg["walls"] + [{"kind": "dTdn", "dTdn": 0.0}, {"kind": "T", "T": 0.5}])
+    _say("case: 3-D FP64 closed box 20x6x20, 300 steps")
+    sim = gpu3.Sim3(cfg)
+    sim.step(300)
+    ref = O3.Oracle3(cfg)
+    ref.step(300)
+    for w in range(6):
+        a, b = sim.nusselt(w), ref.nusselt(w)
+        _say(f"  Nusselt number of wall {w}: {a:.12f} (oracle {b:.12f})")
+        assert abs(a - b) < 1e-10 * max(1.0, abs(b))

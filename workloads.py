@@ -212,13 +212,14 @@ def layer3d(nx=64, ny=64, nz=32, eps=0.6, Da=1e-2, Ra=1e4, Pr=1.0, seed=0, stora
     }
 
 
-def random_case3d(seed, nx, ny, nz, periodic_z=0, storage="f64", eps_field=False, periodic_x=1):
+def random_case3d(seed, nx, ny, nz, periodic_z=0, storage="f64", eps_field=False, periodic_x=1, periodic_y=1):
     """A randomised 3-D problem with a non-trivial initial flow and temperature for parity
     tests: random Da, Ra in [1e2, 1e3], Pr, tau, A, B, eps, forcing and heat source, wall
     kinds and wall velocities, smooth random initial u and T; with eps_field, a smooth
-    random porosity field in [0.4, 0.9]; with periodic_x = 0, walls at x = 0 and x = nx - 1
-    of random kinds and tangential velocities (each drawn after everything before it, so a
-    seed's earlier draws do not depend on these options)."""
+    random porosity field in [0.4, 0.9]; with periodic_x = 0 (periodic_y = 0), walls at
+    x = 0 and x = nx - 1 (y = 0 and y = ny - 1) of random kinds and tangential velocities
+    (each drawn after everything before it, so a seed's earlier draws do not depend on these
+    options)."""
     rng = np.random.default_rng(seed)
     tau_f, tau_T = rng.uniform(0.7, 1.3), rng.uniform(0.7, 1.3)
     walls = []
@@ -255,6 +256,14 @@ def random_case3d(seed, nx, ny, nz, periodic_z=0, storage="f64", eps_field=False
             kind = "T" if rng.uniform() < 0.6 else "dTdn"
             walls.append({"kind": kind, "T": float(rng.uniform(0.0, 1.0)), "dTdn": float(rng.uniform(-0.01, 0.01)),
                           "u": tuple(float(v) for v in rng.uniform(-0.02, 0.02, size=3) * np.array([0.0, 1.0, 1.0]))})
+    if not periodic_y:
+        cfg["periodic_y"] = 0
+        while len(walls) < 4:
+            walls.append({})
+        for k in range(2):
+            kind = "T" if rng.uniform() < 0.6 else "dTdn"
+            walls.append({"kind": kind, "T": float(rng.uniform(0.0, 1.0)), "dTdn": float(rng.uniform(-0.01, 0.01)),
+                          "u": tuple(float(v) for v in rng.uniform(-0.02, 0.02, size=3) * np.array([1.0, 0.0, 1.0]))})
     return cfg
 
 
