@@ -1,6 +1,6 @@
 """The 3-D (D3Q19) HIP path through the C interface against the 3-D oracle: populations and
-every field of seeded random problems (walled and periodic z, walls in x with and without
-z walls, isothermal and prescribed-gradient walls, moving walls, porosity fields, ragged
+every field of seeded random problems (walled and periodic z, walls in x and in y with and
+without z walls, closed boxes, isothermal and prescribed-gradient walls, moving walls, porosity fields, ragged
 sizes, the smallest walled nx and nz), FP64 within
 1e-10 and FP32 within 1e-5 relative L2, the exact conduction fixed point, a larger
 layer heated from below, the porous cavity's wall Nusselt numbers."""
