@@ -291,14 +291,15 @@ __device__ __forceinline__ bool node_xyz(const K3 &K, int &x, int &y, int &z)
 }
 
 // Post-collision populations into the buffer: f as deviations already, g less its rest state.
+// Non-temporal stores: the next step reads them from HBM, not from this launch's caches.
 template <typename S, typename R>
 __device__ __forceinline__ void store(S *__restrict__ dst, const K3 &K, size_t k, const R *f, const R *g)
 {
     const double gT0 = K.sigma * K.T0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        dst[(size_t)q * K.n + k] = S(f[q]);
-        dst[(size_t)(NQ + q) * K.n + k] = S(g[q] - R(W(q) * gT0));
+        __builtin_nontemporal_store(S(f[q]), &dst[(size_t)q * K.n + k]);
+        __builtin_nontemporal_store(S(g[q] - R(W(q) * gT0)), &dst[(size_t)(NQ + q) * K.n + k]);
     }
 }
 
