@@ -177,14 +177,15 @@ def adjoint_run(lbm, torch, W, n=256, steps=5000, storage="f32"):
 
 def three_d_run(torch, W, shape=(192, 192, 96), steps=200, warmup=20):
     """The 3-D (D3Q19) path on a porous layer heated from below (Ra 1e4, Da 1e-2, eps 0.6),
-    FP64 and FP32 storage: one launch per step, each reading and writing 2 x 19 populations
-    per node, timed with events on the stream the launches go to."""
+    FP64, FP32 and FP16 storage: per step one launch over the interior and one over the wall
+    planes, each node reading and writing 2 x 19 populations, timed with events on the
+    stream the launches go to."""
     from paper_1505_02976_amd import lbm3d
     nx, ny, nz = shape
     nodes = nx * ny * nz
     out = {"workload": f"porous layer heated from below {nx}x{ny}x{nz}, Ra 1e4, Da 1e-2, eps 0.6, D3Q19",
            "nodes": nodes}
-    for storage, es in (("f64", 8), ("f32", 4)):
+    for storage, es in (("f64", 8), ("f32", 4), ("f16", 2)):
         sim = lbm3d.Sim3(W.layer3d(nx, ny, nz, Ra=1e4, Da=1e-2, storage=storage))
         sim.step(warmup)
         st = torch.cuda.current_stream()
@@ -324,7 +325,8 @@ def main():
     if not args.no_3d:
         td = three_d_run(torch, W)
         log(f"bench: 3-D f64 {td['f64']['mlups']:.0f} MLUPS ({td['f64']['GBps']:.0f} GB/s), "
-            f"f32 {td['f32']['mlups']:.0f} MLUPS ({td['f32']['GBps']:.0f} GB/s)")
+            f"f32 {td['f32']['mlups']:.0f} MLUPS ({td['f32']['GBps']:.0f} GB/s), "
+            f"f16 {td['f16']['mlups']:.0f} MLUPS ({td['f16']['GBps']:.0f} GB/s)")
     acc = None if args.no_accuracy else accuracy(lbm, W)
     cpu = None if args.no_cpu else cpu_baseline(W, n)
 

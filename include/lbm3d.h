@@ -21,8 +21,9 @@
  * Units, status codes, storage types and thread rules are those of lbm.h.  Arrays are
  * [z][y][x] with x fastest; vector fields are consecutive planes (x, y, z components).
  * The populations live in a caller-provided device workspace as two buffers of 2 x 19
- * planes (flow, temperature), in deviation form as in two dimensions; the arithmetic is in
- * the storage precision (FP64 or FP32), with the drag solve in FP64.
+ * planes (flow, temperature), in deviation form as in two dimensions (FP16 scaled by 256, as
+ * there); the arithmetic is in the storage precision (FP64 or FP32; FP32 for FP16 storage),
+ * with the drag solve in FP64.
  */
 #pragma once
 
@@ -65,7 +66,7 @@ typedef struct {
     double a[3];                 /* external acceleration */
     double T_hot, T_cold;
     double F_eps;                /* NaN => Ergun relation 1.75 / sqrt(150 eps^3) */
-    int32_t storage;             /* LBM_F64 or LBM_F32 */
+    int32_t storage;             /* LBM_F64, LBM_F32 or LBM_F16 */
     int32_t reserved;
     const double *T_init;
     const double *u_init;
@@ -74,7 +75,7 @@ typedef struct {
 
 /* Workspace bytes lbm3_init needs for this problem: two population buffers and 256 bytes
  * for reduction results (0 if the problem is invalid; lbm_last_error says why).  Unusable:
- * nx, ny, nz < 1 (periodic) or < 4 (walled); storage other than F64/F32; tau <= 1/2;
+ * nx, ny, nz < 1 (periodic) or < 4 (walled); storage other than F64/F32/F16; tau <= 1/2;
  * nu_e, alpha_e or K not positive. */
 size_t lbm3_workspace_bytes(const lbm3_params *params);
 

@@ -4,8 +4,9 @@
 // node: pull streaming from the previous step's post-collision buffer, the node's
 // macroscopic state, BGK collision with forcing and sources, store.  Populations are kept
 // as 38 planes [q][z][y][x] (flow 0-18, temperature 19-37) in deviation form (f_0 - rho0,
-// g_i - omega_i sigma T0), FP64 or FP32, with arithmetic in the storage precision (the drag
-// solve in FP64).
+// g_i - omega_i sigma T0), FP64, FP32 or FP16 (scaled by 256), with arithmetic in the storage
+// precision, FP32 for FP16 (the drag solve in FP64).
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -84,6 +85,26 @@ __device__ __forceinline__ Por por_of(const K3 &K, size_t k)
 template <typename S> struct Arith;
 template <> struct Arith<double> { using R = double; };
 template <> struct Arith<float> { using R = float; };
+template <> struct Arith<__half> { using R = float; };
+
+// Load and store of one stored deviation.  FP16 holds 256 times the deviation: the
+// deviations are small, and the scale keeps them clear of FP16's subnormal range.  Stores
+// are non-temporal: the next step reads them from HBM, not from this launch's caches.
+template <typename S> struct St3 {
+    template <typename R> static __device__ __forceinline__ R ld(const S *p) { return R(*p); }
+    template <typename R> static __device__ __forceinline__ void st(S *p, R v) { __builtin_nontemporal_store(S(v), p); }
+};
+template <> struct St3<__half> {
+    template <typename R> static __device__ __forceinline__ R ld(const __half *p)
+    {
+        return R(__half2float(*p) * (1.0f / 256.0f));
+    }
+    template <typename R> static __device__ __forceinline__ void st(__half *p, R v)
+    {
+        __builtin_nontemporal_store(__half_as_ushort(__float2half(float(v) * 256.0f)),
+                                    reinterpret_cast<unsigned short *>(p));
+    }
+};
 
 // Pre-collision populations of node (x, y, z) pulled from the post-collision buffer: f in
 // deviation form, g with the rest state omega_i sigma T0 added back.
@@ -96,8 +117,8 @@ __device__ __forceinline__ void pull(const S *__restrict__ src, const K3 &K, int
         const int xs = wrap(x - CX[q], K.nx), ys = wrap(y - CY[q], K.ny);
         const int zs = K.pz ? wrap(z - CZ[q], K.nz) : z - CZ[q];
         const size_t k = ((size_t)zs * K.ny + ys) * K.nx + xs;
-        f[q] = R(src[(size_t)q * K.n + k]);
-        g[q] = R(src[(size_t)(NQ + q) * K.n + k]) + R(W(q) * gT0);
+        f[q] = St3<S>::template ld<R>(src + (size_t)q * K.n + k);
+        g[q] = St3<S>::template ld<R>(src + (size_t)(NQ + q) * K.n + k) + R(W(q) * gT0);
     }
 }
 
@@ -291,15 +312,14 @@ __device__ __forceinline__ bool node_xyz(const K3 &K, int &x, int &y, int &z)
 }
 
 // Post-collision populations into the buffer: f as deviations already, g less its rest state.
-// Non-temporal stores: the next step reads them from HBM, not from this launch's caches.
 template <typename S, typename R>
 __device__ __forceinline__ void store(S *__restrict__ dst, const K3 &K, size_t k, const R *f, const R *g)
 {
     const double gT0 = K.sigma * K.T0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        __builtin_nontemporal_store(S(f[q]), &dst[(size_t)q * K.n + k]);
-        __builtin_nontemporal_store(S(g[q] - R(W(q) * gT0)), &dst[(size_t)(NQ + q) * K.n + k]);
+        St3<S>::template st<R>(dst + (size_t)q * K.n + k, f[q]);
+        St3<S>::template st<R>(dst + (size_t)(NQ + q) * K.n + k, g[q] - R(W(q) * gT0));
     }
 }
 
@@ -507,7 +527,16 @@ lbm_status fail3(lbm_status st, const char *fmt, ...)
     return lbm::set_error(st, msg);
 }
 
-size_t elem3(int storage) { return storage == LBM_F64 ? 8 : 4; }
+size_t elem3(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
+
+// Calls f with a tag naming the storage type of a context.
+template <typename S> struct Tag { using type = S; };
+template <typename F> void by_storage(int storage, F &&f)
+{
+    if (storage == LBM_F64) f(Tag<double>{});
+    else if (storage == LBM_F32) f(Tag<float>{});
+    else f(Tag<__half>{});
+}
 
 size_t buffer_bytes(const lbm3_params *p)
 {
@@ -526,7 +555,8 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
     if (!p->periodic_z && p->nz < 4) return fail3(LBM_ERR_INVALID, "walled z needs nz >= 4 (got %d)", p->nz);
     if (!p->periodic_x && p->nx < 4) return fail3(LBM_ERR_INVALID, "walled x needs nx >= 4 (got %d)", p->nx);
     if (!p->periodic_y && p->ny < 4) return fail3(LBM_ERR_INVALID, "walled y needs ny >= 4 (got %d)", p->ny);
-    if (p->storage != LBM_F64 && p->storage != LBM_F32) return fail3(LBM_ERR_INVALID, "storage must be LBM_F64 or LBM_F32");
+    if (p->storage != LBM_F64 && p->storage != LBM_F32 && p->storage != LBM_F16)
+        return fail3(LBM_ERR_INVALID, "storage must be LBM_F64, LBM_F32 or LBM_F16");
     if ((double)p->nx * p->ny * p->nz * 2 * NQ > 9.0e18) return fail3(LBM_ERR_INVALID, "grid too large");
     if (!(p->tau_f > 0.5) || !(p->tau_T > 0.5)) return fail3(LBM_ERR_INVALID, "tau_f and tau_T must exceed 1/2");
     if (!(p->eps > 0.0) || !(p->eps <= 1.0) || !(p->sigma > 0.0) || !(p->J > 0.0))
@@ -614,12 +644,11 @@ lbm_status lbm3_init(const lbm3_params *params, void *workspace, size_t workspac
     c->cur = 0;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->t = 0;
-    if (c->storage == LBM_F64)
-        hipLaunchKernelGGL((k3_init<double>), dim3(blocks_for(K.n)), dim3(B3), 0, c->stream,
-                           reinterpret_cast<double *>(c->buf[0]), K, params->T_init, params->u_init);
-    else
-        hipLaunchKernelGGL((k3_init<float>), dim3(blocks_for(K.n)), dim3(B3), 0, c->stream,
-                           reinterpret_cast<float *>(c->buf[0]), K, params->T_init, params->u_init);
+    by_storage(c->storage, [&](auto t) {
+        using S = typename decltype(t)::type;
+        hipLaunchKernelGGL((k3_init<S>), dim3(blocks_for(K.n)), dim3(B3), 0, c->stream,
+                           reinterpret_cast<S *>(c->buf[0]), K, params->T_init, params->u_init);
+    });
     st = launched("initial populations");
     if (st == LBM_OK) {
         const hipError_t e = hipStreamSynchronize(c->stream);
@@ -638,17 +667,13 @@ lbm_status lbm3_step(lbm3_ctx *c, int64_t nsteps)
     const long long n_in = (long long)inner_x(K) * inner_y(K) * inner_z(K), n_w = K.n - n_in;
     const unsigned nb_in = blocks_for(n_in), nb_w = blocks_for(n_w);
     for (int64_t s = 0; s < nsteps; ++s) {
-        if (c->storage == LBM_F64) {
-            const double *src = reinterpret_cast<const double *>(c->buf[c->cur]);
-            double *dst = reinterpret_cast<double *>(c->buf[c->cur ^ 1]);
-            hipLaunchKernelGGL((k3_step_interior<double>), dim3(nb_in), dim3(B3), 0, c->stream, src, dst, c->K);
-            if (n_w) hipLaunchKernelGGL((k3_step_walls<double>), dim3(nb_w), dim3(B3), 0, c->stream, src, dst, c->K);
-        } else {
-            const float *src = reinterpret_cast<const float *>(c->buf[c->cur]);
-            float *dst = reinterpret_cast<float *>(c->buf[c->cur ^ 1]);
-            hipLaunchKernelGGL((k3_step_interior<float>), dim3(nb_in), dim3(B3), 0, c->stream, src, dst, c->K);
-            if (n_w) hipLaunchKernelGGL((k3_step_walls<float>), dim3(nb_w), dim3(B3), 0, c->stream, src, dst, c->K);
-        }
+        by_storage(c->storage, [&](auto t) {
+            using S = typename decltype(t)::type;
+            const S *src = reinterpret_cast<const S *>(c->buf[c->cur]);
+            S *dst = reinterpret_cast<S *>(c->buf[c->cur ^ 1]);
+            hipLaunchKernelGGL((k3_step_interior<S>), dim3(nb_in), dim3(B3), 0, c->stream, src, dst, c->K);
+            if (n_w) hipLaunchKernelGGL((k3_step_walls<S>), dim3(nb_w), dim3(B3), 0, c->stream, src, dst, c->K);
+        });
         c->cur ^= 1;
         c->t += 1;
     }
@@ -659,24 +684,22 @@ lbm_status lbm3_fields(lbm3_ctx *c, double *p, double *u, double *T, double *S, 
 {
     if (!c) return fail3(LBM_ERR_INVALID, "ctx is NULL");
     const FieldOut3 o{p, u, T, S, gradT};
-    if (c->storage == LBM_F64)
-        hipLaunchKernelGGL((k3_fields<double>), dim3(blocks_for(c->K.n)), dim3(B3), 0, c->stream,
-                           reinterpret_cast<const double *>(c->buf[c->cur]), c->K, o);
-    else
-        hipLaunchKernelGGL((k3_fields<float>), dim3(blocks_for(c->K.n)), dim3(B3), 0, c->stream,
-                           reinterpret_cast<const float *>(c->buf[c->cur]), c->K, o);
+    by_storage(c->storage, [&](auto t) {
+        using S = typename decltype(t)::type;
+        hipLaunchKernelGGL((k3_fields<S>), dim3(blocks_for(c->K.n)), dim3(B3), 0, c->stream,
+                           reinterpret_cast<const S *>(c->buf[c->cur]), c->K, o);
+    });
     return launched("3-D fields");
 }
 
 lbm_status lbm3_populations(lbm3_ctx *c, double *f, double *g)
 {
     if (!c) return fail3(LBM_ERR_INVALID, "ctx is NULL");
-    if (c->storage == LBM_F64)
-        hipLaunchKernelGGL((k3_populations<double>), dim3(blocks_for(c->K.n)), dim3(B3), 0, c->stream,
-                           reinterpret_cast<const double *>(c->buf[c->cur]), c->K, f, g);
-    else
-        hipLaunchKernelGGL((k3_populations<float>), dim3(blocks_for(c->K.n)), dim3(B3), 0, c->stream,
-                           reinterpret_cast<const float *>(c->buf[c->cur]), c->K, f, g);
+    by_storage(c->storage, [&](auto t) {
+        using S = typename decltype(t)::type;
+        hipLaunchKernelGGL((k3_populations<S>), dim3(blocks_for(c->K.n)), dim3(B3), 0, c->stream,
+                           reinterpret_cast<const S *>(c->buf[c->cur]), c->K, f, g);
+    });
     return launched("3-D populations");
 }
 
@@ -688,12 +711,11 @@ lbm_status lbm3_nusselt(lbm3_ctx *c, int32_t wall, double *nu_host)
     if (wall < 2 ? c->K.pz : (wall < 4 ? c->K.px : c->K.py))
         return fail3(LBM_ERR_INVALID, "wall %d does not exist (periodic direction)", (int)wall);
     if (!(c->K.dT != 0.0)) return fail3(LBM_ERR_INVALID, "T_hot - T_cold is zero");
-    if (c->storage == LBM_F64)
-        hipLaunchKernelGGL((k3_nusselt<double>), dim3(1), dim3(256), 0, c->stream,
-                           reinterpret_cast<const double *>(c->buf[c->cur]), c->K, (int)wall, c->result);
-    else
-        hipLaunchKernelGGL((k3_nusselt<float>), dim3(1), dim3(256), 0, c->stream,
-                           reinterpret_cast<const float *>(c->buf[c->cur]), c->K, (int)wall, c->result);
+    by_storage(c->storage, [&](auto t) {
+        using S = typename decltype(t)::type;
+        hipLaunchKernelGGL((k3_nusselt<S>), dim3(1), dim3(256), 0, c->stream,
+                           reinterpret_cast<const S *>(c->buf[c->cur]), c->K, (int)wall, c->result);
+    });
     lbm_status st = launched("3-D Nusselt number");
     if (st != LBM_OK) return st;
     hipError_t e = hipMemcpyAsync(nu_host, c->result, sizeof(double), hipMemcpyDeviceToHost, c->stream);

@@ -9,7 +9,7 @@ import math
 
 from . import lbm as _lbm
 
-STORAGE3 = {"f64": 0, "f32": 1}
+STORAGE3 = {"f64": 0, "f32": 1, "f16": 2}
 
 
 class _Wall3(C.Structure):

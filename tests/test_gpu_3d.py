@@ -293,3 +293,40 @@ def test_closed_box_nusselt_numbers_against_oracle(gpu3):
         a, b = sim.nusselt(w), ref.nusselt(w)
         _say(f"  Nusselt number of wall {w}: {a:.12f} (oracle {b:.12f})")
         assert abs(a - b) < 1e-10 * max(1.0, abs(b))
+
+
+@pytest.mark.parametrize("case", ["layer", "closed_box"])
+def test_fp16_against_fp64_oracle(gpu3, case):
+    """FP16 storage (deviations scaled by 256, FP32 arithmetic): u and T within 5e-2
+    relative L2 of the FP64 oracle after 200 steps, the bound the two-dimensional FP16
+    storage meets on the cavity."""
+    import oracle.oracle3 as O3
+    if case == "layer":
+        cfg = W.layer3d(32, 24, 16, Ra=1e4, Da=1e-2, storage="f16")
+    else:
+        cfg = W.random_case3d(21, 11, 8, 10, storage="f16", periodic_x=0, periodic_y=0)
+    _say(f"case: 3-D FP16 {case}, 200 steps")
+    sim = gpu3.Sim3(cfg)
+    sim.step(200)
+    ref = O3.Oracle3(cfg)
+    ref.step(200)
+    a = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+    b = ref.fields()
+    du = np.sqrt(sum(np.linalg.norm(a[k] - b[k]) ** 2 for k in ("ux", "uy", "uz")))
+    nu = np.sqrt(sum(np.linalg.norm(b[k]) ** 2 for k in ("ux", "uy", "uz")))
+    rel = {"u": du / nu, "T": np.linalg.norm(a["T"] - b["T"]) / np.linalg.norm(b["T"])}
+    _say(f"  rel L2: u {rel['u']:.2e}, T {rel['T']:.2e}")
+    assert rel["u"] < 5e-2 and rel["T"] < 5e-2, rel
+
+
+def test_fp16_bench_size_against_oracle(gpu3):
+    """The bench's FP16 3-D workload at its full size (192 x 192 x 96), 5 steps: T and u
+    within 5e-3 relative L2 of the FP64 oracle."""
+    cfg = W.layer3d(192, 192, 96, Ra=1e4, Da=1e-2, storage="f16")
+    _say("case: 3-D f16 bench layer 192x192x96, 5 steps")
+    _, _, a, b = _compare(gpu3, cfg, 5, None, None)
+    du = np.sqrt(sum(np.linalg.norm(a[k] - b[k]) ** 2 for k in ("ux", "uy", "uz")))
+    rel = {"T": float(np.linalg.norm(a["T"] - b["T"]) / np.linalg.norm(b["T"])),
+           "u": float(du / np.sqrt(sum(np.linalg.norm(b[k]) ** 2 for k in ("ux", "uy", "uz"))))}
+    _say(f"  rel L2 {rel}")
+    assert rel["u"] < 5e-3 and rel["T"] < 5e-3, rel
