@@ -175,6 +175,10 @@ def test_conduction_fixed_point_between_x_walls():
     assert np.abs(f["T"] - (0.9 + slope * x)[None, None, :]).max() < 1e-12
     assert np.abs(f["dTdx"] - slope).max() < 1e-12
     assert np.abs(f["dTdz"]).max() < 1e-12
+    # Nu = -L dT/dx / dT with L = nx - 1 and dT = 1: 0.8 at both x walls (trapezoid weights
+    # along the walled z direction sum to the plane's width), 0 at the adiabatic z walls
+    for w, nu in ((2, 0.8), (3, 0.8), (0, 0.0), (1, 0.0)):
+        assert abs(o.nusselt(w) - nu) < 1e-12, (w, o.nusselt(w))
 
 
 def test_cavity_between_x_walls_matches_the_paper():
@@ -229,3 +233,8 @@ def test_conduction_fixed_point_in_a_closed_box():
     assert np.abs(f["T"] - (0.1 + slope * z)[:, None, None]).max() < 1e-12
     assert np.abs(f["dTdz"] - slope).max() < 1e-12
     assert max(np.abs(f[k]).max() for k in ("ux", "uy", "uz", "dTdx", "dTdy")) < 1e-12
+    # Nu = -L dT/dz / dT, L = nx - 1 (walls in x), dT = 1: at both z walls; 0 at the
+    # adiabatic x and y walls
+    nu_z = -(nx - 1) * slope
+    for w, nu in ((0, nu_z), (1, nu_z), (2, 0.0), (3, 0.0), (4, 0.0), (5, 0.0)):
+        assert abs(o.nusselt(w) - nu) < 1e-12, (w, o.nusselt(w))
