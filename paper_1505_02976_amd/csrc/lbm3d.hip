@@ -425,28 +425,32 @@ __global__ void __launch_bounds__(256) k3_nusselt(const S *__restrict__ src, K3 
 {
     using R = typename Arith<S>::R;
     __shared__ double part[256];
-    const int nn[3] = {K.nx, K.ny, K.nz}, per[3] = {K.px, K.py, K.pz};
     const int ax = w < 2 ? 2 : (w < 4 ? 0 : 1), hi = w & 1;          // normal axis, far wall
-    const int b0 = ax == 0 ? 1 : 0, b1 = ax == 2 ? 1 : 2;             // the in-plane axes
-    const long long cells = (long long)nn[b0] * nn[b1];
+    // the in-plane axes: the first is y for x walls and x otherwise, the second y for z walls
+    // and z otherwise (selected explicitly, so nothing is indexed at run time)
+    const int na = ax == 0 ? K.nx : (ax == 1 ? K.ny : K.nz);
+    const int n0 = ax == 0 ? K.ny : K.nx, p0 = ax == 0 ? K.py : K.px;
+    const int n1 = ax == 2 ? K.ny : K.nz, p1 = ax == 2 ? K.py : K.pz;
+    const long long cells = (long long)n0 * n1;
     double acc = 0.0;
     for (long long c = threadIdx.x; c < cells; c += 256) {
-        int e[3];
-        e[b0] = (int)(c % nn[b0]);
-        e[b1] = (int)(c / nn[b0]);
+        const int i0 = (int)(c % n0), i1 = (int)(c / n0);
         double T[3];
         for (int d = 0; d < 3; ++d) {
-            e[ax] = hi ? nn[ax] - 1 - d : d;
+            const int ia = hi ? na - 1 - d : d;
+            const int x = ax == 0 ? ia : i0;
+            const int y = ax == 1 ? ia : (ax == 0 ? i0 : i1);
+            const int z = ax == 2 ? ia : i1;
             R f[NQ], g[NQ];
             Mac<R> m;
             Por p;
-            node_state<S, R>(src, K, e[0], e[1], e[2], f, g, m, p);
+            node_state<S, R>(src, K, x, y, z, f, g, m, p);
             T[d] = double(m.T);
         }
         const double d1 = (-3.0 * T[0] + 4.0 * T[1] - T[2]) / 2.0;   // along the inward normal
         double wt = 1.0;
-        if (!per[b0] && (e[b0] == 0 || e[b0] == nn[b0] - 1)) wt *= 0.5;
-        if (!per[b1] && (e[b1] == 0 || e[b1] == nn[b1] - 1)) wt *= 0.5;
+        if (!p0 && (i0 == 0 || i0 == n0 - 1)) wt *= 0.5;
+        if (!p1 && (i1 == 0 || i1 == n1 - 1)) wt *= 0.5;
         acc += wt * (-K.L * (hi ? -d1 : d1) / K.dT);
     }
     part[threadIdx.x] = acc;
@@ -456,7 +460,7 @@ __global__ void __launch_bounds__(256) k3_nusselt(const S *__restrict__ src, K3 
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        *out = part[0] / (double(per[b0] ? nn[b0] : nn[b0] - 1) * double(per[b1] ? nn[b1] : nn[b1] - 1));
+        *out = part[0] / (double(p0 ? n0 : n0 - 1) * double(p1 ? n1 : n1 - 1));
 }
 
 struct FieldOut3 { double *p, *u, *T, *S, *gT; };

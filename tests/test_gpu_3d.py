@@ -299,7 +299,7 @@ def test_closed_box_nusselt_numbers_against_oracle(gpu3):
 def test_fp16_against_fp64_oracle(gpu3, case):
     """FP16 storage (deviations scaled by 256, FP32 arithmetic): u and T within 5e-2
     relative L2 of the FP64 oracle after 200 steps, the bound the two-dimensional FP16
-    storage meets on the cavity."""
+    storage meets on the cavity; the wall Nusselt numbers within 1e-2 of the oracle's."""
     import oracle.oracle3 as O3
     if case == "layer":
         cfg = W.layer3d(32, 24, 16, Ra=1e4, Da=1e-2, storage="f16")
@@ -317,6 +317,10 @@ def test_fp16_against_fp64_oracle(gpu3, case):
     rel = {"u": du / nu, "T": np.linalg.norm(a["T"] - b["T"]) / np.linalg.norm(b["T"])}
     _say(f"  rel L2: u {rel['u']:.2e}, T {rel['T']:.2e}")
     assert rel["u"] < 5e-2 and rel["T"] < 5e-2, rel
+    for w in ((0, 1) if case == "layer" else range(6)):
+        nu_a, nu_b = sim.nusselt(w), ref.nusselt(w)
+        _say(f"  Nusselt number of wall {w}: {nu_a:.6f} (oracle {nu_b:.6f})")
+        assert abs(nu_a - nu_b) < 1e-2 * max(1.0, abs(nu_b))
 
 
 def test_fp16_bench_size_against_oracle(gpu3):
