@@ -575,3 +575,76 @@ double o3_nusselt(const o3_sim *s, int w)
     free(T);
     return acc / cells;
 }
+
+/* ---------------------------------------------------------------------------- */
+/* Single-node building blocks, exposed for the identity pins.  They run the same */
+/* functions as the time step on one node of the problem p (its derived constants */
+/* A, B, nu, K, ...), with the porosity eps given.                                */
+/* ---------------------------------------------------------------------------- */
+static int node_context(const o3_params *p, o3_sim *s)
+{
+    build_lattice();
+    memset(s, 0, sizeof(*s));
+    s->prm = *p;
+    return derive(p, &s->d);
+}
+
+/* Macroscopic state of a node from its pre-collision populations f[19], g[19]:
+ * out = T, G (3), u (3), F (3), p, S (9, row-major), grad T (3): 23 values. */
+int o3_node_macro(const o3_params *p, double eps, const double *f, const double *g, double *out)
+{
+    o3_sim s;
+    int r = node_context(p, &s);
+    o3_macro m;
+    node_macro(&s, eps, f, g, &m);
+    int k = 0;
+    out[k++] = m.T;
+    for (int a = 0; a < 3; ++a) out[k++] = m.G[a];
+    for (int a = 0; a < 3; ++a) out[k++] = m.u[a];
+    for (int a = 0; a < 3; ++a) out[k++] = m.F[a];
+    out[k++] = m.p;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) out[k++] = m.S[a][b];
+    for (int a = 0; a < 3; ++a) out[k++] = m.dT[a];
+    return r;
+}
+
+/* The discrete terms of one node for prescribed macroscopic values (T, u[3], p, S[9]
+ * row-major, grad T[3], F[3]): out rows of 19 values, in order f^{e(0)} (Eq. EQFIN
+ * without the shear-rate term), r_i (the A S term of Eq. EQTSHIN, without rho0),
+ * g^{e(0)} (Eq. TeEDFEQ without the gradient term), the B grad T term of g^eq, F_i
+ * (Eq. FtermF), P_i and Q_i (Eq. Eq:Tforce): 7 x 19 values. */
+int o3_node_terms(const o3_params *p, double eps, double T, const double *u, double pr, const double *S9,
+                  const double *dT, const double *F, double *out)
+{
+    o3_sim s;
+    int r = node_context(p, &s);
+    double S[3][3], full[Q19];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) S[a][b] = S9[3 * a + b];
+    feq0(eps, pr, u, out);
+    feq_full(&s, eps, pr, u, S, full);
+    for (int i = 0; i < Q19; ++i) out[Q19 + i] = (full[i] - out[i]) / RHO0;
+    geq0(&s, eps, T, u, pr, out + 2 * Q19);
+    geq_full(&s, eps, T, u, pr, dT, full);
+    for (int i = 0; i < Q19; ++i) out[3 * Q19 + i] = full[i] - out[2 * Q19 + i];
+    o3_macro m;
+    memset(&m, 0, sizeof(m));
+    m.eps = eps;
+    m.T = T;
+    m.p = pr;
+    for (int a = 0; a < 3; ++a) { m.u[a] = u[a]; m.F[a] = F[a]; m.dT[a] = dT[a]; }
+    sources(&s, &m, out + 4 * Q19, out + 5 * Q19, out + 6 * Q19);
+    return r;
+}
+
+/* Collision of one bulk node: pre-collision f, g -> post-collision fo, go. */
+int o3_node_collide(const o3_params *p, double eps, const double *f, const double *g, double *fo, double *go)
+{
+    o3_sim s;
+    int r = node_context(p, &s);
+    o3_macro m;
+    node_macro(&s, eps, f, g, &m);
+    collide_state(&s, &m, f, g, fo, go);
+    return r;
+}

@@ -91,6 +91,12 @@ def _lib():
     L.o3_lattice.argtypes = [vp, vp]
     L.o3_derive.restype = C.c_int
     L.o3_derive.argtypes = [C.POINTER(_Params), vp]
+    L.o3_node_macro.restype = C.c_int
+    L.o3_node_macro.argtypes = [C.POINTER(_Params), C.c_double, vp, vp, vp]
+    L.o3_node_terms.restype = C.c_int
+    L.o3_node_terms.argtypes = [C.POINTER(_Params), C.c_double, C.c_double, vp, C.c_double, vp, vp, vp, vp]
+    L.o3_node_collide.restype = C.c_int
+    L.o3_node_collide.argtypes = [C.POINTER(_Params), C.c_double, vp, vp, vp, vp]
     _lib_handle = L
     return L
 
@@ -168,3 +174,37 @@ class Oracle3:
 
     def nusselt(self, wall: int = 0) -> float:
         return float(self.lib.o3_nusselt(self.h, int(wall)))
+
+
+def _vec(v, n):
+    a = np.ascontiguousarray(np.asarray(v, np.float64).reshape(n))
+    return a
+
+
+def node_macro(cfg: dict, eps: float, f, g) -> dict:
+    """Macroscopic state of one bulk node from its pre-collision populations f[19], g[19]:
+    T, G (3), u (3), F (3), p, S (3 x 3), grad T (3)."""
+    f, g = _vec(f, 19), _vec(g, 19)
+    out = np.zeros(23)
+    _lib().o3_node_macro(C.byref(params_from_dict(cfg)), float(eps), _ptr(f), _ptr(g), _ptr(out))
+    return {"T": out[0], "G": out[1:4].copy(), "u": out[4:7].copy(), "F": out[7:10].copy(),
+            "p": out[10], "S": out[11:20].reshape(3, 3).copy(), "dT": out[20:23].copy()}
+
+
+def node_terms(cfg: dict, eps, T, u, p, S, dT, F) -> dict:
+    """Discrete terms of one node for prescribed macroscopic values: arrays of 19 for
+    feq0, r, geq0, gB, F, P, Q."""
+    u, S, dT, F = _vec(u, 3), _vec(S, 9), _vec(dT, 3), _vec(F, 3)
+    out = np.zeros(7 * 19)
+    _lib().o3_node_terms(C.byref(params_from_dict(cfg)), float(eps), float(T), _ptr(u), float(p), _ptr(S),
+                         _ptr(dT), _ptr(F), _ptr(out))
+    names = ("feq0", "r", "geq0", "gB", "F", "P", "Q")
+    return {k: out[19 * i:19 * i + 19].copy() for i, k in enumerate(names)}
+
+
+def node_collide(cfg: dict, eps: float, f, g):
+    """Post-collision populations (fo, go) of one bulk node."""
+    f, g = _vec(f, 19), _vec(g, 19)
+    fo, go = np.zeros(19), np.zeros(19)
+    _lib().o3_node_collide(C.byref(params_from_dict(cfg)), float(eps), _ptr(f), _ptr(g), _ptr(fo), _ptr(go))
+    return fo, go

@@ -1,12 +1,15 @@
 """Pins of the 3-D (D3Q19) oracle against what the paper and the mathematics fix: lattice
 isotropy and its projection onto D2Q9, the decay rates nu_e k^2 and alpha_e k^2 that the
-Chapman-Enskog analysis gives (Sec. 3.1, Eq. Therdiff) in a periodic box, the exact
-conduction fixed point between walls (Sec. 3.4 boundary scheme), the Brinkman closed form
-between plates with second-order convergence, and mass conservation."""
+Chapman-Enskog analysis gives (Sec. 3.1, Eq. Therdiff) in a periodic box, a temperature
+wave carried by a uniform stream with eps != sigma != 1 (decay alpha_e k^2 / sigma, speed
+u / sigma), the exact conduction fixed point between walls (Sec. 3.4 boundary scheme),
+the Brinkman closed form and the Brinkman-Forchheimer profile (an independent Newton
+solve) between plates with second-order convergence, and mass conservation.  The
+single-node identities are in test_oracle3_identities.py."""
 import numpy as np
 import pytest
 
-from closed_forms import E, brinkman_profile, order, poiseuille_cfg
+from closed_forms import CS2, E, brinkman_profile, forchheimer_bvp, order, poiseuille_cfg
 import oracle.oracle3 as O3
 
 
@@ -79,6 +82,42 @@ def test_temperature_wave_decay(B):
     assert abs(rate - 1) < 2e-3, rate
 
 
+def _advected_wave(n, B, sigma, eps, U):
+    """Temperature wave along x carried by a uniform stream u = (U, 0, 0) in a periodic
+    box without drag or force: (decay-rate ratio, phase-speed ratio) against
+    alpha_e k^2 / sigma and U / sigma."""
+    x = np.arange(n, dtype=float)
+    k = 2 * np.pi / n
+    u = np.zeros((3, 2, 2, n))
+    u[0] = U
+    T = np.broadcast_to((0.5 + 0.1 * np.sin(k * x))[None, None, :], (2, 2, n)).copy()
+    o = O3.Oracle3(_box(n, 2, 2, 1, tau_T=1.0, B=B, sigma=sigma, eps=eps, T_init=T, u_init=u))
+    alpha = sigma * CS2 * (1.0 - B - 0.5)
+    t1, t2 = int(0.1 / (alpha / sigma * k * k)), int(0.6 / (alpha / sigma * k * k))
+    o.step(t1)
+    c1 = ((o.fields()["T"][0, 0] - 0.5) * np.exp(-1j * k * x)).sum()
+    o.step(t2 - t1)
+    c2 = ((o.fields()["T"][0, 0] - 0.5) * np.exp(-1j * k * x)).sum()
+    rate = np.log(abs(c1) / abs(c2)) / (t2 - t1) / (alpha / sigma * k * k)
+    # the phase speed only where the phase advance is below pi (not ambiguous)
+    speed = -np.angle(c2 / c1) / k / (t2 - t1) / (U / sigma) if k * U / sigma * (t2 - t1) < 0.9 * np.pi else None
+    return rate, speed
+
+
+@pytest.mark.parametrize("sigma,eps,U,B", [(1.5, 0.4, 0.05, 0.35), (1.3, 0.5, 0.02, 0.2)])
+def test_advected_temperature_wave(sigma, eps, U, B):
+    """eps != sigma != 1 with grad T along u: the decay rate depends on the (1/eps - 1/sigma)
+    u u terms of <M> (Eq. MatrM) and of P_i (Eq. Eq:Tforce), which together keep the
+    effective diffusivity at alpha_e (Eq. Therdiff); a sign slip in either moves the rate of
+    the first case by 2 % or more.  Second order in k."""
+    r32, s32 = _advected_wave(32, B, sigma, eps, U)
+    r64, s64 = _advected_wave(64, B, sigma, eps, U)
+    assert abs(r64 - 1) < 2e-3, (r32, r64)
+    assert abs(r64 - 1) < 0.4 * abs(r32 - 1) + 1e-4, (r32, r64)
+    speed = s64 if s64 is not None else s32
+    assert speed is not None and abs(speed - 1) < 2e-3, (s32, s64)
+
+
 @pytest.mark.parametrize("kind", ["dirichlet", "neumann"])
 def test_conduction_fixed_point(kind):
     """A linear temperature between walls is an exact steady state of the scheme with the
@@ -117,6 +156,34 @@ def test_brinkman_between_plates():
         errs.append(E(ua, o.fields()["ux"][:, 1, 1]))
     assert errs[-1] < 5e-3, errs
     assert order(errs[1], errs[2], ns[1], ns[2]) > 1.65, errs
+
+
+def test_forchheimer_between_plates():
+    """Force-driven porous flow between plates with the Ergun F_eps (u != 0 in the quadratic
+    drag of Eq. ForceEq) at a drive about 12 times that of the Re = 1 channel: the profile of
+    an independent Newton solve of nu_e u'' - (eps nu / K) u - (eps F_eps / sqrt K) |u| u
+    + eps a = 0, second order in the plate distance; the quadratic drag changes the profile
+    by more than 1 % against the Brinkman one."""
+    ns = (17, 33)
+    errs = []
+    for nz in ns:
+        cfg2, c = poiseuille_cfg(nz, 0.1, F_eps=None)
+        c["a"] *= 12.0
+        Feps = 1.75 / np.sqrt(150 * c["eps"] ** 3)
+        cfg = _box(3, 3, nz, 0, walls=[{"kind": "T", "T": 0.0}, {"kind": "T", "T": 0.0}],
+                   Da=cfg2["Da"], eps=cfg2["eps"], tau_f=cfg2["tau_f"], tau_T=cfg2["tau_T"],
+                   A=cfg2["A"], B=cfg2["B"], F_eps=None, a=(c["a"], 0.0, 0.0), T_hot=0.0, T_cold=0.0)
+        o = O3.Oracle3(cfg)
+        o.step(int(6 * (nz - 1) ** 2 / c["nu"]))
+        ref, m = forchheimer_bvp(c, Feps)
+        z = np.arange(nz, dtype=float)
+        ua = np.interp(z, np.linspace(0, c["H"], m), ref)
+        un = o.fields()["ux"][:, 1, 1]
+        errs.append(E(ua, un))
+        brink, _ = brinkman_profile(z, c)
+        assert E(brink, ua) > 0.01
+    assert errs[-1] < 5e-3, errs
+    assert order(errs[0], errs[1], ns[0], ns[1]) > 1.65, errs
 
 
 def test_mass_conservation():

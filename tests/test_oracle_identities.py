@@ -217,3 +217,30 @@ def test_collision_conserves_mass_and_balances_energy(oracle_mod, lat, seed):
     assert np.allclose(mom, np.array([m["ux"], m["uy"]]) + 0.5 * np.array([m["Fx"], m["Fy"]]),
                        atol=1e-15)
     assert abs(go.sum() - (cfg["sigma"] * m["T"] + 0.5 * cfg["Q"])) < 1e-15
+
+
+def test_uniformly_accelerating_flow_has_no_shear(oracle_mod):
+    """A porous flow that is uniform in space and accelerates under an oblique body force
+    (Darcy and Forchheimer drag on) has no velocity gradient.  Its non-equilibrium second
+    moment is -(u F + F u) / (2 eps) to leading order, which the forcing term of
+    Eq. ShearEqCom cancels; without it (or with its sign flipped) the recovered S would
+    carry (u F + F u) / eps over cs^2 (tau_f - A), off the diagonal too.  The traceless
+    part of S must stay three orders of magnitude below that size."""
+    cfg = {"nx": 4, "ny": 4, "periodic_x": 1, "periodic_y": 1, "walls": [{}] * 4,
+           "tau_f": 0.9, "tau_T": 0.8, "A": 0.2, "B": 0.1, "sigma": 1.3, "Q": 0.0,
+           "Da": 1e-2, "Ra": 0.0, "Pr": 1.0, "J": 1.0, "eps": 0.5, "ax": 3e-4, "ay": -2e-4,
+           "T_hot": 1.0, "T_cold": 0.0, "F_eps": None, "L": 16}
+    o = oracle_mod.Oracle(cfg)
+    for t in (10, 60):
+        o.step(t - o.time)
+        f = o.fields()
+        u = np.array([f["ux"][0, 0], f["uy"][0, 0]])
+        o.step(1)
+        f1 = o.fields()
+        dudt = np.array([f1["ux"][0, 0], f1["uy"][0, 0]]) - u
+        half_diff = 0.5 * (f1["Sxx"] - f1["Syy"])
+        dev = max(np.abs(f1["Sxy"]).max(), np.abs(half_diff).max())
+        scale = 2 * np.linalg.norm(u) * np.linalg.norm(dudt) / cfg["eps"] / (CS2 * (cfg["tau_f"] - cfg["A"]))
+        assert scale > 1e-6
+        assert dev < 1e-3 * scale, (t, dev, scale)
+        assert np.abs(f1["ux"] - f1["ux"].mean()).max() < 1e-16
