@@ -232,19 +232,21 @@ lbm_ctx *lbm_batch_problem(lbm_batch *batch, int32_t k);
  * is NaN or infinite).  Synchronizes. */
 lbm_status lbm_batch_check(lbm_batch *batch, int32_t *nonfinite_host);
 
-/* Block-width autotuner of the batched one-step update (with two steps per pass it serves
- * the single steps only).  Times each candidate width (threads per
- * block along x: 64, 128, 256, in that order) over `steps` steps and keeps the fastest for
- * later lbm_batch_step calls.  The problems' states are unchanged (the timed launches read
- * the current populations and overwrite only the buffers the next step writes anyway) and
- * the results of later steps do not depend on the width.  *width (optional) receives the
- * chosen width; ms_per_step (optional, host, LBM_BATCH_NUM_WIDTHS entries) the timings.
- * Synchronizes. */
+/* Block-width autotuner of the batched launches that run under the current steps per pass:
+ * with two steps per pass, the threads per block of the two-step main launch (64, 128 or
+ * 256, i.e. 1, 2 or 4 independent wavefronts per block); with one step per pass, the block
+ * width along x of the one-step update (64, 128, 256).  Times each candidate, in that
+ * order, over `steps` steps and keeps the fastest for later lbm_batch_step calls.  The
+ * problems' states are unchanged (the timed launches read the current populations and
+ * overwrite only the buffers the next step writes anyway) and the results of later steps
+ * do not depend on the width.  *width (optional) receives the chosen width; ms_per_step
+ * (optional, host, LBM_BATCH_NUM_WIDTHS entries) the timings.  Synchronizes. */
 #define LBM_BATCH_NUM_WIDTHS 3
 lbm_status lbm_batch_autotune(lbm_batch *batch, int32_t steps, int32_t *width, double *ms_per_step);
 
-/* Sets the block width of the batched update without timing (64 after lbm_batch_init);
- * LBM_ERR_INVALID for any other value than 64, 128, 256.  Synchronizes. */
+/* Sets, without timing, the width the autotuner would choose for the current steps per
+ * pass (256 for the two-step main launch, 64 for the one-step update after
+ * lbm_batch_init); LBM_ERR_INVALID for any other value than 64, 128, 256.  Synchronizes. */
 lbm_status lbm_batch_set_width(lbm_batch *batch, int32_t width);
 
 /* Releases the batch and its contexts (host memory only). */

@@ -28,6 +28,33 @@ __device__ constexpr int CY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 
 __device__ constexpr int CZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 __host__ __device__ constexpr double W(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
+// Per-launch constants in the arithmetic type R, computed once on the host (no division or
+// conversion of launch constants is left to the node code).
+template <typename R> struct C3 {
+    R itf, itT, of, og;            // 1 / tau, 1 - 1 / tau
+    R fF, fT;                      // 1 - 1 / (2 tau)
+    R tfh;                         // tau_f - 1/2
+    R sig, isig, Q, halfQ, T0, gb;
+    R a[3];
+    R Sden;                        // 1 / (cs^2 (A - tau_f))
+    R aM0;                         // cs^2 sigma (B - tau_T)
+    R sigB3;                       // sigma B / 3 (the gradient term of g^eq per 3 omega)
+    R A, A15;                      // A, 1.5 A
+    R eps, ieps, dlin, dquad, bM;  // the uniform porosity's coefficients
+};
+
+// 1 / tau and 1 - 1 / tau in R with it + o == 1 exactly (o = fl(1 - fl(1 / tau)),
+// it = fl(1 - o); for tau > 1/2 one of the two subtractions is exact by Sterbenz's lemma,
+// and then so is the other): the collision's o f + it (...) then carries the state's zeroth
+// moment with the factor 1, where a rounded pair would scale the temperature deviation by
+// up to 1 + 6e-8 per FP32 step.
+template <typename R> inline void relax_pair(double tau, R &it, R &o)
+{
+    const R i0 = R(1.0 / tau);
+    o = R(1) - i0;
+    it = R(1) - o;
+}
+
 // Launch constants (host-computed, passed by value).
 struct K3 {
     int nx, ny, nz, px, py, pz;
@@ -42,7 +69,33 @@ struct K3 {
     // walls: 0 z = 0, 1 z = nz - 1, 2 x = 0, 3 x = nx - 1, 4 y = 0, 5 y = ny - 1
     int wkind[6];
     double wu[6][3], wT[6], wdTdn[6];
+    C3<double> cd;
+    C3<float> cf;
 };
+
+template <typename R> __device__ __forceinline__ const C3<R> &cst3(const K3 &K);
+template <> __device__ __forceinline__ const C3<double> &cst3<double>(const K3 &K) { return K.cd; }
+template <> __device__ __forceinline__ const C3<float> &cst3<float>(const K3 &K) { return K.cf; }
+
+// FP64 reciprocal and square root for the drag solve of the FP32 and FP16 paths, whose
+// results are rounded to FP32: the hardware estimates refined by Newton steps (relative
+// error below 1e-13).  The FP64 path keeps IEEE division and square root.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double sqrt_nr(double x)
+{
+    const double r = __builtin_amdgcn_rsq(x);
+    const double s = x * r;
+    return x > 0.0 ? fma(fma(-s, s, x), 0.5 * r, s) : 0.0;
+}
+template <typename R> __device__ __forceinline__ double drag_rcp(double x) { return rcp_nr(x); }
+template <> __device__ __forceinline__ double drag_rcp<double>(double x) { return 1.0 / x; }
+template <typename R> __device__ __forceinline__ double drag_sqrt(double x) { return sqrt_nr(x); }
+template <> __device__ __forceinline__ double drag_sqrt<double>(double x) { return sqrt(x); }
 
 // The walls node (x, y, z) lies on: zw in {-1, 0, 1}, xw in {-1, 2, 3}, yw in {-1, 4, 5}.
 __device__ __forceinline__ void wall_of(const K3 &K, int x, int y, int z, int &xw, int &yw, int &zw)
@@ -54,26 +107,32 @@ __device__ __forceinline__ void wall_of(const K3 &K, int x, int y, int z, int &x
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// Porosity-dependent coefficients of one node (Sec. 2, Eq. ForceEq; Sec. 3.1 drag solve).
-struct Por {
-    double eps, ieps, c0, c1, dlin, dquad;
+// Porosity-dependent coefficients of one node (Sec. 2, Eq. ForceEq; Sec. 3.1 drag solve; b of
+// Eq. MatrM), in R; c0 and c1 of the drag solve in FP64.
+template <typename R> struct Por {
+    R eps, ieps, dlin, dquad, bM;
+    double c0, c1;
 };
 
-__device__ __forceinline__ Por por_of(const K3 &K, size_t k)
+template <typename R> __device__ __forceinline__ Por<R> por_of(const K3 &K, size_t k)
 {
-    Por e;
+    Por<R> e;
     if (!K.eps_field) {
-        e.eps = K.eps; e.c0 = K.c0; e.c1 = K.c1; e.dlin = K.dlin; e.dquad = K.dquad;
+        const C3<R> &c = cst3<R>(K);
+        e.eps = c.eps; e.ieps = c.ieps; e.dlin = c.dlin; e.dquad = c.dquad; e.bM = c.bM;
+        e.c0 = K.c0; e.c1 = K.c1;
     } else {
         const double eps = K.eps_field[k];
         const double Feps = K.ergun ? 1.75 / sqrt(150.0 * eps * eps * eps) : K.Feps;
-        e.eps = eps;
+        const double ie = 1.0 / eps;
+        e.eps = R(eps);
+        e.ieps = R(ie);
         e.c0 = 0.5 * (1.0 + eps * 0.5 * K.nuK);
         e.c1 = eps * 0.5 * Feps * K.isqK;
-        e.dlin = eps * K.nuK;
-        e.dquad = eps * Feps * K.isqK;
+        e.dlin = R(eps * K.nuK);
+        e.dquad = R(eps * Feps * K.isqK);
+        e.bM = R(0.5 * (ie - 1.0 / K.sigma));
     }
-    e.ieps = 1.0 / e.eps;
     return e;
 }
 
@@ -106,139 +165,242 @@ template <> struct St3<__half> {
     }
 };
 
-// Pre-collision populations of node (x, y, z) pulled from the post-collision buffer: f in
-// deviation form, g with the rest state omega_i sigma T0 added back.
+// Pre-collision populations of node (x, y, z) pulled from the post-collision buffer, in the
+// deviation form they are stored in (f_0 - rho0, g_q - omega_q sigma T0).  The source node of
+// direction q is (x - c_q) with periodic wrap (a walled direction never leaves the grid:
+// only nodes off its walls are pulled).  Offsets within a plane of populations are 32-bit
+// (the host keeps a plane below 2^31 nodes), so each load adds one offset to the plane's
+// base address.
 template <typename S, typename R>
 __device__ __forceinline__ void pull(const S *__restrict__ src, const K3 &K, int x, int y, int z, R *f, R *g)
 {
-    const double gT0 = K.sigma * K.T0;
+    // source column, row and plane offsets for c = 0, +1 (from x - 1) and -1 (from x + 1)
+    const unsigned nx = (unsigned)K.nx, pl = (unsigned)K.nx * (unsigned)K.ny;
+    const unsigned xo[3] = {(unsigned)x, (unsigned)wrap(x - 1, K.nx), (unsigned)wrap(x + 1, K.nx)};
+    const unsigned yo[3] = {(unsigned)y * nx, (unsigned)wrap(y - 1, K.ny) * nx, (unsigned)wrap(y + 1, K.ny) * nx};
+    const unsigned zo[3] = {(unsigned)z * pl, (unsigned)wrap(z - 1, K.nz) * pl, (unsigned)wrap(z + 1, K.nz) * pl};
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int xs = wrap(x - CX[q], K.nx), ys = wrap(y - CY[q], K.ny);
-        const int zs = K.pz ? wrap(z - CZ[q], K.nz) : z - CZ[q];
-        const size_t k = ((size_t)zs * K.ny + ys) * K.nx + xs;
+        const int ix = CX[q] == 0 ? 0 : (CX[q] > 0 ? 1 : 2);
+        const int iy = CY[q] == 0 ? 0 : (CY[q] > 0 ? 1 : 2);
+        const int iz = CZ[q] == 0 ? 0 : (CZ[q] > 0 ? 1 : 2);
+        const unsigned k = zo[iz] + yo[iy] + xo[ix];
         f[q] = St3<S>::template ld<R>(src + (size_t)q * K.n + k);
-        g[q] = St3<S>::template ld<R>(src + (size_t)(NQ + q) * K.n + k) + R(W(q) * gT0);
+        g[q] = St3<S>::template ld<R>(src + (size_t)(NQ + q) * K.n + k);
     }
 }
 
-// G and F (Eq. ForceEq) at velocity u and temperature T.
+// G and F (Eq. ForceEq) at velocity u and temperature T = T0 + Td.
 template <typename R>
-__device__ __forceinline__ void force(const K3 &K, const Por &e, const R *u, R T, R *F)
+__device__ __forceinline__ void force(const K3 &K, const Por<R> &e, const R *u, R Td, R *F)
 {
+    const C3<R> &c = cst3<R>(K);
     const R um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    const R dl = R(e.dlin) + R(e.dquad) * um, eps = R(e.eps);
-    F[0] = eps * R(K.a[0]) - dl * u[0];
-    F[1] = eps * R(K.a[1]) - dl * u[1];
-    F[2] = eps * (R(K.a[2]) + R(K.gbeta) * (T - R(K.T0))) - dl * u[2];
+    const R dl = e.dlin + e.dquad * um;
+    F[0] = e.eps * c.a[0] - dl * u[0];
+    F[1] = e.eps * c.a[1] - dl * u[1];
+    F[2] = e.eps * (c.a[2] + c.gb * Td) - dl * u[2];
 }
 
-// Macroscopic state; S as xx, xy, xz, yy, yz, zz.
+// Macroscopic state; Td = T - T0; S as xx, xy, xz, yy, yz, zz.
 template <typename R> struct Mac {
-    R T, u[3], F[3], p, S[6], gT[3];
+    R Td, T, u[3], F[3], p, S[6], gT[3];
 };
+
+// Contractions with the lattice velocities over their nonzero components only.  D3Q19 has
+// no velocity component other than 0 and +-1, and q is a compile-time constant once the
+// loops over directions are unrolled, so the selections fold away and no multiplication by
+// 0 or 1 is left (which IEEE arithmetic would otherwise have to carry out).
+// c_q . v
+template <typename R> __device__ __forceinline__ R cdot(int q, const R *v)
+{
+    const int c[3] = {CX[q], CY[q], CZ[q]};
+    R r = R(0);
+    bool any = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (c[a] == 0) continue;
+        const R t = c[a] > 0 ? v[a] : -v[a];
+        r = any ? r + t : t;
+        any = true;
+    }
+    return r;
+}
+// c_q . S . c_q for the symmetric S stored as xx, xy, xz, yy, yz, zz
+template <typename R> __device__ __forceinline__ R cScq(int q, const R *S)
+{
+    const int c[3] = {CX[q], CY[q], CZ[q]};
+    constexpr int ix[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    R r = R(0);
+    bool any = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (c[a] == 0) continue;
+        r = any ? r + S[ix[a][a]] : S[ix[a][a]];
+        any = true;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a + 1; b < 3; ++b) {
+            if (c[a] == 0 || c[b] == 0) continue;
+            const R t = R(2) * S[ix[a][b]];
+            r = c[a] * c[b] > 0 ? r + t : r - t;
+        }
+    return r;
+}
+// acc += c_q,a v (the a-th component of c_q v), only where c_q,a is not zero
+template <typename R> __device__ __forceinline__ void cacc(int cq, R &acc, R v)
+{
+    if (cq > 0) acc += v;
+    else if (cq < 0) acc -= v;
+}
 
 // State of an interior node from its populations: T (Sec. 3.2), v and u (drag solve in
 // FP64, Sec. 3.1), F, p (Sec. 3.1 with omega_0 = 1/3 in the closed forms of App. A), S from
 // the non-equilibrium second moment (Eq. ShearEqCom; the D3Q19 equilibrium's second moment
 // is eps p I + u u / eps), grad T = <M>^-1 <N> by the Sherman-Morrison form of
-// <M> = a I - b u u.
+// <M> = a I - b u u.  Directions come in opposite pairs (q, q + 1), q odd: the first
+// moments take the pair's difference, the second moments its sum.
 template <typename R>
-__device__ __forceinline__ void macro3(const R *f, const R *g, const K3 &K, const Por &e, Mac<R> &m)
+__device__ __forceinline__ void macro3(const R *f, const R *g, const K3 &K, const Por<R> &e, Mac<R> &m)
 {
-    R sg = R(0), s18 = R(0), j[3] = {R(0), R(0), R(0)}, P[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    R sg = g[0], s18 = R(0), j[3] = {R(0), R(0), R(0)}, P[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     R h[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const R cx = R(CX[q]), cy = R(CY[q]), cz = R(CZ[q]);
-        sg += g[q];
-        if (q) s18 += f[q];
-        j[0] += cx * f[q]; j[1] += cy * f[q]; j[2] += cz * f[q];
-        P[0] += cx * cx * f[q]; P[1] += cx * cy * f[q]; P[2] += cx * cz * f[q];
-        P[3] += cy * cy * f[q]; P[4] += cy * cz * f[q]; P[5] += cz * cz * f[q];
-        h[0] += cx * g[q]; h[1] += cy * g[q]; h[2] += cz * g[q];
+    for (int q = 1; q < NQ; q += 2) {
+        const R sf = f[q] + f[q + 1], df = f[q] - f[q + 1];
+        const R dg = g[q] - g[q + 1];
+        sg += g[q] + g[q + 1];
+        s18 += sf;
+        cacc(CX[q], j[0], df); cacc(CY[q], j[1], df); cacc(CZ[q], j[2], df);
+        cacc(CX[q], h[0], dg); cacc(CY[q], h[1], dg); cacc(CZ[q], h[2], dg);
+        cacc(CX[q] * CX[q], P[0], sf); cacc(CX[q] * CY[q], P[1], sf); cacc(CX[q] * CZ[q], P[2], sf);
+        cacc(CY[q] * CY[q], P[3], sf); cacc(CY[q] * CZ[q], P[4], sf); cacc(CZ[q] * CZ[q], P[5], sf);
     }
-    const R eps = R(e.eps), ieps = R(e.ieps), isig = R(1.0 / K.sigma), Q = R(K.Q);
-    m.T = (sg + R(0.5) * Q) * isig;
-    const R G[3] = {R(K.a[0]), R(K.a[1]), R(K.a[2]) + R(K.gbeta) * (m.T - R(K.T0))};
+    const C3<R> &c = cst3<R>(K);
+    const R eps = e.eps, ieps = e.ieps, isig = c.isig, Q = c.Q;
+    m.Td = (sg + c.halfQ) * isig;      // sigma T = sum g + Q/2, the rest state sigma T0 taken out
+    m.T = c.T0 + m.Td;
+    const R G[3] = {c.a[0], c.a[1], c.a[2] + c.gb * m.Td};
     double v[3];
     for (int a = 0; a < 3; ++a) v[a] = double(j[a] + R(0.5) * eps * G[a]);
-    const double vm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    const double iden = 1.0 / (e.c0 + sqrt(e.c0 * e.c0 + e.c1 * vm));
+    const double vm = drag_sqrt<R>(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const double iden = drag_rcp<R>(e.c0 + drag_sqrt<R>(e.c0 * e.c0 + e.c1 * vm));
     for (int a = 0; a < 3; ++a) m.u[a] = R(v[a] * iden);
-    force<R>(K, e, m.u, m.T, m.F);
+    force<R>(K, e, m.u, m.Td, m.F);
     const R uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
     const R uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
     // rho0 s_0 = -omega_0 |u|^2 / (2 eps cs^2) = -|u|^2 / (2 eps); tau_f F_0 = -tau_f (1 - 1/(2 tau_f)) u.F / eps
-    const R s0 = R(-0.5) * uu * ieps, tF0 = -R(K.tau_f - 0.5) * uF * ieps;
+    const R s0 = R(-0.5) * uu * ieps, tF0 = -c.tfh * uF * ieps;
     m.p = R(0.5) * ieps * (s18 + tF0 + s0);            // cs^2 / (eps (1 - omega_0)) = 1 / (2 eps)
     const R ep = eps * m.p;
     const int ia[6] = {0, 0, 0, 1, 1, 2}, ib[6] = {0, 1, 2, 1, 2, 2};
-    const R Sden = R(3.0 / (K.A - K.tau_f));
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const R neq = P[c] - (ia[c] == ib[c] ? ep : R(0)) - m.u[ia[c]] * m.u[ib[c]] * ieps;
-        m.S[c] = (neq + R(0.5) * (m.u[ia[c]] * m.F[ib[c]] + m.F[ia[c]] * m.u[ib[c]]) * ieps) * Sden;
+    for (int t = 0; t < 6; ++t) {
+        const R neq = P[t] - (ia[t] == ib[t] ? ep : R(0)) - m.u[ia[t]] * m.u[ib[t]] * ieps;
+        m.S[t] = (neq + R(0.5) * (m.u[ia[t]] * m.F[ib[t]] + m.F[ia[t]] * m.u[ib[t]]) * ieps) * c.Sden;
     }
     R N[3];
     for (int a = 0; a < 3; ++a) N[a] = h[a] - m.T * m.u[a] + R(0.5) * (m.T * m.F[a] + m.u[a] * Q * isig);
-    const R am = R(K.sigma * (K.B - K.tau_T) / 3.0) - R(0.5) * ep;
-    const R bm = R(0.5 * (e.ieps - 1.0 / K.sigma));
+    const R am = c.aM0 - R(0.5) * ep;
+    const R bm = e.bM;
     const R uN = m.u[0] * N[0] + m.u[1] * N[1] + m.u[2] * N[2];
-    const R c = bm * uN / (am - bm * uu);
-    for (int a = 0; a < 3; ++a) m.gT[a] = (N[a] + c * m.u[a]) / am;
+    const R sm = bm * uN / (am - bm * uu);
+    const R iam = R(1) / am;
+    for (int a = 0; a < 3; ++a) m.gT[a] = (N[a] + sm * m.u[a]) * iam;
 }
+
+// 3 omega_q for an axis and an edge direction with 2 w3a + 8 w3e = 1 exactly in R: the
+// first moment of every term 3 omega_q (c_q . v) is then exactly v in the arithmetic
+// itself (sum over the lattice of omega c c = cs^2 I), not only up to the rounding of the
+// weights, which would scale the momentum and the heat flux by a fixed factor every step.
+template <typename R> __device__ __forceinline__ R w3e() { return R(1.0 / 12.0); }
+template <typename R> __device__ __forceinline__ R w3a() { return (R(1) - R(8) * w3e<R>()) * R(0.5); }
+template <typename R> __device__ __forceinline__ R w3(int q) { return q < 7 ? w3a<R>() : w3e<R>(); }
 
 // Equilibria (Eqs. EQFIN, EQTSHIN, TeEDFEQ) of direction q for pressure term ep = eps p;
-// the flow equilibrium as a deviation (f_0^eq - rho0 for q = 0).
+// the flow equilibrium as a deviation (f_0^eq - rho0 for q = 0).  Used by the boundary
+// scheme and the initialisation; the collision below evaluates the same terms pairwise.
 template <typename R>
-__device__ __forceinline__ R feq(int q, const K3 &K, const Por &e, R ep, const R *u, const R *S)
+__device__ __forceinline__ R feq(int q, const K3 &K, const Por<R> &e, R ep, const R *u, const R *S)
 {
-    const R cx = R(CX[q]), cy = R(CY[q]), cz = R(CZ[q]), w = R(W(q));
-    const R cu = cx * u[0] + cy * u[1] + cz * u[2];
+    const R w = R(W(q));
+    const R cu = cdot<R>(q, u);
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const R cSc = cx * cx * S[0] + R(2) * cx * cy * S[1] + R(2) * cx * cz * S[2] + cy * cy * S[3]
-                + R(2) * cy * cz * S[4] + cz * cz * S[5];
+    const R cSc = cScq<R>(q, S);
     const R trS = S[0] + S[3] + S[5];
     const R base = q == 0 ? R(-2) * ep : R(3) * w * ep;      // -(1 - omega_0) eps p / cs^2; omega_q eps p / cs^2
-    return base + w * (R(3) * cu + R(4.5) * (cu * cu - uu * R(1.0 / 3.0)) * R(e.ieps))
-         + w * R(1.5 * K.A) * (cSc - trS * R(1.0 / 3.0));
+    return base + (q == 0 ? R(0) : w3<R>(q) * cu) + w * R(4.5) * (cu * cu - uu * R(1.0 / 3.0)) * e.ieps
+         + w * cst3<R>(K).A15 * (cSc - trS * R(1.0 / 3.0));
 }
 
+// The temperature equilibrium as a deviation, g^eq_q - omega_q sigma T0, for T = T0 + Td.
 template <typename R>
-__device__ __forceinline__ R geq(int q, const K3 &K, const Por &e, R T, R ep, const R *u, const R *gT)
+__device__ __forceinline__ R geq(int q, const K3 &K, const Por<R> &e, R Td, R T, R ep, const R *u, const R *gT)
 {
-    const R cx = R(CX[q]), cy = R(CY[q]), cz = R(CZ[q]), w = R(W(q));
-    const R cu = cx * u[0] + cy * u[1] + cz * u[2];
+    const R w = R(W(q));
+    const R cu = cdot<R>(q, u);
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const R cg = cx * gT[0] + cy * gT[1] + cz * gT[2];
+    const R cg = cdot<R>(q, gT);
     const R pres = q == 0 ? R(-2) * T * ep : R(3) * w * T * ep;   // varpi_q T eps p / (cs^2 rho0)
-    return w * T * (R(K.sigma) + R(3) * cu + R(4.5) * (cu * cu - uu * R(1.0 / 3.0)) * R(e.ieps)) + pres
-         + R(K.sigma * K.B) * w * cg;
+    return w * (cst3<R>(K).sig * Td + T * R(4.5) * (cu * cu - uu * R(1.0 / 3.0)) * e.ieps) + pres
+         + (q == 0 ? R(0) : w3<R>(q) * (T * cu + cst3<R>(K).sigB3 * cg));
 }
 
-// BGK collision with forcing and sources (Eqs. LBEeq, FtermF, TEqColli, Eq:Tforce).
+// BGK collision with forcing and sources (Eqs. LBEeq, FtermF, TEqColli, Eq:Tforce),
+//   f* = f - (f - f^eq) / tau_f + F_q,   g* = g - (g - g^eq) / tau_T + P_q + Q_q.
+// Opposite directions (q, q + 1) are updated together from the parts of every term that are
+// even and odd in c (as in two dimensions):
+//   f*_q = (1 - 1/tau_f) f_q + Ae + Ao,   f*_q+1 = (1 - 1/tau_f) f_q+1 + Ae - Ao,
+// Ae = omega [(b0 + 4.5 (c.u)^2 / eps + 1.5 A c.S.c) / tau_f + fF (9 (c.u)(c.F) - 3 u.F) / eps],
+// Ao = 3 omega [(c.u) / tau_f + fF c.F], and for the temperature
+// Ge = omega [(b1 + 4.5 T (c.u)^2 / eps) / tau_T + fT Q] (b1 with sigma (T - T0): the
+// populations are deviations from omega sigma T0),
+// Go = 3 omega [s (c.u) + sigma B c.grad T / (3 tau_T) + fT c.(T F + eps p grad T / rho0)].
+// The rest direction takes what the other 18 leave of the zeroth moments the moment lists
+// fix (App. A; Sec. 3.2): sum_q (f^eq_q / tau_f + F_q) = rho0 / tau_f and
+// sum_q (g^eq_q / tau_T + P_q + Q_q) = sigma T / tau_T + (1 - 1/(2 tau_T)) Q, i.e. 0 and
+// sigma (T - T0) / tau_T + (1 - 1/(2 tau_T)) Q for the deviations, so that mass and thermal
+// energy are conserved by the arithmetic, not only up to the rounding of the lattice
+// weights (in FP32 that rounding biases the heat balance by about 1e-8 sigma T / tau_T per
+// step).
 template <typename R>
-__device__ __forceinline__ void collide(R *f, R *g, const Mac<R> &m, const K3 &K, const Por &e)
+__device__ __forceinline__ void collide(R *f, R *g, const Mac<R> &m, const K3 &K, const Por<R> &e)
 {
-    const R ep = R(e.eps) * m.p, ieps = R(e.ieps), isig = R(1.0 / K.sigma);
-    const R fF = R(1.0 - 0.5 / K.tau_f), fT = R(1.0 - 0.5 / K.tau_T);
-    const R itf = R(1.0 / K.tau_f), itT = R(1.0 / K.tau_T), Q = R(K.Q);
+    const C3<R> &c = cst3<R>(K);
+    const R ep = e.eps * m.p, ieps = e.ieps;
+    const R uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
     const R uF = m.u[0] * m.F[0] + m.u[1] * m.F[1] + m.u[2] * m.F[2];
     const R ugT = m.u[0] * m.gT[0] + m.u[1] * m.gT[1] + m.u[2] * m.gT[2];
+    const R trS = m.S[0] + m.S[3] + m.S[5];
     const R V[3] = {m.T * m.F[0] + ep * m.gT[0], m.T * m.F[1] + ep * m.gT[1], m.T * m.F[2] + ep * m.gT[2]};
+    // per-node coefficients
+    const R b0 = R(3) * ep - R(1.5) * uu * ieps - R(0.5) * c.A * trS;
+    const R k45 = R(4.5) * ieps, c9 = R(9) * c.fF * ieps, m3b5 = R(-3) * (c.fF * uF * ieps);
+    const R b1 = c.sig * m.Td - R(1.5) * m.T * uu * ieps + R(3) * m.T * ep;
+    const R T45 = k45 * m.T;
+    const R sc = c.itT * m.T + c.fT * ((ieps - c.isig) * ugT + c.Q * c.isig);
+    const R bsg = c.itT * c.sigB3;
+    R Ef = R(0), Eg = R(0);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const R cx = R(CX[q]), cy = R(CY[q]), cz = R(CZ[q]), w = R(W(q));
-        const R cu = cx * m.u[0] + cy * m.u[1] + cz * m.u[2];
-        const R cF = cx * m.F[0] + cy * m.F[1] + cz * m.F[2];
-        const R cV = cx * V[0] + cy * V[1] + cz * V[2];
-        const R Fi = w * fF * (R(3) * cF + R(4.5) * ieps * (R(2) * cu * cF - R(2.0 / 3.0) * uF));
-        const R Pi = w * fT * (R(3) * cV + R(3) * (ieps - isig) * cu * ugT);
-        const R Qi = w * fT * (R(1) + R(3) * cu * isig) * Q;
-        f[q] += (feq<R>(q, K, e, ep, m.u, m.S) - f[q]) * itf + Fi;
-        g[q] += (geq<R>(q, K, e, m.T, ep, m.u, m.gT) - g[q]) * itT + Pi + Qi;
+    for (int q = 1; q < NQ; q += 2) {
+        const R w = R(W(q)), w3q = w3<R>(q);
+        const R cu = cdot<R>(q, m.u), cF = cdot<R>(q, m.F), cV = cdot<R>(q, V), cg = cdot<R>(q, m.gT);
+        const R cSc = cScq<R>(q, m.S), cu2 = cu * cu;
+        const R Ae = w * (c.itf * (c.A15 * cSc + (k45 * cu2 + b0)) + (c9 * (cu * cF) + m3b5));
+        const R Ao = w3q * (c.itf * cu + c.fF * cF);
+        const R Ge = w * (c.itT * (T45 * cu2 + b1) + c.fT * c.Q);
+        const R Go = w3q * (sc * cu + (bsg * cg + c.fT * cV));
+        f[q] = c.of * f[q] + (Ae + Ao);
+        f[q + 1] = c.of * f[q + 1] + (Ae - Ao);
+        g[q] = c.og * g[q] + (Ge + Go);
+        g[q + 1] = c.og * g[q + 1] + (Ge - Go);
+        Ef += Ae;
+        Eg += Ge;
     }
+    f[0] = c.of * f[0] - R(2) * Ef;
+    g[0] = c.og * g[0] + (c.sig * m.Td * c.itT + c.fT * c.Q - R(2) * Eg);
 }
 
 // Pre-collision populations and state of node (x, y, z).  Interior: pulled populations
@@ -251,10 +413,10 @@ __device__ __forceinline__ void collide(R *f, R *g, const Mac<R> &m, const K3 &K
 // grad T, as at the corners in two dimensions.
 template <typename S, typename R, bool WALLS = true>
 __device__ __forceinline__ void node_state(const S *__restrict__ src, const K3 &K, int x, int y, int z,
-                                           R *f, R *g, Mac<R> &m, Por &e)
+                                           R *f, R *g, Mac<R> &m, Por<R> &e)
 {
     const size_t plane = (size_t)K.nx * K.ny, k = (size_t)z * plane + (size_t)y * K.nx + x;
-    e = por_of(K, k);
+    e = por_of<R>(K, k);
     int xw = -1, yw = -1, zw = -1;
     if (WALLS) wall_of(K, x, y, z, xw, yw, zw);
     if (xw < 0 && yw < 0 && zw < 0) {
@@ -266,38 +428,39 @@ __device__ __forceinline__ void node_state(const S *__restrict__ src, const K3 &
     const int dy = yw == 4 ? 1 : (yw == 5 ? -1 : 0);
     R ff[NQ], gf[NQ];
     pull<S, R>(src, K, x + dx, y + dy, z + dz, ff, gf);
-    const Por ef = por_of(K, (size_t)((long long)k + dz * (long long)plane + dy * (long long)K.nx + dx));
+    const Por<R> ef = por_of<R>(K, (size_t)((long long)k + dz * (long long)plane + dy * (long long)K.nx + dx));
     Mac<R> mf;
     macro3<R>(ff, gf, K, ef, mf);
-    R Tb, gb[3] = {mf.gT[0], mf.gT[1], mf.gT[2]};
+    R Tdb, gb[3] = {mf.gT[0], mf.gT[1], mf.gT[2]};
     const int iso = (xw >= 0 && K.wkind[xw] == 0) ? xw
                   : ((yw >= 0 && K.wkind[yw] == 0) ? yw : ((zw >= 0 && K.wkind[zw] == 0) ? zw : -1));
     if (iso >= 0) {
-        Tb = R(K.wT[iso]);
+        Tdb = R(K.wT[iso] - K.T0);
     } else {
         R f2[NQ], g2[NQ];
         pull<S, R>(src, K, x + 2 * dx, y + 2 * dy, z + 2 * dz, f2, g2);
         R sg = R(0);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) sg += g2[q];
-        const R Tff = (sg + R(0.5 * K.Q)) * R(1.0 / K.sigma);
+        const R Tdff = (sg + cst3<R>(K).halfQ) * cst3<R>(K).isig;
         if (xw >= 0) gb[0] = R(dx * K.wdTdn[xw]);
         if (yw >= 0) gb[1] = R(dy * K.wdTdn[yw]);
         if (zw >= 0) gb[2] = R(dz * K.wdTdn[zw]);
-        Tb = (R(4) * mf.T - Tff - R(2) * (R(dx) * gb[0] + R(dy) * gb[1] + R(dz) * gb[2])) * R(1.0 / 3.0);
+        Tdb = (R(4) * mf.Td - Tdff - R(2) * (R(dx) * gb[0] + R(dy) * gb[1] + R(dz) * gb[2])) * R(1.0 / 3.0);
     }
-    m.T = Tb;
+    m.Td = Tdb;
+    m.T = cst3<R>(K).T0 + Tdb;
     const int nwall = (xw >= 0) + (yw >= 0) + (zw >= 0);
     const int wu = nwall > 1 ? -1 : (xw >= 0 ? xw : (yw >= 0 ? yw : zw));   // an edge or a vertex is at rest
     for (int a = 0; a < 3; ++a) { m.u[a] = wu < 0 ? R(0) : R(K.wu[wu][a]); m.gT[a] = gb[a]; }
-    force<R>(K, e, m.u, m.T, m.F);
+    force<R>(K, e, m.u, m.Td, m.F);
     m.p = mf.p;
     for (int c = 0; c < 6; ++c) m.S[c] = mf.S[c];
-    const R epb = R(e.eps) * mf.p, epf = R(ef.eps) * mf.p;   // the wall node's porosity, x_f's pressure
+    const R epb = e.eps * mf.p, epf = ef.eps * mf.p;   // the wall node's porosity, x_f's pressure
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         f[q] = feq<R>(q, K, e, epb, m.u, mf.S) + (ff[q] - feq<R>(q, K, ef, epf, mf.u, mf.S));
-        g[q] = geq<R>(q, K, e, Tb, epb, m.u, gb) + (gf[q] - geq<R>(q, K, ef, mf.T, epf, mf.u, mf.gT));
+        g[q] = geq<R>(q, K, e, m.Td, m.T, epb, m.u, gb) + (gf[q] - geq<R>(q, K, ef, mf.Td, mf.T, epf, mf.u, mf.gT));
     }
 }
 
@@ -311,15 +474,14 @@ __device__ __forceinline__ bool node_xyz(const K3 &K, int &x, int &y, int &z)
     return true;
 }
 
-// Post-collision populations into the buffer: f as deviations already, g less its rest state.
+// Post-collision populations (deviations) into the buffer.
 template <typename S, typename R>
-__device__ __forceinline__ void store(S *__restrict__ dst, const K3 &K, size_t k, const R *f, const R *g)
+__device__ __forceinline__ void store(S *__restrict__ dst, const K3 &K, unsigned k, const R *f, const R *g)
 {
-    const double gT0 = K.sigma * K.T0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         St3<S>::template st<R>(dst + (size_t)q * K.n + k, f[q]);
-        St3<S>::template st<R>(dst + (size_t)(NQ + q) * K.n + k, g[q] - R(W(q) * gT0));
+        St3<S>::template st<R>(dst + (size_t)(NQ + q) * K.n + k, g[q]);
     }
 }
 
@@ -333,22 +495,27 @@ __host__ __device__ __forceinline__ int inner_z(const K3 &K) { return K.pz ? K.n
 
 // One time step, pull, state, collide, store, in two launches: the interior nodes (no
 // boundary-scheme code, so fewer registers and more waves per SIMD) and the wall nodes.
+// Interior launch: blockIdx.y is the interior plane, blockIdx.x * B3 + threadIdx.x the node
+// within the plane's interior (32-bit index arithmetic: planes and the grid stay below 2^31
+// nodes, and the interior planes below 65536, checked on the host).
+// FP32 and FP16: at most 128 registers, four waves per SIMD.
 template <typename S>
-__global__ void __launch_bounds__(B3) k3_step_interior(const S *__restrict__ src, S *__restrict__ dst, K3 K)
+__global__ void __launch_bounds__(B3, sizeof(S) == 8 ? 2 : 4) k3_step_interior(const S *__restrict__ src, S *__restrict__ dst, K3 K)
 {
     using R = typename Arith<S>::R;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int nxi = inner_x(K), nyi = inner_y(K);
-    if (i >= (long long)nxi * nyi * inner_z(K)) return;
-    const int x = (int)(i % nxi) + (K.px ? 0 : 1), y = (int)((i / nxi) % nyi) + (K.py ? 0 : 1);
-    const int z = (int)(i / ((long long)nxi * nyi)) + (K.pz ? 0 : 1);
-    const long long k = ((long long)z * K.ny + y) * K.nx + x;
+    const unsigned nxi = (unsigned)inner_x(K), nyi = (unsigned)inner_y(K);
+    const unsigned i = blockIdx.x * B3 + threadIdx.x;
+    if (i >= nxi * nyi) return;
+    const unsigned yi = i / nxi;
+    const int x = (int)(i - yi * nxi) + (K.px ? 0 : 1), y = (int)yi + (K.py ? 0 : 1);
+    const int z = (int)blockIdx.y + (K.pz ? 0 : 1);
+    const unsigned k = ((unsigned)z * (unsigned)K.ny + (unsigned)y) * (unsigned)K.nx + (unsigned)x;
     R f[NQ], g[NQ];
     Mac<R> m;
-    Por e;
+    Por<R> e;
     node_state<S, R, false>(src, K, x, y, z, f, g, m, e);
     collide<R>(f, g, m, K, e);
-    store<S, R>(dst, K, (size_t)k, f, g);
+    store<S, R>(dst, K, k, f, g);
 }
 
 template <typename S>
@@ -379,10 +546,10 @@ __global__ void __launch_bounds__(B3) k3_step_walls(const S *__restrict__ src, S
     const long long k = ((long long)z * K.ny + y) * K.nx + x;
     R f[NQ], g[NQ];
     Mac<R> m;
-    Por e;
+    Por<R> e;
     node_state<S, R>(src, K, x, y, z, f, g, m, e);
     collide<R>(f, g, m, K, e);
-    store<S, R>(dst, K, (size_t)k, f, g);
+    store<S, R>(dst, K, (unsigned)k, f, g);
 }
 
 // Initial post-collision populations: the equilibria of the initial fields (S = 0,
@@ -404,14 +571,14 @@ __global__ void __launch_bounds__(B3) k3_init(S *__restrict__ dst, K3 K, const d
     if (u_init)
         for (int a = 0; a < 3; ++a) u[a] = u_init[(size_t)a * K.n + k];
     const double S0[6] = {0, 0, 0, 0, 0, 0}, g0[3] = {0, 0, 0};
-    const Por e = por_of(K, k);
+    const Por<double> e = por_of<double>(K, k);
     double f[NQ], g[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         f[q] = feq<double>(q, K, e, 0.0, u, S0);
-        g[q] = geq<double>(q, K, e, T, 0.0, u, g0);
+        g[q] = geq<double>(q, K, e, T - K.T0, T, 0.0, u, g0);
     }
-    store<S, double>(dst, K, k, f, g);
+    store<S, double>(dst, K, (unsigned)k, f, g);
 }
 
 // Average Nusselt number of wall w (0: z = 0, 1: z = nz - 1, 2: x = 0, 3: x = nx - 1,
@@ -443,7 +610,7 @@ __global__ void __launch_bounds__(256) k3_nusselt(const S *__restrict__ src, K3 
             const int z = ax == 2 ? ia : i1;
             R f[NQ], g[NQ];
             Mac<R> m;
-            Por p;
+            Por<R> p;
             node_state<S, R>(src, K, x, y, z, f, g, m, p);
             T[d] = double(m.T);
         }
@@ -473,7 +640,7 @@ __global__ void __launch_bounds__(B3) k3_fields(const S *__restrict__ src, K3 K,
     if (!node_xyz(K, x, y, z)) return;
     R f[NQ], g[NQ];
     Mac<R> m;
-    Por e;
+    Por<R> e;
     node_state<S, R>(src, K, x, y, z, f, g, m, e);
     const size_t k = ((size_t)z * K.ny + y) * K.nx + x, n = (size_t)K.n;
     if (o.p) o.p[k] = double(m.p);
@@ -495,12 +662,12 @@ __global__ void __launch_bounds__(B3) k3_populations(const S *__restrict__ src, 
     if (!node_xyz(K, x, y, z)) return;
     R f[NQ], g[NQ];
     Mac<R> m;
-    Por e;
+    Por<R> e;
     node_state<S, R>(src, K, x, y, z, f, g, m, e);
     const size_t k = ((size_t)z * K.ny + y) * K.nx + x;
     for (int q = 0; q < NQ; ++q) {
         if (fo) fo[(size_t)q * K.n + k] = double(f[q]) + (q == 0 ? 1.0 : 0.0);
-        if (go) go[(size_t)q * K.n + k] = double(g[q]);
+        if (go) go[(size_t)q * K.n + k] = double(g[q]) + W(q) * K.sigma * K.T0;
     }
 }
 
@@ -561,7 +728,8 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
     if (!p->periodic_y && p->ny < 4) return fail3(LBM_ERR_INVALID, "walled y needs ny >= 4 (got %d)", p->ny);
     if (p->storage != LBM_F64 && p->storage != LBM_F32 && p->storage != LBM_F16)
         return fail3(LBM_ERR_INVALID, "storage must be LBM_F64, LBM_F32 or LBM_F16");
-    if ((double)p->nx * p->ny * p->nz * 2 * NQ > 9.0e18) return fail3(LBM_ERR_INVALID, "grid too large");
+    if ((double)p->nx * p->ny * p->nz >= 2147483648.0 || (p->periodic_z ? p->nz : p->nz - 2) > 65535)
+        return fail3(LBM_ERR_INVALID, "grid too large (at most 2^31 - 1 nodes and 65535 interior z planes)");
     if (!(p->tau_f > 0.5) || !(p->tau_T > 0.5)) return fail3(LBM_ERR_INVALID, "tau_f and tau_T must exceed 1/2");
     if (!(p->eps > 0.0) || !(p->eps <= 1.0) || !(p->sigma > 0.0) || !(p->J > 0.0))
         return fail3(LBM_ERR_INVALID, "eps must lie in (0, 1]; sigma and J must be positive");
@@ -599,6 +767,39 @@ lbm_status make_constants(const lbm3_params *p, K3 &K)
     K.isqK = 1.0 / sqrt(Kp);
     K.ergun = std::isnan(p->F_eps) ? 1 : 0;
     K.Feps = K.ergun ? 0.0 : p->F_eps;
+    C3<double> &c = K.cd;
+    relax_pair(p->tau_f, c.itf, c.of);
+    relax_pair(p->tau_T, c.itT, c.og);
+    c.fF = 1.0 - 0.5 / p->tau_f;
+    c.fT = 1.0 - 0.5 / p->tau_T;
+    c.tfh = p->tau_f - 0.5;
+    c.sig = p->sigma;
+    c.isig = 1.0 / p->sigma;
+    c.Q = p->Q;
+    c.halfQ = 0.5 * p->Q;
+    c.T0 = K.T0;
+    c.gb = K.gbeta;
+    for (int a = 0; a < 3; ++a) c.a[a] = p->a[a];
+    c.Sden = 3.0 / (A - p->tau_f);
+    c.aM0 = p->sigma * (B - p->tau_T) / 3.0;
+    c.sigB3 = p->sigma * B / 3.0;
+    c.A = A;
+    c.A15 = 1.5 * A;
+    c.eps = p->eps;
+    c.ieps = 1.0 / p->eps;
+    c.dlin = K.dlin;
+    c.dquad = K.dquad;
+    c.bM = 0.5 * (1.0 / p->eps - 1.0 / p->sigma);
+    C3<float> &cf = K.cf;
+    relax_pair(p->tau_f, cf.itf, cf.of);
+    relax_pair(p->tau_T, cf.itT, cf.og);
+    cf.fF = (float)c.fF; cf.fT = (float)c.fT; cf.tfh = (float)c.tfh; cf.sig = (float)c.sig;
+    cf.isig = (float)c.isig; cf.Q = (float)c.Q; cf.halfQ = (float)c.halfQ; cf.T0 = (float)c.T0;
+    cf.gb = (float)c.gb;
+    for (int a = 0; a < 3; ++a) cf.a[a] = (float)c.a[a];
+    cf.Sden = (float)c.Sden; cf.aM0 = (float)c.aM0; cf.sigB3 = (float)c.sigB3; cf.A = (float)c.A; cf.A15 = (float)c.A15;
+    cf.eps = (float)c.eps; cf.ieps = (float)c.ieps; cf.dlin = (float)c.dlin; cf.dquad = (float)c.dquad;
+    cf.bM = (float)c.bM;
     for (int w = 0; w < 6; ++w) {
         K.wkind[w] = p->wall[w].t_kind == LBM_T_NEUMANN ? 1 : 0;
         for (int a = 0; a < 3; ++a) K.wu[w][a] = p->wall[w].u[a];
@@ -668,14 +869,16 @@ lbm_status lbm3_step(lbm3_ctx *c, int64_t nsteps)
     if (!c) return fail3(LBM_ERR_INVALID, "ctx is NULL");
     if (nsteps < 0) return fail3(LBM_ERR_INVALID, "nsteps must be >= 0");
     const K3 &K = c->K;
-    const long long n_in = (long long)inner_x(K) * inner_y(K) * inner_z(K), n_w = K.n - n_in;
-    const unsigned nb_in = blocks_for(n_in), nb_w = blocks_for(n_w);
+    const long long n_plane = (long long)inner_x(K) * inner_y(K), n_w = K.n - n_plane * inner_z(K);
+    const dim3 nb_in(blocks_for(n_plane), (unsigned)inner_z(K));
+    const unsigned nb_w = blocks_for(n_w);
     for (int64_t s = 0; s < nsteps; ++s) {
         by_storage(c->storage, [&](auto t) {
             using S = typename decltype(t)::type;
             const S *src = reinterpret_cast<const S *>(c->buf[c->cur]);
             S *dst = reinterpret_cast<S *>(c->buf[c->cur ^ 1]);
-            hipLaunchKernelGGL((k3_step_interior<S>), dim3(nb_in), dim3(B3), 0, c->stream, src, dst, c->K);
+            if (n_plane > 0 && inner_z(K) > 0)
+                hipLaunchKernelGGL((k3_step_interior<S>), nb_in, dim3(B3), 0, c->stream, src, dst, c->K);
             if (n_w) hipLaunchKernelGGL((k3_step_walls<S>), dim3(nb_w), dim3(B3), 0, c->stream, src, dst, c->K);
         });
         c->cur ^= 1;

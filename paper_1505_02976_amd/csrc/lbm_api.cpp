@@ -179,10 +179,8 @@ void fill_kparams(const lbm_params *p, const lbm_derived &d, lbm::KParams &k)
     k.hinv = 1.0f / k.hscale;
 
     lbm::Cst<double> &c = k.cd;
-    c.itf = 1.0 / p->tau_f;
-    c.itT = 1.0 / p->tau_T;
-    c.of = 1.0 - c.itf;
-    c.og = 1.0 - c.itT;
+    lbm::relax_pair(p->tau_f, c.itf, c.of);
+    lbm::relax_pair(p->tau_T, c.itT, c.og);
     c.fF = 1.0 - 0.5 / p->tau_f;
     c.fT = 1.0 - 0.5 / p->tau_T;
     c.tau_f = p->tau_f;
@@ -202,7 +200,8 @@ void fill_kparams(const lbm_params *p, const lbm_derived &d, lbm::KParams &k)
     c.w3a = 1.0 / 3.0;
     c.w3d = (1.0 - 2.0 * c.w3a) / 4.0;
     lbm::Cst<float> &cf = k.cf;
-    cf.itf = (float)c.itf; cf.itT = (float)c.itT; cf.of = (float)c.of; cf.og = (float)c.og;
+    lbm::relax_pair(p->tau_f, cf.itf, cf.of);
+    lbm::relax_pair(p->tau_T, cf.itT, cf.og);
     cf.fF = (float)c.fF; cf.fT = (float)c.fT; cf.tau_f = (float)c.tau_f; cf.A = (float)c.A;
     cf.sigB = (float)c.sigB; cf.sig = (float)c.sig; cf.isig = (float)c.isig; cf.Q = (float)c.Q;
     cf.halfQ = (float)c.halfQ; cf.gb = (float)c.gb; cf.ax = (float)c.ax; cf.ay = (float)c.ay;
@@ -836,7 +835,8 @@ struct lbm_batch {
     int graph_steps;
     int graph_cur;              // value of cur the graph's launches assume (replays keep it)
     int graph_fuse;
-    int bx;                     // block width of the batched update
+    int bx;                     // block width of the batched one-step update
+    int w2;                     // wavefronts per block of the batched two-step main launch
     size_t edge_cap;            // capacity of the edge item table (items)
     std::vector<lbm::BatchProblem> hp;
 };
@@ -933,13 +933,13 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
 constexpr int GRAPH_STEPS = 64;   // even, and even in two-step passes: a replay keeps `cur`
 
 hipError_t add_kernel_node(hipGraph_t g, const void *func, int grid, int threads, void **args,
-                           const std::vector<hipGraphNode_t> &deps, hipGraphNode_t *node)
+                           const std::vector<hipGraphNode_t> &deps, hipGraphNode_t *node, size_t lds_bytes = 0)
 {
     hipKernelNodeParams kp = {};
     kp.func = const_cast<void *>(func);
     kp.gridDim = dim3(grid);
     kp.blockDim = dim3(threads);
-    kp.sharedMemBytes = 0;
+    kp.sharedMemBytes = (unsigned)lds_bytes;
     kp.kernelParams = args;
     kp.extra = nullptr;
     return hipGraphAddKernelNode(node, g, deps.empty() ? nullptr : deps.data(), deps.size(), &kp);
@@ -957,7 +957,6 @@ lbm_status batch_build_graph(lbm_batch *b)
     std::vector<hipGraphNode_t> prev;
     if (b->fuse == 2) {
         const lbm::Batch2Kernels K = lbm::batch2_kernels(b->storage);
-        const int W = K.waves_per_block;
         for (int s = 0; s < GRAPH_STEPS / 2 && e == hipSuccess; ++s) {
             int parity = (b->cur + s) & 1;
             std::vector<hipGraphNode_t> cur;
@@ -976,7 +975,10 @@ lbm_status batch_build_graph(lbm_batch *b)
                 args[m][1] = (void *)&items[m];
                 args[m][2] = (void *)&nitems[m];
                 args[m][3] = (void *)&parity;
-                e = add_kernel_node(b->graph, K.main[m], (nitems[m] + W - 1) / W, K.threads, args[m], prev, &node);
+                // the full launch with the widest blocks, the main one with the tuned width
+                const int W = m == lbm::STEP2_MAIN ? b->w2 : K.waves_per_block;
+                e = add_kernel_node(b->graph, K.main[m], (nitems[m] + W - 1) / W, 64 * W, args[m], prev, &node,
+                                    m == lbm::STEP2_MAIN ? (size_t)W * K.lds_per_wave : 0);
                 if (e == hipSuccess) cur.push_back(node);
                 if (m == lbm::STEP2_FULL) full = node;
             }
@@ -1057,6 +1059,18 @@ lbm_status batch_set_width(lbm_batch *b, int bx)
     return LBM_OK;
 }
 
+// Wavefronts per block of the batched two-step main launch (1, 2 or 4).
+lbm_status batch_set_waves2(lbm_batch *b, int waves)
+{
+    if (waves < 1 || waves > lbm::STEP2_WAVES_PER_BLOCK || (waves & (waves - 1)))
+        return fail(LBM_ERR_INVALID, "wavefronts per block %d", waves);
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch width");
+    if (waves != b->w2) batch_drop_graph(b);
+    b->w2 = waves;
+    return LBM_OK;
+}
+
 }  // namespace
 
 size_t lbm_batch_workspace_bytes(const lbm_params *params, int32_t n)
@@ -1091,6 +1105,7 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
     b->graph_cur = 0;
     b->graph_fuse = 0;
     b->bx = lbm::batch_width(0);
+    b->w2 = lbm::STEP2_WAVES_PER_BLOCK;
     b->edge_cap = B.edge.size();
     std::vector<lbm::BatchProblem> &hp = b->hp;
     hp.resize(n);
@@ -1172,7 +1187,7 @@ hipError_t batch_single(lbm_batch *b)
 hipError_t batch_pass(lbm_batch *b)
 {
     hipError_t e = lbm::launch_batch_step2(b->storage, b->probs, b->items2, b->nitems2, b->rows2, b->nrows2,
-                                           b->cur, b->stream);
+                                           b->cur, b->w2, b->stream);
     if (e == hipSuccess) {
         b->t += 2;
         b->cur ^= 1;
@@ -1258,6 +1273,7 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *width, doubl
     if (!b) return fail(LBM_ERR_INVALID, "batch is NULL");
     if (steps < 1) return fail(LBM_ERR_INVALID, "steps must be >= 1");
     const int parity = b->cur;
+    const bool two = b->fuse == 2;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -1266,25 +1282,31 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *width, doubl
     lbm_status st = LBM_OK;
     for (int i = 0; i < LBM_BATCH_NUM_WIDTHS && e == hipSuccess && st == LBM_OK; ++i) {
         const int bx = lbm::batch_width(i);
-        st = batch_set_width(b, bx);
-        if (st != LBM_OK) break;
-        // every launch reads the current buffers and writes the other ones: the state is kept
+        if (!two) {
+            st = batch_set_width(b, bx);
+            if (st != LBM_OK) break;
+        }
+        // every launch reads the current buffers and writes the other ones (and, for
+        // two-step passes, the scratch rows), so the state is kept
         auto run = [&](int n) {
             hipError_t r = hipSuccess;
             for (int s = 0; s < n && r == hipSuccess; ++s)
-                r = lbm::launch_batch_step(b->storage, b->bx, b->probs, b->bulk_items, b->nbulk, b->edge_items,
-                                           b->nedge, b->wall_items, b->nwall, parity, b->stream);
+                r = two ? lbm::launch_batch_step2(b->storage, b->probs, b->items2, b->nitems2, b->rows2, b->nrows2,
+                                                  parity, bx / 64, b->stream)
+                        : lbm::launch_batch_step(b->storage, b->bx, b->probs, b->bulk_items, b->nbulk,
+                                                 b->edge_items, b->nedge, b->wall_items, b->nwall, parity, b->stream);
             return r;
         };
+        const int reps = two ? (steps + 1) / 2 : steps;
         e = run(2);
         if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-        if (e == hipSuccess) e = run(steps);
+        if (e == hipSuccess) e = run(reps);
         if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         if (e == hipSuccess) {
-            ms /= steps;
+            ms /= (two ? 2 * reps : reps);
             if (ms_per_step) ms_per_step[i] = ms;
             if (best < 0 || ms < best_ms) { best = i; best_ms = ms; }
         }
@@ -1293,9 +1315,9 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *width, doubl
     if (e1) (void)hipEventDestroy(e1);
     if (st != LBM_OK) return st;
     if (e != hipSuccess) return hip_fail(e, "batch autotune");
-    st = batch_set_width(b, lbm::batch_width(best));
+    st = two ? batch_set_waves2(b, lbm::batch_width(best) / 64) : batch_set_width(b, lbm::batch_width(best));
     if (st != LBM_OK) return st;
-    if (width) *width = b->bx;
+    if (width) *width = two ? 64 * b->w2 : b->bx;
     return LBM_OK;
 }
 
@@ -1303,7 +1325,8 @@ lbm_status lbm_batch_set_width(lbm_batch *b, int32_t width)
 {
     if (!b) return fail(LBM_ERR_INVALID, "batch is NULL");
     for (int i = 0; i < LBM_BATCH_NUM_WIDTHS; ++i)
-        if (lbm::batch_width(i) == width) return batch_set_width(b, width);
+        if (lbm::batch_width(i) == width)
+            return b->fuse == 2 ? batch_set_waves2(b, width / 64) : batch_set_width(b, width);
     return fail(LBM_ERR_INVALID, "width %d is not one of 64, 128, 256", width);
 }
 

@@ -78,6 +78,18 @@ using ::sqrt;   // keep the FP32/FP64 overloads visible next to the dual one
 template <typename R> struct DragT { using T = double; };
 template <> struct DragT<Dual> { using T = Dual; };
 
+// 1 / tau and 1 - 1 / tau in the arithmetic type R with it + o == 1 exactly: the collision
+// forms o f + it (...), whose zeroth moment then carries the state's own moment with the
+// factor o + it = 1 (a rounded pair would scale the temperature deviation by 1 + 6e-8 per
+// FP32 step).  o = fl(1 - fl(1 / tau)) and it = fl(1 - o): for tau > 1/2 one of the two
+// subtractions is exact by Sterbenz's lemma, and then so is the other.
+template <typename R> inline void relax_pair(double tau, R &it, R &o)
+{
+    const R i0 = R(1.0 / tau);
+    o = R(1) - i0;
+    it = R(1) - o;
+}
+
 // Per-launch constants in the arithmetic type R, computed once on the host.
 template <typename R> struct Cst {
     R itf, itT;        // 1 / tau

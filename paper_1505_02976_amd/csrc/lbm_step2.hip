@@ -380,21 +380,27 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KPa
     march2_any<S, LAUNCH>(src, dst, scr, P, Pm, w % ncx, w / ncx, threadIdx.x & 63, lds[threadIdx.x >> 6]);
 }
 
-// Batched: item (problem, wavefront index); one item list per launch.
+// Batched: item (problem, wavefront index); one item list per launch.  The block holds
+// blockDim.x / 64 (1, 2 or 4) independent wavefronts, chosen by the batch autotuner; the
+// main launch's LDS (S2_LDS values per wavefront) is dynamic shared memory.
 template <typename S, int LAUNCH>
 __global__ void __launch_bounds__(S2_B)
 k_batch_step2(const BatchProblem *__restrict__ probs, const int2 *__restrict__ items, int nitems, int parity)
 {
     using R = typename Prec<S>::R;
-    __shared__ R lds[S2_B / 64][LAUNCH == STEP2_FULL ? 1 : S2_LDS];
-    const int wi = xcd_block(blockIdx.x, gridDim.x) * (S2_B / 64) + (threadIdx.x >> 6);
-    if (wi >= nitems) return;                            // wavefront-uniform
+    extern __shared__ __align__(16) unsigned char s2_lds[];
+    // the item, and with it the problem's parameters, are wavefront-uniform: reading them
+    // through wavefront-uniform indices keeps them in scalar registers (scalar loads)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wi = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave);
+    if (wi >= nitems) return;
     const int2 it = items[wi];
-    const BatchProblem &B = probs[it.x];
+    const int pk = __builtin_amdgcn_readfirstlane(it.x), w = __builtin_amdgcn_readfirstlane(it.y);
+    const BatchProblem &B = probs[pk];
     const int ncx = (B.P.nx + S2_OUT - 1) / S2_OUT;
+    R *lds = LAUNCH == STEP2_FULL ? nullptr : reinterpret_cast<R *>(s2_lds) + wave * S2_LDS;
     march2_any<S, LAUNCH>(static_cast<const S *>(B.buf[parity]), static_cast<S *>(B.buf[parity ^ 1]),
-                          static_cast<S *>(B.scr), B.P, B.Pm, it.y % ncx, it.y / ncx, threadIdx.x & 63,
-                          lds[threadIdx.x >> 6]);
+                          static_cast<S *>(B.scr), B.P, B.Pm, w % ncx, w / ncx, threadIdx.x & 63, lds);
 }
 
 // Final step of the walled rows y = 0 and y = ny - 1 from the intermediate rows in the
@@ -532,27 +538,30 @@ hipError_t launch_step2_rows(int storage, void *dst, const void *scr, const KPar
 
 template <typename S>
 static hipError_t batch_step2_t(const BatchProblem *probs, const int2 *const *items, const int *nitems,
-                                const int2 *rows, int nrows, int parity, hipStream_t st)
+                                const int2 *rows, int nrows, int parity, int main_waves, hipStream_t st)
 {
+    using R = typename Prec<S>::R;
     constexpr int W = S2_B / 64;
+    if (main_waves < 1 || main_waves > W) return hipErrorInvalidValue;
     if (nitems[STEP2_FULL] > 0)
         hipLaunchKernelGGL((k_batch_step2<S, STEP2_FULL>), dim3((nitems[STEP2_FULL] + W - 1) / W), dim3(S2_B), 0, st,
                            probs, items[STEP2_FULL], nitems[STEP2_FULL], parity);
     if (nrows > 0)   // after the full launch, whose scratch rows it reads
         hipLaunchKernelGGL((k_batch_step2_rows<S>), dim3(nrows), dim3(64), 0, st, probs, rows, parity);
     if (nitems[STEP2_MAIN] > 0)
-        hipLaunchKernelGGL((k_batch_step2<S, STEP2_MAIN>), dim3((nitems[STEP2_MAIN] + W - 1) / W), dim3(S2_B), 0, st,
+        hipLaunchKernelGGL((k_batch_step2<S, STEP2_MAIN>), dim3((nitems[STEP2_MAIN] + main_waves - 1) / main_waves),
+                           dim3(64 * main_waves), (size_t)main_waves * S2_LDS * sizeof(R), st,
                            probs, items[STEP2_MAIN], nitems[STEP2_MAIN], parity);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_step2(int storage, const BatchProblem *probs, const int2 *const *items, const int *nitems,
-                              const int2 *rows, int nrows, int parity, hipStream_t st)
+                              const int2 *rows, int nrows, int parity, int main_waves, hipStream_t st)
 {
     switch (storage) {
-    case 0: return batch_step2_t<double>(probs, items, nitems, rows, nrows, parity, st);
-    case 1: return batch_step2_t<float>(probs, items, nitems, rows, nrows, parity, st);
-    case 2: return batch_step2_t<__half>(probs, items, nitems, rows, nrows, parity, st);
+    case 0: return batch_step2_t<double>(probs, items, nitems, rows, nrows, parity, main_waves, st);
+    case 1: return batch_step2_t<float>(probs, items, nitems, rows, nrows, parity, main_waves, st);
+    case 2: return batch_step2_t<__half>(probs, items, nitems, rows, nrows, parity, main_waves, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -565,6 +574,7 @@ template <typename S> static Batch2Kernels batch2_kernels_t()
     k.rows = (const void *)k_batch_step2_rows<S>;
     k.threads = S2_B;
     k.waves_per_block = S2_B / 64;
+    k.lds_per_wave = S2_LDS * sizeof(typename Prec<S>::R);
     return k;
 }
 

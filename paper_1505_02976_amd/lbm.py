@@ -466,14 +466,17 @@ class Batch:
         _check(lib().lbm_batch_step(self.h, int(n)))
 
     def autotune(self, steps: int = 10):
-        """Times the candidate block widths (64, 128, 256) and keeps the fastest; returns
-        (chosen width, {width: ms per step}).  The problems' states are unchanged."""
+        """Times the candidate block widths (64, 128, 256 threads) of the launches that run
+        under the current steps per pass (the two-step main launch, or the one-step update)
+        and keeps the fastest; returns (chosen width, {width: ms per step}).  The problems'
+        states are unchanged."""
         w = C.c_int32()
         ms = (C.c_double * 3)()
         _check(lib().lbm_batch_autotune(self.h, int(steps), C.byref(w), ms))
         return w.value, {64: ms[0], 128: ms[1], 256: ms[2]}
 
     def set_width(self, width: int):
+        """Block width (64, 128, 256 threads) of the launches of the current steps per pass."""
         _check(lib().lbm_batch_set_width(self.h, int(width)))
 
     @property
