@@ -101,11 +101,13 @@ def mixed_convection_cfg(ny, tau, Re=5.0, A=None):
     z1 = Re / (2 * eps * J)
     z2 = np.sqrt(Re ** 2 + 4 * eps ** 3 * J / Da) / (2 * eps * J)
     eta = np.arange(ny) / H
-    ua = u0 * np.exp(z1 * (eta - 1)) * np.sinh(z2 * eta) / np.sinh(z2)
-    dua = u0 / np.sinh(z2) * np.exp(z1 * (eta - 1)) * (z1 * np.sinh(z2 * eta) + z2 * np.cosh(z2 * eta)) / H
+    # the closed forms with the growing exponentials factored out (no overflow at large Re)
+    grow = np.exp((z1 + z2) * (eta - 1)) / (1 - np.exp(-2 * z2))
+    ua = u0 * grow * (1 - np.exp(-2 * z2 * eta))
+    dua = u0 * grow * (z1 * (1 - np.exp(-2 * z2 * eta)) + z2 * (1 + np.exp(-2 * z2 * eta))) / H
     Pe = Pr * Re
-    Ta = (np.exp(Pe * eta) - 1) / (np.exp(Pe) - 1)
-    dTa = Pe / H * np.exp(Pe * eta) / (np.exp(Pe) - 1)
+    Ta = (np.exp(Pe * (eta - 1)) - np.exp(-Pe)) / (1 - np.exp(-Pe))
+    dTa = Pe / H * np.exp(Pe * (eta - 1)) / (1 - np.exp(-Pe))
     return cfg, int(3 * H * H / nu), (ua, Ta, dua, dTa, v0)
 
 
