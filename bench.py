@@ -67,16 +67,36 @@ def kernel_sources_hash():
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
+WARMUP_S = 0.5     # minimum wall time of the untimed warm-up (clocks and caches settle)
+
+
+def warm(sim, warmup, min_s=WARMUP_S):
+    """`warmup` untimed steps, then more untimed steps until at least min_s of wall time has
+    passed, so that a short --warmup still starts the timed region at steady clocks.
+    Returns (steps, seconds) of the warm-up."""
+    t0 = time.perf_counter()
+    n = warmup
+    sim.step(warmup)
+    sim.stream.synchronize()
+    chunk = max(2, warmup)
+    while time.perf_counter() - t0 < min_s:
+        sim.step(chunk)
+        sim.stream.synchronize()
+        n += chunk
+        chunk = min(2 * chunk, 512)
+    return n, time.perf_counter() - t0
+
+
 def timed_run(lbm, torch, cfg, warmup, steps, every=8, fusion=None):
-    """Warm up, then time `steps` steps with HIP events on the simulation's stream; inside
-    that region the launches of every `every`-th pass are bracketed by further events,
-    which give the mean launch durations (the events cost a few microseconds per bracketed
-    pass, included in the total).  A pass is one step, or two with the two-step kernel."""
+    """Warm up (warm), then time `steps` steps with HIP events on the simulation's stream;
+    inside that region the launches of every `every`-th pass are bracketed by further
+    events, which give the mean launch durations (the events cost a few microseconds per
+    bracketed pass, included in the total).  A pass is one step, or two with the two-step
+    kernel."""
     sim = lbm.Sim(cfg)
     if fusion is not None:
         sim.fusion = fusion
-    sim.step(warmup)
-    sim.stream.synchronize()
+    warm_steps, warm_s = warm(sim, warmup)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(sim.stream):
@@ -99,17 +119,19 @@ def timed_run(lbm, torch, cfg, warmup, steps, every=8, fusion=None):
         "main_kernel_us": main_ms * 1e3, "rest_us": rest_ms * 1e3,
         "main_nodes": main_nodes, "timed_every": every,
         "main_bytes_per_launch": bytes_per_launch, "main_GBps": achieved,
-        "frac": achieved / HBM_PEAK_GBS,
+        "frac": achieved / HBM_PEAK_GBS, "warmup_steps_run": warm_steps, "warmup_s": warm_s,
     }
     del sim
     torch.cuda.synchronize()
     return res
 
 
-def ensemble_run(lbm, torch, W, count=256, steps=10000, warmup=64):
+def ensemble_run(lbm, torch, W, count=256, steps=10000, warmup=64, max_cell_re=None):
     """Aggregate throughput of an ensemble of cavities of uneven size and parameters,
-    advanced together by the batched kernels replayed from a HIP graph."""
-    cfgs = W.ensemble(count=count, seed=0, storage="f32")
+    advanced together by the batched kernels replayed from a HIP graph.  max_cell_re caps
+    Ra per cavity at Pr (max_cell_re (N - 1))^2 (None: Ra log-uniform on [1e3, 1e6] for
+    every cavity, the unresolved ones diverging and flagged)."""
+    cfgs = W.ensemble(count=count, seed=0, storage="f32", max_cell_re=max_cell_re)
     nodes = sum(c["nx"] * c["ny"] for c in cfgs)
     b = lbm.Batch(cfgs)
     b.step(warmup)
@@ -138,7 +160,9 @@ def ensemble_run(lbm, torch, W, count=256, steps=10000, warmup=64):
         ms1 = timed(n1)
         one_step = {"steps": n1, "mlups": nodes * n1 / (ms1 * 1e-3) / 1e6, "ms_per_step": ms1 / n1}
         b.fusion = fusion
-    res = {"workload": f"{count} porous cavities, side U{{64..512}}, Ra 10^U(3,6), Da 10^U(-4,-1), "
+    ra = ("Ra log-uniform on [1e3, min(1e6, Pr (%g (N-1))^2)] (grid cell Reynolds number at most %g)"
+          % (max_cell_re, max_cell_re)) if max_cell_re else "Ra log-uniform on [1e3, 1e6]"
+    res = {"workload": f"{count} porous cavities, side N ~ U{{64..512}}, {ra}, Da 10^U(-4,-1), "
                        f"eps U(0.4,0.9), Pr 1, FP32 storage, seed 0",
            "nodes": nodes, "steps": steps, "mlups": nodes * steps / (ms * 1e-3) / 1e6,
            "ms_per_step": ms / steps, "GBps_algorithmic": nodes * 144 * steps / (ms * 1e-3) / 1e9,
@@ -204,15 +228,20 @@ def three_d_run(torch, W, shape=(192, 192, 96), steps=200, warmup=20):
     return out
 
 
-def accuracy(lbm, W, n=128, tol=1e-9, max_steps=200000):
-    """Steady average Nusselt number of the hot wall on the n x n cavity per precision."""
+def accuracy(lbm, W, n=128, tol=1e-9, max_steps=600000):
+    """Average Nusselt number of the hot wall on the n x n cavity per precision: FP64 run
+    until both residuals of Sec. 4 fall below tol (or max_steps), FP32 and FP16 storage the
+    same number of steps, each compared with FP64 at that state."""
     out = {}
     steps = None
+    converged, reached = None, None
     for storage in ("f64", "f32", "f16"):
         sim = lbm.Sim(W.cavity(n, storage=storage))
         if storage == "f64":
-            sim.run_to_steady(tol, max_steps)
+            converged = sim.run_to_steady(tol, max_steps)
+            reached = sim.last_residual
             steps = sim.time
+            log(f"accuracy f64: residuals {reached} after {steps} steps (converged: {converged})")
         else:
             sim.step(steps)
         out[storage] = {"Nu": sim.nusselt(0), "steps": sim.time}
@@ -220,34 +249,66 @@ def accuracy(lbm, W, n=128, tol=1e-9, max_steps=200000):
     ref = out["f64"]["Nu"]
     for s in ("f32", "f16"):
         out[s]["abs_err_vs_f64"] = abs(out[s]["Nu"] - ref)
+        out[s]["rel_err_vs_f64"] = abs(out[s]["Nu"] - ref) / abs(ref)
+    state = (f"FP64 run until both residuals < {tol:g} (reached {reached[0]:.2e} / {reached[1]:.2e} "
+             f"after {steps} steps)" if converged else
+             f"FP64 run {steps} steps (cap {max_steps}); residuals there {reached[0]:.2e} / {reached[1]:.2e}, "
+             f"above the {tol:g} target")
     return {
-        "workload": f"cavity {n}x{n}, eps 0.6, Da 1e-2, Ra 1e5, Pr 1; FP64 run to residual {tol:g}, "
+        "workload": f"cavity {n}x{n}, eps 0.6, Da 1e-2, Ra 1e5, Pr 1; {state}; "
                     "FP32/FP16 run the same number of steps",
+        "converged": bool(converged), "residual_target": tol,
+        "residual_reached": {"u": reached[0], "T": reached[1]}, "steps": steps,
         "results": out,
         "paper_context": {"Nu": 3.463, "grid": "120x120", "source": "Table Tab:Square1"},
     }
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_steps(n, budget_s, threads):
+    """The FP64 oracle on the n x n throughput cavity, stepped until budget_s has passed,
+    in a child process with `threads` OpenMP threads.  Returns (steps, seconds, threads)."""
+    import subprocess
+    code = (
+        "import sys, time, json; sys.path.insert(0, %r)\n"
+        "import workloads as W\n"
+        "from oracle import oracle as O\n"
+        "o = O.Oracle(W.large_cavity(%d, storage='f64'))\n"
+        "steps, t0 = 0, time.time()\n"
+        "while True:\n"
+        "    o.step(1); steps += 1; el = time.time() - t0\n"
+        "    print('cpu baseline: step %%d, %%.1f s' %% (steps, el), file=sys.stderr, flush=True)\n"
+        "    if el > %f: break\n"
+        "print(json.dumps({'steps': steps, 's': el}))\n" % (ROOT, n, budget_s))
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+    sys.stderr.write(r.stderr[-400:])
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    return rec["steps"], rec["s"], threads
+
+
 def cpu_baseline(W, n, budget_s=15.0):
-    """The FP64 oracle on the same workload for a bounded number of steps."""
-    from oracle import oracle as O
-    cfg = W.large_cavity(n, storage="f64")
-    t = time.time()
-    o = O.Oracle(cfg)
-    log(f"cpu baseline: oracle initialised {n}x{n} in {time.time() - t:.1f} s")
-    steps = 0
-    t0 = time.time()
-    while True:
-        o.step(1)
-        steps += 1
-        el = time.time() - t0
-        log(f"cpu baseline: step {steps}, {el:.1f} s")
-        if el > budget_s:
-            break
+    """The FP64 oracle on the same workload (the n x n cavity) for a bounded number of
+    steps: all host threads (OpenMP over rows), then one thread."""
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n * n * steps / el / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{n}x{n} cavity, {steps} full time steps after initialisation, FP64, "
-                      f"OpenMP over rows ({threads} threads)"}
+    st, el, _ = _oracle_steps(n, budget_s, threads)
+    st1, el1, _ = _oracle_steps(n, budget_s, 1)
+    return {"value": n * n * st / el / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n}x{n} cavity, {st} full time steps after initialisation, FP64, "
+                      f"OpenMP over rows ({threads} threads)",
+            "single_thread": {"value": n * n * st1 / el1 / 1e6, "unit": "MLUPS", "cores": 1,
+                              "sample": f"{n}x{n} cavity, {st1} full time steps, one thread"},
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 def main():
@@ -266,6 +327,7 @@ def main():
     ap.add_argument("--fusion", type=int, default=None, choices=(1, 2),
                     help="time steps per pass (default: the library's choice, 2 on large grids)")
     ap.add_argument("--ensemble-steps", type=int, default=10000)
+    ap.add_argument("--no-ensemble-capped", action="store_true")
     ap.add_argument("--copy-reference-gib", type=float, default=0.0,
                     help="first run a plain device-to-device copy of this size, as the "
                          "reference for scaling hardware byte counters")
@@ -312,10 +374,14 @@ def main():
                              max(100, args.steps // 5), fusion=1)
         log(f"bench: {args.storage} one step per pass: {one_step['mlups']:.0f} MLUPS")
 
-    ens = None
+    ens = ens_c = None
     if not args.no_ensemble:
         ens = ensemble_run(lbm, torch, W, steps=args.ensemble_steps)
         log(f"bench: ensemble {ens['mlups']:.0f} MLUPS aggregate, {ens['nonfinite_problems']} non-finite")
+        if not args.no_ensemble_capped:
+            ens_c = ensemble_run(lbm, torch, W, steps=args.ensemble_steps, max_cell_re=5.0)
+            log(f"bench: ensemble with Ra capped at cell Reynolds number 5: {ens_c['mlups']:.0f} MLUPS "
+                f"aggregate, {ens_c['nonfinite_problems']} non-finite")
     adj = None
     if not args.no_adjoint:
         adj = adjoint_run(lbm, torch, W)
@@ -356,6 +422,7 @@ def main():
         "modes": {s: {k: v for k, v in r.items()} for s, r in modes.items()},
         "one_step_per_pass": one_step,
         "ensemble": ens,
+        "ensemble_capped": ens_c,
         "adjoint": adj,
         "three_d": td,
         "accuracy": acc,

@@ -324,10 +324,15 @@ class Sim:
         return (None, None) if ru.value < 0 else (ru.value, rT.value)
 
     def run_to_steady(self, tol: float, max_steps: int, every: int = 100) -> bool:
+        """Steps until both residuals of Sec. 4 (against the state `every` steps earlier) fall
+        below tol or the time reaches max_steps; returns whether they did.  The last pair of
+        residuals is kept in self.last_residual."""
         self.residual()
+        self.last_residual = (None, None)
         while self.time < max_steps:
             self.step(every)
             ru, rT = self.residual()
+            self.last_residual = (ru, rT)
             if ru < tol and rT < tol:
                 return True
         return False

@@ -64,7 +64,7 @@ def test_batch_fp64_matches_single_and_oracle(gpu, oracle_mod):
 
 
 def test_batch_fp32_bitwise_equals_single(gpu):
-    cfgs = W.ensemble(count=6, side_lo=32, side_hi=80, storage="f32")
+    cfgs = W.ensemble(count=6, side_lo=32, side_hi=80, storage="f32", max_cell_re=5.0)
     _say("case: ensemble of 6 FP32 cavities, 200 steps")
     batch = gpu.Batch(cfgs)
     batch.step(200)

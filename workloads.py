@@ -171,18 +171,16 @@ def adjoint_cavity(n=256, storage="f32", seed=0):
     return cfg
 
 
-def ensemble(count=256, seed=0, side_lo=64, side_hi=512, storage="f32", max_cell_re=5.0):
+def ensemble(count=256, seed=0, side_lo=64, side_hi=512, storage="f32", max_cell_re=None):
     """Many cavities of uneven size and parameters: side N ~ U{lo..hi}, Da ~ 10^U(-4,-1),
-    eps ~ U(0.4, 0.9), Pr = 1, and Ra log-uniform on [1e3, min(1e6, Ra_max(N))] where
-    Ra_max(N) = Pr (max_cell_re (N - 1))^2 keeps the grid cell Reynolds number
-    sqrt(Ra / Pr) / (N - 1) at or below max_cell_re.  (Drawn without that bound, every
-    cavity with a cell Reynolds number above about 5 diverges within 2000 steps; such
-    grids are coarser for their Ra than any the paper uses.)"""
+    eps ~ U(0.4, 0.9), Pr = 1, and Ra log-uniform on [1e3, 1e6], or, with max_cell_re, on
+    [1e3, min(1e6, Ra_max(N))] where Ra_max(N) = Pr (max_cell_re (N - 1))^2 keeps the grid
+    cell Reynolds number sqrt(Ra / Pr) / (N - 1) at or below max_cell_re."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(count):
         n = int(rng.integers(side_lo, side_hi + 1))
-        hi = min(6.0, np.log10(1.0 * (max_cell_re * (n - 1)) ** 2))
+        hi = 6.0 if max_cell_re is None else min(6.0, np.log10(1.0 * (max_cell_re * (n - 1)) ** 2))
         Ra = float(10 ** rng.uniform(3, max(3.0, hi)))
         Da = float(10 ** rng.uniform(-4, -1))
         eps = float(rng.uniform(0.4, 0.9))
