@@ -134,7 +134,8 @@ size_t lbm_workspace_bytes(const lbm_params *params);
 lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_bytes,
                     void *hip_stream, lbm_ctx **out);
 
-/* Enqueues nsteps >= 0 time steps (asynchronous).  With two steps per pass (see
+/* Enqueues nsteps >= 0 time steps (asynchronous, unless non-finite checks are on: see
+ * lbm_set_check_interval).  With two steps per pass (see
  * lbm_set_fusion) pairs of steps run as one pass over the populations: the intermediate
  * state of every node is computed from the source buffer in registers and the final
  * state written once, so each pair reads and writes the populations once instead of
@@ -144,6 +145,14 @@ lbm_status lbm_init(const lbm_params *params, void *workspace, size_t workspace_
  * single step is two launches: the interior columns, then the columns next to the walls
  * x = 0, x = nx - 1 together with the walled rows. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
+
+/* Non-finite detection inside lbm_step: with every > 0, whenever the context's time
+ * reaches a multiple of `every` during lbm_step, the call waits for the stream and checks
+ * every population of the grid; if one is NaN or infinite it returns LBM_ERR_NONFINITE at
+ * that time (later steps of the call are not enqueued; lbm_time reports where it stopped).
+ * every = 0 (the default) turns the checks off, and lbm_step stays asynchronous.  Each
+ * check reads the populations once (about one step's read traffic). */
+lbm_status lbm_set_check_interval(lbm_ctx *ctx, int64_t every);
 
 /* Time steps per pass, 1 or 2.  The default is 2 for FP64 and FP32 storage when nx >= 4
  * and ny >= 8, else 1 (FP16 storage is faster with one step per pass).

@@ -23,10 +23,7 @@ constexpr int ADJ_B = 128;
 // node would leave a 256^2 grid with one wavefront per SIMD and its memory latency exposed
 // (backward sweep of the 256^2 cavity over 5000 steps: 1.84 s with one thread per node,
 // 1.44 / 1.24 / 1.11 s with 2 / 4 / 8 column groups).
-#ifndef LBM_ADJ_SPLIT
-#define LBM_ADJ_SPLIT 8
-#endif
-constexpr int ADJ_SPLIT = LBM_ADJ_SPLIT;
+constexpr int ADJ_SPLIT = 8;
 
 __device__ __forceinline__ Cst<Dual> dual_cst(const Cst<double> &c)
 {

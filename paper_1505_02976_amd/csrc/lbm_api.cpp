@@ -97,33 +97,20 @@ lbm_status derive(const lbm_params *p, lbm_derived *d)
 }
 
 struct Layout {
-    int pitch, ntx;
-    long long plane;
+    int ntx;              // tiles per row
     size_t pop_bytes;     // one population buffer
     size_t off_a, off_b, off_eps, off_snap, off_part, off_scalar, off_scr, off_items, total;
-    long long plane_scr;  // plane size of the eight-row scratch grid (plane layout)
     long long nparts;
 };
 
-// Rows padded to 256 bytes; consecutive planes offset by an extra 256 bytes so that the
-// 18 planes of a node do not map to the same HBM channel when the plane size is a large
-// power of two.
+// Populations in rows of tiles (TileOf in lbm_device.h), the last tile of a row padded.
 Layout layout(const lbm_params *p, const lbm::KParams &kp)
 {
     Layout L;
     const size_t es = elem_size(p->storage);
     const int tile = lbm::tile_of_storage(p->storage);
-    if (tile > 0) {
-        L.pitch = 0;
-        L.plane = 0;
-        L.ntx = (p->nx + tile - 1) / tile;
-        L.pop_bytes = align_up((size_t)p->ny * L.ntx * 18 * tile * es, 256);
-    } else {
-        L.ntx = 0;
-        L.pitch = (int)align_up((size_t)p->nx, 256 / es);
-        L.plane = (long long)align_up((size_t)L.pitch * p->ny, 256 / es) + (long long)(256 / es);
-        L.pop_bytes = align_up((size_t)L.plane * 18 * es, 256);
-    }
+    L.ntx = (p->nx + tile - 1) / tile;
+    L.pop_bytes = align_up((size_t)p->ny * L.ntx * 18 * tile * es, 256);
     const size_t N = (size_t)p->nx * p->ny;
     L.nparts = lbm::residual_partials(kp) + 1;
     size_t o = 0;
@@ -134,15 +121,7 @@ Layout layout(const lbm_params *p, const lbm::KParams &kp)
     L.off_part = o; o += align_up((size_t)L.nparts * 5 * 8, 256);
     L.off_scalar = o; o += 256;
     // eight rows of intermediate populations for the two-step pass (walled rows)
-    size_t scr;
-    if (tile > 0) {
-        scr = align_up((size_t)8 * L.ntx * 18 * tile * es, 256);
-        L.plane_scr = 0;
-    } else {
-        L.plane_scr = (long long)align_up((size_t)L.pitch * 8, 256 / es) + (long long)(256 / es);
-        scr = align_up((size_t)L.plane_scr * 18 * es, 256);
-    }
-    L.off_scr = o; o += scr;
+    L.off_scr = o; o += align_up((size_t)8 * L.ntx * 18 * tile * es, 256);
     // wavefront lists of the two-step pass's launches
     L.off_items = o; o += align_up(lbm::step2_supported(kp) ? (size_t)lbm::step2_waves(kp) * sizeof(int) : 0, 256);
     L.total = o;
@@ -233,6 +212,7 @@ struct lbm_ctx {
     int in_batch;
     int cur;             // buffer holding the current populations (0: a, 1: b)
     int fuse;            // time steps per pass over the populations (1 or 2)
+    int64_t check_every; // lbm_step checks for non-finite populations at multiples of this time (0: never)
     lbm::KParams kpm;    // parameters of the eight-row scratch grid of the two-step pass
     int n_main2, n_full2;       // wavefronts of the two-step pass's main and full launches
     long long main_nodes2;      // output nodes of the main launch
@@ -279,8 +259,6 @@ static lbm_status init_ctx(const lbm_params *params, void *workspace, size_t wor
     const Layout lay = layout(params, kp);
     if (workspace_bytes < lay.total)
         return fail(LBM_ERR_INVALID, "workspace too small: %zu < %zu bytes", workspace_bytes, lay.total);
-    kp.pitch = lay.pitch;
-    kp.plane = lay.plane;
     kp.ntx = lay.ntx;
 
     lbm_ctx *c = new (std::nothrow) lbm_ctx;
@@ -295,6 +273,7 @@ static lbm_status init_ctx(const lbm_params *params, void *workspace, size_t wor
     c->have_snap = 0;
     c->in_batch = 0;
     c->cur = 0;
+    c->check_every = 0;
     c->side = nullptr;
     c->ev_join = c->ev_main = c->ev_side = nullptr;
     if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
@@ -311,7 +290,6 @@ static lbm_status init_ctx(const lbm_params *params, void *workspace, size_t wor
     c->kpm = kp;
     c->kpm.ny = 8;
     c->kpm.py = 0;
-    c->kpm.plane = lay.plane_scr;
     // two-step passes by default where they are faster: FP32 and FP64 storage, whose tiles
     // match the two-step wavefronts (see lbm_step2.hip)
     c->fuse = (params->storage != LBM_F16 && lbm::step2_supported(kp)) ? 2 : 1;
@@ -352,10 +330,6 @@ namespace {
 // rest (on the side stream for two-step passes).
 struct StepEvents { hipEvent_t i0, i1, e0, e1; };
 
-#ifndef LBM_STEP2_STREAMS
-#define LBM_STEP2_STREAMS 2
-#endif
-
 hipError_t ensure_side(lbm_ctx *c)
 {
     if (c->side) return hipSuccess;
@@ -379,19 +353,15 @@ hipError_t run_passes(lbm_ctx *c, int64_t npass, const StepEvents *tev, int ever
     const int sto = c->prm.storage;
     void *scr = c->ws + c->lay.off_scr;
     const int *items = reinterpret_cast<const int *>(c->ws + c->lay.off_items);
-    hipStream_t side = LBM_STEP2_STREAMS == 2 ? c->side : c->stream;
-    hipError_t e = hipSuccess;
-    if (LBM_STEP2_STREAMS == 2) {
-        e = ensure_side(c);
-        side = c->side;
-        if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->stream);
-        if (e == hipSuccess) e = hipStreamWaitEvent(side, c->ev_join, 0);
-    }
+    hipError_t e = ensure_side(c);
+    hipStream_t side = c->side;
+    if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, c->ev_join, 0);
     for (int64_t p = 0; p < npass && e == hipSuccess; ++p) {
         void *src = cur_buf(c), *dst = next_buf(c);
         const int64_t gi = gi0 + p;
         const StepEvents *t = (tev && gi % every == 0) ? tev + gi / every : nullptr;
-        if (LBM_STEP2_STREAMS == 2 && p > 0) {
+        if (p > 0) {
             e = hipStreamWaitEvent(c->stream, c->ev_side, 0);
             if (e == hipSuccess) e = hipStreamWaitEvent(side, c->ev_main, 0);
         }
@@ -403,19 +373,19 @@ hipError_t run_passes(lbm_ctx *c, int64_t npass, const StepEvents *tev, int ever
                                        c->n_full2, side);
         if (e == hipSuccess) e = lbm::launch_step2_rows(sto, dst, scr, c->kp, c->kpm, side);
         if (e == hipSuccess && t) e = hipEventRecord(t->e1, side);
-        if (e == hipSuccess && LBM_STEP2_STREAMS == 2) e = hipEventRecord(c->ev_side, side);
+        if (e == hipSuccess) e = hipEventRecord(c->ev_side, side);
         if (e == hipSuccess && t) e = hipEventRecord(t->i0, c->stream);
         if (e == hipSuccess)
             e = lbm::launch_step2_main(sto, lbm::STEP2_MAIN, src, dst, scr, c->kp, c->kpm, items, c->n_main2,
                                        c->stream);
         if (e == hipSuccess && t) e = hipEventRecord(t->i1, c->stream);
-        if (e == hipSuccess && LBM_STEP2_STREAMS == 2) e = hipEventRecord(c->ev_main, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(c->ev_main, c->stream);
         if (e == hipSuccess) {
             c->t += 2;
             c->cur ^= 1;
         }
     }
-    if (e == hipSuccess && LBM_STEP2_STREAMS == 2 && npass > 0) e = hipStreamWaitEvent(c->stream, c->ev_side, 0);
+    if (e == hipSuccess && npass > 0) e = hipStreamWaitEvent(c->stream, c->ev_side, 0);
     return e;
 }
 
@@ -457,14 +427,52 @@ hipError_t run_steps(lbm_ctx *c, int64_t nsteps, const StepEvents *tev, int ever
 
 }  // namespace
 
+// Non-finite check of the current populations (synchronizes).
+static lbm_status check_state(lbm_ctx *c)
+{
+    int *flag = reinterpret_cast<int *>(c->ws + c->lay.off_scalar + 192);
+    int h = 0;
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), c->stream);
+    if (e == hipSuccess) e = lbm::launch_check(c->prm.storage, cur_buf(c), c->kp, flag, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "non-finite check");
+    if (h) return fail(LBM_ERR_NONFINITE, "populations hold non-finite values at time %lld", (long long)c->t);
+    return LBM_OK;
+}
+
 lbm_status lbm_step(lbm_ctx *c, int64_t nsteps)
 {
     if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
     if (c->in_batch) return fail(LBM_ERR_INVALID, "problem belongs to a batch: use lbm_batch_step");
     if (nsteps < 0) return fail(LBM_ERR_INVALID, "nsteps < 0");
     if (nsteps == 0) return LBM_OK;
-    hipError_t e = run_steps(c, nsteps, nullptr, 1, nullptr);
-    if (e != hipSuccess) return hip_fail(e, "step launch");
+    if (c->check_every <= 0) {
+        hipError_t e = run_steps(c, nsteps, nullptr, 1, nullptr);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        return LBM_OK;
+    }
+    // chunks that end on multiples of check_every, each followed by the check
+    int64_t left = nsteps;
+    while (left > 0) {
+        const int64_t to_check = c->check_every - c->t % c->check_every;
+        const int64_t n = left < to_check ? left : to_check;
+        hipError_t e = run_steps(c, n, nullptr, 1, nullptr);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        left -= n;
+        if (c->t % c->check_every == 0) {
+            const lbm_status st = check_state(c);
+            if (st != LBM_OK) return st;
+        }
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_check_interval(lbm_ctx *c, int64_t every)
+{
+    if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
+    if (every < 0) return fail(LBM_ERR_INVALID, "every must be >= 0");
+    c->check_every = every;
     return LBM_OK;
 }
 
@@ -586,13 +594,11 @@ lbm_status lbm_nusselt(lbm_ctx *c, int32_t wall, double *nu_host)
     return LBM_OK;
 }
 
-lbm_status lbm_residual(lbm_ctx *c, double *r_u, double *r_T)
+// The residual of Sec. 4 with the reduction's partial sums in `part` (residual_partials x 5
+// doubles) and its five totals in `res`.
+static lbm_status residual_into(lbm_ctx *c, double *part, double *res, double *r_u, double *r_T)
 {
-    if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
-    if (!r_u || !r_T) return fail(LBM_ERR_INVALID, "outputs are NULL");
     double *snap = reinterpret_cast<double *>(c->ws + c->lay.off_snap);
-    double *part = reinterpret_cast<double *>(c->ws + c->lay.off_part);
-    double *res = reinterpret_cast<double *>(c->ws + c->lay.off_scalar) + 8;
     hipError_t e = lbm::launch_residual(c->prm.storage, cur_buf(c), c->kp, snap, part, res, c->stream);
     if (e != hipSuccess) return hip_fail(e, "residual launch");
     double h[5];
@@ -606,6 +612,15 @@ lbm_status lbm_residual(lbm_ctx *c, double *r_u, double *r_T)
     *r_u = h[1] > 0 ? h[0] / h[1] : (h[0] > 0 ? INFINITY : 0.0);
     *r_T = h[3] > 0 ? h[2] / h[3] : (h[2] > 0 ? INFINITY : 0.0);
     return LBM_OK;
+}
+
+lbm_status lbm_residual(lbm_ctx *c, double *r_u, double *r_T)
+{
+    if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
+    if (!r_u || !r_T) return fail(LBM_ERR_INVALID, "outputs are NULL");
+    double *part = reinterpret_cast<double *>(c->ws + c->lay.off_part);
+    double *res = reinterpret_cast<double *>(c->ws + c->lay.off_scalar) + 8;
+    return residual_into(c, part, res, r_u, r_T);
 }
 
 lbm_status lbm_get_state(lbm_ctx *c, double *dst)
@@ -875,8 +890,6 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
         lbm::KParams kp;
         fill_kparams(&params[k], d, kp);
         const Layout lay = layout(&params[k], kp);
-        kp.pitch = lay.pitch;
-        kp.plane = lay.plane;
         kp.ntx = lay.ntx;
         B.kp[k] = kp;
         B.off[k] = o;

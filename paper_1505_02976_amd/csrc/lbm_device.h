@@ -14,34 +14,26 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
-// Population layout per storage type.  Tile 0: 18 planes [q][y][pitch].  Tile n > 0 (a
-// power of two): rows of tiles of n consecutive nodes, each tile holding its 18 directions
-// contiguously, [y][x / n][q][x % n], so that the 36 streams of a wavefront touch one
-// contiguous block of memory per row instead of 36 distant planes.
-#ifndef LBM_TILE_F64
-#define LBM_TILE_F64 62
-#endif
-#ifndef LBM_TILE_F32
-#define LBM_TILE_F32 62
-#endif
-#ifndef LBM_TILE_F16
-#define LBM_TILE_F16 128
-#endif
+// Population layout per storage type: rows of tiles of T consecutive nodes, each tile
+// holding its 18 directions contiguously, [y][x / T][q][x % T], so that the 36 streams of a
+// wavefront touch one contiguous block of memory per row instead of 36 distant planes.
+// T = 62 for FP64 and FP32 (a two-step wavefront writes exactly one tile segment per
+// direction), 128 for FP16.
 
 namespace lbm {
 
 template <typename S> struct TileOf;
-template <> struct TileOf<double> { static constexpr int v = LBM_TILE_F64; };
-template <> struct TileOf<float> { static constexpr int v = LBM_TILE_F32; };
-template <> struct TileOf<__half> { static constexpr int v = LBM_TILE_F16; };
+template <> struct TileOf<double> { static constexpr int v = 62; };
+template <> struct TileOf<float> { static constexpr int v = 62; };
+template <> struct TileOf<__half> { static constexpr int v = 128; };
 // Columns one wavefront updates: a whole tile when tiles are narrower than a wavefront
 // (so that its stores cover whole tile segments), else 64.
 template <typename S> struct Wspan {
-    static constexpr int v = (TileOf<S>::v > 0 && TileOf<S>::v < 64) ? TileOf<S>::v : 64;
+    static constexpr int v = TileOf<S>::v < 64 ? TileOf<S>::v : 64;
 };
 inline constexpr int tile_of_storage(int storage)
 {
-    return storage == 0 ? LBM_TILE_F64 : (storage == 1 ? LBM_TILE_F32 : LBM_TILE_F16);
+    return storage == 0 ? TileOf<double>::v : (storage == 1 ? TileOf<float>::v : TileOf<__half>::v);
 }
 
 // D2Q9 (Sec. 3.1)
@@ -112,11 +104,9 @@ template <typename R> struct EpsR {
 // Kernel parameter block (plain data, passed by value).
 struct KParams {
     int nx, ny, px, py;          // grid, periodic flags
-    int pitch;                   // row pitch in elements (plane layout)
     int ntx;                     // tiles per row (tiled layout)
     int nwall;                   // number of wall-node slots enumerated by the wall kernels
     int nwall_rows;              // slots of the two walled rows (the step's wall launch)
-    long long plane;             // stride between population planes, elements
     double tau_f, tau_T, A, B, sigma, Q, gbeta, T0, ax, ay;
     double nu_over_K, inv_sqrtK; // 0 when K is infinite
     double Feps;                 // Forchheimer coefficient when not from Ergun
@@ -152,10 +142,7 @@ template <typename S>
 __device__ __forceinline__ long long pidx(const KParams &P, int q, int x, int y)
 {
     constexpr int T = TileOf<S>::v;
-    if constexpr (T > 0)
-        return ((long long)(y * P.ntx + x / T) * 18 + q) * T + (x % T);
-    else
-        return q * P.plane + (long long)y * P.pitch + x;
+    return ((long long)(y * P.ntx + x / T) * 18 + q) * T + (x % T);
 }
 
 // FP64 reciprocal from the hardware estimate refined by two Newton steps (used by the
@@ -178,26 +165,9 @@ __device__ __forceinline__ double sqrt_nr(double x)
     return x > 0.0 ? fma(e, 0.5 * r, s) : 0.0;
 }
 
-#ifndef LBM_NT_LOAD
-#define LBM_NT_LOAD 0
-#endif
-#ifndef LBM_F32_MOMENTS_F64
-#define LBM_F32_MOMENTS_F64 0
-#endif
-#ifndef LBM_F32_COLLIDE_F64
-#define LBM_F32_COLLIDE_F64 0
-#endif
-
 // Storage traits: load/store of a deviation value.  Stores are non-temporal (the next
-// step reads them from HBM anyway); loads optionally so.
-template <typename T> __device__ __forceinline__ T ld_stream(const T *p)
-{
-#if LBM_NT_LOAD
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
+// step reads them from HBM anyway); loads are plain (non-temporal loads measured slower).
+template <typename T> __device__ __forceinline__ T ld_stream(const T *p) { return *p; }
 template <typename S> struct Store;
 template <> struct Store<double> {
     static __device__ __forceinline__ double ld(const double *p, float) { return ld_stream(p); }
@@ -542,26 +512,15 @@ __device__ __forceinline__ void gather(const S *__restrict__ src, const KParams 
     const int yp = (y == P.ny - 1) ? 0 : y + 1;
     const float inv = P.hinv;
     constexpr int T = TileOf<S>::v;
-    if constexpr (T > 0) {
-        // three row bases and three in-row offsets; direction i comes from (x - cx_i, y - cy_i)
-        const long long row = (long long)P.ntx * (18 * T);
-        const S *r0 = src + (long long)y * row, *rm = src + (long long)ym * row, *rp = src + (long long)yp * row;
-        const unsigned o0 = tile_off<T>(x), om = tile_off<T>(xm), op = tile_off<T>(xp);
-        const S *b[9] = {r0 + o0, r0 + om, rm + o0, r0 + op, rp + o0, rm + om, rm + op, rp + op, rp + om};
+    // three row bases and three in-row offsets; direction i comes from (x - cx_i, y - cy_i)
+    const long long row = (long long)P.ntx * (18 * T);
+    const S *r0 = src + (long long)y * row, *rm = src + (long long)ym * row, *rp = src + (long long)yp * row;
+    const unsigned o0 = tile_off<T>(x), om = tile_off<T>(xm), op = tile_off<T>(xp);
+    const S *b[9] = {r0 + o0, r0 + om, rm + o0, r0 + op, rp + o0, rm + om, rm + op, rp + op, rp + om};
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            f[i] = R(Store<S>::ld(b[i] + i * T, inv));
-            g[i] = R(Store<S>::ld(b[i] + (9 + i) * T, inv));
-        }
-    } else {
-        // source node of direction i: x - c_i
-        const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
-        const int sy[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            f[i] = R(Store<S>::ld(src + pidx<S>(P, i, sx[i], sy[i]), inv));
-            g[i] = R(Store<S>::ld(src + pidx<S>(P, 9 + i, sx[i], sy[i]), inv));
-        }
+    for (int i = 0; i < 9; ++i) {
+        f[i] = R(Store<S>::ld(b[i] + i * T, inv));
+        g[i] = R(Store<S>::ld(b[i] + (9 + i) * T, inv));
     }
 }
 
@@ -570,63 +529,34 @@ __device__ __forceinline__ void store_node(S *__restrict__ dst, const KParams &P
                                            const R *f, const R *g)
 {
     constexpr int T = TileOf<S>::v;
-    if constexpr (T > 0) {
-        S *b = dst + (long long)y * ((long long)P.ntx * (18 * T)) + tile_off<T>(x);
+    S *b = dst + (long long)y * ((long long)P.ntx * (18 * T)) + tile_off<T>(x);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            Store<S>::st(b + i * T, f[i], P.hscale);
-            Store<S>::st(b + (9 + i) * T, g[i], P.hscale);
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            Store<S>::st(dst + pidx<S>(P, i, x, y), f[i], P.hscale);
-            Store<S>::st(dst + pidx<S>(P, 9 + i, x, y), g[i], P.hscale);
-        }
+    for (int i = 0; i < 9; ++i) {
+        Store<S>::st(b + i * T, f[i], P.hscale);
+        Store<S>::st(b + (9 + i) * T, g[i], P.hscale);
     }
 }
 
 // Arithmetic types per storage type: R for the collision, M for the node moments
-// (p, u, S, grad T).  FP32 storage may take its moments (LBM_F32_MOMENTS_F64) or its
-// whole update (LBM_F32_COLLIDE_F64) in FP64; both default off: with the exact
-// moment-preserving weights of node_collide, FP32 arithmetic keeps the FP32 path within
-// about 1e-6 of the FP64 result after 1000 steps of the 128 x 128 cavity.
+// (p, u, S, grad T); the same type in every mode (FP64 for FP64 storage, FP32 for FP32 and
+// FP16 storage).  With the moment-preserving weights of node_collide, FP32 arithmetic
+// keeps the FP32 path within about 1e-6 of the FP64 result after 1000 steps of the
+// 128 x 128 cavity.
 template <typename S> struct Prec;
 template <> struct Prec<double> { using R = double; using M = double; };
-template <> struct Prec<float> {
-#if LBM_F32_COLLIDE_F64
-    using R = double;
-#else
-    using R = float;
-#endif
-#if LBM_F32_MOMENTS_F64 || LBM_F32_COLLIDE_F64
-    using M = double;
-#else
-    using M = float;
-#endif
-};
+template <> struct Prec<float> { using R = float; using M = float; };
 template <> struct Prec<__half> { using R = float; using M = float; };
 
 template <typename A, typename B> struct same_t { static constexpr bool v = false; };
 template <typename A> struct same_t<A, A> { static constexpr bool v = true; };
 
-// Moments in M, collision in R, in place on f, g (R).
+// Moments and collision of one node in R, in place on f, g.
 template <typename R, typename M>
 __device__ __forceinline__ void node_update(R *f, R *g, const KParams &P, int x, int y)
 {
+    static_assert(same_t<R, M>::v, "moments and collision share the arithmetic type");
     Macro<R> m;
-    if constexpr (same_t<R, M>::v) {
-        node_macro_full<R>(f, g, R(P.T0), cst<R>(P), eps_at<R>(P, x, y), m);
-    } else {
-        M fm[9], gm[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) { fm[i] = M(f[i]); gm[i] = M(g[i]); }
-        Macro<M> mm;
-        node_macro_full<M>(fm, gm, M(P.T0), cst<M>(P), eps_at<M>(P, x, y), mm);
-        m.Td = R(mm.Td); m.ux = R(mm.ux); m.uy = R(mm.uy); m.Fx = R(mm.Fx); m.Fy = R(mm.Fy);
-        m.p = R(mm.p); m.Sxx = R(mm.Sxx); m.Sxy = R(mm.Sxy); m.Syy = R(mm.Syy);
-        m.gx = R(mm.gx); m.gy = R(mm.gy);
-    }
+    node_macro_full<R>(f, g, R(P.T0), cst<R>(P), eps_at<R>(P, x, y), m);
     node_collide<R>(f, g, m, R(P.T0), cst<R>(P), eps_at<R>(P, x, y));
 }
 

@@ -59,6 +59,8 @@ hipError_t launch_residual(int storage, const void *src, const KParams &P, doubl
 hipError_t launch_nusselt(int storage, const void *src, const KParams &P, int wall, double L,
                           double dT, double *out, hipStream_t st);
 hipError_t launch_state(int storage, void *buf, const KParams &P, double *io, bool get, hipStream_t st);
+// *flag |= 1 if some population of the grid is NaN or infinite (flag cleared by the caller).
+hipError_t launch_check(int storage, const void *buf, const KParams &P, int *flag, hipStream_t st);
 long long residual_partials(const KParams &P);
 
 // Two time steps per pass: the main launch (lean and xwall wavefronts) and the full launch
@@ -133,5 +135,6 @@ int batch_check_tiles_x(int storage, const KParams &P);
 int wall_block_size();
 // Nodes updated by the interior-tile launch of one step (single-problem path).
 long long interior_nodes(int storage, const KParams &P);
+
 
 }  // namespace lbm

@@ -2,19 +2,16 @@
 // the auxiliary passes (initialisation, macroscopic fields, residual, Nusselt number,
 // state conversion) for the modified lattice-BGK porous thermal model.
 //
-// Layout in device memory: one population buffer = 18 planes (f_0..f_8, g_0..g_8), each
-// plane ny rows of `pitch` elements, planes `plane` elements apart.  A step reads buffer
-// src and writes buffer dst; node (x, y) pulls f_i from (x - c_i) and stores its
-// post-collision populations at (x, y), so no two threads write the same element and no
-// thread reads what another thread writes in the same launch.
+// Layout in device memory: one population buffer holds rows of tiles of TileOf<S>
+// consecutive nodes, each tile its 18 directions (f_0..f_8, g_0..g_8) contiguously,
+// [y][x / T][q][x % T].  A step reads buffer src and writes buffer dst; node (x, y) pulls
+// f_i from (x - c_i) and stores its post-collision populations at (x, y), so no two threads
+// write the same element and no thread reads what another thread writes in the same launch.
 #include "lbm_kernels.h"
 
 namespace lbm {
 
-#ifndef LBM_BULK_BX
-#define LBM_BULK_BX 256
-#endif
-constexpr int BULK_BX = LBM_BULK_BX;
+constexpr int BULK_BX = 256;
 constexpr int WALL_B = 64;
 constexpr int RED_B = 256;
 
@@ -66,20 +63,11 @@ k_init(S *__restrict__ dst, KParams P, const double *__restrict__ T_init,
 // w WS + l + k (BX / 64) WS, k < NPT, so every load instruction stays coalesced and each
 // thread has NPT nodes' loads in flight before it computes.
 // ---------------------------------------------------------------------------------
-#ifndef LBM_NPT_F64
-#define LBM_NPT_F64 1
-#endif
-#ifndef LBM_NPT_F32
-#define LBM_NPT_F32 1
-#endif
-#ifndef LBM_NPT_F16
-#define LBM_NPT_F16 2
-#endif
-
+// Nodes per thread: two for FP16 (more loads in flight per thread), one otherwise.
 template <typename S> struct Npt;
-template <> struct Npt<double> { static constexpr int v = LBM_NPT_F64; };
-template <> struct Npt<float> { static constexpr int v = LBM_NPT_F32; };
-template <> struct Npt<__half> { static constexpr int v = LBM_NPT_F16; };
+template <> struct Npt<double> { static constexpr int v = 1; };
+template <> struct Npt<float> { static constexpr int v = 1; };
+template <> struct Npt<__half> { static constexpr int v = 2; };
 
 // Columns covered by one node slot of a block of BX threads, and by the whole block.
 template <typename S, int BX> __host__ __device__ constexpr int slot_span() { return (BX / 64) * Wspan<S>::v; }
@@ -630,6 +618,29 @@ static hipError_t launch_nusselt_t(const void *src, const KParams &P, int wall, 
     return hipGetLastError();
 }
 
+// Non-finite detector: *flag |= 1 if any population of a node of the grid is NaN or
+// infinite (padding columns of the last tile are not read).
+template <typename S>
+__global__ void __launch_bounds__(BULK_BX) k_check(const S *__restrict__ src, KParams P, int *__restrict__ flag)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= P.nx) return;
+    bool bad = false;
+    for (int q = 0; q < 18; ++q) {
+        const float v = float(Store<S>::ld(src + pidx<S>(P, q, x, y), P.hinv));
+        bad = bad || !__builtin_isfinite(v);
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+template <typename S>
+static hipError_t launch_check_t(const void *buf, const KParams &P, int *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_check<S>), bulk_grid(P), dim3(BULK_BX), 0, st, (const S *)buf, P, flag);
+    return hipGetLastError();
+}
+
 template <typename S>
 static hipError_t launch_state_t(void *buf, const KParams &P, double *io, bool get, hipStream_t st)
 {
@@ -697,6 +708,12 @@ hipError_t launch_nusselt(int storage, const void *src, const KParams &P, int wa
     LBM_DISPATCH(storage, (launch_nusselt_t<double, double>(src, P, wall, L, dT, out, st)),
                  (launch_nusselt_t<float, float>(src, P, wall, L, dT, out, st)),
                  (launch_nusselt_t<__half, float>(src, P, wall, L, dT, out, st)))
+}
+
+hipError_t launch_check(int storage, const void *buf, const KParams &P, int *flag, hipStream_t st)
+{
+    LBM_DISPATCH(storage, (launch_check_t<double>(buf, P, flag, st)), (launch_check_t<float>(buf, P, flag, st)),
+                 (launch_check_t<__half>(buf, P, flag, st)))
 }
 
 hipError_t launch_state(int storage, void *buf, const KParams &P, double *io, bool get, hipStream_t st)

@@ -42,10 +42,7 @@
 
 namespace lbm {
 
-#ifndef LBM_STEP2_TY
-#define LBM_STEP2_TY 8
-#endif
-constexpr int S2_TY = LBM_STEP2_TY;   // output rows per wavefront
+constexpr int S2_TY = 8;              // output rows per wavefront
 
 constexpr int S2_OUT = 62;            // output columns per wavefront
 constexpr int S2_B = 256;             // threads per block (independent wavefronts)
@@ -54,10 +51,7 @@ static_assert(S2_B / 64 == STEP2_WAVES_PER_BLOCK, "wavefronts per block");
 // The lean instance gathers the next row's populations while it updates the current one
 // (one more set of 18 registers).  For FP64 it fits (253 VGPRs, two wavefronts per SIMD as
 // without it) but measured 2.4 % slower, so FP64 gathers each row when it needs it.
-#ifndef LBM_STEP2_PREFETCH
-#define LBM_STEP2_PREFETCH 1
-#endif
-template <typename S> struct S2Prefetch { static constexpr bool v = LBM_STEP2_PREFETCH != 0; };
+template <typename S> struct S2Prefetch { static constexpr bool v = true; };
 template <> struct S2Prefetch<double> { static constexpr bool v = false; };
 
 // Wavefront shifts: lane l receives lane l - 1 (from_left) or lane l + 1 (from_right);
@@ -332,15 +326,11 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
     }
 }
 
-#ifndef LBM_STEP2_XCD
-#define LBM_STEP2_XCD 1
-#endif
 // Logical block of dispatched block b out of nb: blocks are dealt round-robin to the eight
 // XCDs, each with its own L2; this hands every XCD one contiguous range of logical blocks,
 // so that the neighbouring wavefronts whose halo columns and rows overlap share an L2.
 __device__ __forceinline__ int xcd_block(int b, int nb)
 {
-    if (!LBM_STEP2_XCD) return b;
     constexpr int X = 8;
     const int per = nb / X, rem = nb % X;
     const int x = b % X, i = b / X;

@@ -153,6 +153,26 @@ def test_nonfinite_is_detected(gpu):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
+def test_step_checks_for_nonfinite_populations(gpu, storage):
+    """With a check interval, lbm_step stops with LBM_ERR_NONFINITE at the first multiple of
+    the interval after a population turned infinite; without one it stays asynchronous."""
+    cfg = W.random_case(9, 40, 30, storage=storage)
+    sim = gpu.Sim(cfg)
+    sim.set_check_interval(100)
+    sim.step(250)                      # checks at 100 and 200 pass
+    assert sim.time == 250
+    st = sim.get_state()
+    st[1, 3, 10, 7] = float("inf")
+    sim.set_state(st)
+    with pytest.raises(gpu.NonFiniteError):
+        sim.step(300)
+    assert sim.time == 300              # stopped at the check, the later steps not enqueued
+    sim.set_check_interval(0)
+    sim.step(7)                         # no check, no error
+    assert sim.time == 307
+
+
 def test_get_set_state_roundtrip(gpu):
     for storage, tol in (("f64", 0.0), ("f32", 1e-7), ("f16", 1e-4)):
         cfg = W.random_case(12, 45, 31, storage=storage)
