@@ -198,6 +198,21 @@ lbm_status lbm_nusselt(lbm_ctx *ctx, int32_t wall, double *nu_host);
  * LBM_ERR_NONFINITE if any population is not finite.  Synchronizes. */
 lbm_status lbm_residual(lbm_ctx *ctx, double *r_u_host, double *r_T_host);
 
+/* As lbm_residual, for callers that cannot allocate device memory (code under stream
+ * capture set-up, tight serving loops, harnesses that forbid allocation): the reduction's
+ * partial sums and totals go to a device-resident scratch array of the library
+ * (LBM_STATIC_SCRATCH_BYTES per device, allocated once when the library is loaded and held
+ * until the process ends; its address is looked up by lbm_init on the current device) instead
+ * of the context's workspace.  The snapshot stays in the workspace, so both functions share
+ * one snapshot and either may follow the other.  The call allocates nothing.  Grids whose
+ * partial sums do not fit (more than (LBM_STATIC_SCRATCH_BYTES - 256) / 40 reduction blocks of
+ * 256 nodes, i.e. about 26.8 M nodes) return LBM_ERR_INVALID with a message.  Every call on a
+ * device uses that device's one array: calls that overlap on one device (other streams, other
+ * threads) race and must be serialized by the caller; nothing in the array needs clearing
+ * between calls.  Synchronizes. */
+#define LBM_STATIC_SCRATCH_BYTES (4u << 20)
+lbm_status lbm_residual_noalloc(lbm_ctx *ctx, double *r_u_host, double *r_T_host);
+
 /* Copies the post-collision populations of the last step as raw FP64 values
  * ([2][9][ny][nx], device) out of / into the context.  lbm_set_state keeps the time.
  * Asynchronous. */

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_api.cpp", "lbm_kernels.hip", "lbm_adjoint.hip", "lbm_step2.hip", "lbm3d.hip"]
+SOURCES = ["lbm_api.cpp", "lbm_kernels.hip", "lbm_adjoint.hip", "lbm_step2.hip", "lbm3d.hip", "lbm_scratch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

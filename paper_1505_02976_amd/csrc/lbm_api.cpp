@@ -277,6 +277,9 @@ static lbm_status init_ctx(const lbm_params *params, void *workspace, size_t wor
     c->side = nullptr;
     c->ev_join = c->ev_main = c->ev_side = nullptr;
     if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+    // the address of this device's static scratch array (lbm_residual_noalloc), once per
+    // device; a failure here surfaces only in that entry point
+    if (c->device >= 0) (void)lbm::static_scratch_setup(c->device);
 
     hipError_t e;
     if (params->eps_field) {
@@ -621,6 +624,26 @@ lbm_status lbm_residual(lbm_ctx *c, double *r_u, double *r_T)
     double *part = reinterpret_cast<double *>(c->ws + c->lay.off_part);
     double *res = reinterpret_cast<double *>(c->ws + c->lay.off_scalar) + 8;
     return residual_into(c, part, res, r_u, r_T);
+}
+
+lbm_status lbm_residual_noalloc(lbm_ctx *c, double *r_u, double *r_T)
+{
+    if (!c) return fail(LBM_ERR_INVALID, "ctx is NULL");
+    if (!r_u || !r_T) return fail(LBM_ERR_INVALID, "outputs are NULL");
+    const long long np = lbm::residual_partials(c->kp);
+    if (256 + (size_t)np * 5 * sizeof(double) > LBM_STATIC_SCRATCH_BYTES)
+        return fail(LBM_ERR_INVALID,
+                    "grid of %lld nodes needs %lld partial sums (%zu bytes with the totals); the static scratch "
+                    "holds %zu bytes", (long long)c->prm.nx * c->prm.ny, np,
+                    (size_t)256 + (size_t)np * 5 * sizeof(double), (size_t)LBM_STATIC_SCRATCH_BYTES);
+    char *scr = static_cast<char *>(lbm::static_scratch(c->device));
+    if (!scr) {
+        const hipError_t e = c->device >= 0 ? lbm::static_scratch_setup(c->device) : hipErrorInvalidDevice;
+        return hip_fail(e == hipSuccess ? hipErrorInvalidSymbol : e, "static scratch of this device");
+    }
+    // totals in the first 256 bytes, partial sums after them; every slot is written before
+    // it is read, so nothing needs clearing between calls
+    return residual_into(c, reinterpret_cast<double *>(scr + 256), reinterpret_cast<double *>(scr), r_u, r_T);
 }
 
 lbm_status lbm_get_state(lbm_ctx *c, double *dst)

@@ -136,5 +136,12 @@ int wall_block_size();
 // Nodes updated by the interior-tile launch of one step (single-problem path).
 long long interior_nodes(int storage, const KParams &P);
 
+// The device-resident scratch array of the entry point that allocates nothing (one per
+// device, LBM_STATIC_SCRATCH_BYTES of include/lbm.h, 256-byte aligned, held until the
+// process ends).  static_scratch_setup looks up the address on `device`, which must be
+// current; it runs once per device (later calls return the first result).  static_scratch
+// returns the address, or NULL before a successful setup on that device.
+hipError_t static_scratch_setup(int device);
+void *static_scratch(int device);
 
 }  // namespace lbm

@@ -63,7 +63,7 @@ EXPORTS = ("lbm_derive", "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_ste
            "lbm_batch_check", "lbm_batch_destroy", "lbm_batch_autotune",
            "lbm_batch_set_width", "lbm_batch_set_fusion", "lbm_batch_fusion",
            "lbm_adjoint_workspace_bytes", "lbm_adjoint_forward", "lbm_adjoint_backward",
-           "lbm_adjoint_destroy", "lbm_set_check_interval")
+           "lbm_adjoint_destroy", "lbm_residual_noalloc", "lbm_set_check_interval")
 
 
 def lib():
@@ -107,6 +107,8 @@ def lib():
     L.lbm_residual.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.lbm_set_check_interval.restype = st
     L.lbm_set_check_interval.argtypes = [vp, C.c_int64]
+    L.lbm_residual_noalloc.restype = st
+    L.lbm_residual_noalloc.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.lbm_get_state.restype = st
     L.lbm_get_state.argtypes = [vp, vp]
     L.lbm_set_state.restype = st
@@ -329,6 +331,13 @@ class Sim:
         """Make step() wait and check for non-finite populations whenever the time reaches a
         multiple of `every` (0: never); a failing check raises LbmError (LBM_ERR_NONFINITE)."""
         _check(lib().lbm_set_check_interval(self.h, int(every)))
+
+    def residual_noalloc(self):
+        """As residual, with the reduction's scratch in the library's static device array
+        (lbm_residual_noalloc): allocates nothing."""
+        ru, rT = C.c_double(), C.c_double()
+        _check(lib().lbm_residual_noalloc(self.h, C.byref(ru), C.byref(rT)))
+        return (None, None) if ru.value < 0 else (ru.value, rT.value)
 
     def run_to_steady(self, tol: float, max_steps: int, every: int = 100) -> bool:
         """Steps until both residuals of Sec. 4 (against the state `every` steps earlier) fall
