@@ -682,7 +682,7 @@ struct lbm_adjoint {
     int64_t nsteps, K, nck;
     char *ws;
     size_t pop;
-    size_t off_ck, off_seg, off_lam0, off_lam1, off_mu, off_wf, off_wt, off_we, off_wtj;
+    size_t off_ck, off_seg, off_lam0, off_lam1, off_wf, off_wt, off_we, off_wtj;
     double J;
 };
 
@@ -690,7 +690,7 @@ namespace {
 
 struct AdjLayout {
     int64_t K, nck;
-    size_t off_ck, off_seg, off_lam0, off_lam1, off_mu, off_wf, off_wt, off_we, off_wtj, total;
+    size_t off_ck, off_seg, off_lam0, off_lam1, off_wf, off_wt, off_we, off_wtj, total;
 };
 
 AdjLayout adj_layout(const lbm_ctx *c, int64_t nsteps)
@@ -707,7 +707,6 @@ AdjLayout adj_layout(const lbm_ctx *c, int64_t nsteps)
     L.off_seg = o; o += (size_t)K * pop;
     L.off_lam0 = o; o += align_up(18 * N * 8, 256);
     L.off_lam1 = o; o += align_up(18 * N * 8, 256);
-    L.off_mu = o; o += align_up(18 * N * 8, 256);
     L.off_wf = o; o += align_up(18 * N * 8, 256);
     L.off_wt = o; o += align_up(N * 8, 256);
     L.off_we = o; o += align_up(N * 8, 256);
@@ -798,7 +797,7 @@ lbm_status lbm_adjoint_forward(lbm_ctx *c, int32_t wall, int64_t nsteps, void *w
     a->ctx = c; a->wall = wall; a->nsteps = nsteps; a->K = L.K; a->nck = L.nck; a->ws = ws;
     a->pop = c->lay.pop_bytes;
     a->off_ck = L.off_ck; a->off_seg = L.off_seg; a->off_lam0 = L.off_lam0; a->off_lam1 = L.off_lam1;
-    a->off_mu = L.off_mu; a->off_wf = L.off_wf; a->off_wt = L.off_wt; a->off_we = L.off_we;
+    a->off_wf = L.off_wf; a->off_wt = L.off_wt; a->off_we = L.off_we;
     a->off_wtj = L.off_wtj;
     a->J = J;
     *nu_host = J;
@@ -816,7 +815,6 @@ lbm_status lbm_adjoint_backward(lbm_adjoint *a, double dJ, double *grad)
     char *ws = a->ws;
     double *lam[2] = {reinterpret_cast<double *>(ws + a->off_lam0), reinterpret_cast<double *>(ws + a->off_lam1)};
     lbm::AdjBufs A;
-    A.mu = reinterpret_cast<double *>(ws + a->off_mu);
     A.wf = reinterpret_cast<double *>(ws + a->off_wf);
     A.wt = reinterpret_cast<double *>(ws + a->off_wt);
     A.we = reinterpret_cast<double *>(ws + a->off_we);

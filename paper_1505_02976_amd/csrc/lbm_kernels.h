@@ -33,7 +33,6 @@ struct Batch2Kernels {
 struct AdjBufs {
     const double *lam_next;   // adjoint of s_{t+1}
     double *lam;              // adjoint of s_t (output)
-    double *mu;               // adjoint of the pre-collision populations
     double *wf;               // wall nodes: adjoint of the reference node's populations
     double *wt;               // wall nodes: adjoint of T at x_ff
     double *we;               // wall nodes: adjoint of eps at the reference node
