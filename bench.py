@@ -188,7 +188,7 @@ def adjoint_run(lbm, torch, W, n=256, steps=5000, storage="f32"):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     res = {"workload": f"adjoint cavity {n}x{n} (Ra 1e5, Pr 1, Da 1e-2, porosity field), {steps} steps, "
-                       f"{storage} storage, FP64 adjoint arithmetic",
+                       f"{storage} storage, adjoint arithmetic " + ("FP64" if storage == "f64" else "FP32"),
            "Nu": adj.value, "forward_s": t1 - t0, "backward_s": t2 - t1,
            "backward_us_per_step": (t2 - t1) / steps * 1e6,
            "backward_node_steps_per_s": n * n * steps / (t2 - t1),

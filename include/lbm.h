@@ -280,8 +280,10 @@ void lbm_batch_destroy(lbm_batch *batch);
 /* Adjoint: gradient of an average Nusselt number (Eq. AvNuss) after nsteps steps with   */
 /* respect to the porosity of every node, by the discrete adjoint of the step           */
 /* (reverse sweep over sqrt(nsteps)-spaced checkpoints, forward states recomputed per    */
-/* segment; vector-Jacobian products of each node update from FP64 dual numbers through  */
-/* the same node code as the forward step).                                             */
+/* segment).  Off the walls each node update is reversed by hand in the storage's        */
+/* arithmetic (FP64 for FP64 storage, FP32 for FP32 and FP16; drag solve in FP64); at     */
+/* wall nodes the Jacobian comes from FP64 dual numbers pushed through the boundary      */
+/* scheme's own code.                                                                    */
 /* ---------------------------------------------------------------------------------- */
 typedef struct lbm_adjoint lbm_adjoint;
 
