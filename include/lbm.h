@@ -222,7 +222,7 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const double *src_device);
 /* ---------------------------------------------------------------------------------- */
 /* Batches: many independent problems (uneven grids and parameters, one storage type)  */
 /* advanced together: the same launches per step (or per two-step pass) for all of    */
-/* them, replayed from a HIP graph.                                                    */
+/* them.                                                                               */
 /* ---------------------------------------------------------------------------------- */
 typedef struct lbm_batch lbm_batch;
 
@@ -238,9 +238,13 @@ size_t lbm_batch_workspace_bytes(const lbm_params *params, int32_t n);
 lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, size_t workspace_bytes,
                           void *hip_stream, lbm_batch **out);
 
-/* Enqueues nsteps time steps of every problem: whole graphs of 64 steps, then two-step
- * passes and single steps for the remainder.  The graph is built on the first call that
- * needs it.  Results are bitwise those of lbm_step on each problem alone.  Asynchronous. */
+/* Enqueues nsteps time steps of every problem.  With two steps per pass: nsteps / 2
+ * passes (each pass's launches for the wavefronts next to the walled rows run on a second
+ * stream of the batch beside its main launch, ordered by events; the call is ordered like
+ * launches on the batch's stream), then one single step if nsteps is odd.  With one step
+ * per pass: whole HIP graphs of 64 steps (built on the first call that needs one), then
+ * single steps.  Results are bitwise those of lbm_step on each problem alone.
+ * Asynchronous. */
 lbm_status lbm_batch_step(lbm_batch *batch, int64_t nsteps);
 
 /* Time steps per batched pass, 1 or 2 (as lbm_set_fusion, for all problems at once).  The

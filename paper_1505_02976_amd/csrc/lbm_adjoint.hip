@@ -88,13 +88,7 @@ __device__ __forceinline__ void node_vjp(const R *f, const R *g, double eps_d, c
     const R X = s18 + cuu * uu + cuF * uF;
     const R p = (R(0.6) * ieps) * X;
     const R ep = eps * p;
-    const R Pxx = ((f[1] + f[3]) + (f[5] + f[6])) + (f[7] + f[8]);
-    const R Pyy = ((f[2] + f[4]) + (f[5] + f[6])) + (f[7] + f[8]);
-    const R Pxy = (f[5] - f[6]) + (f[7] - f[8]);
     const R qxx = ux * ux - ux * Fx, qyy = uy * uy - uy * Fy, qxy = ux * uy - R(0.5) * (ux * Fy + Fx * uy);
-    const R Sxx = (Pxx - ep - qxx * ieps) * k.Sden;
-    const R Syy = (Pyy - ep - qyy * ieps) * k.Sden;
-    const R Sxy = (Pxy - qxy * ieps) * k.Sden;
     const R hx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
     const R hy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
     const R T = R(P.T0) + Td;
@@ -107,10 +101,9 @@ __device__ __forceinline__ void node_vjp(const R *f, const R *g, double eps_d, c
     const R cc = bM * uN / d;
     const R ia = R(1) / a;
     const R gx = (Nx + cc * ux) * ia, gy = (Ny + cc * uy) * ia;
-    // collision coefficients (node_collide)
-    const R trS = Sxx + Syy;
+    // collision coefficients (node_collide; the collision is linear in S, whose value the
+    // reverse pass does not need)
     const R ugT = ux * gx + uy * gy;
-    const R vvx = T * Fx + ep * gx, vvy = T * Fy + ep * gy;
     const R k45 = R(4.5) * ieps, c9 = R(9) * k.fF * ieps;
     const R T45 = k45 * T;
     const R sco = k.itT * T + k.fT * ((ieps - k.isig) * ugT + k.Q * k.isig);

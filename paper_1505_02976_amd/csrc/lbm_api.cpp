@@ -660,9 +660,8 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *src)
     return e == hipSuccess ? LBM_OK : hip_fail(e, "set_state");
 }
 
-void lbm_destroy(lbm_ctx *c)
+static void release_ctx(lbm_ctx *c)
 {
-    if (!c || c->in_batch) return;
     if (c->side) {
         (void)hipStreamSynchronize(c->side);
         (void)hipStreamDestroy(c->side);
@@ -671,6 +670,12 @@ void lbm_destroy(lbm_ctx *c)
     if (c->ev_main) (void)hipEventDestroy(c->ev_main);
     if (c->ev_side) (void)hipEventDestroy(c->ev_side);
     delete c;
+}
+
+void lbm_destroy(lbm_ctx *c)
+{
+    if (!c || c->in_batch) return;
+    release_ctx(c);
 }
 
 // ---------------------------------------------------------------------------------
@@ -866,11 +871,14 @@ struct lbm_batch {
     int2 *items2[lbm::STEP2_LAUNCHES];   // item tables of the batched two-step pass per launch
     int2 *rows2;
     int nitems2[lbm::STEP2_LAUNCHES], nrows2;
-    hipGraph_t graph;
+    hipGraph_t graph;           // one-step mode: GRAPH_STEPS steps replayed as one graph
     hipGraphExec_t exec;
     int graph_steps;
     int graph_cur;              // value of cur the graph's launches assume (replays keep it)
-    int graph_fuse;
+    // Two-step passes: the full launch and the walled rows go to a second stream beside the
+    // main launch (a graph replays its independent launches one after the other).
+    hipStream_t side;
+    hipEvent_t ev_join, ev_main, ev_side;
     int bx;                     // block width of the batched one-step update
     int w2;                     // wavefronts per block of the batched two-step main launch
     size_t edge_cap;            // capacity of the edge item table (items)
@@ -932,11 +940,13 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
             int rb = 0;
             long long mn = 0;
             lbm::step2_lists(kp, xw, lean, fullv, rb, mn);
-            // per problem its xwall then its lean wavefronts: the XCD ranges of logical blocks
-            // then hold whole problems (their halos stay in one L2) and share the heavier
-            // xwall wavefronts about evenly
-            for (int w : xw) B.items2[lbm::STEP2_MAIN].push_back(make_int2(k, w));
-            for (int w : lean) B.items2[lbm::STEP2_MAIN].push_back(make_int2(k, w));
+            // per problem its main wavefronts in row-major order (xwall and lean merged by
+            // index): neighbouring column chunks of a band then run side by side on one XCD
+            // and fetch the cache lines their halo columns share once
+            std::vector<int> mainv(xw);
+            mainv.insert(mainv.end(), lean.begin(), lean.end());
+            std::sort(mainv.begin(), mainv.end());
+            for (int w : mainv) B.items2[lbm::STEP2_MAIN].push_back(make_int2(k, w));
             for (int w : fullv) B.items2[lbm::STEP2_FULL].push_back(make_int2(k, w));
             for (int r = 0; r < rb; ++r) B.rows2.push_back(make_int2(k, r));
         } else {
@@ -964,88 +974,49 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
     return LBM_OK;
 }
 
-constexpr int GRAPH_STEPS = 64;   // even, and even in two-step passes: a replay keeps `cur`
+constexpr int GRAPH_STEPS = 64;   // even: a replay leaves the state in the buffer it started from
 
 hipError_t add_kernel_node(hipGraph_t g, const void *func, int grid, int threads, void **args,
-                           const std::vector<hipGraphNode_t> &deps, hipGraphNode_t *node, size_t lds_bytes = 0)
+                           const std::vector<hipGraphNode_t> &deps, hipGraphNode_t *node)
 {
     hipKernelNodeParams kp = {};
     kp.func = const_cast<void *>(func);
     kp.gridDim = dim3(grid);
     kp.blockDim = dim3(threads);
-    kp.sharedMemBytes = (unsigned)lds_bytes;
+    kp.sharedMemBytes = 0;
     kp.kernelParams = args;
     kp.extra = nullptr;
     return hipGraphAddKernelNode(node, g, deps.empty() ? nullptr : deps.data(), deps.size(), &kp);
 }
 
-// GRAPH_STEPS steps of every problem as one graph, starting from buffer b->cur.  One-step
-// mode: per step the bulk and the wall launches, both after the previous step.  Two-step
-// mode: per pass the full and main launches after the previous pass, the walled-row
-// launch after the full one (it reads the scratch rows the full launch writes).
+// GRAPH_STEPS one-step updates of every problem as one graph, starting from buffer b->cur:
+// per step the bulk and the wall launches, both after the previous step.
 lbm_status batch_build_graph(lbm_batch *b)
 {
     hipError_t e = hipGraphCreate(&b->graph, 0);
     if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
     const lbm::BatchProblem *probs = b->probs;
     std::vector<hipGraphNode_t> prev;
-    if (b->fuse == 2) {
-        const lbm::Batch2Kernels K = lbm::batch2_kernels(b->storage);
-        for (int s = 0; s < GRAPH_STEPS / 2 && e == hipSuccess; ++s) {
-            int parity = (b->cur + s) & 1;
-            std::vector<hipGraphNode_t> cur;
-            hipGraphNode_t full = nullptr, node;
-            const int2 *items[lbm::STEP2_LAUNCHES], *rows = b->rows2;
-            int nitems[lbm::STEP2_LAUNCHES];
-            void *args[lbm::STEP2_LAUNCHES][4];
-            // the full launch first: its few wavefronts then start beside the main ones
-            const int order[lbm::STEP2_LAUNCHES] = {lbm::STEP2_FULL, lbm::STEP2_MAIN};
-            for (int m : order) {
-                if (e != hipSuccess) break;
-                items[m] = b->items2[m];
-                nitems[m] = b->nitems2[m];
-                if (nitems[m] == 0) continue;
-                args[m][0] = (void *)&probs;
-                args[m][1] = (void *)&items[m];
-                args[m][2] = (void *)&nitems[m];
-                args[m][3] = (void *)&parity;
-                // the full launch with the widest blocks, the main one with the tuned width
-                const int W = m == lbm::STEP2_MAIN ? b->w2 : K.waves_per_block;
-                e = add_kernel_node(b->graph, K.main[m], (nitems[m] + W - 1) / W, 64 * W, args[m], prev, &node,
-                                    m == lbm::STEP2_MAIN ? (size_t)W * K.lds_per_wave : 0);
-                if (e == hipSuccess) cur.push_back(node);
-                if (m == lbm::STEP2_FULL) full = node;
-            }
-            void *ar[3] = {(void *)&probs, (void *)&rows, (void *)&parity};
-            if (e == hipSuccess && b->nrows2 > 0) {
-                std::vector<hipGraphNode_t> dep = full ? std::vector<hipGraphNode_t>{full} : prev;
-                e = add_kernel_node(b->graph, K.rows, b->nrows2, 64, ar, dep, &node);
-                if (e == hipSuccess) cur.push_back(node);
-            }
-            prev.swap(cur);
+    lbm::BatchKernels K;
+    if (!lbm::batch_kernels(b->storage, b->bx, K)) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+        return fail(LBM_ERR_INVALID, "block width %d", b->bx);
+    }
+    for (int s = 0; s < GRAPH_STEPS && e == hipSuccess; ++s) {
+        int parity = (b->cur + s) & 1;
+        std::vector<hipGraphNode_t> cur;
+        for (int w = 0; w < 3 && e == hipSuccess; ++w) {
+            const int nblk = w == 0 ? b->nbulk : (w == 1 ? b->nedge : b->nwall);
+            if (nblk == 0) continue;
+            const int2 *items = w == 0 ? b->bulk_items : (w == 1 ? b->edge_items : b->wall_items);
+            void *args[3] = {(void *)&probs, (void *)&items, (void *)&parity};
+            hipGraphNode_t node;
+            e = add_kernel_node(b->graph, w == 0 ? K.bulk : (w == 1 ? K.edge : K.wall), nblk,
+                                w < 2 ? K.bulk_threads : K.wall_threads, args, prev, &node);
+            if (e == hipSuccess) cur.push_back(node);
         }
-    } else {
-        lbm::BatchKernels K;
-        if (!lbm::batch_kernels(b->storage, b->bx, K)) {
-            (void)hipGraphDestroy(b->graph);
-            b->graph = nullptr;
-            return fail(LBM_ERR_INVALID, "block width %d", b->bx);
-        }
-        for (int s = 0; s < GRAPH_STEPS && e == hipSuccess; ++s) {
-            int parity = (b->cur + s) & 1;
-            std::vector<hipGraphNode_t> cur;
-            for (int w = 0; w < 3 && e == hipSuccess; ++w) {
-                const int nblk = w == 0 ? b->nbulk : (w == 1 ? b->nedge : b->nwall);
-                if (nblk == 0) continue;
-                const int2 *items = w == 0 ? b->bulk_items : (w == 1 ? b->edge_items : b->wall_items);
-                void *args[3] = {(void *)&probs, (void *)&items, (void *)&parity};
-                hipGraphNode_t node;
-                e = add_kernel_node(b->graph, w == 0 ? K.bulk : (w == 1 ? K.edge : K.wall), nblk,
-                                    w < 2 ? K.bulk_threads : K.wall_threads, args, prev, &node);
-                if (e == hipSuccess) cur.push_back(node);
-            }
-            prev.swap(cur);
-        }
+        prev.swap(cur);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -1055,7 +1026,6 @@ lbm_status batch_build_graph(lbm_batch *b)
     }
     b->graph_steps = GRAPH_STEPS;
     b->graph_cur = b->cur;
-    b->graph_fuse = b->fuse;
     return LBM_OK;
 }
 
@@ -1100,7 +1070,6 @@ lbm_status batch_set_waves2(lbm_batch *b, int waves)
         return fail(LBM_ERR_INVALID, "wavefronts per block %d", waves);
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "batch width");
-    if (waves != b->w2) batch_drop_graph(b);
     b->w2 = waves;
     return LBM_OK;
 }
@@ -1137,7 +1106,8 @@ lbm_status lbm_batch_init(const lbm_params *params, int32_t n, void *workspace, 
     b->exec = nullptr;
     b->graph_steps = 0;
     b->graph_cur = 0;
-    b->graph_fuse = 0;
+    b->side = nullptr;
+    b->ev_join = b->ev_main = b->ev_side = nullptr;
     b->bx = lbm::batch_width(0);
     b->w2 = lbm::STEP2_WAVES_PER_BLOCK;
     b->edge_cap = B.edge.size();
@@ -1216,16 +1186,44 @@ hipError_t batch_single(lbm_batch *b)
     return e;
 }
 
-// One two-step pass of every problem from buffer b->cur (the state two steps later lands
-// in the other buffer).
-hipError_t batch_pass(lbm_batch *b)
+hipError_t batch_ensure_side(lbm_batch *b)
 {
-    hipError_t e = lbm::launch_batch_step2(b->storage, b->probs, b->items2, b->nitems2, b->rows2, b->nrows2,
-                                           b->cur, b->w2, b->stream);
-    if (e == hipSuccess) {
-        b->t += 2;
-        b->cur ^= 1;
+    if (b->side) return hipSuccess;
+    hipError_t e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_main, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_side, hipEventDisableTiming);
+    return e;
+}
+
+// npass two-step passes of every problem, ordered as run_passes orders one problem's: the
+// main launch on the batch's stream, the full launch and the walled rows on the side stream;
+// pass p's main launch waits for the side stream's pass p - 1, its full launch for the main
+// launch of pass p - 1.  advance: pass p reads buffer cur and writes the other one, then cur
+// flips (the time advances); otherwise every pass reads and writes the same buffers (the
+// autotuner's timing passes, which leave the state as it is).  waves: wavefronts per block
+// of the main launch.
+hipError_t batch_passes(lbm_batch *b, int64_t npass, bool advance, int waves)
+{
+    hipError_t e = batch_ensure_side(b);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_join, 0);
+    for (int64_t p = 0; p < npass && e == hipSuccess; ++p) {
+        if (p > 0) {
+            e = hipStreamWaitEvent(b->stream, b->ev_side, 0);
+            if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_main, 0);
+        }
+        if (e == hipSuccess)
+            e = lbm::launch_batch_step2(b->storage, b->probs, b->items2, b->nitems2, b->rows2, b->nrows2, b->cur,
+                                        waves, b->stream, b->side);
+        if (e == hipSuccess) e = hipEventRecord(b->ev_side, b->side);
+        if (e == hipSuccess) e = hipEventRecord(b->ev_main, b->stream);
+        if (e == hipSuccess && advance) {
+            b->t += 2;
+            b->cur ^= 1;
+        }
     }
+    if (e == hipSuccess && npass > 0) e = hipStreamWaitEvent(b->stream, b->ev_side, 0);
     return e;
 }
 
@@ -1237,27 +1235,27 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
     if (nsteps < 0) return fail(LBM_ERR_INVALID, "nsteps < 0");
     int64_t left = nsteps;
     hipError_t e = hipSuccess;
-    if (b->exec && b->graph_fuse != b->fuse) batch_drop_graph(b);
-    // a graph replays from the buffer it was built for: one single step realigns `cur`
-    if (b->exec && b->cur != b->graph_cur && left > GRAPH_STEPS) {
-        e = batch_single(b);
-        if (e != hipSuccess) return hip_fail(e, "batch step");
-        --left;
-    }
-    if (left >= GRAPH_STEPS && !b->exec) {
-        lbm_status st = batch_build_graph(b);
-        if (st != LBM_OK) return st;
-    }
-    while (left >= GRAPH_STEPS && b->cur == b->graph_cur) {
-        e = hipGraphLaunch(b->exec, b->stream);
-        if (e != hipSuccess) return hip_fail(e, "batch graph launch");
-        left -= GRAPH_STEPS;
-        b->t += GRAPH_STEPS;
-    }
-    while (b->fuse == 2 && left >= 2) {
-        e = batch_pass(b);
-        if (e != hipSuccess) return hip_fail(e, "batch pass");
-        left -= 2;
+    if (b->fuse == 2) {
+        e = batch_passes(b, left / 2, true, b->w2);
+        if (e != hipSuccess) return hip_fail(e, "batch passes");
+        left %= 2;
+    } else {
+        // a graph replays from the buffer it was built for: one single step realigns `cur`
+        if (b->exec && b->cur != b->graph_cur && left > GRAPH_STEPS) {
+            e = batch_single(b);
+            if (e != hipSuccess) return hip_fail(e, "batch step");
+            --left;
+        }
+        if (left >= GRAPH_STEPS && !b->exec) {
+            lbm_status st = batch_build_graph(b);
+            if (st != LBM_OK) return st;
+        }
+        while (left >= GRAPH_STEPS && b->cur == b->graph_cur) {
+            e = hipGraphLaunch(b->exec, b->stream);
+            if (e != hipSuccess) return hip_fail(e, "batch graph launch");
+            left -= GRAPH_STEPS;
+            b->t += GRAPH_STEPS;
+        }
     }
     while (left > 0) {
         e = batch_single(b);
@@ -1323,12 +1321,11 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t steps, int32_t *width, doubl
         // every launch reads the current buffers and writes the other ones (and, for
         // two-step passes, the scratch rows), so the state is kept
         auto run = [&](int n) {
+            if (two) return batch_passes(b, n, false, bx / 64);
             hipError_t r = hipSuccess;
             for (int s = 0; s < n && r == hipSuccess; ++s)
-                r = two ? lbm::launch_batch_step2(b->storage, b->probs, b->items2, b->nitems2, b->rows2, b->nrows2,
-                                                  parity, bx / 64, b->stream)
-                        : lbm::launch_batch_step(b->storage, b->bx, b->probs, b->bulk_items, b->nbulk,
-                                                 b->edge_items, b->nedge, b->wall_items, b->nwall, parity, b->stream);
+                r = lbm::launch_batch_step(b->storage, b->bx, b->probs, b->bulk_items, b->nbulk, b->edge_items,
+                                           b->nedge, b->wall_items, b->nwall, parity, b->stream);
             return r;
         };
         const int reps = two ? (steps + 1) / 2 : steps;
@@ -1368,7 +1365,14 @@ void lbm_batch_destroy(lbm_batch *b)
 {
     if (!b) return;
     batch_drop_graph(b);
-    for (lbm_ctx *c : b->ctx) delete c;
+    if (b->side) {
+        (void)hipStreamSynchronize(b->side);
+        (void)hipStreamDestroy(b->side);
+    }
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->ev_main) (void)hipEventDestroy(b->ev_main);
+    if (b->ev_side) (void)hipEventDestroy(b->ev_side);
+    for (lbm_ctx *c : b->ctx) release_ctx(c);
     delete b;
 }
 

@@ -22,13 +22,6 @@ struct BatchProblem {
 enum : int { STEP2_LEAN = 0, STEP2_FULL = 1, STEP2_XWALL = 2 };
 enum : int { STEP2_MAIN = 0, STEP2_LAUNCHES = 2 };
 
-struct Batch2Kernels {
-    const void *main[STEP2_LAUNCHES];   // k_batch_step2 per launch (STEP2_MAIN, STEP2_FULL)
-    const void *rows;
-    int threads, waves_per_block;       // block shape of the full launch (the most wavefronts per block)
-    size_t lds_per_wave;                // dynamic LDS bytes per wavefront of the main launch
-};
-
 // Device buffers of the adjoint sweep (FP64, [18][ny][nx] for the 18-component arrays).
 struct AdjBufs {
     const double *lam_next;   // adjoint of s_{t+1}
@@ -110,10 +103,11 @@ hipError_t launch_step2_rows(int storage, void *dst, const void *scr, const KPar
 
 // Batched two-step passes: items[l] (problem, wavefront index) for launch l, nitems[l] of
 // them; rows: (problem, block of 64 walled-row nodes); main_waves: wavefronts per block of
-// the main launch (1, 2 or 4).
+// the main launch (1, 2 or 4).  The full launch and then the walled rows go to st_side, the
+// main launch to st_main; the caller orders the two streams (they may be the same one).
 hipError_t launch_batch_step2(int storage, const BatchProblem *probs, const int2 *const *items, const int *nitems,
-                              const int2 *rows, int nrows, int parity, int main_waves, hipStream_t st);
-Batch2Kernels batch2_kernels(int storage);
+                              const int2 *rows, int nrows, int parity, int main_waves, hipStream_t st_main,
+                              hipStream_t st_side);
 
 // Adjoint sweep.
 hipError_t launch_adjoint_step(int storage, const void *state, const KParams &P, const AdjBufs &A,

@@ -20,10 +20,11 @@
 // the boundary scheme inline, with the wall node taking its reference node's pulled
 // populations from the neighbouring lanes, as in the one-step kernel).  The walled rows
 // y = 0 and y = ny - 1 need the intermediate populations of three more rows for their
-// reference nodes, so the full instance writes P1 of rows 0-3 and ny-4..ny-1 to a small
-// scratch grid and a last launch finishes those two rows.  A pass is two launches over
-// wavefront lists built on the host: the main one (xwall and lean wavefronts, the instance
-// chosen per wavefront) and the full one, then the walled rows.
+// reference nodes, so the full instance, which runs the bands of rows 0-3 and ny-4..ny-1,
+// writes P1 of those rows to a small scratch grid and a last launch finishes the two
+// walled rows.  A pass is two launches over wavefront lists built on the host: the main
+// one (xwall and lean wavefronts, the instance chosen per wavefront) and the full one, then
+// the walled rows.
 //
 // Every node update is the one-step node code with the same inputs, so two steps here are
 // bitwise identical to two one-step launches (FP16 storage rounds P1 to the stored format
@@ -109,12 +110,38 @@ __host__ __device__ __forceinline__ int s2_x0(const KParams &P, int cxi)
     return P.px ? min(cxi * S2_OUT, P.nx - S2_OUT) : min(cxi * S2_OUT, P.nx - 3);
 }
 
+// Row bands.  Periodic y: bands of S2_TY rows from y = 0 (the last one may be shorter).
+// Walls in y: band 0 holds rows 0-3 and the last band rows ny-4..ny-1, both for the full
+// instance (the walled rows, and the intermediate rows their boundary scheme reads from the
+// scratch grid); between them bands of S2_TY rows from y = 4, the last one ending at ny - 4
+// (their halo rows 3 and ny - 4 are recomputed but not written to the scratch grid).
+__host__ __device__ __forceinline__ int s2_nbands(const KParams &P)
+{
+    return P.py ? (P.ny + S2_TY - 1) / S2_TY : 2 + (P.ny - 8 + S2_TY - 1) / S2_TY;
+}
+
+__host__ __device__ __forceinline__ void s2_band(const KParams &P, int cyi, int &Y0, int &Y1)
+{
+    if (P.py) {
+        Y0 = cyi * S2_TY;
+        Y1 = min(Y0 + S2_TY, P.ny);
+    } else if (cyi == 0) {
+        Y0 = 0;
+        Y1 = 4;
+    } else if (cyi == s2_nbands(P) - 1) {
+        Y0 = P.ny - 4;
+        Y1 = P.ny;
+    } else {
+        Y0 = 4 + (cyi - 1) * S2_TY;
+        Y1 = min(Y0 + S2_TY, P.ny - 4);
+    }
+}
+
 __host__ __device__ __forceinline__ int s2_kind(const KParams &P, int cxi, int cyi)
 {
     const int X0 = s2_x0(P, cxi);
-    const int Y0 = cyi * S2_TY, Y1 = min(Y0 + S2_TY, P.ny);
     const bool xin = P.px || (X0 - 1 >= 1 && X0 + S2_OUT <= P.nx - 2);
-    const bool yin = P.py || (Y0 - 1 >= 4 && Y1 <= P.ny - 5);
+    const bool yin = P.py || (cyi > 0 && cyi < s2_nbands(P) - 1);
     return yin ? (xin ? STEP2_LEAN : STEP2_XWALL) : STEP2_FULL;
 }
 
@@ -150,7 +177,8 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
     else xok = x >= 0 && x < P.nx;
     const bool xout = lane >= 1 && lane <= S2_OUT && xok;
     const bool vwall = xok && !P.px && (x == 0 || x == P.nx - 1);
-    const int Y0 = cyi * S2_TY, Y1 = min(Y0 + S2_TY, P.ny);
+    int Y0, Y1;
+    s2_band(P, cyi, Y0, Y1);
     // xwall: lanes outside the grid compute on the nearest column (results unused); wl[0],
     // wl[1] = lanes of the columns x = 0 and x = nx - 1, -1 when not in this wavefront
     const int xs = XW ? min(max(x, 0), P.nx - 1) : x;
@@ -339,11 +367,13 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 
 // One wavefront's walk with the instance chosen at run time: the main launch runs the lean
 // and the xwall wavefronts (both about 135 VGPRs), the full launch the full ones.
+// w: wavefront index cyi * ncx + cxi.
 template <typename S, int LAUNCH>
 __device__ __forceinline__ void march2_any(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr,
-                                           const KParams &P, const KParams &Pm, int cxi, int cyi, int lane,
+                                           const KParams &P, const KParams &Pm, int w, int ncx, int lane,
                                            typename Prec<S>::R *lds)
 {
+    const int cxi = w % ncx, cyi = w / ncx;
     if constexpr (LAUNCH == STEP2_FULL)
         march2<S, STEP2_FULL>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
     else if (s2_kind(P, cxi, cyi) == STEP2_XWALL)     // wavefront-uniform
@@ -366,8 +396,7 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KPa
     __shared__ R lds[S2_B / 64][LAUNCH == STEP2_FULL ? 1 : S2_LDS];
     const int wi = xcd_block(blockIdx.x, gridDim.x) * (S2_B / 64) + (threadIdx.x >> 6);
     if (wi >= nitems) return;                            // wavefront-uniform
-    const int w = items[wi];
-    march2_any<S, LAUNCH>(src, dst, scr, P, Pm, w % ncx, w / ncx, threadIdx.x & 63, lds[threadIdx.x >> 6]);
+    march2_any<S, LAUNCH>(src, dst, scr, P, Pm, items[wi], ncx, threadIdx.x & 63, lds[threadIdx.x >> 6]);
 }
 
 // Batched: item (problem, wavefront index); one item list per launch.  The block holds
@@ -390,7 +419,7 @@ k_batch_step2(const BatchProblem *__restrict__ probs, const int2 *__restrict__ i
     const int ncx = (B.P.nx + S2_OUT - 1) / S2_OUT;
     R *lds = LAUNCH == STEP2_FULL ? nullptr : reinterpret_cast<R *>(s2_lds) + wave * S2_LDS;
     march2_any<S, LAUNCH>(static_cast<const S *>(B.buf[parity]), static_cast<S *>(B.buf[parity ^ 1]),
-                          static_cast<S *>(B.scr), B.P, B.Pm, w % ncx, w / ncx, threadIdx.x & 63, lds);
+                          static_cast<S *>(B.scr), B.P, B.Pm, w, ncx, threadIdx.x & 63, lds);
 }
 
 // Final step of the walled rows y = 0 and y = ny - 1 from the intermediate rows in the
@@ -459,12 +488,15 @@ static hipError_t step2_rows_t(void *dst, const void *scr, const KParams &P, con
 // rows 0-3 and ny-4..ny-1 without overlap).  Grids narrower than a wavefront have one
 // column chunk: from x = 0 with lanes past the wall x = nx - 1 idle, or, periodic in x,
 // starting left of x = 0 with the lanes wrapped.
-bool step2_supported(const KParams &P) { return P.nx >= 4 && P.ny >= 8; }
+bool step2_supported(const KParams &P)
+{
+    return P.nx >= 4 && P.ny >= 8 && (long long)((P.nx + S2_OUT - 1) / S2_OUT) * s2_nbands(P) <= 0x7fffffff;
+}
 
 
 int step2_waves(const KParams &P)
 {
-    return ((P.nx + S2_OUT - 1) / S2_OUT) * ((P.ny + S2_TY - 1) / S2_TY);
+    return ((P.nx + S2_OUT - 1) / S2_OUT) * s2_nbands(P);
 }
 
 // Wavefront indices of the xwall, lean and full instances (the main launch runs the first
@@ -473,7 +505,7 @@ void step2_lists(const KParams &P, std::vector<int> &xwall, std::vector<int> &le
                  int &row_blocks, long long &main_nodes)
 {
     const int ncx = (P.nx + S2_OUT - 1) / S2_OUT;
-    const int ncy = (P.ny + S2_TY - 1) / S2_TY;
+    const int ncy = s2_nbands(P);
     xwall.clear();
     lean.clear();
     full.clear();
@@ -487,7 +519,8 @@ void step2_lists(const KParams &P, std::vector<int> &xwall, std::vector<int> &le
             }
             (kind == STEP2_XWALL ? xwall : lean).push_back(w);
             const int X0 = s2_x0(P, cx);
-            const int Y0 = cy * S2_TY, Y1 = min(Y0 + S2_TY, P.ny);
+            int Y0, Y1;
+            s2_band(P, cy, Y0, Y1);
             int cols = 0;
             for (int l = 1; l <= S2_OUT; ++l) cols += P.px || (X0 - 1 + l >= 0 && X0 - 1 + l < P.nx);
             main_nodes += (long long)cols * (Y1 - Y0);
@@ -526,54 +559,37 @@ hipError_t launch_step2_rows(int storage, void *dst, const void *scr, const KPar
     }
 }
 
+// The side stream's launches are issued first, so that their wavefronts are dispatched
+// beside the main launch's first ones rather than after its last ones.
 template <typename S>
 static hipError_t batch_step2_t(const BatchProblem *probs, const int2 *const *items, const int *nitems,
-                                const int2 *rows, int nrows, int parity, int main_waves, hipStream_t st)
+                                const int2 *rows, int nrows, int parity, int main_waves, hipStream_t st_main,
+                                hipStream_t st_side)
 {
     using R = typename Prec<S>::R;
     constexpr int W = S2_B / 64;
     if (main_waves < 1 || main_waves > W) return hipErrorInvalidValue;
     if (nitems[STEP2_FULL] > 0)
-        hipLaunchKernelGGL((k_batch_step2<S, STEP2_FULL>), dim3((nitems[STEP2_FULL] + W - 1) / W), dim3(S2_B), 0, st,
-                           probs, items[STEP2_FULL], nitems[STEP2_FULL], parity);
+        hipLaunchKernelGGL((k_batch_step2<S, STEP2_FULL>), dim3((nitems[STEP2_FULL] + W - 1) / W), dim3(S2_B), 0,
+                           st_side, probs, items[STEP2_FULL], nitems[STEP2_FULL], parity);
     if (nrows > 0)   // after the full launch, whose scratch rows it reads
-        hipLaunchKernelGGL((k_batch_step2_rows<S>), dim3(nrows), dim3(64), 0, st, probs, rows, parity);
+        hipLaunchKernelGGL((k_batch_step2_rows<S>), dim3(nrows), dim3(64), 0, st_side, probs, rows, parity);
     if (nitems[STEP2_MAIN] > 0)
         hipLaunchKernelGGL((k_batch_step2<S, STEP2_MAIN>), dim3((nitems[STEP2_MAIN] + main_waves - 1) / main_waves),
-                           dim3(64 * main_waves), (size_t)main_waves * S2_LDS * sizeof(R), st,
+                           dim3(64 * main_waves), (size_t)main_waves * S2_LDS * sizeof(R), st_main,
                            probs, items[STEP2_MAIN], nitems[STEP2_MAIN], parity);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_step2(int storage, const BatchProblem *probs, const int2 *const *items, const int *nitems,
-                              const int2 *rows, int nrows, int parity, int main_waves, hipStream_t st)
+                              const int2 *rows, int nrows, int parity, int main_waves, hipStream_t st_main,
+                              hipStream_t st_side)
 {
     switch (storage) {
-    case 0: return batch_step2_t<double>(probs, items, nitems, rows, nrows, parity, main_waves, st);
-    case 1: return batch_step2_t<float>(probs, items, nitems, rows, nrows, parity, main_waves, st);
-    case 2: return batch_step2_t<__half>(probs, items, nitems, rows, nrows, parity, main_waves, st);
+    case 0: return batch_step2_t<double>(probs, items, nitems, rows, nrows, parity, main_waves, st_main, st_side);
+    case 1: return batch_step2_t<float>(probs, items, nitems, rows, nrows, parity, main_waves, st_main, st_side);
+    case 2: return batch_step2_t<__half>(probs, items, nitems, rows, nrows, parity, main_waves, st_main, st_side);
     default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename S> static Batch2Kernels batch2_kernels_t()
-{
-    Batch2Kernels k;
-    k.main[STEP2_MAIN] = (const void *)k_batch_step2<S, STEP2_MAIN>;
-    k.main[STEP2_FULL] = (const void *)k_batch_step2<S, STEP2_FULL>;
-    k.rows = (const void *)k_batch_step2_rows<S>;
-    k.threads = S2_B;
-    k.waves_per_block = S2_B / 64;
-    k.lds_per_wave = S2_LDS * sizeof(typename Prec<S>::R);
-    return k;
-}
-
-Batch2Kernels batch2_kernels(int storage)
-{
-    switch (storage) {
-    case 0: return batch2_kernels_t<double>();
-    case 1: return batch2_kernels_t<float>();
-    default: return batch2_kernels_t<__half>();
     }
 }
 
