@@ -128,9 +128,9 @@ def timed_run(lbm, torch, cfg, warmup, steps, every=8, fusion=None):
 
 def ensemble_run(lbm, torch, W, count=256, steps=10000, warmup=64, max_cell_re=None):
     """Aggregate throughput of an ensemble of cavities of uneven size and parameters,
-    advanced together by the batched kernels replayed from a HIP graph.  max_cell_re caps
+    advanced together by the batched kernels (two-step passes).  max_cell_re caps
     Ra per cavity at Pr (max_cell_re (N - 1))^2 (None: Ra log-uniform on [1e3, 1e6] for
-    every cavity, the unresolved ones diverging and flagged)."""
+    every cavity); cavities that turn non-finite are counted."""
     cfgs = W.ensemble(count=count, seed=0, storage="f32", max_cell_re=max_cell_re)
     nodes = sum(c["nx"] * c["ny"] for c in cfgs)
     b = lbm.Batch(cfgs)

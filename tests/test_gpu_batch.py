@@ -1,7 +1,7 @@
 """Batched stepping of many problems (the same launches per step, or per two-step pass,
-for all problems, replayed from a HIP graph of 64 steps) against the single-problem path
-and the oracle.  Graph replays are interleaved with eager work and synchronisations, and
-every replay is checked."""
+for all problems: two-step passes on two streams, one-step updates replayed from a HIP graph
+of 64 steps) against the single-problem path and the oracle.  Graph replays are
+interleaved with eager work and synchronisations, and every replay is checked."""
 import numpy as np
 import pytest
 
@@ -38,7 +38,7 @@ def _cases(storage):
 def test_batch_fp64_matches_single_and_oracle(gpu, oracle_mod):
     import torch
     cfgs = _cases("f64")
-    _say(f"case: batch of {len(cfgs)} FP64 problems, 64 + 64 (graph) + 7 (eager) steps")
+    _say(f"case: batch of {len(cfgs)} FP64 problems, 64 + 64 + 7 steps")
     batch = gpu.Batch(cfgs)
     singles = [gpu.Sim(c) for c in cfgs]
     for chunk in (64, 64, 7):
@@ -105,7 +105,7 @@ def test_batch_block_widths_and_autotune(gpu, storage):
     for width in (64, 128, 256):
         batch = gpu.Batch(cfgs)
         batch.set_width(width)
-        batch.step(70)          # one graph replay and 6 eager steps
+        batch.step(70)          # FP16: one graph replay and 6 single steps; else 35 passes
         torch.cuda.synchronize()
         for k, s in enumerate(singles):
             assert bool((batch[k].get_state() == s.get_state()).all()), (width, k)
@@ -127,8 +127,9 @@ def test_batch_block_widths_and_autotune(gpu, storage):
 
 @pytest.mark.parametrize("storage", ["f32", "f64"])
 def test_batch_two_step_passes_bitwise(gpu, storage):
-    """Two-step batched passes, graphs realigned after odd step counts and a switch of the
-    steps per pass mid-run all give bitwise the single-problem states."""
+    """Two-step batched passes, odd step counts and a switch to one step per pass (graph
+    replays, realigned after odd counts) and back all give bitwise the single-problem
+    states."""
     import torch
     cfgs = _cases(storage) + [W.random_case(26, 4, 8, storage=storage),
                               W.random_case(27, 70, 8, periodic_x=1, storage=storage)]
