@@ -185,4 +185,7 @@ class Sim3:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:      # interpreter shutdown: the module's globals may be gone
+            pass
