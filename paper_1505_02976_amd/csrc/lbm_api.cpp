@@ -887,6 +887,10 @@ struct lbm_batch {
 
 namespace {
 
+// Cost of a two-step wavefront next to a vertical wall relative to a lean one (its
+// wall-column work before and after the walk; measured with per-wavefront clock stamps).
+constexpr double XWALL_COST = 1.34;
+
 struct BatchLayout {
     std::vector<size_t> off;    // workspace offset of each problem
     size_t off_probs, off_bulk, off_edge, off_wall, off_all, off_flags, off_items2[lbm::STEP2_LAUNCHES], off_rows2, total;
@@ -910,6 +914,8 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
     for (auto &v : B.items2) v.clear();
     B.rows2.clear();
     B.two = params[0].storage != LBM_F16;
+    std::vector<std::vector<int2>> mainp(n);   // main-launch items of each problem
+    std::vector<double> cost(n, 0.0);          // their cost in lean wavefronts
     for (int k = 0; k < n; ++k) {
         if (params[k].storage != params[0].storage)
             return fail(LBM_ERR_INVALID, "problem %d: all problems of a batch share one storage type", k);
@@ -946,7 +952,8 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
             std::vector<int> mainv(xw);
             mainv.insert(mainv.end(), lean.begin(), lean.end());
             std::sort(mainv.begin(), mainv.end());
-            for (int w : mainv) B.items2[lbm::STEP2_MAIN].push_back(make_int2(k, w));
+            for (int w : mainv) mainp[k].push_back(make_int2(k, w));
+            cost[k] = (double)lean.size() + XWALL_COST * (double)xw.size();
             for (int w : fullv) B.items2[lbm::STEP2_FULL].push_back(make_int2(k, w));
             for (int r = 0; r < rb; ++r) B.rows2.push_back(make_int2(k, r));
         } else {
@@ -956,6 +963,23 @@ lbm_status batch_layout(const lbm_params *params, int32_t n, BatchLayout &B)
     if (!B.two) {
         for (auto &v : B.items2) v.clear();
         B.rows2.clear();
+    } else {
+        // The main launch deals equal-count contiguous ranges of its list to the eight XCDs.
+        // Problems are assigned to eight groups, the costliest first, each to the group with
+        // the least cost so far, and the groups are listed one after another: every XCD's
+        // range then holds a similar mix of narrow and wide problems.
+        std::vector<int> order(n);
+        for (int k = 0; k < n; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        std::vector<std::vector<int>> groups(8);
+        double gcost[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int k : order) {
+            const int g = (int)(std::min_element(gcost, gcost + 8) - gcost);
+            groups[g].push_back(k);
+            gcost[g] += cost[k];
+        }
+        for (const auto &grp : groups)
+            for (int k : grp) B.items2[lbm::STEP2_MAIN].insert(B.items2[lbm::STEP2_MAIN].end(), mainp[k].begin(), mainp[k].end());
     }
     B.off_probs = o; o += align_up((size_t)n * sizeof(lbm::BatchProblem), 256);
     B.off_bulk = o; o += align_up(B.bulk.size() * sizeof(int2) + 8, 256);
