@@ -167,3 +167,32 @@ def test_3d_struct_sizes_and_validation(lbm):
     c = L3.lattice()
     assert len(set(c)) == 19 and (0, 0, 0) in c
     assert sorted(sum(abs(v) for v in ci) for ci in c) == [0] + [1] * 6 + [2] * 12
+
+
+def test_null_handles_are_rejected_without_touching_the_device(lbm):
+    """Every entry point that takes a handle returns LBM_ERR_INVALID for a NULL one, with a
+    message, and never reaches the device (these calls run without a GPU)."""
+    lib = C.CDLL(lbm.LIB_PATH)
+    lib.lbm_last_error.restype = C.c_char_p
+    d = C.c_double()
+    two = (C.c_double * 2)()
+    calls = {
+        "lbm_step": lambda: lib.lbm_step(None, C.c_int64(5)),
+        "lbm_set_check_interval": lambda: lib.lbm_set_check_interval(None, C.c_int64(10)),
+        "lbm_set_fusion": lambda: lib.lbm_set_fusion(None, C.c_int32(2)),
+        "lbm_nusselt": lambda: lib.lbm_nusselt(None, C.c_int32(0), C.byref(d)),
+        "lbm_residual": lambda: lib.lbm_residual(None, C.byref(two, 0), C.byref(two, 8)),
+        "lbm_residual_noalloc": lambda: lib.lbm_residual_noalloc(None, C.byref(two, 0), C.byref(two, 8)),
+        "lbm_batch_step": lambda: lib.lbm_batch_step(None, C.c_int64(2)),
+        "lbm_batch_set_fusion": lambda: lib.lbm_batch_set_fusion(None, C.c_int32(1)),
+        "lbm_adjoint_backward": lambda: lib.lbm_adjoint_backward(None, C.c_double(1.0), None),
+        "lbm3_step": lambda: lib.lbm3_step(None, C.c_int64(1)),
+        "lbm3_nusselt": lambda: lib.lbm3_nusselt(None, C.c_int32(0), C.byref(d)),
+    }
+    for name, call in calls.items():
+        assert call() == lbm.ERR_INVALID, name
+        assert lib.lbm_last_error(), name
+    # handle-less destructors accept NULL
+    lib.lbm_destroy(None)
+    lib.lbm_batch_destroy(None)
+    lib.lbm_adjoint_destroy(None)

@@ -212,3 +212,36 @@ def test_full_size_cavity(gpu, oracle_mod, storage, tol):
         errs = {k: _rel_l2(g[k], o[k]) for k in ("ux", "uy", "T", "p")}
         _say(f"  rel L2 {errs}")
         assert max(errs.values()) < tol, errs
+
+
+def test_degenerate_step_counts(gpu):
+    """Zero steps leave the state and the time untouched (single problem, batch, with and
+    without a check interval); negative counts and intervals are rejected with
+    LBM_ERR_INVALID and change nothing."""
+    import torch
+    for storage in ("f64", "f32", "f16"):
+        cfg = W.random_case(31, 40, 24, storage=storage)
+        sim = gpu.Sim(cfg)
+        sim.step(3)
+        before = sim.get_state()
+        sim.step(0)
+        sim.set_check_interval(7)
+        sim.step(0)
+        with pytest.raises(gpu.LbmError):
+            sim.step(-1)
+        with pytest.raises(gpu.LbmError):
+            sim.set_check_interval(-2)
+        torch.cuda.synchronize()
+        assert sim.time == 3
+        assert bool((sim.get_state() == before).all()), storage
+        batch = gpu.Batch([cfg, W.random_case(32, 17, 9, storage=storage)])
+        batch.step(2)
+        snap = [p.get_state() for p in batch.problems]
+        batch.step(0)
+        with pytest.raises(gpu.LbmError):
+            batch.step(-3)
+        torch.cuda.synchronize()
+        assert batch[0].time == 2
+        for k, p in enumerate(batch.problems):
+            assert bool((p.get_state() == snap[k]).all()), (storage, k)
+        batch.close()
