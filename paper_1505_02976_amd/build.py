@@ -23,19 +23,31 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link liblbm.so; returns its path."""
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source (in parallel, `jobs` at a time; 0: one per source, at most 8)
+    and link liblbm.so; returns its path."""
     objs = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
+    cmds = []
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append([HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    jobs = jobs or min(len(cmds), 8)
+    running = []
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        running.append((cmd, subprocess.Popen(cmd)))
+        while len(running) >= jobs:
+            c, p = running.pop(0)
+            if p.wait() != 0:
+                raise subprocess.CalledProcessError(p.returncode, c)
+    for c, p in running:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, c)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
