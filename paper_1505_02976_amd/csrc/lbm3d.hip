@@ -131,7 +131,7 @@ template <typename R> __device__ __forceinline__ Por<R> por_of(const K3 &K, size
         e.c1 = eps * 0.5 * Feps * K.isqK;
         e.dlin = R(eps * K.nuK);
         e.dquad = R(eps * Feps * K.isqK);
-        e.bM = R(0.5 * (ie - 1.0 / K.sigma));
+        e.bM = R(0.5 * (ie - K.cd.isig));   // isig = 1 / sigma, rounded once on the host
     }
     return e;
 }

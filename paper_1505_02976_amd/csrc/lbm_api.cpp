@@ -188,6 +188,8 @@ void fill_kparams(const lbm_params *p, const lbm_derived &d, lbm::KParams &k)
     cf.w1 = (float)c.w1; cf.w5 = (float)c.w5;
     cf.w3a = 1.0f / 3.0f;
     cf.w3d = (1.0f - 2.0f * cf.w3a) / 4.0f;   // 2 w3a + 4 w3d == 1 exactly in FP32
+    lbm::derive_consts(c);
+    lbm::derive_consts(cf);
     k.ed.eps = p->eps;
     k.ed.ieps = 1.0 / p->eps;
     k.ed.dlin = k.dlin;

@@ -93,8 +93,75 @@ template <typename R> struct Cst {
     R aM0;             // cs^2 sigma (B - tau_T)
     R w1, w5;          // lattice weights 1/9, 1/36
     R w3a, w3d;        // 3 omega of axis / diagonal directions with 2 w3a + 4 w3d = 1 in R
-
+    // Products of the constants above used by the collision, per direction class
+    // (0 axes, 1 diagonals), rounded in R in the order the node update would form them
+    // (derive_consts): precomputed so that no launch spends vector instructions on them.
+    R w[2], w3[2];               // omega, 3 omega
+    R witf[2], witT[2];          // omega / tau_f, omega / tau_T
+    R wQ[2];                     // (omega fT) Q
+    R bsg[2];                    // (omega / tau_T) sigma B
+    R w3fT[2], w3fF[2];          // 3 omega fT, 3 omega fF
+    R A15, hA;                   // 1.5 A, 0.5 A
+    R itTsig, fTQ, Qisig;        // sigma / tau_T, fT Q, Q / sigma
+    R c9fF, cuFc;                // 9 fF, (-4/3 fF) tau_f
 };
+
+// Fills the derived products of a Cst whose base constants are set.
+template <typename R> inline void derive_consts(Cst<R> &c)
+{
+    for (int k = 0; k < 2; ++k) {
+        const R w = k == 0 ? c.w1 : c.w5, w3 = k == 0 ? c.w3a : c.w3d;
+        c.w[k] = w;
+        c.w3[k] = w3;
+        c.witf[k] = w * c.itf;
+        c.witT[k] = w * c.itT;
+        c.wQ[k] = (w * c.fT) * c.Q;
+        c.bsg[k] = (c.itT * w) * c.sigB;
+        c.w3fT[k] = w3 * c.fT;
+        c.w3fF[k] = w3 * c.fF;
+    }
+    c.A15 = R(1.5) * c.A;
+    c.hA = R(0.5) * c.A;
+    c.itTsig = c.itT * c.sig;
+    c.fTQ = c.fT * c.Q;
+    c.Qisig = c.Q * c.isig;
+    c.c9fF = R(9) * c.fF;
+    c.cuFc = (R(-4.0 / 3.0) * c.fF) * c.tau_f;
+}
+
+// The derived products of one direction class and of the node, read from the Cst
+// (PRE) or formed from its base constants in the same order (then the compiler keeps
+// them in registers; the two give identical values).  A kernel that updates many nodes
+// per wavefront keeps the register-resident form when that holds fewer registers.
+template <typename R> struct ClassK { R w, w3, witf, witT, wQ, bsg, w3fT, w3fF; };
+template <typename R> struct NodeK { R A15, hA, itTsig, fTQ, Qisig, c9fF, cuFc; };
+
+template <bool PRE, typename R> __device__ __forceinline__ ClassK<R> class_k(const Cst<R> &k, int c)
+{
+    ClassK<R> d;
+    if constexpr (PRE) {
+        d.w = k.w[c]; d.w3 = k.w3[c]; d.witf = k.witf[c]; d.witT = k.witT[c];
+        d.wQ = k.wQ[c]; d.bsg = k.bsg[c]; d.w3fT = k.w3fT[c]; d.w3fF = k.w3fF[c];
+    } else {
+        const R w = c == 0 ? k.w1 : k.w5, w3 = c == 0 ? k.w3a : k.w3d;
+        d.w = w; d.w3 = w3; d.witf = w * k.itf; d.witT = w * k.itT;
+        d.wQ = (w * k.fT) * k.Q; d.bsg = (k.itT * w) * k.sigB; d.w3fT = w3 * k.fT; d.w3fF = w3 * k.fF;
+    }
+    return d;
+}
+
+template <bool PRE, typename R> __device__ __forceinline__ NodeK<R> node_k(const Cst<R> &k)
+{
+    NodeK<R> d;
+    if constexpr (PRE) {
+        d.A15 = k.A15; d.hA = k.hA; d.itTsig = k.itTsig; d.fTQ = k.fTQ; d.Qisig = k.Qisig;
+        d.c9fF = k.c9fF; d.cuFc = k.cuFc;
+    } else {
+        d.A15 = R(1.5) * k.A; d.hA = R(0.5) * k.A; d.itTsig = k.itT * k.sig; d.fTQ = k.fT * k.Q;
+        d.Qisig = k.Q * k.isig; d.c9fF = R(9) * k.fF; d.cuFc = (R(-4.0 / 3.0) * k.fF) * k.tau_f;
+    }
+    return d;
+}
 
 // Porosity-dependent coefficients in R (uniform porosity: computed on the host).
 template <typename R> struct EpsR {
@@ -235,7 +302,7 @@ __device__ __forceinline__ EpsC<R> eps_coeffs(const KParams &P, typename DragT<R
     e.c1 = D(0.5) * eps * Fe * D(P.inv_sqrtK);
     e.dlin = R(eps * D(P.nu_over_K));
     e.dquad = R(eps * Fe * D(P.inv_sqrtK));
-    e.bM = R(D(0.5) * (ie - D(1.0 / P.sigma)));
+    e.bM = R(D(0.5) * (ie - D(P.cd.isig)));   // isig = 1 / sigma, rounded once on the host
     return e;
 }
 
@@ -280,7 +347,7 @@ __device__ __forceinline__ double drag_factor<float, double>(double vx, double v
 //   of App. A); S (Eq. ShearEqCom) with sum c c f^{e(0)} = eps p I + u u / eps;
 //   grad T = <M>^{-1} <N> (Eqs. MatrM, MatrN) for <M> = a I - b u u by the
 //   Sherman-Morrison form, whose denominator is the second factor of Eq. detMatr.
-template <typename R>
+template <typename R, bool PRE = true>
 __device__ __forceinline__ void node_macro(const R *f, const R *g, const Cst<R> &k,
                                            const EpsC<R> &e, Macro<R> &m)
 {
@@ -309,7 +376,7 @@ __device__ __forceinline__ void node_macro(const R *f, const R *g, const Cst<R> 
     const R s18 = ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
     // rho0 s_0 = -omega_0 |u|^2 / (2 eps cs^2),  tau_f F_0 = -omega_0 tau_f fF (u.F) / (eps cs^2);
     // their coefficients depend only on the porosity and the launch constants
-    const R cuu = R(-2.0 / 3.0) * e.ieps, cuF = R(-4.0 / 3.0) * k.fF * k.tau_f * e.ieps;
+    const R cuu = R(-2.0 / 3.0) * e.ieps, cuF = node_k<PRE>(k).cuFc * e.ieps;
     m.p = (R(0.6) * e.ieps) * (s18 + cuu * uu + cuF * uF);
 
     const R ep = e.eps * m.p;
@@ -343,11 +410,11 @@ __device__ __forceinline__ void node_gradT(Macro<R> &m, R T0, const Cst<R> &k, c
     m.gy = (Ny + c * m.uy) * ia;
 }
 
-template <typename R>
+template <typename R, bool PRE = true>
 __device__ __forceinline__ void node_macro_full(const R *f, const R *g, R T0, const Cst<R> &k,
                                                 const EpsC<R> &e, Macro<R> &m)
 {
-    node_macro(f, g, k, e, m);
+    node_macro<R, PRE>(f, g, k, e, m);
     node_gradT(m, T0, k, e);
 }
 
@@ -414,14 +481,13 @@ template <typename R> struct PairC {
 //
 // c = class of the pair (0 axes, 1 diagonals); cu = c.u, cF = c.F, cSc = c.S.c,
 // cg = c.grad T, cv = c.(T F + eps p grad T / rho0).
-template <typename R>
+template <typename R, bool PRE>
 __device__ __forceinline__ void collide_pair(R &fa, R &fb, R &ga, R &gb, int c, R cu, R cF, R cSc, R cg, R cv,
                                              const PairC<R> &q, const Cst<R> &k, R &Ef_sum, R &Eg_sum)
 {
-    const R w = c == 0 ? k.w1 : k.w5, w3 = c == 0 ? k.w3a : k.w3d;
-    // products of launch constants (the compiler keeps them out of the row loops)
-    const R witf = w * k.itf, witT = w * k.itT, wQ = w * k.fT * k.Q, bsg = k.itT * w * k.sigB;
-    const R w3fT = w3 * k.fT, w3fF = w3 * k.fF, A15 = R(1.5) * k.A;
+    const ClassK<R> d = class_k<PRE>(k, c);
+    const R w = d.w, w3 = d.w3, witf = d.witf, witT = d.witT, wQ = d.wQ, bsg = d.bsg;
+    const R w3fT = d.w3fT, w3fF = d.w3fF, A15 = node_k<PRE>(k).A15;
     const R cu2 = cu * cu;
     // f: E = omega [(b0 + 4.5 (c.u)^2 / eps + 1.5 A c.S.c) / tau_f + fF (9 (c.u)(c.F) - 3 u.F) / eps],
     //    O = 3 omega [(c.u) / tau_f + fF c.F]
@@ -448,10 +514,11 @@ __device__ __forceinline__ void collide_pair(R &fa, R &fb, R &ga, R &gb, int c, 
 // arithmetic itself, not only up to the rounding of the lattice weights: the zeroth
 // moments are what a step accumulates, so a rounding bias there would drift the mass
 // and the thermal energy.
-template <typename R>
+template <typename R, bool PRE = true>
 __device__ __forceinline__ void node_collide(R *f, R *g, const Macro<R> &m, R T0,
                                              const Cst<R> &k, const EpsC<R> &e)
 {
+    const NodeK<R> n = node_k<PRE>(k);
     const R T = T0 + m.Td;
     const R ep = e.eps * m.p;
     const R uu = m.ux * m.ux + m.uy * m.uy;
@@ -462,27 +529,27 @@ __device__ __forceinline__ void node_collide(R *f, R *g, const Macro<R> &m, R T0
     const R vy = T * m.Fy + ep * m.gy;
 
     PairC<R> q;
-    q.b0 = R(3) * ep - R(1.5) * uu * e.ieps - R(0.5) * k.A * trS;
+    q.b0 = R(3) * ep - R(1.5) * uu * e.ieps - n.hA * trS;
     q.b1 = k.sig * m.Td - R(1.5) * T * uu * e.ieps + R(3) * T * ep;
     q.k45 = R(4.5) * e.ieps;
-    q.c9 = R(9) * k.fF * e.ieps;
+    q.c9 = n.c9fF * e.ieps;
     q.m3b5 = R(-3) * (k.fF * uF * e.ieps);
     q.T45 = q.k45 * T;
-    q.s = k.itT * T + k.fT * ((e.ieps - k.isig) * ugT + k.Q * k.isig);
+    q.s = k.itT * T + k.fT * ((e.ieps - k.isig) * ugT + n.Qisig);
     R Ef = R(0), Eg = R(0);
     // (1, 3): c = (1, 0)
-    collide_pair<R>(f[1], f[3], g[1], g[3], 0, m.ux, m.Fx, m.Sxx, m.gx, vx, q, k, Ef, Eg);
+    collide_pair<R, PRE>(f[1], f[3], g[1], g[3], 0, m.ux, m.Fx, m.Sxx, m.gx, vx, q, k, Ef, Eg);
     // (2, 4): c = (0, 1)
-    collide_pair<R>(f[2], f[4], g[2], g[4], 0, m.uy, m.Fy, m.Syy, m.gy, vy, q, k, Ef, Eg);
+    collide_pair<R, PRE>(f[2], f[4], g[2], g[4], 0, m.uy, m.Fy, m.Syy, m.gy, vy, q, k, Ef, Eg);
     // (5, 7): c = (1, 1)
-    collide_pair<R>(f[5], f[7], g[5], g[7], 1, m.ux + m.uy, m.Fx + m.Fy, m.Sxx + R(2) * m.Sxy + m.Syy,
+    collide_pair<R, PRE>(f[5], f[7], g[5], g[7], 1, m.ux + m.uy, m.Fx + m.Fy, m.Sxx + R(2) * m.Sxy + m.Syy,
                     m.gx + m.gy, vx + vy, q, k, Ef, Eg);
     // (6, 8): c = (-1, 1)
-    collide_pair<R>(f[6], f[8], g[6], g[8], 1, m.uy - m.ux, m.Fy - m.Fx, m.Sxx - R(2) * m.Sxy + m.Syy,
+    collide_pair<R, PRE>(f[6], f[8], g[6], g[8], 1, m.uy - m.ux, m.Fy - m.Fx, m.Sxx - R(2) * m.Sxy + m.Syy,
                     m.gy - m.gx, vy - vx, q, k, Ef, Eg);
     // rest direction: f^eq_0 + tau_f F_0 and g^eq_0 + tau_T Q_0 from the zeroth moments
     f[0] = k.of * f[0] - R(2) * Ef;
-    g[0] = k.og * g[0] + (k.itT * k.sig * m.Td + k.fT * k.Q) - R(2) * Eg;
+    g[0] = k.og * g[0] + (n.itTsig * m.Td + n.fTQ) - R(2) * Eg;
 }
 
 // ---------------------------------------------------------------------------------
@@ -551,13 +618,13 @@ template <typename A, typename B> struct same_t { static constexpr bool v = fals
 template <typename A> struct same_t<A, A> { static constexpr bool v = true; };
 
 // Moments and collision of one node in R, in place on f, g.
-template <typename R, typename M>
+template <typename R, typename M, bool PRE = true>
 __device__ __forceinline__ void node_update(R *f, R *g, const KParams &P, int x, int y)
 {
     static_assert(same_t<R, M>::v, "moments and collision share the arithmetic type");
     Macro<R> m;
-    node_macro_full<R>(f, g, R(P.T0), cst<R>(P), eps_at<R>(P, x, y), m);
-    node_collide<R>(f, g, m, R(P.T0), cst<R>(P), eps_at<R>(P, x, y));
+    node_macro_full<R, PRE>(f, g, R(P.T0), cst<R>(P), eps_at<R>(P, x, y), m);
+    node_collide<R, PRE>(f, g, m, R(P.T0), cst<R>(P), eps_at<R>(P, x, y));
 }
 
 // Wall classification: xw in {-1, 0, 1}, yw in {-1, 2, 3}; inward step (dx, dy).
@@ -611,7 +678,7 @@ __device__ __forceinline__ R gather_Td(const S *__restrict__ src, const KParams 
 // G and F (Eq. ForceEq) at u_b and T_b.  The node collides with that state (wall_collide),
 // which gives the post-collision form of the extrapolation,
 // f^eq(x_b) + (1 - 1/tau) f^neq(x_f) plus the source terms.
-template <typename R>
+template <typename R, bool PRE = true>
 __device__ __forceinline__ void wall_from_ref(const KParams &P, const Cst<R> &k, int x, int y,
                                               const EpsC<R> &ef, const EpsC<R> &eb,
                                               const R *ff, const R *gf, R Tdff, R *f, R *g,
@@ -620,7 +687,7 @@ __device__ __forceinline__ void wall_from_ref(const KParams &P, const Cst<R> &k,
     const WallInfo w = wall_info(P, x, y);
     Macro<R> mf;
     const R T0 = R(P.T0);
-    node_macro_full<R>(ff, gf, T0, k, ef, mf);
+    node_macro_full<R, PRE>(ff, gf, T0, k, ef, mf);
     const R Tf = T0 + mf.Td;
     const R epf = ef.eps * mf.p;
 
@@ -675,14 +742,14 @@ __device__ __forceinline__ void wall_from_ref(const KParams &P, const Cst<R> &k,
 }
 
 // Collision of wall node (x, y) with the state mb the boundary scheme assigned to it.
-template <typename R>
+template <typename R, bool PRE = true>
 __device__ __forceinline__ void wall_collide(R *f, R *g, const Macro<R> &mb, const KParams &P, int x, int y)
 {
-    node_collide<R>(f, g, mb, R(P.T0), cst<R>(P), eps_at<R>(P, x, y));
+    node_collide<R, PRE>(f, g, mb, R(P.T0), cst<R>(P), eps_at<R>(P, x, y));
 }
 
 // The boundary scheme with the reference nodes' populations gathered from memory.
-template <typename S, typename R>
+template <typename S, typename R, bool PRE = true>
 __device__ __forceinline__ void wall_populations(const S *__restrict__ src, const KParams &P,
                                                  const Cst<R> &k, int x, int y, R *f, R *g,
                                                  Macro<R> &mb)
@@ -692,7 +759,7 @@ __device__ __forceinline__ void wall_populations(const S *__restrict__ src, cons
     gather<S, R>(src, P, x + w.dx, y + w.dy, ff, gf);
     R Tdff = R(0);
     if (thermal_dirichlet_wall(P, w) < 0) Tdff = gather_Td<S, R>(src, P, k, x + 2 * w.dx, y + 2 * w.dy);
-    wall_from_ref<R>(P, k, x, y, eps_at<R>(P, x + w.dx, y + w.dy), eps_at<R>(P, x, y), ff, gf, Tdff, f, g, mb);
+    wall_from_ref<R, PRE>(P, k, x, y, eps_at<R>(P, x + w.dx, y + w.dy), eps_at<R>(P, x, y), ff, gf, Tdff, f, g, mb);
 }
 
 // Wall-node slot s -> (x, y); returns false for slots that are not wall nodes of this

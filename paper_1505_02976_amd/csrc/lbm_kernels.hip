@@ -73,8 +73,9 @@ template <> struct Npt<__half> { static constexpr int v = 2; };
 template <typename S, int BX> __host__ __device__ constexpr int slot_span() { return (BX / 64) * Wspan<S>::v; }
 template <typename S, int BX> __host__ __device__ constexpr int block_span() { return slot_span<S, BX>() * Npt<S>::v; }
 
-// One row segment of the bulk update: nodes x = xbeg + tid + k BX (k < NPT) with
-// x < xend, of row y (tid: the thread's index among the BX threads of the segment).
+// One row segment of the bulk update: nodes x = xbeg + (tid / 64) WS + tid % 64 +
+// k (BX / 64) WS (k < NPT) with x < xend, of row y (tid: the thread's index among the BX
+// threads of the segment).
 //
 // Nodes on the walls x = 0 and x = nx - 1 (outside the walled rows) are updated here too:
 // the lanes of a wavefront hold consecutive x, so the reference node x_f = x -+ 1 of a
@@ -82,12 +83,11 @@ template <typename S, int BX> __host__ __device__ constexpr int block_span() { r
 // neighbouring lane, whose streamed populations are taken by cross-lane shuffles; only
 // when it falls in another wavefront is it gathered from memory.  Only wavefronts that
 // contain such a node take this branch.
-template <typename S, bool WALLS, int BX>
+template <typename S, bool WALLS, int BX, int NPT = Npt<S>::v>
 __device__ __forceinline__ void bulk_tile(const S *__restrict__ src, S *__restrict__ dst,
                                           const KParams &P, int y, int xbeg, int xend,
                                           int tid)
 {
-    constexpr int NPT = Npt<S>::v;
     constexpr int WS = Wspan<S>::v, SPAN = slot_span<S, BX>();
     using RC = typename Prec<S>::R;
     const int wl = tid & 63;
@@ -164,8 +164,10 @@ __device__ __forceinline__ void wall_node(const S *__restrict__ src, S *__restri
 
 // Columns of the interior launch: [xa, xb) of every non-walled row, no node of the walls
 // x = 0, x = nx - 1.  The edge launch covers the rest of those rows in segments of one
-// wavefront (EDGE_BX * NPT nodes): [0, xa) and [xb, nx) -- a single segment at each end
-// when the row is at least two segments long, else the whole row -- and the walled rows.
+// wavefront with one node per lane (Wspan nodes): [0, xa) and [xb, nx) -- a single segment
+// at each end when the row is at least two segments long, else the whole row -- and the
+// walled rows.  One node per lane keeps the edge instance's registers, and so the share of
+// the edge nodes in the slower wall-aware code, small.
 constexpr int EDGE_BX = 64;
 
 struct Cols { int xa, xb, nseg, span_e; bool split; };
@@ -173,7 +175,7 @@ struct Cols { int xa, xb, nseg, span_e; bool split; };
 template <typename S> __host__ __device__ __forceinline__ Cols step_cols(const KParams &P)
 {
     Cols c;
-    c.span_e = block_span<S, EDGE_BX>();
+    c.span_e = slot_span<S, EDGE_BX>();
     c.split = !P.px && P.nx >= 2 * c.span_e;
     if (P.px) { c.xa = 0; c.xb = P.nx; c.nseg = 0; }
     else if (c.split) { c.xa = c.span_e; c.xb = P.nx - c.span_e; c.nseg = 2; }
@@ -221,7 +223,7 @@ __device__ __forceinline__ void edge_item(const S *__restrict__ src, S *__restri
         xbeg = s * c.span_e;
         xend = min(P.nx, xbeg + c.span_e);
     }
-    bulk_tile<S, true, EDGE_BX>(src, dst, P, rows_begin(P) + r, xbeg, xend, lane);
+    bulk_tile<S, true, EDGE_BX, 1>(src, dst, P, rows_begin(P) + r, xbeg, xend, lane);
 }
 
 template <typename S, typename R>

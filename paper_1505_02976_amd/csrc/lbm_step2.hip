@@ -82,16 +82,16 @@ template <> __device__ __forceinline__ float as_stored<__half, float>(float v, c
 }
 
 // Post-collision populations of node (x, y) one step after src (the one-step node code).
-template <typename S, typename R>
+template <typename S, typename R, bool PRE>
 __device__ __forceinline__ void p1_node(const S *__restrict__ src, const KParams &P, int x, int y, R *f, R *g)
 {
     if (on_wall(P, x, y)) {
         Macro<R> mb;
-        wall_populations<S, R>(src, P, make_cst<R>(P), x, y, f, g, mb);
-        wall_collide<R>(f, g, mb, P, x, y);
+        wall_populations<S, R, PRE>(src, P, make_cst<R>(P), x, y, f, g, mb);
+        wall_collide<R, PRE>(f, g, mb, P, x, y);
     } else {
         gather<S, R>(src, P, x, y, f, g);
-        node_update<R, typename Prec<S>::M>(f, g, P, x, y);
+        node_update<R, typename Prec<S>::M, PRE>(f, g, P, x, y);
     }
 }
 
@@ -162,7 +162,7 @@ __device__ __forceinline__ void wave_sync()
 
 // One wavefront's walk: column chunk cxi, row band cyi.  lds: S2_LDS values of the
 // wavefront's own (xwall instance only).
-template <typename S, int MODE>
+template <typename S, int MODE, bool PRE>
 __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr,
                                        const KParams &P, const KParams &Pm, int cxi, int cyi, int lane,
                                        typename Prec<S>::R *lds)
@@ -193,7 +193,7 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
         if (side < 2 && wl >= 0 && yy <= Y1) {
             const int yr = P.py ? (yy + P.ny) % P.ny : yy;
             R f[9], g[9];
-            p1_node<S, R>(src, P, side == 0 ? 0 : P.nx - 1, yr, f, g);
+            p1_node<S, R, PRE>(src, P, side == 0 ? 0 : P.nx - 1, yr, f, g);
             R *q = P1w + (side * (S2_TY + 2) + r) * 18;
 #pragma unroll
             for (int i = 0; i < 9; ++i) { q[i] = as_stored<S, R>(f[i], P); q[9 + i] = as_stored<S, R>(g[i], P); }
@@ -225,7 +225,7 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
             } else {
                 gather<S, R>(src, P, xs, yr, f, g);
             }
-            node_update<R, M>(f, g, P, xs, yr);
+            node_update<R, M, PRE>(f, g, P, xs, yr);
 #pragma unroll
             for (int i = 0; i < 9; ++i) { f[i] = as_stored<S, R>(f[i], P); g[i] = as_stored<S, R>(g[i], P); }
             if (XW && (lane == wl0 || lane == wl1)) {
@@ -234,7 +234,7 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
                 for (int i = 0; i < 9; ++i) { f[i] = q[i]; g[i] = q[9 + i]; }
             }
         } else if (xok && yok) {
-            p1_node<S, R>(src, P, x, yr, f, g);
+            p1_node<S, R, PRE>(src, P, x, yr, f, g);
 #pragma unroll
             for (int i = 0; i < 9; ++i) { f[i] = as_stored<S, R>(f[i], P); g[i] = as_stored<S, R>(g[i], P); }
         } else {
@@ -287,9 +287,9 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
                 if (vwall && xout) {
                     const R Tn = thermal_dirichlet_wall(P, wall_info(P, x, orow)) < 0 ? Tdff : R(0);
                     Macro<R> mb;
-                    wall_from_ref<R>(P, c, x, orow, eps_at<R>(P, x + dx, orow), eps_at<R>(P, x, orow),
+                    wall_from_ref<R, PRE>(P, c, x, orow, eps_at<R>(P, x + dx, orow), eps_at<R>(P, x, orow),
                                      ff, gf, Tn, pf, pg, mb);
-                    wall_collide<R>(pf, pg, mb, P, x, orow);
+                    wall_collide<R, PRE>(pf, pg, mb, P, x, orow);
                     store_node<S, R>(dst, P, x, orow, pf, pg);
                 }
             }
@@ -316,7 +316,7 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
                 }
             }
             if (xout && !((XW || FULL) && vwall)) {     // wall nodes: above, or after the walk
-                node_update<R, M>(pf, pg, P, x, orow);
+                node_update<R, M, PRE>(pf, pg, P, x, orow);
                 store_node<S, R>(dst, P, x, orow, pf, pg);
             }
         }
@@ -346,9 +346,9 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
             const Cst<R> &c = make_cst<R>(P);
             const R Tn = thermal_dirichlet_wall(P, wall_info(P, xw, orow)) < 0 ? q[18] : R(0);
             Macro<R> mb;
-            wall_from_ref<R>(P, c, xw, orow, eps_at<R>(P, xw + dx, orow), eps_at<R>(P, xw, orow), ff, gf, Tn,
+            wall_from_ref<R, PRE>(P, c, xw, orow, eps_at<R>(P, xw + dx, orow), eps_at<R>(P, xw, orow), ff, gf, Tn,
                              pf, pg, mb);
-            wall_collide<R>(pf, pg, mb, P, xw, orow);
+            wall_collide<R, PRE>(pf, pg, mb, P, xw, orow);
             store_node<S, R>(dst, P, xw, orow, pf, pg);
         }
     }
@@ -367,19 +367,24 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 
 // One wavefront's walk with the instance chosen at run time: the main launch runs the lean
 // and the xwall wavefronts (both about 135 VGPRs), the full launch the full ones.
-// w: wavefront index cyi * ncx + cxi.
-template <typename S, int LAUNCH>
+// w: wavefront index cyi * ncx + cxi.  PRE: the collision's constant products read from
+// the parameter block, or formed once per wavefront in vector registers (node_k).  The
+// main launches take the second form: for FP32 the single-grid one holds 137 VGPRs with
+// it and 179 with the first, and the batched one, though it holds 113 VGPRs with the first
+// form against 131, ran 1.7 % slower with it.  The full launches take the first (FP32:
+// 175 VGPRs against 194).
+template <typename S, int LAUNCH, bool PRE>
 __device__ __forceinline__ void march2_any(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr,
                                            const KParams &P, const KParams &Pm, int w, int ncx, int lane,
                                            typename Prec<S>::R *lds)
 {
     const int cxi = w % ncx, cyi = w / ncx;
     if constexpr (LAUNCH == STEP2_FULL)
-        march2<S, STEP2_FULL>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
+        march2<S, STEP2_FULL, PRE>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
     else if (s2_kind(P, cxi, cyi) == STEP2_XWALL)     // wavefront-uniform
-        march2<S, STEP2_XWALL>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
+        march2<S, STEP2_XWALL, PRE>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
     else
-        march2<S, STEP2_LEAN>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
+        march2<S, STEP2_LEAN, PRE>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
 }
 
 // items: wavefront indices cyi * ncx + cxi of this launch (the main launch lists the xwall
@@ -396,7 +401,7 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KPa
     __shared__ R lds[S2_B / 64][LAUNCH == STEP2_FULL ? 1 : S2_LDS];
     const int wi = xcd_block(blockIdx.x, gridDim.x) * (S2_B / 64) + (threadIdx.x >> 6);
     if (wi >= nitems) return;                            // wavefront-uniform
-    march2_any<S, LAUNCH>(src, dst, scr, P, Pm, items[wi], ncx, threadIdx.x & 63, lds[threadIdx.x >> 6]);
+    march2_any<S, LAUNCH, LAUNCH == STEP2_FULL>(src, dst, scr, P, Pm, items[wi], ncx, threadIdx.x & 63, lds[threadIdx.x >> 6]);
 }
 
 // Batched: item (problem, wavefront index); one item list per launch.  The block holds
@@ -418,7 +423,7 @@ k_batch_step2(const BatchProblem *__restrict__ probs, const int2 *__restrict__ i
     const BatchProblem &B = probs[pk];
     const int ncx = (B.P.nx + S2_OUT - 1) / S2_OUT;
     R *lds = LAUNCH == STEP2_FULL ? nullptr : reinterpret_cast<R *>(s2_lds) + wave * S2_LDS;
-    march2_any<S, LAUNCH>(static_cast<const S *>(B.buf[parity]), static_cast<S *>(B.buf[parity ^ 1]),
+    march2_any<S, LAUNCH, LAUNCH == STEP2_FULL>(static_cast<const S *>(B.buf[parity]), static_cast<S *>(B.buf[parity ^ 1]),
                           static_cast<S *>(B.scr), B.P, B.Pm, w, ncx, threadIdx.x & 63, lds);
 }
 
