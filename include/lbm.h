@@ -102,7 +102,8 @@ typedef struct {
     double ax, ay;                    /* external acceleration a (Sec. 2)                  */
     double T_hot, T_cold;
     double F_eps;
-    const double *eps_field;          /* device, optional                                   */
+    const double *eps_field;          /* device, optional; values in (0, 1] like eps (device
+                                         memory: not checked)                               */
     const double *T_init;             /* device, optional                                   */
     const double *p_init;             /* device, optional                                   */
     const double *ux_init;            /* device, optional                                   */

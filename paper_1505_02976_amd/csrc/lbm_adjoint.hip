@@ -33,13 +33,7 @@ __device__ __forceinline__ Cst<Dual> dual_cst(const Cst<double> &c)
     d.halfQ = Dual(c.halfQ); d.gb = Dual(c.gb); d.ax = Dual(c.ax); d.ay = Dual(c.ay);
     d.Sden = Dual(c.Sden); d.aM0 = Dual(c.aM0); d.w1 = Dual(c.w1); d.w5 = Dual(c.w5);
     d.w3a = Dual(c.w3a); d.w3d = Dual(c.w3d);
-    for (int k = 0; k < 2; ++k) {
-        d.w[k] = Dual(c.w[k]); d.w3[k] = Dual(c.w3[k]); d.witf[k] = Dual(c.witf[k]);
-        d.witT[k] = Dual(c.witT[k]); d.wQ[k] = Dual(c.wQ[k]); d.bsg[k] = Dual(c.bsg[k]);
-        d.w3fT[k] = Dual(c.w3fT[k]); d.w3fF[k] = Dual(c.w3fF[k]);
-    }
-    d.A15 = Dual(c.A15); d.hA = Dual(c.hA); d.itTsig = Dual(c.itTsig); d.fTQ = Dual(c.fTQ);
-    d.Qisig = Dual(c.Qisig); d.c9fF = Dual(c.c9fF); d.cuFc = Dual(c.cuFc);
+    derive_consts(d);   // products of constants: the FP64 values, derivative 0
     return d;
 }
 

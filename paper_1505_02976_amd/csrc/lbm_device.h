@@ -82,6 +82,21 @@ template <typename R> inline void relax_pair(double tau, R &it, R &o)
     it = R(1) - o;
 }
 
+// Products of launch constants that the collision uses, per direction class (0 axes,
+// 1 diagonals) and per node, in the arithmetic type R.
+template <typename R> struct ClassK {
+    R w, w3;                     // omega, 3 omega
+    R witf, witT;                // omega / tau_f, omega / tau_T
+    R wQ;                        // (omega fT) Q
+    R bsg;                       // (omega / tau_T) sigma B
+    R w3fT, w3fF;                // 3 omega fT, 3 omega fF
+};
+template <typename R> struct NodeK {
+    R A15, hA;                   // 1.5 A, 0.5 A
+    R itTsig, fTQ, Qisig;        // sigma / tau_T, fT Q, Q / sigma
+    R c9fF, cuFc;                // 9 fF, (-4/3 fF) tau_f
+};
+
 // Per-launch constants in the arithmetic type R, computed once on the host.
 template <typename R> struct Cst {
     R itf, itT;        // 1 / tau
@@ -93,74 +108,62 @@ template <typename R> struct Cst {
     R aM0;             // cs^2 sigma (B - tau_T)
     R w1, w5;          // lattice weights 1/9, 1/36
     R w3a, w3d;        // 3 omega of axis / diagonal directions with 2 w3a + 4 w3d = 1 in R
-    // Products of the constants above used by the collision, per direction class
-    // (0 axes, 1 diagonals), rounded in R in the order the node update would form them
-    // (derive_consts): precomputed so that no launch spends vector instructions on them.
-    R w[2], w3[2];               // omega, 3 omega
-    R witf[2], witT[2];          // omega / tau_f, omega / tau_T
-    R wQ[2];                     // (omega fT) Q
-    R bsg[2];                    // (omega / tau_T) sigma B
-    R w3fT[2], w3fF[2];          // 3 omega fT, 3 omega fF
-    R A15, hA;                   // 1.5 A, 0.5 A
-    R itTsig, fTQ, Qisig;        // sigma / tau_T, fT Q, Q / sigma
-    R c9fF, cuFc;                // 9 fF, (-4/3 fF) tau_f
+    ClassK<R> cls[2];  // the products above, formed by derive_consts
+    NodeK<R> nod;
 };
 
-// Fills the derived products of a Cst whose base constants are set.
-template <typename R> inline void derive_consts(Cst<R> &c)
-{
-    for (int k = 0; k < 2; ++k) {
-        const R w = k == 0 ? c.w1 : c.w5, w3 = k == 0 ? c.w3a : c.w3d;
-        c.w[k] = w;
-        c.w3[k] = w3;
-        c.witf[k] = w * c.itf;
-        c.witT[k] = w * c.itT;
-        c.wQ[k] = (w * c.fT) * c.Q;
-        c.bsg[k] = (c.itT * w) * c.sigB;
-        c.w3fT[k] = w3 * c.fT;
-        c.w3fF[k] = w3 * c.fF;
-    }
-    c.A15 = R(1.5) * c.A;
-    c.hA = R(0.5) * c.A;
-    c.itTsig = c.itT * c.sig;
-    c.fTQ = c.fT * c.Q;
-    c.Qisig = c.Q * c.isig;
-    c.c9fF = R(9) * c.fF;
-    c.cuFc = (R(-4.0 / 3.0) * c.fF) * c.tau_f;
-}
-
-// The derived products of one direction class and of the node, read from the Cst
-// (PRE) or formed from its base constants in the same order (then the compiler keeps
-// them in registers; the two give identical values).  A kernel that updates many nodes
-// per wavefront keeps the register-resident form when that holds fewer registers.
-template <typename R> struct ClassK { R w, w3, witf, witT, wQ, bsg, w3fT, w3fF; };
-template <typename R> struct NodeK { R A15, hA, itTsig, fTQ, Qisig, c9fF, cuFc; };
-
-template <bool PRE, typename R> __device__ __forceinline__ ClassK<R> class_k(const Cst<R> &k, int c)
+// The products, formed from the base constants of a Cst in R (host and device: the
+// stored copies and the ones a kernel forms itself are the same values).
+template <typename R> __host__ __device__ inline ClassK<R> class_k_formed(const Cst<R> &k, int c)
 {
     ClassK<R> d;
-    if constexpr (PRE) {
-        d.w = k.w[c]; d.w3 = k.w3[c]; d.witf = k.witf[c]; d.witT = k.witT[c];
-        d.wQ = k.wQ[c]; d.bsg = k.bsg[c]; d.w3fT = k.w3fT[c]; d.w3fF = k.w3fF[c];
-    } else {
-        const R w = c == 0 ? k.w1 : k.w5, w3 = c == 0 ? k.w3a : k.w3d;
-        d.w = w; d.w3 = w3; d.witf = w * k.itf; d.witT = w * k.itT;
-        d.wQ = (w * k.fT) * k.Q; d.bsg = (k.itT * w) * k.sigB; d.w3fT = w3 * k.fT; d.w3fF = w3 * k.fF;
-    }
+    const R w = c == 0 ? k.w1 : k.w5, w3 = c == 0 ? k.w3a : k.w3d;
+    d.w = w;
+    d.w3 = w3;
+    d.witf = w * k.itf;
+    d.witT = w * k.itT;
+    d.wQ = (w * k.fT) * k.Q;
+    d.bsg = (k.itT * w) * k.sigB;
+    d.w3fT = w3 * k.fT;
+    d.w3fF = w3 * k.fF;
     return d;
+}
+
+template <typename R> __host__ __device__ inline NodeK<R> node_k_formed(const Cst<R> &k)
+{
+    NodeK<R> d;
+    d.A15 = R(1.5) * k.A;
+    d.hA = R(0.5) * k.A;
+    d.itTsig = k.itT * k.sig;
+    d.fTQ = k.fT * k.Q;
+    d.Qisig = k.Q * k.isig;
+    d.c9fF = R(9) * k.fF;
+    d.cuFc = (R(-4.0 / 3.0) * k.fF) * k.tau_f;
+    return d;
+}
+
+// Stores the products in a Cst whose base constants are set.
+template <typename R> __host__ __device__ inline void derive_consts(Cst<R> &c)
+{
+    c.cls[0] = class_k_formed(c, 0);
+    c.cls[1] = class_k_formed(c, 1);
+    c.nod = node_k_formed(c);
+}
+
+// The products as a kernel uses them: read from the Cst (PRE), or formed from its base
+// constants (then the compiler keeps them in vector registers across the kernel's loops).
+// Kernels that update one or two nodes per thread read them; a kernel that updates many
+// nodes per wavefront forms them when that holds fewer registers.
+template <bool PRE, typename R> __device__ __forceinline__ ClassK<R> class_k(const Cst<R> &k, int c)
+{
+    if constexpr (PRE) return k.cls[c];
+    else return class_k_formed(k, c);
 }
 
 template <bool PRE, typename R> __device__ __forceinline__ NodeK<R> node_k(const Cst<R> &k)
 {
-    NodeK<R> d;
-    if constexpr (PRE) {
-        d.A15 = k.A15; d.hA = k.hA; d.itTsig = k.itTsig; d.fTQ = k.fTQ; d.Qisig = k.Qisig;
-        d.c9fF = k.c9fF; d.cuFc = k.cuFc;
-    } else {
-        d.A15 = R(1.5) * k.A; d.hA = R(0.5) * k.A; d.itTsig = k.itT * k.sig; d.fTQ = k.fT * k.Q;
-        d.Qisig = k.Q * k.isig; d.c9fF = R(9) * k.fF; d.cuFc = (R(-4.0 / 3.0) * k.fF) * k.tau_f;
-    }
-    return d;
+    if constexpr (PRE) return k.nod;
+    else return node_k_formed(k);
 }
 
 // Porosity-dependent coefficients in R (uniform porosity: computed on the host).
@@ -223,13 +226,19 @@ __device__ __forceinline__ double rcp_nr(double x)
 }
 
 // FP64 square root from the hardware reciprocal-square-root estimate and one Newton step
-// (relative error below 1e-13, used where the result is rounded to FP32); 0 for x <= 0.
-__device__ __forceinline__ double sqrt_nr(double x)
+// (relative error below 1e-13, used where the result is rounded to FP32): sqrt_pos_nr for
+// x > 0, sqrt_nr for x >= 0 (0 for x <= 0, where the estimate is infinite).
+__device__ __forceinline__ double sqrt_pos_nr(double x)
 {
     const double r = __builtin_amdgcn_rsq(x);
     const double s = x * r;
     const double e = fma(-s, s, x);
-    return x > 0.0 ? fma(e, 0.5 * r, s) : 0.0;
+    return fma(e, 0.5 * r, s);
+}
+__device__ __forceinline__ double sqrt_nr(double x)
+{
+    const double s = sqrt_pos_nr(x);
+    return x > 0.0 ? s : 0.0;
 }
 
 // Storage traits: load/store of a deviation value.  Stores are non-temporal (the next
@@ -337,7 +346,7 @@ __device__ __forceinline__ double drag_factor<float, double>(double vx, double v
                                                              double &vm)
 {
     vm = sqrt_nr(vx * vx + vy * vy);
-    return rcp_nr(c0 + sqrt_nr(c0 * c0 + c1 * vm));
+    return rcp_nr(c0 + sqrt_pos_nr(c0 * c0 + c1 * vm));   // c0 > 0, c1 >= 0
 }
 
 // Local quantities from pre-collision deviations f'[9], g'[9]:
