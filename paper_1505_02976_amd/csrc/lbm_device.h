@@ -710,13 +710,6 @@ __device__ __forceinline__ void wall_from_ref(const KParams &P, const Cst<R> &k,
     }
     const R epb = eb.eps * mf.p;   // eps at the wall node, pressure of x_f
 
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const R feb = feq_i<R>(i, epb, ubx, uby, eb.ieps, mf.Sxx, mf.Sxy, mf.Syy, k.A);
-        const R fef = feq_i<R>(i, epf, mf.ux, mf.uy, ef.ieps, mf.Sxx, mf.Sxy, mf.Syy, k.A);
-        f[i] = feb + (ff[i] - fef);
-    }
-
     const int dir = thermal_dirichlet_wall(P, w);
     R Tdb, gbx, gby;
     if (dir >= 0) {
@@ -729,11 +722,28 @@ __device__ __forceinline__ void wall_from_ref(const KParams &P, const Cst<R> &k,
         Tdb = (R(4) * mf.Td - Tdff - R(2) * (R(w.dx) * gbx + R(w.dy) * gby)) * R(1.0 / 3.0);
     }
     const R Tb = T0 + Tdb;
+
+    // f_i = f_i(x_f) + f^eq_i(x_b) - f^eq_i(x_f), and likewise g, with the equilibria of
+    // feq_i and geq_i written as differences: both take the shear rate of x_f, so their
+    // shear terms cancel and are not formed.  Per node: the differences of eps p, of
+    // |u|^2 / eps, and for g of sigma Td, T |u|^2 / eps and T eps p.
+    const R uub = (ubx * ubx + uby * uby) * eb.ieps;
+    const R uuf = (mf.ux * mf.ux + mf.uy * mf.uy) * ef.ieps;
+    const R dep = epb - epf, duu = uub - uuf;
+    const R dsT = k.sig * (Tdb - mf.Td), dTuu = Tb * uub - Tf * uuf, dTep = Tb * epb - Tf * epf;
+    const R Tbi = Tb * eb.ieps, Tfi = Tf * ef.ieps;
+    f[0] = ff[0] + (R(-5.0 / 3.0) * dep - R(2.0 / 3.0) * duu);
+    g[0] = gf[0] + (R(4.0 / 9.0) * dsT - R(2.0 / 3.0) * dTuu - R(5.0 / 3.0) * dTep);
+    const R fe = R(3) * dep - R(1.5) * duu;                  // even, direction-independent
+    const R ge = dsT - R(1.5) * dTuu + R(3) * dTep;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const R geb = geq_i<R>(i, Tdb, Tb, ubx, uby, eb.ieps, epb, gbx, gby, k);
-        const R gef = geq_i<R>(i, mf.Td, Tf, mf.ux, mf.uy, ef.ieps, epf, mf.gx, mf.gy, k);
-        g[i] = geb + (gf[i] - gef);
+    for (int i = 1; i < 9; ++i) {
+        const R cx = R(CXd[i]), cy = R(CYd[i]), wi = R(Wd(i));
+        const R cub = cx * ubx + cy * uby, cuf = cx * mf.ux + cy * mf.uy;
+        const R cgb = cx * gbx + cy * gby, cgf = cx * mf.gx + cy * mf.gy;
+        f[i] = ff[i] + wi * (fe + R(3) * (cub - cuf) + R(4.5) * (cub * cub * eb.ieps - cuf * cuf * ef.ieps));
+        g[i] = gf[i] + wi * (ge + R(3) * (Tb * cub - Tf * cuf) + R(4.5) * (Tbi * cub * cub - Tfi * cuf * cuf)
+                             + k.sigB * (cgb - cgf));
     }
 
     mb.Td = Tdb;
