@@ -372,7 +372,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 // main launches take the second form: for FP32 the single-grid one holds 137 VGPRs with
 // it and 179 with the first, and the batched one, though it holds 113 VGPRs with the first
 // form against 131, ran 1.7 % slower with it.  The full launches take the first (FP32:
-// 175 VGPRs against 194).
+// 152 VGPRs against 170).
 template <typename S, int LAUNCH, bool PRE>
 __device__ __forceinline__ void march2_any(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr,
                                            const KParams &P, const KParams &Pm, int w, int ncx, int lane,
@@ -389,9 +389,9 @@ __device__ __forceinline__ void march2_any(const S *__restrict__ src, S *__restr
 
 // items: wavefront indices cyi * ncx + cxi of this launch (the main launch lists the xwall
 // wavefronts first, so that they start beside the first lean ones rather than at the tail).
-// The FP64 full launch is held to two waves per SIMD (256 registers, a few spilled): it runs
-// beside the main launch, whose FP64 waves take 217 of a SIMD's 512 registers per lane, and
-// a full wave of more than 295 would wait for a SIMD with no main wave on it.
+// The FP64 full launch is held to two waves per SIMD (at most 256 registers; it needs 236):
+// it runs beside the main launch, whose FP64 waves take 217 of a SIMD's 512 registers per
+// lane, and a full wave of more than 295 would wait for a SIMD with no main wave on it.
 template <typename S, int LAUNCH>
 __global__ void __launch_bounds__(S2_B, (LAUNCH == STEP2_FULL && sizeof(S) == 8) ? 2 : 1)
 k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KParams P, KParams Pm,
