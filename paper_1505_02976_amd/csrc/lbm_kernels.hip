@@ -166,8 +166,8 @@ __device__ __forceinline__ void wall_node(const S *__restrict__ src, S *__restri
 // x = 0, x = nx - 1.  The edge launch covers the rest of those rows in segments of one
 // wavefront with one node per lane (Wspan nodes): [0, xa) and [xb, nx) -- a single segment
 // at each end when the row is at least two segments long, else the whole row -- and the
-// walled rows.  One node per lane keeps the edge instance's registers, and so the share of
-// the edge nodes in the slower wall-aware code, small.
+// walled rows.  One node per lane keeps the edge instance's register count low and leaves
+// fewer nodes to its slower wall-aware code.
 constexpr int EDGE_BX = 64;
 
 struct Cols { int xa, xb, nseg, span_e; bool split; };
