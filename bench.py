@@ -72,8 +72,9 @@ WARMUP_S = 0.5     # minimum wall time of the untimed warm-up (clocks and caches
 
 def warm(sim, warmup, min_s=WARMUP_S):
     """`warmup` untimed steps, then more untimed steps until at least min_s of wall time has
-    passed, so that a short --warmup still starts the timed region at steady clocks.
-    Returns (steps, seconds) of the warm-up."""
+    passed, so that a short --warmup still starts the timed region at steady clocks.  The
+    last two go through step_timed, which creates the timing events outside the timed
+    region.  Returns (steps, seconds) of the warm-up."""
     t0 = time.perf_counter()
     n = warmup
     sim.step(warmup)
@@ -84,6 +85,9 @@ def warm(sim, warmup, min_s=WARMUP_S):
         sim.stream.synchronize()
         n += chunk
         chunk = min(2 * chunk, 512)
+    sim.step_timed(2)
+    sim.stream.synchronize()
+    n += 2
     return n, time.perf_counter() - t0
 
 

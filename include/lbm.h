@@ -167,9 +167,11 @@ int32_t lbm_fusion(const lbm_ctx *ctx);
  * of the wavefronts whose reach holds no wall or only the walls x = 0, x = nx - 1) and of
  * the remaining launches of the pass (for two-step passes these run on a second stream,
  * beside the main launch), the number of nodes the main launch writes, and the steps one
- * pass advances (host outputs; any may be NULL).  An odd last step of a two-step schedule runs untimed.  Used for measurement;
- * events between launches cost a few microseconds per bracketed pass.  Synchronizes on
- * the events, not on the stream. */
+ * pass advances (host outputs; any may be NULL).  An odd last step of a two-step schedule
+ * runs untimed.  Used for measurement; events between launches cost a few microseconds per
+ * bracketed pass.  The first call creates the context's timing events (kept until
+ * lbm_destroy; a call before a timed region keeps their creation out of it).
+ * Synchronizes on the events, not on the stream. */
 lbm_status lbm_step_timed(lbm_ctx *ctx, int64_t nsteps, int32_t every, double *main_ms_host,
                           double *rest_ms_host, int64_t *main_nodes_host, int32_t *steps_per_launch_host);
 

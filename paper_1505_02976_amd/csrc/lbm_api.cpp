@@ -201,6 +201,9 @@ void fill_kparams(const lbm_params *p, const lbm_derived &d, lbm::KParams &k)
 
 }  // namespace
 
+// HIP events of one bracketed pass of lbm_step_timed (i: main launch, e: the rest).
+struct StepEvents { hipEvent_t i0, i1, e0, e1; };
+
 struct lbm_ctx {
     lbm_params prm;
     lbm_derived d;
@@ -222,6 +225,9 @@ struct lbm_ctx {
     // there beside the lean launch; events order each launch after both of the previous pass.
     hipStream_t side;
     hipEvent_t ev_join, ev_main, ev_side;
+    // lbm_step_timed's events, created by its first call and kept, so that a timed region
+    // that starts with a call does not also time the host creating them
+    std::vector<StepEvents> tev;
 };
 
 static void *cur_buf(lbm_ctx *c) { return c->ws + (c->cur ? c->lay.off_b : c->lay.off_a); }
@@ -333,7 +339,16 @@ namespace {
 
 // Timing events of one launch group: i0 .. i1 around the main launch, e0 .. e1 around the
 // rest (on the side stream for two-step passes).
-struct StepEvents { hipEvent_t i0, i1, e0, e1; };
+static void destroy_step_events(std::vector<StepEvents> &ev)
+{
+    for (auto &x : ev) {
+        if (x.i0) (void)hipEventDestroy(x.i0);
+        if (x.i1) (void)hipEventDestroy(x.i1);
+        if (x.e0) (void)hipEventDestroy(x.e0);
+        if (x.e1) (void)hipEventDestroy(x.e1);
+    }
+    ev.clear();
+}
 
 hipError_t ensure_side(lbm_ctx *c)
 {
@@ -490,15 +505,21 @@ lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, int32_t every, double *mai
     if (every < 1) return fail(LBM_ERR_INVALID, "every < 1");
     // events are read back in groups so that the stream is not drained after every step
     constexpr int GROUP = 32;
-    std::vector<StepEvents> ev(GROUP);
-    int made = 0;
     hipError_t e = hipSuccess;
-    for (; made < GROUP && e == hipSuccess; ++made) {
-        e = hipEventCreate(&ev[made].i0);
-        if (e == hipSuccess) e = hipEventCreate(&ev[made].i1);
-        if (e == hipSuccess) e = hipEventCreate(&ev[made].e0);
-        if (e == hipSuccess) e = hipEventCreate(&ev[made].e1);
+    if (c->tev.empty()) {
+        c->tev.assign(GROUP, StepEvents{nullptr, nullptr, nullptr, nullptr});
+        for (int k = 0; k < GROUP && e == hipSuccess; ++k) {
+            e = hipEventCreate(&c->tev[k].i0);
+            if (e == hipSuccess) e = hipEventCreate(&c->tev[k].i1);
+            if (e == hipSuccess) e = hipEventCreate(&c->tev[k].e0);
+            if (e == hipSuccess) e = hipEventCreate(&c->tev[k].e1);
+        }
+        if (e != hipSuccess) {
+            destroy_step_events(c->tev);
+            return hip_fail(e, "timing events");
+        }
     }
+    std::vector<StepEvents> &ev = c->tev;
     double tb = 0.0, tw = 0.0;
     int64_t done = 0, sampled = 0;
     // only whole passes are timed; a leftover single step runs untimed at the end
@@ -522,12 +543,6 @@ lbm_status lbm_step_timed(lbm_ctx *c, int64_t nsteps, int32_t every, double *mai
         done += nb;
     }
     if (e == hipSuccess && nsteps > timed) e = run_steps(c, nsteps - timed, nullptr, 1, nullptr);
-    for (auto &x : ev) {
-        if (x.i0) (void)hipEventDestroy(x.i0);
-        if (x.i1) (void)hipEventDestroy(x.i1);
-        if (x.e0) (void)hipEventDestroy(x.e0);
-        if (x.e1) (void)hipEventDestroy(x.e1);
-    }
     if (e != hipSuccess) return hip_fail(e, "timed step");
     if (main_ms) *main_ms = tb / (double)sampled;
     if (rest_ms) *rest_ms = tw / (double)sampled;
@@ -671,6 +686,7 @@ static void release_ctx(lbm_ctx *c)
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->ev_main) (void)hipEventDestroy(c->ev_main);
     if (c->ev_side) (void)hipEventDestroy(c->ev_side);
+    destroy_step_events(c->tev);
     delete c;
 }
 

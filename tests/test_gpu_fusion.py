@@ -91,3 +91,25 @@ def test_fusion_setting(gpu):
     assert big.fusion == 1
     assert gpu.Sim(W.cavity(128, storage="f32")).fusion == 2
     assert gpu.Sim(W.cavity(128, storage="f16")).fusion == 1
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_timed_steps_equal_plain_steps(gpu, storage):
+    """lbm_step_timed advances exactly as lbm_step (the events it brackets passes with do
+    not change the work), over repeated calls that reuse the context's timing events,
+    with an odd count (a two-step schedule's last step single) and a count spanning more
+    than one group of read-back events; it reports positive launch times, the main
+    launch's node count and the steps per pass."""
+    cfg = W.random_case(58, 150, 70, storage=storage, moving_walls=True)
+    a = gpu.Sim(cfg)
+    b = gpu.Sim(cfg)
+    per = a.fusion
+    for n, every in ((2, 1), (7, 1), (600, 1), (33, 8)):
+        main_ms, rest_ms, nodes, k = a.step_timed(n, every)
+        b.step(n)
+        assert k == per
+        assert main_ms > 0.0 and rest_ms >= 0.0
+        assert 0 < nodes <= cfg["nx"] * cfg["ny"]
+        sa, sb = a.get_state(), b.get_state()
+        assert bool((sa == sb).all()), (n, float((sa - sb).abs().max()))
+    assert a.time == b.time == 642
