@@ -196,3 +196,16 @@ def test_null_handles_are_rejected_without_touching_the_device(lbm):
     lib.lbm_destroy(None)
     lib.lbm_batch_destroy(None)
     lib.lbm_adjoint_destroy(None)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more it exits with status 2 and says why,
+    before touching torch or the library."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "8"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and "asked for 8" in r.stderr
+    assert r.stdout == ""
