@@ -246,15 +246,14 @@ __device__ __forceinline__ void node_vjp(const R *f, const R *g, double eps_d, c
 // Steps 1 and 2 at the nodes z off the walls: mu(z) = (dC_z/dpre)^T lambda_{t+1}(z) and the
 // porosity derivative by the reverse-mode product above, one thread per node; streaming is
 // transposed by scattering, lambda_t(z - c_q, q) = mu(z, q) (each entry has exactly one
-// source node z; the wall nodes' part and the wall-reference sums follow in k_adj_wall and
-// k_adj_fix).
+// source node z; the wall nodes' part and the wall-reference sums follow in adj_wall_node and
+// k_adj_fix).  n: the node.
 template <typename S>
-__global__ void __launch_bounds__(ADJ_B)
-k_adj_interior(const S *__restrict__ src, KParams P, AdjBufs A)
+__device__ __forceinline__ void adj_interior_node(const S *__restrict__ src, const KParams &P, const AdjBufs &A,
+                                                  long long n)
 {
     using R = typename Prec<S>::R;
     const long long N = (long long)P.nx * P.ny;
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     const int x = int(n % P.nx), y = int(n / P.nx);
     if (on_wall(P, x, y)) return;
@@ -285,8 +284,8 @@ k_adj_interior(const S *__restrict__ src, KParams P, AdjBufs A)
 // (sum_{i>0} f, j, Pxx, Pyy, Pxy of f; sum g and the first moment of g).  Its Jacobian is
 // therefore taken by forward-mode dual numbers along nine population directions e_k with
 // unit moment k (and zero other moments), plus T(x_ff), eps(x_b) and eps(x_f): 12 passes of
-// the same templated boundary-scheme code as the forward step, column k in block
-// blockIdx.y.  wf[k] receives the adjoint a_k of moment k (the pass's product with lambda
+// the same templated boundary-scheme code as the forward step, column j = k for wall slot
+// s.  wf[k] receives the adjoint a_k of moment k (the pass's product with lambda
 // less its direct part); k_adj_fix rebuilds the adjoint of each reference population from
 // them (wall_ref_mu).  Every output has one writer.
 constexpr int ADJ_WCOLS = 12;
@@ -305,15 +304,13 @@ __device__ constexpr double ADJ_EK[9][9] = {
 };
 
 template <typename S>
-__global__ void __launch_bounds__(ADJ_WB)
-k_adj_wall(const S *__restrict__ src, KParams P, AdjBufs A)
+__device__ __forceinline__ void adj_wall_node(const S *__restrict__ src, const KParams &P, const AdjBufs &A, int s,
+                                              int j)
 {
     const long long N = (long long)P.nx * P.ny;
     int x, y;
-    const int s = blockIdx.x * ADJ_WB + threadIdx.x;
     if (s >= P.nwall || !wall_slot(P, s, x, y)) return;
     const long long n = (long long)y * P.nx + x;
-    const int j = blockIdx.y;
     double lam[18];
 #pragma unroll
     for (int q = 0; q < 18; ++q) lam[q] = A.lam_next[q * N + n];
@@ -370,6 +367,23 @@ k_adj_wall(const S *__restrict__ src, KParams P, AdjBufs A)
             if (zx < 0 || zx >= P.nx || zy < 0 || zy >= P.ny) A.lam[q * N + n] = 0.0;
         }
     }
+}
+
+// Steps 1 and 2 in one launch of 64-thread blocks: blocks [0, 12 nwb) take the wall nodes'
+// Jacobian columns (wall slot (b % nwb) * 64 + lane, column b / nwb), the longest work,
+// first; the remaining blocks the nodes off the walls.  The two parts write disjoint
+// entries (each adjoint entry has one source node; grad and the wall arrays per node), so
+// they run side by side.
+template <typename S>
+__global__ void __launch_bounds__(ADJ_WB)
+k_adj_step(const S *__restrict__ src, KParams P, AdjBufs A, int nwb)
+{
+    const int b = blockIdx.x;
+    if (b < nwb * ADJ_WCOLS) {
+        adj_wall_node<S>(src, P, A, (b % nwb) * ADJ_WB + (int)threadIdx.x, b / nwb);
+        return;
+    }
+    adj_interior_node<S>(src, P, A, (long long)(b - nwb * ADJ_WCOLS) * ADJ_WB + threadIdx.x);
 }
 
 // Adjoint of the wall node b's update with respect to population q of its reference node's
@@ -436,7 +450,7 @@ __device__ __forceinline__ void band_node(const KParams &P, long long b, int &x,
 // adjoints with respect to the pulled populations of their reference node z = y + c_q, and
 // T(x_ff); for q = 0, eps(y) gains the wall nodes' adjoints with respect to the porosity of
 // their reference node y.  One thread per band node and direction (q = blockIdx.y), after
-// k_adj_interior and k_adj_wall.
+// k_adj_step (both parts).
 __global__ void __launch_bounds__(ADJ_B) k_adj_fix(KParams P, AdjBufs A)
 {
     const long long N = (long long)P.nx * P.ny;
@@ -484,11 +498,11 @@ template <typename S>
 static hipError_t adj_step_t(const void *state, const KParams &P, const AdjBufs &A, hipStream_t st)
 {
     const long long N = (long long)P.nx * P.ny;
-    const int nb = int((N + ADJ_B - 1) / ADJ_B);
-    hipLaunchKernelGGL((k_adj_interior<S>), dim3(nb), dim3(ADJ_B), 0, st, (const S *)state, P, A);
+    const int nwb = (P.nwall + ADJ_WB - 1) / ADJ_WB;
+    const long long nb = nwb * ADJ_WCOLS + (N + ADJ_WB - 1) / ADJ_WB;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_adj_step<S>), dim3((unsigned)nb), dim3(ADJ_WB), 0, st, (const S *)state, P, A, nwb);
     if (P.nwall > 0) {
-        hipLaunchKernelGGL((k_adj_wall<S>), dim3((P.nwall + ADJ_WB - 1) / ADJ_WB, ADJ_WCOLS), dim3(ADJ_WB), 0, st,
-                           (const S *)state, P, A);
         const long long nband = band_size(P);
         hipLaunchKernelGGL(k_adj_fix, dim3(unsigned((nband + ADJ_B - 1) / ADJ_B), 18), dim3(ADJ_B), 0, st, P, A);
     }
