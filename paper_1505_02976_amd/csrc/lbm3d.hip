@@ -493,22 +493,22 @@ __host__ __device__ __forceinline__ int inner_x(const K3 &K) { return K.px ? K.n
 __host__ __device__ __forceinline__ int inner_y(const K3 &K) { return K.py ? K.ny : K.ny - 2; }
 __host__ __device__ __forceinline__ int inner_z(const K3 &K) { return K.pz ? K.nz : K.nz - 2; }
 
-// One time step, pull, state, collide, store, in two launches: the interior nodes (no
-// boundary-scheme code, so fewer registers and more waves per SIMD) and the wall nodes.
-// Interior launch: blockIdx.y is the interior plane, blockIdx.x * B3 + threadIdx.x the node
-// within the plane's interior (32-bit index arithmetic: planes and the grid stay below 2^31
-// nodes, and the interior planes below 65536, checked on the host).
-// FP32 and FP16: at most 128 registers, four waves per SIMD.
+// One time step, pull, state, collide, store, in one launch: its first blocks take the
+// wall nodes (boundary scheme), the remaining ones the interior nodes (no boundary-scheme
+// code).  Run side by side, the short wall blocks no longer add a launch of their own to
+// every step.
+// Interior node i of interior plane `plane` (32-bit index arithmetic: planes and the grid
+// stay below 2^31 nodes, checked on the host).
 template <typename S>
-__global__ void __launch_bounds__(B3, sizeof(S) == 8 ? 2 : 4) k3_step_interior(const S *__restrict__ src, S *__restrict__ dst, K3 K)
+__device__ __forceinline__ void k3_interior_node(const S *__restrict__ src, S *__restrict__ dst, const K3 &K,
+                                                 unsigned i, int plane)
 {
     using R = typename Arith<S>::R;
     const unsigned nxi = (unsigned)inner_x(K), nyi = (unsigned)inner_y(K);
-    const unsigned i = blockIdx.x * B3 + threadIdx.x;
     if (i >= nxi * nyi) return;
     const unsigned yi = i / nxi;
     const int x = (int)(i - yi * nxi) + (K.px ? 0 : 1), y = (int)yi + (K.py ? 0 : 1);
-    const int z = (int)blockIdx.y + (K.pz ? 0 : 1);
+    const int z = plane + (K.pz ? 0 : 1);
     const unsigned k = ((unsigned)z * (unsigned)K.ny + (unsigned)y) * (unsigned)K.nx + (unsigned)x;
     R f[NQ], g[NQ];
     Mac<R> m;
@@ -518,14 +518,16 @@ __global__ void __launch_bounds__(B3, sizeof(S) == 8 ? 2 : 4) k3_step_interior(c
     store<S, R>(dst, K, k, f, g);
 }
 
+// Wall node i: the z wall planes first, then the x wall planes less their z rows, then the
+// y wall planes less both.
 template <typename S>
-__global__ void __launch_bounds__(B3) k3_step_walls(const S *__restrict__ src, S *__restrict__ dst, K3 K)
+__device__ __forceinline__ void k3_wall_node(const S *__restrict__ src, S *__restrict__ dst, const K3 &K,
+                                             long long i)
 {
     using R = typename Arith<S>::R;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long plane = (long long)K.nx * K.ny, zn = K.pz ? 0 : 2 * plane;   // z wall planes first
-    const long long xside = K.px ? 0 : (long long)K.ny * inner_z(K);             // then the x wall planes less their z rows
-    const long long yside = K.py ? 0 : (long long)inner_x(K) * inner_z(K);       // then the y wall planes less both
+    const long long plane = (long long)K.nx * K.ny, zn = K.pz ? 0 : 2 * plane;
+    const long long xside = K.px ? 0 : (long long)K.ny * inner_z(K);
+    const long long yside = K.py ? 0 : (long long)inner_x(K) * inner_z(K);
     if (i >= zn + 2 * xside + 2 * yside) return;
     int x, y, z;
     if (i < zn) {
@@ -550,6 +552,22 @@ __global__ void __launch_bounds__(B3) k3_step_walls(const S *__restrict__ src, S
     node_state<S, R>(src, K, x, y, z, f, g, m, e);
     collide<R>(f, g, m, K, e);
     store<S, R>(dst, K, (unsigned)k, f, g);
+}
+
+// Blocks [0, nbw): wall nodes; then nbx blocks per interior plane.  Registers held to the
+// interior's own count (FP32/FP16 five waves per SIMD, FP64 three); the wall blocks, 2 %
+// of the nodes, absorb any spill.
+template <typename S>
+__global__ void __launch_bounds__(B3, sizeof(S) == 8 ? 3 : 5)
+k3_step(const S *__restrict__ src, S *__restrict__ dst, K3 K, unsigned nbw, unsigned nbx)
+{
+    const unsigned b = blockIdx.x;
+    if (b < nbw) {
+        k3_wall_node<S>(src, dst, K, (long long)b * B3 + threadIdx.x);
+        return;
+    }
+    const unsigned bi = b - nbw, plane = bi / nbx, bx = bi - plane * nbx;
+    k3_interior_node<S>(src, dst, K, bx * B3 + threadIdx.x, (int)plane);
 }
 
 // Initial post-collision populations: the equilibria of the initial fields (S = 0,
@@ -870,16 +888,17 @@ lbm_status lbm3_step(lbm3_ctx *c, int64_t nsteps)
     if (nsteps < 0) return fail3(LBM_ERR_INVALID, "nsteps must be >= 0");
     const K3 &K = c->K;
     const long long n_plane = (long long)inner_x(K) * inner_y(K), n_w = K.n - n_plane * inner_z(K);
-    const dim3 nb_in(blocks_for(n_plane), (unsigned)inner_z(K));
-    const unsigned nb_w = blocks_for(n_w);
+    const unsigned nbx = n_plane > 0 ? blocks_for(n_plane) : 0, nbw = blocks_for(n_w);
+    const long long nb = (long long)nbw + (long long)nbx * (n_plane > 0 ? inner_z(K) : 0);
+    if (nb > 0x7fffffff) return fail3(LBM_ERR_INVALID, "grid too large for one launch");
     for (int64_t s = 0; s < nsteps; ++s) {
         by_storage(c->storage, [&](auto t) {
             using S = typename decltype(t)::type;
             const S *src = reinterpret_cast<const S *>(c->buf[c->cur]);
             S *dst = reinterpret_cast<S *>(c->buf[c->cur ^ 1]);
-            if (n_plane > 0 && inner_z(K) > 0)
-                hipLaunchKernelGGL((k3_step_interior<S>), nb_in, dim3(B3), 0, c->stream, src, dst, c->K);
-            if (n_w) hipLaunchKernelGGL((k3_step_walls<S>), dim3(nb_w), dim3(B3), 0, c->stream, src, dst, c->K);
+            if (nb > 0)
+                hipLaunchKernelGGL((k3_step<S>), dim3((unsigned)nb), dim3(B3), 0, c->stream, src, dst, c->K, nbw,
+                                   nbx > 0 ? nbx : 1u);
         });
         c->cur ^= 1;
         c->t += 1;
