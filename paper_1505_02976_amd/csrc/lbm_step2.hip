@@ -161,8 +161,13 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // One wavefront's walk: column chunk cxi, row band cyi.  lds: S2_LDS values of the
-// wavefront's own (xwall instance only).
-template <typename S, int MODE, bool PRE>
+// wavefront's own (xwall instance only).  PRIO: the wavefront raises its issue priority
+// while it issues the next row's loads (lean and xwall instances with the row gathered
+// ahead), so that they leave before the arithmetic of the other wavefronts on its SIMD.
+// The single-grid launch takes it (FP32 on the 4096^2 cavity: 533 against 536 us); the
+// batched one ran 0.4 % slower with it, and FP16's one-step kernel, bound by vector
+// issue, 5 % slower with the same around its gathers.
+template <typename S, int MODE, bool PRE, bool PRIO = false>
 __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr,
                                        const KParams &P, const KParams &Pm, int cxi, int cyi, int lane,
                                        typename Prec<S>::R *lds)
@@ -221,7 +226,9 @@ __device__ __forceinline__ void march2(const S *__restrict__ src, S *__restrict_
             if constexpr (PF) {
 #pragma unroll
                 for (int i = 0; i < 9; ++i) { f[i] = nf[i]; g[i] = ng[i]; }
+                if constexpr (PRIO) __builtin_amdgcn_s_setprio(3);
                 if (yy < Y1) gather<S, R>(src, P, xs, P.py ? (yy + 1) % P.ny : yy + 1, nf, ng);
+                if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
             } else {
                 gather<S, R>(src, P, xs, yr, f, g);
             }
@@ -373,7 +380,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 // it and 179 with the first, and the batched one, though it holds 113 VGPRs with the first
 // form against 131, ran 1.7 % slower with it.  The full launches take the first (FP32:
 // 152 VGPRs against 170).
-template <typename S, int LAUNCH, bool PRE>
+template <typename S, int LAUNCH, bool PRE, bool PRIO = false>
 __device__ __forceinline__ void march2_any(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr,
                                            const KParams &P, const KParams &Pm, int w, int ncx, int lane,
                                            typename Prec<S>::R *lds)
@@ -382,9 +389,9 @@ __device__ __forceinline__ void march2_any(const S *__restrict__ src, S *__restr
     if constexpr (LAUNCH == STEP2_FULL)
         march2<S, STEP2_FULL, PRE>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
     else if (s2_kind(P, cxi, cyi) == STEP2_XWALL)     // wavefront-uniform
-        march2<S, STEP2_XWALL, PRE>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
+        march2<S, STEP2_XWALL, PRE, PRIO>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
     else
-        march2<S, STEP2_LEAN, PRE>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
+        march2<S, STEP2_LEAN, PRE, PRIO>(src, dst, scr, P, Pm, cxi, cyi, lane, lds);
 }
 
 // items: wavefront indices cyi * ncx + cxi of this launch (the main launch lists the xwall
@@ -401,7 +408,8 @@ k_step2(const S *__restrict__ src, S *__restrict__ dst, S *__restrict__ scr, KPa
     __shared__ R lds[S2_B / 64][LAUNCH == STEP2_FULL ? 1 : S2_LDS];
     const int wi = xcd_block(blockIdx.x, gridDim.x) * (S2_B / 64) + (threadIdx.x >> 6);
     if (wi >= nitems) return;                            // wavefront-uniform
-    march2_any<S, LAUNCH, LAUNCH == STEP2_FULL>(src, dst, scr, P, Pm, items[wi], ncx, threadIdx.x & 63, lds[threadIdx.x >> 6]);
+    march2_any<S, LAUNCH, LAUNCH == STEP2_FULL, true>(src, dst, scr, P, Pm, items[wi], ncx, threadIdx.x & 63,
+                                                     lds[threadIdx.x >> 6]);
 }
 
 // Batched: item (problem, wavefront index); one item list per launch.  The block holds
